@@ -1,0 +1,269 @@
+"""ctypes front end of the C oracle (``oracle.c``) -- TEST INFRASTRUCTURE ONLY.
+
+Every function takes and returns numpy complex128 arrays in the canonical
+layouts (see ``oracle.c``).  The library is compiled with gcc by ``build()``;
+``lib()`` compiles it on first use when it is missing or older than its source.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+SO = os.path.join(HERE, "liboracle.so")
+
+_lib = None
+
+_d = C.c_double
+_i = C.c_int
+_l = C.c_long
+_p = C.c_void_p
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP)."""
+    if force or not os.path.exists(SO) or os.path.getmtime(SO) < os.path.getmtime(SRC):
+        tmp = SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, SO)
+    return SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(SO)
+        sig = {
+            "or_gamma": [_i, _p],
+            "or_dirichlet": [_p, _p, _p, _p],
+            "or_hop": [_p, _i, _p, _p, _p, _i],
+            "or_dw": [_p, _i, _d, _p, _p, _p, _i],
+            "or_p5": [_l, _i, _d, _p, _p, _i],
+            "or_d5": [_p, _i, _d, _d, _d, _d, _p, _p, _p, _i],
+            "or_pick": [_p, _i, _p, _i, _p],
+            "or_embed": [_p, _i, _p, _i, _p],
+            "or_mooee": [_l, _i, _d, _d, _d, _d, _p, _p, _i],
+            "or_mooeeinv": [_l, _i, _d, _d, _d, _d, _p, _p, _i],
+            "or_meo": [_p, _i, _d, _d, _d, _d, _p, _p, _i, _p, _i],
+            "or_mpc": [_p, _i, _d, _d, _d, _d, _p, _p, _p, _i],
+            "or_cgne": [_p, _i, _d, _d, _d, _d, _p, _p, _p, _d, _i, _i, _p],
+            "or_schur_source": [_p, _i, _d, _d, _d, _d, _p, _p, _p],
+            "or_multishift": [_p, _i, _d, _d, _d, _d, _p, _p, _i, _p, _p, _d, _i, _p, _p],
+            "or_ptc_layer": [_p, _i, _p, _i, _i, _p, _p, _p],
+            "or_ptc_layer_backward": [_p, _i, _p, _i, _i, _p, _p, _p, _p, _p],
+            "or_net_apply": [_p, _i, _p, _i, _p, _p, _p, _p],
+            "or_fgcr": [_p, _i, _d, _d, _d, _d, _p, _i, _p, _p, _p, _p, _d, _i, _i, _i, _p],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = _i if name in ("or_cgne", "or_multishift", "or_fgcr") else None
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _dims(L):
+    return np.ascontiguousarray(L, dtype=np.int32)
+
+
+class Params:
+    """Moebius domain-wall parameters on a 4D lattice of extents L (all even)."""
+
+    def __init__(self, L, Ls, b, c, M5, mf):
+        self.L = tuple(int(x) for x in L)
+        self.Ls, self.b, self.c, self.M5, self.mf = int(Ls), float(b), float(c), float(M5), float(mf)
+        self._L = _dims(self.L)
+
+    @property
+    def V(self):
+        return int(np.prod(self.L))
+
+    def full_shape(self):
+        return (self.V, self.Ls, 4, 3)
+
+    def half_shape(self):
+        return (self.V // 2, self.Ls, 4, 3)
+
+    def args(self):
+        return (self.b, self.c, self.M5, self.mf)
+
+
+def gamma(mu: int) -> np.ndarray:
+    """gamma_mu (mu = 0..3 for x,y,z,t) or gamma_5 (mu = 4), 4x4."""
+    out = np.zeros((4, 4), dtype=np.complex128)
+    lib().or_gamma(mu, _ptr(out))
+    return out
+
+
+def dirichlet(L, U, mask) -> np.ndarray:
+    U = _c128(U)
+    out = np.empty_like(U)
+    lib().or_dirichlet(_ptr(_dims(L)), _ptr(np.ascontiguousarray(mask, dtype=np.int32)), _ptr(U), _ptr(out))
+    return out
+
+
+def hop(P: Params, U, psi, dagger=False) -> np.ndarray:
+    U, psi = _c128(U), _c128(psi)
+    out = np.empty_like(psi)
+    lib().or_hop(_ptr(P._L), P.Ls, _ptr(U), _ptr(psi), _ptr(out), int(dagger))
+    return out
+
+
+def dw(P: Params, U, psi, dagger=False) -> np.ndarray:
+    U, psi = _c128(U), _c128(psi)
+    out = np.empty_like(psi)
+    lib().or_dw(_ptr(P._L), P.Ls, P.M5, _ptr(U), _ptr(psi), _ptr(out), int(dagger))
+    return out
+
+
+def p5(P: Params, psi, dagger=False) -> np.ndarray:
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    lib().or_p5(psi.shape[0], P.Ls, P.mf, _ptr(psi), _ptr(out), int(dagger))
+    return out
+
+
+def d5(P: Params, U, psi, dagger=False) -> np.ndarray:
+    U, psi = _c128(U), _c128(psi)
+    out = np.empty_like(psi)
+    lib().or_d5(_ptr(P._L), P.Ls, *P.args(), _ptr(U), _ptr(psi), _ptr(out), int(dagger))
+    return out
+
+
+def pick(P: Params, full, parity) -> np.ndarray:
+    full = _c128(full)
+    out = np.empty(P.half_shape(), dtype=np.complex128)
+    lib().or_pick(_ptr(P._L), P.Ls, _ptr(full), int(parity), _ptr(out))
+    return out
+
+
+def embed(P: Params, half, parity) -> np.ndarray:
+    half = _c128(half)
+    out = np.empty(P.full_shape(), dtype=np.complex128)
+    lib().or_embed(_ptr(P._L), P.Ls, _ptr(half), int(parity), _ptr(out))
+    return out
+
+
+def mooee(P: Params, psi, dagger=False) -> np.ndarray:
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    lib().or_mooee(psi.shape[0], P.Ls, *P.args(), _ptr(psi), _ptr(out), int(dagger))
+    return out
+
+
+def mooeeinv(P: Params, psi, dagger=False) -> np.ndarray:
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    lib().or_mooeeinv(psi.shape[0], P.Ls, *P.args(), _ptr(psi), _ptr(out), int(dagger))
+    return out
+
+
+def meo(P: Params, U, half, p_in, dagger=False) -> np.ndarray:
+    """Block of D5 (or D5^+) from parity p_in to parity 1-p_in."""
+    U, half = _c128(U), _c128(half)
+    out = np.empty(P.half_shape(), dtype=np.complex128)
+    lib().or_meo(_ptr(P._L), P.Ls, *P.args(), _ptr(U), _ptr(half), int(p_in), _ptr(out), int(dagger))
+    return out
+
+
+def mpc(P: Params, U, odd, dagger=False) -> np.ndarray:
+    U, odd = _c128(U), _c128(odd)
+    out = np.empty_like(odd)
+    lib().or_mpc(_ptr(P._L), P.Ls, *P.args(), _ptr(U), _ptr(odd), _ptr(out), int(dagger))
+    return out
+
+
+def schur_source(P: Params, U, b_full) -> np.ndarray:
+    U, b_full = _c128(U), _c128(b_full)
+    out = np.empty(P.half_shape(), dtype=np.complex128)
+    lib().or_schur_source(_ptr(P._L), P.Ls, *P.args(), _ptr(U), _ptr(b_full), _ptr(out))
+    return out
+
+
+def cgne(P: Params, U, b_full, tol, maxit=100000, x0=None):
+    """Red-black CGNE solve of D5 x = b. Returns (x_full, iters, [res_normal, res_schur, res_full])."""
+    U, b_full = _c128(U), _c128(b_full)
+    x = np.zeros_like(b_full) if x0 is None else _c128(x0).copy()
+    res = np.zeros(3)
+    it = lib().or_cgne(_ptr(P._L), P.Ls, *P.args(), _ptr(U), _ptr(b_full), _ptr(x), float(tol), int(maxit),
+                       int(x0 is not None), _ptr(res))
+    return x, it, res
+
+
+def multishift(P: Params, U, b_odd, shifts, tol, maxit=100000):
+    """Multi-shift CG on Mpc^+Mpc + sigma_k.  Returns (x[k], base_iters, iters_k, res_k)."""
+    U, b_odd = _c128(U), _c128(b_odd)
+    shifts = np.ascontiguousarray(shifts, dtype=np.float64)
+    n = len(shifts)
+    x = np.zeros((n,) + b_odd.shape, dtype=np.complex128)
+    iters = np.zeros(n, dtype=np.int32)
+    res = np.zeros(n)
+    it = lib().or_multishift(_ptr(P._L), P.Ls, *P.args(), _ptr(U), _ptr(b_odd), n, _ptr(shifts), _ptr(x),
+                             float(tol), int(maxit), _ptr(iters), _ptr(res))
+    return x, it, iters, res
+
+
+NPATH = 11
+
+
+def ptc_layer(L, Ls, U, W, phi):
+    """One parallel-transport convolution layer. W: (11, Cout, Cin); phi: (V, Ls, Cin, 3)."""
+    U, W, phi = _c128(U), _c128(W), _c128(phi)
+    npath, cout, cin = W.shape
+    out = np.empty(phi.shape[:2] + (cout, 3), dtype=np.complex128)
+    lib().or_ptc_layer(_ptr(_dims(L)), int(Ls), _ptr(U), cin, cout, _ptr(W), _ptr(phi), _ptr(out))
+    return out
+
+
+def ptc_layer_backward(L, Ls, U, W, phi, gout, want_in=True, want_w=True):
+    """Real-pair gradients (dL/dRe + i dL/dIm) of one layer: returns (g_in, g_W)."""
+    U, W, phi, gout = _c128(U), _c128(W), _c128(phi), _c128(gout)
+    npath, cout, cin = W.shape
+    gin = np.empty_like(phi) if want_in else None
+    gW = np.zeros_like(W) if want_w else None
+    lib().or_ptc_layer_backward(_ptr(_dims(L)), int(Ls), _ptr(U), cin, cout, _ptr(W), _ptr(phi), _ptr(gout),
+                                _ptr(gin), _ptr(gW))
+    return gin, gW
+
+
+def net_apply(P: Params, U, weights, odd):
+    """Network preconditioner on an odd half field. weights: list of (11, Cout, Cin) arrays."""
+    U, odd = _c128(U), _c128(odd)
+    chans = np.array([weights[0].shape[2]] + [w.shape[1] for w in weights], dtype=np.int32)
+    W = np.concatenate([_c128(w).ravel() for w in weights])
+    out = np.empty_like(odd)
+    lib().or_net_apply(_ptr(P._L), P.Ls, _ptr(U), len(weights), _ptr(chans), _ptr(W), _ptr(odd), _ptr(out))
+    return out
+
+
+def fgcr(P: Params, U, b_odd, tol, maxit=10000, m=16, weights=None, normal=False):
+    """Flexible GCR(m) on Mpc x = b (or Mpc^+ Mpc x = b when ``normal``), optionally
+    right-preconditioned by the network."""
+    U, b_odd = _c128(U), _c128(b_odd)
+    x = np.zeros_like(b_odd)
+    res = np.zeros(1)
+    if weights:
+        chans = np.array([weights[0].shape[2]] + [w.shape[1] for w in weights], dtype=np.int32)
+        W = np.concatenate([_c128(w).ravel() for w in weights])
+        nl = len(weights)
+    else:
+        chans = np.zeros(1, dtype=np.int32)
+        W = np.zeros(1, dtype=np.complex128)
+        nl = 0
+    it = lib().or_fgcr(_ptr(P._L), P.Ls, *P.args(), _ptr(U), nl, _ptr(chans), _ptr(W), _ptr(b_odd), _ptr(x),
+                       float(tol), int(maxit), int(m), int(normal), _ptr(res))
+    return x, it, res[0]

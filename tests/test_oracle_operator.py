@@ -1,0 +1,212 @@
+"""Pins of the oracle's operator against closed forms and invariants.
+
+Nothing here compares the oracle with a retyped copy of itself.  Each test
+checks a fact fixed by the mathematics:
+
+* the gamma table satisfies the Clifford algebra and gamma5 = g1 g2 g3 g4 is
+  diagonal (chiral basis);
+* free field: the Wilson kernel on a plane wave is the textbook momentum-space
+  symbol 4 - M5 - sum cos p + i sum gamma sin p (pins hop sign and normalisation);
+* Ls = 1 Shamir reduces D5 to the Wilson-Dirac operator of mass 1 - M5 + mf;
+* the Moebius determinant ratio det D5(mf)/det D5(1) equals the determinant of
+  the 4D overlap-type operator (1+mf)/2 + (1-mf)/2 g5 eps_Ls(H_M), with
+  H_M = g5 (b+c) D_W / ((b-c) D_W + 2) (pins b, c, mf and the s structure);
+* adjoints (<y, A x> = <A^+ y, x>) and gamma5-R5 hermiticity;
+* gauge covariance under random SU(3) rotations (pins link placement).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Params
+from paper_2203_17119_amd import synth
+from helpers import coords, dense_matrix, gauge_rotate, parity_sites, relerr
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+MOB = dict(b=1.5, c=0.5, M5=1.8)
+
+
+def unit_gauge(L):
+    V = int(np.prod(L))
+    U = np.zeros((V, 4, 3, 3), dtype=np.complex128)
+    U[:, :, 0, 0] = U[:, :, 1, 1] = U[:, :, 2, 2] = 1.0
+    return U
+
+
+# --------------------------------------------------------------- gammas
+
+def test_gamma_clifford_and_chiral_basis():
+    g = [oracle.gamma(mu) for mu in range(4)]
+    for m in range(4):
+        assert np.allclose(g[m], g[m].conj().T)
+        for n in range(4):
+            assert np.allclose(g[m] @ g[n] + g[n] @ g[m], 2.0 * np.eye(4) * (m == n))
+    g5 = g[0] @ g[1] @ g[2] @ g[3]
+    assert np.allclose(oracle.gamma(4), g5)
+    assert np.allclose(g5, np.diag([1, 1, -1, -1]))
+
+
+def test_gamma_table_is_the_documented_basis():
+    # convention of the library: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_t = [[0, 1], [1, 0]]
+    sig = [np.array([[0, 1], [1, 0]]), np.array([[0, -1j], [1j, 0]]), np.array([[1, 0], [0, -1]])]
+    Z = np.zeros((2, 2))
+    for k in range(3):
+        expect = np.block([[Z, -1j * sig[k]], [1j * sig[k], Z]])
+        assert np.allclose(oracle.gamma(k), expect)
+    assert np.allclose(oracle.gamma(3), np.block([[Z, np.eye(2)], [np.eye(2), Z]]))
+
+
+# --------------------------------------------------------------- free field
+
+@pytest.mark.parametrize("nvec", [(0, 0, 0, 0), (1, 0, 0, 0), (0, 1, 1, 0), (1, 2, 1, 3), (3, 5, 1, 7)])
+def test_free_field_plane_wave(nvec, rng):
+    L = (4, 6, 2, 8)
+    Ls, M5 = 3, 1.8
+    P = Params(L, Ls, 1.0, 0.0, M5, 0.0)
+    p = 2 * np.pi * np.array(nvec) / np.array(L)
+    x = coords(L)
+    phase = np.exp(1j * (x @ p))
+    u = rng.standard_normal((Ls, 4)) + 1j * rng.standard_normal((Ls, 4))
+    col = 1
+    psi = np.zeros(P.full_shape(), dtype=np.complex128)
+    psi[:, :, :, col] = phase[:, None, None] * u[None]
+    g = [oracle.gamma(mu) for mu in range(4)]
+    symbol = (4 - M5 - np.sum(np.cos(p))) * np.eye(4) + 1j * sum(g[mu] * np.sin(p[mu]) for mu in range(4))
+    expect = np.zeros_like(psi)
+    expect[:, :, :, col] = phase[:, None, None] * (u @ symbol.T)[None]
+    out = oracle.dw(P, unit_gauge(L), psi)
+    assert relerr(out, expect) < 1e-13
+    # the adjoint kernel has the conjugate symbol
+    out = oracle.dw(P, unit_gauge(L), psi, dagger=True)
+    expect[:, :, :, col] = phase[:, None, None] * (u @ symbol.conj())[None]
+    assert relerr(out, expect) < 1e-13
+
+
+def test_shamir_ls1_is_wilson(rng):
+    L = (2, 4, 2, 4)
+    M5, mf = 1.8, 0.07
+    P = Params(L, 1, 1.0, 0.0, M5, mf)
+    U = synth.gauge_field(L, 0.6, 11)
+    psi = synth.gaussian_fermion(L, 1, 12)
+    mW = 1 - M5 + mf
+    expect = (4 + mW) * psi - 0.5 * oracle.hop(P, U, psi)
+    assert relerr(oracle.d5(P, U, psi), expect) < 1e-14
+
+
+# --------------------------------------------------------------- overlap determinant
+
+@pytest.mark.parametrize("b,c,Ls", [(1.5, 0.5, 4), (1.0, 0.0, 4), (2.0, 1.0, 3)])
+def test_moebius_det_ratio_is_overlap_determinant(b, c, Ls):
+    L = (2, 2, 2, 4)
+    M5 = 1.8
+    U = synth.gauge_field(L, 0.5, 7)
+    P1 = Params(L, 1, 1.0, 0.0, M5, 0.0)
+    DW = dense_matrix(lambda e: oracle.dw(P1, U, e), P1.full_shape())
+    N4 = DW.shape[0]
+    I = np.eye(N4)
+    g5 = np.kron(np.eye(P1.V), np.kron(np.diag([1.0, 1.0, -1.0, -1.0]), np.eye(3)))
+    H = g5 @ ((b + c) * DW) @ np.linalg.inv((b - c) * DW + 2 * I)
+    Ap = np.linalg.matrix_power(I + H, Ls)
+    Am = np.linalg.matrix_power(I - H, Ls)
+    eps = np.linalg.solve(Ap + Am, Ap - Am)  # (1 - T^Ls)/(1 + T^Ls), T = (1+H)^-1 (1-H)
+
+    def logdet_d5(mf):
+        P = Params(L, Ls, b, c, M5, mf)
+        return np.linalg.slogdet(dense_matrix(lambda e: oracle.d5(P, U, e), P.full_shape()))
+
+    s1, l1 = logdet_d5(1.0)
+    for mf in (0.01, 0.3):
+        s, l = logdet_d5(mf)
+        se, le = np.linalg.slogdet((1 + mf) / 2 * I + (1 - mf) / 2 * g5 @ eps)
+        assert abs((l - l1) - le) < 1e-9
+        assert abs(s / s1 - se) < 1e-9
+
+
+# --------------------------------------------------------------- adjoints, hermiticity
+
+def _fields(L, Ls, seed):
+    U = synth.gauge_field(L, 0.8, seed)
+    a = synth.gaussian_fermion(L, Ls, seed + 1)
+    b = synth.gaussian_fermion(L, Ls, seed + 2)
+    return U, a, b
+
+
+def test_adjoints(rng):
+    L, Ls = (2, 4, 2, 6), 5
+    P = Params(L, Ls, **MOB, mf=0.03)
+    U, x, y = _fields(L, Ls, 21)
+    for f in (lambda v, d: oracle.hop(P, U, v, d), lambda v, d: oracle.d5(P, U, v, d),
+              lambda v, d: oracle.p5(P, v, d), lambda v, d: oracle.mooee(P, v, d),
+              lambda v, d: oracle.mooeeinv(P, v, d)):
+        lhs = np.vdot(y, f(x, False))
+        rhs = np.vdot(f(y, True), x)
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs) + 1e-10
+    xo, yo = oracle.pick(P, x, 1), oracle.pick(P, y, 1)
+    lhs = np.vdot(yo, oracle.mpc(P, U, xo))
+    rhs = np.vdot(oracle.mpc(P, U, yo, True), xo)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def _g5r5(psi):
+    out = psi[:, ::-1].copy()
+    out[:, :, 2:] *= -1
+    return out
+
+
+def test_gamma5_r5_hermiticity():
+    L, Ls = (2, 4, 2, 4), 4
+    U, x, _ = _fields(L, Ls, 31)
+    # Shamir (c = 0): exactly Gamma5 R5 hermitian
+    P = Params(L, Ls, 1.0, 0.0, 1.8, 0.02)
+    assert relerr(_g5r5(oracle.d5(P, U, _g5r5(x))), oracle.d5(P, U, x, True)) < 1e-14
+    # Moebius c != 0: not Gamma5 R5 hermitian, but D5^+ = G5R5 (D+ + P5 D-) G5R5
+    P = Params(L, Ls, **MOB, mf=0.02)
+    assert relerr(_g5r5(oracle.d5(P, U, _g5r5(x))), oracle.d5(P, U, x, True)) > 1e-2
+    y = _g5r5(x)
+    dwy = oracle.dw(P, U, y)
+    other = P.b * dwy + y + oracle.p5(P, P.c * dwy - y)
+    assert relerr(_g5r5(other), oracle.d5(P, U, x, True)) < 1e-14
+
+
+def test_dminus_inverse_d5_is_gamma5_r5_hermitian():
+    L, Ls = (2, 2, 2, 4), 3
+    P = Params(L, Ls, **MOB, mf=0.05)
+    U, _, _ = _fields(L, Ls, 41)
+    shape = P.full_shape()
+    D5 = dense_matrix(lambda e: oracle.d5(P, U, e), shape)
+    Dm = dense_matrix(lambda e: P.c * oracle.dw(P, U, e) - e, shape)
+    G = dense_matrix(_g5r5, shape)
+    K = np.linalg.solve(Dm, D5)
+    assert np.abs(G @ K @ G - K.conj().T).max() < 1e-11 * np.abs(K).max()
+
+
+# --------------------------------------------------------------- gauge covariance
+
+def test_gauge_covariance():
+    L, Ls = (4, 2, 2, 4), 4
+    P = Params(L, Ls, **MOB, mf=0.01)
+    U, x, _ = _fields(L, Ls, 51)
+    g = synth.gauge_transform(L, 52)
+    Ug = gauge_rotate(L, U, g)
+    gx = np.einsum("nab,nsib->nsia", g, x)
+    lhs = oracle.d5(P, Ug, gx)
+    rhs = np.einsum("nab,nsib->nsia", g, oracle.d5(P, U, x))
+    assert relerr(lhs, rhs) < 1e-14
+    # the odd Schur complement inherits it (sites are rotated parity by parity)
+    xo = oracle.pick(P, x, 1)
+    go = g[parity_sites(L, 1)]
+    lhs = oracle.mpc(P, Ug, np.einsum("nab,nsib->nsia", go, xo))
+    rhs = np.einsum("nab,nsib->nsia", go, oracle.mpc(P, U, xo))
+    assert relerr(lhs, rhs) < 1e-13
+
+
+def test_dirichlet_mask_zeroes_only_face_links():
+    L = (4, 2, 6, 4)
+    U = synth.gauge_field(L, 0.5, 61)
+    Ud = oracle.dirichlet(L, U, (1, 0, 1, 0))
+    x = coords(L)
+    for mu in range(4):
+        face = (x[:, mu] == L[mu] - 1) & (mu in (0, 2))
+        assert np.all(Ud[face, mu] == 0)
+        assert np.array_equal(Ud[~face, mu], U[~face, mu])

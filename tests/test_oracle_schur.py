@@ -1,0 +1,126 @@
+"""Pins of the oracle's red-black and Dirichlet-block structure.
+
+* Mooee^-1 against the closed form of the inverse of d + e S (S^Ls = -mf);
+* det D5 = det Mee * det Mpc (Schur complement on odd sites);
+* the Schur solve plus reconstruction solves D5 x = b (dense solve as judge);
+* the Dirichlet operator (face links zeroed, Sec. 2.4) is the diagonal block
+  D_Omega of the operator on a lattice twice as long, and the determinant
+  identity det D / (det D_Omega det D_Omegabar) = det chi of eq. (schur) and
+  eq. (ddrhmc) holds with chi = 1 - D_Omega^-1 D_d D_Omegabar^-1 D_dbar.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Params
+from paper_2203_17119_amd import synth
+from helpers import coords, dense_matrix, relerr, site_index
+
+MOB = dict(b=1.5, c=0.5, M5=1.8)
+
+
+@pytest.mark.parametrize("Ls,mf,dagger", [(4, 0.01, False), (7, 0.2, False), (6, 0.05, True)])
+def test_mooeeinv_closed_form(Ls, mf, dagger, rng):
+    P = Params((2, 2, 2, 2), Ls, **MOB, mf=mf)
+    d = P.b * (4 - P.M5) + 1
+    e = P.c * (4 - P.M5) - 1
+    a = e / d
+    norm = d * (1 + mf * (-a) ** Ls)
+    # inverse of d + e S on the P+ spins, S row s takes s-1 with S[0, Ls-1] = -mf
+    Mi = np.zeros((Ls, Ls))
+    for s in range(Ls):
+        for t in range(Ls):
+            Mi[s, t] = (-a) ** (s - t) / norm if s >= t else -mf * (-a) ** (s - t + Ls) / norm
+    up, lo = (Mi.T, Mi) if dagger else (Mi, Mi.T)
+    psi = rng.standard_normal((3, Ls, 4, 3)) + 1j * rng.standard_normal((3, Ls, 4, 3))
+    expect = np.empty_like(psi)
+    expect[:, :, :2] = np.einsum("st,ntac->nsac", up, psi[:, :, :2])
+    expect[:, :, 2:] = np.einsum("st,ntac->nsac", lo, psi[:, :, 2:])
+    assert relerr(oracle.mooeeinv(P, psi, dagger), expect) < 1e-13
+    assert relerr(oracle.mooee(P, oracle.mooeeinv(P, psi, dagger), dagger), psi) < 1e-13
+
+
+def test_schur_determinant():
+    L, Ls = (2, 2, 2, 4), 3
+    P = Params(L, Ls, **MOB, mf=0.02)
+    U = synth.gauge_field(L, 0.7, 71)
+    D5 = dense_matrix(lambda e: oracle.d5(P, U, e), P.full_shape())
+    Mpc = dense_matrix(lambda e: oracle.mpc(P, U, e), P.half_shape())
+    Mee = dense_matrix(lambda e: oracle.mooee(P, e), (1, Ls, 4, 3))
+    s1, l1 = np.linalg.slogdet(D5)
+    s2, l2 = np.linalg.slogdet(Mpc)
+    s3, l3 = np.linalg.slogdet(Mee)
+    nh = P.V // 2
+    assert abs(l1 - (l2 + nh * l3)) < 1e-10 * abs(l1)
+    assert abs(s1 - s2 * s3 ** nh) < 1e-9
+
+
+def test_schur_solve_matches_dense_solve():
+    L, Ls = (2, 4, 2, 2), 4
+    P = Params(L, Ls, **MOB, mf=0.05)
+    U = synth.gauge_field(L, 0.6, 81)
+    b = synth.gaussian_fermion(L, Ls, 82)
+    x, it, res = oracle.cgne(P, U, b, 1e-13)
+    assert it > 0
+    D5 = dense_matrix(lambda e: oracle.d5(P, U, e), P.full_shape())
+    xd = np.linalg.solve(D5, b.ravel()).reshape(b.shape)
+    assert relerr(x, xd) < 1e-9
+    assert res[0] < 1e-13 and res[2] < 1e-10
+
+
+def test_cgne_4x4x4x4_ls8_reaches_tolerance():
+    w = synth.WORKLOADS["4^4x8_periodic"]
+    P = Params(w.dims, w.Ls, w.b, w.c, w.M5, w.mf)
+    U = synth.gauge_field(w.dims, w.eps, w.gauge_seed)
+    b = synth.gaussian_fermion(w.dims, w.Ls, w.source_seeds[0])
+    x, it, res = oracle.cgne(P, U, b, w.tol)
+    assert it > 0
+    assert res[0] <= w.tol
+    # the true residual D5 x - b, recomputed from scratch
+    r = b - oracle.d5(P, U, x)
+    assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-7
+    assert abs(np.linalg.norm(r) / np.linalg.norm(b) - res[2]) < 1e-12
+
+
+def _block_map(Lfull, Lblk, origin):
+    """Global lexicographic index of every site of a sub-block in its own lexicographic order."""
+    xb = coords(Lblk)
+    return site_index(np.array(Lfull), xb + np.array(origin))
+
+
+def _dof(sites, Ls):
+    return (sites[:, None] * Ls * 12 + np.arange(Ls * 12)[None]).ravel()
+
+
+@pytest.mark.parametrize("mu", [3, 0])
+def test_dirichlet_block_is_diagonal_block_and_ddrhmc_identity(mu):
+    Ls = 2
+    Lblk = [2, 2, 2, 2]
+    Lfull = list(Lblk)
+    Lfull[mu] *= 2
+    U = synth.gauge_field(Lfull, 0.6, 91)
+    Pf = Params(Lfull, Ls, **MOB, mf=0.1)
+    Pb = Params(Lblk, Ls, **MOB, mf=0.1)
+    D = dense_matrix(lambda e: oracle.d5(Pf, U, e), Pf.full_shape())
+    mask = [0, 0, 0, 0]
+    mask[mu] = 1
+    origins = [[0, 0, 0, 0], [0, 0, 0, 0]]
+    origins[1][mu] = Lblk[mu]
+    blocks = []
+    for org in origins:
+        sites = _block_map(Lfull, Lblk, org)
+        Ub = oracle.dirichlet(Lblk, U[sites], mask)
+        Dd = dense_matrix(lambda e: oracle.d5(Pb, Ub, e), Pb.full_shape())
+        idx = _dof(sites, Ls)
+        assert np.abs(D[np.ix_(idx, idx)] - Dd).max() < 1e-14
+        blocks.append(idx)
+    o, ob = blocks
+    DO, DOb = D[np.ix_(o, o)], D[np.ix_(ob, ob)]
+    Dd_, Ddb = D[np.ix_(o, ob)], D[np.ix_(ob, o)]
+    chi = np.eye(len(o)) - np.linalg.solve(DO, Dd_ @ np.linalg.solve(DOb, Ddb))
+    l_full = np.linalg.slogdet(D)[1]
+    l_dir = np.linalg.slogdet(DO)[1] + np.linalg.slogdet(DOb)[1]
+    l_chi = np.linalg.slogdet(chi)[1]
+    assert abs((l_full - l_dir) - l_chi) < 1e-10 * abs(l_full)
+    # chi differs from one: the boundary determinant is a real factor
+    assert abs(l_chi) > 1e-3
