@@ -1,0 +1,586 @@
+// C ABI of the library: context lifetime, gauge preparation, workspaces,
+// kernel timing and the operator entry points.  Solvers live in solvers.cpp.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dwf_internal.h"
+
+using namespace dwf;
+
+namespace dwf {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &m) { g_err = m; }
+
+[[noreturn]] void fail(dwf_status code, const std::string &m) { throw Error{code, m}; }
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory) fail(DWF_ENOMEM, std::string(what) + ": out of device memory");
+        fail(DWF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+size_t elem_bytes(int prec)
+{
+    switch (prec) {
+    case P_F64: return 16;
+    case P_F32: return 8;
+    default: return 4;
+    }
+}
+
+size_t field_bytes(const Context &c, long n5, int prec)
+{
+    (void)c;
+    size_t b = (size_t)12 * n5 * elem_bytes(prec);
+    if (prec == P_F16) b += (size_t)n5 * sizeof(float);
+    return b;
+}
+
+Field make_field(const Context &c, void *data, int prec)
+{
+    Field f;
+    f.data = data;
+    f.n = c.n5h;
+    f.norm = (prec == P_F16) ? (float *)((char *)data + (size_t)12 * c.n5h * elem_bytes(prec)) : nullptr;
+    return f;
+}
+
+Field ws_field(Context &c, const std::string &name, int prec)
+{
+    const std::string key = name + "#" + std::to_string(prec);
+    auto it = c.ws.find(key);
+    if (it == c.ws.end()) {
+        Context::Buf b;
+        b.bytes = field_bytes(c, c.n5h, prec);
+        HIPCHECK(hipMalloc(&b.data, b.bytes));
+        HIPCHECK(hipMemsetAsync(b.data, 0, b.bytes, c.stream));
+        b.prec = prec;
+        it = c.ws.emplace(key, b).first;
+    }
+    return make_field(c, it->second.data, prec);
+}
+
+const void *slmat(const Context &c, int op, bool f64)
+{
+    const size_t off = (size_t)op * 2 * c.Ls * c.Ls;
+    return f64 ? (const void *)(c.slmat64 + off) : (const void *)(c.slmat32 + off);
+}
+
+Timer::Timer(Context &c_, int k, double by, double fl) : c(c_), kclass(k), bytes(by), flops(fl)
+{
+    if (!c.timing) return;
+    if (c.event_pool.empty()) {
+        hipEvent_t e;
+        HIPCHECK(hipEventCreate(&e));
+        c.event_pool.push_back(e);
+    }
+    a = c.event_pool.back();
+    c.event_pool.pop_back();
+    HIPCHECK(hipEventRecord(a, c.stream));
+}
+
+Timer::~Timer()
+{
+    if (!a) return;
+    if (c.event_pool.empty()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        c.event_pool.push_back(e);
+    }
+    hipEvent_t b = c.event_pool.back();
+    c.event_pool.pop_back();
+    if (hipEventRecord(b, c.stream) != hipSuccess) return;
+    c.pending.push_back(TimedLaunch{kclass, a, b, bytes, flops});
+}
+
+static void drain_timing(Context &c)
+{
+    if (c.pending.empty()) return;
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    for (auto &t : c.pending) {
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, t.a, t.b));
+        KStats &s = c.stats[t.kclass];
+        s.launches++;
+        s.ms += ms;
+        s.bytes += t.bytes;
+        s.flops += t.flops;
+        c.event_pool.push_back(t.a);
+        c.event_pool.push_back(t.b);
+    }
+    c.pending.clear();
+}
+
+void read_scalars(Context &c, int first, int count)
+{
+    HIPCHECK(hipMemcpyAsync(c.hscal + first, c.dscal + first, count * sizeof(double), hipMemcpyDeviceToHost,
+                            c.stream));
+    HIPCHECK(hipStreamSynchronize(c.stream));
+}
+
+// ----------------------------------------------------- s-local matrices
+
+// Upper (P+) and lower (P-) blocks of the fifth-dimension operators.  P5 moves
+// the P+ spins from s-1 and the P- spins from s+1, with -mf at the walls.
+static void build_slocal(Context &c)
+{
+    const int n = c.Ls;
+    const double mf = c.p.mf, b = c.p.b, cc = c.p.c, d = c.d, e = c.e;
+    auto idx = [n](int r, int col) { return (size_t)r * n + col; };
+    std::vector<double> Sup(n * n, 0.0), Slo(n * n, 0.0), I(n * n, 0.0);
+    for (int s = 0; s < n; s++) {
+        I[idx(s, s)] = 1.0;
+        if (s >= 1) Sup[idx(s, s - 1)] += 1.0;
+        else Sup[idx(0, n - 1)] += -mf;
+        if (s + 1 < n) Slo[idx(s, s + 1)] += 1.0;
+        else Slo[idx(n - 1, 0)] += -mf;
+    }
+    auto lin = [&](double a0, double a1, const std::vector<double> &S) {
+        std::vector<double> m(n * n);
+        for (size_t k = 0; k < m.size(); k++) m[k] = a0 * I[k] + a1 * S[k];
+        return m;
+    };
+    auto mul = [&](const std::vector<double> &A, const std::vector<double> &B) {
+        std::vector<double> m(n * n, 0.0);
+        for (int r = 0; r < n; r++)
+            for (int k = 0; k < n; k++)
+                for (int col = 0; col < n; col++) m[idx(r, col)] += A[idx(r, k)] * B[idx(k, col)];
+        return m;
+    };
+    auto tr = [&](const std::vector<double> &A) {
+        std::vector<double> m(n * n);
+        for (int r = 0; r < n; r++)
+            for (int col = 0; col < n; col++) m[idx(r, col)] = A[idx(col, r)];
+        return m;
+    };
+    // closed-form inverse of d + e S_up: S_up^n = -mf, so
+    // (d + e S)^-1 = sum_k (-e/d)^k S^k / (d (1 + mf (-e/d)^n))
+    std::vector<double> Minv(n * n);
+    const double al = -e / d;
+    const double norm = d * (1.0 + mf * std::pow(al, n));
+    for (int s = 0; s < n; s++)
+        for (int t = 0; t < n; t++)
+            Minv[idx(s, t)] = (s >= t) ? std::pow(al, s - t) / norm : -mf * std::pow(al, s - t + n) / norm;
+    std::vector<std::vector<double>> blocks(2 * SL_NOP);
+    auto setop = [&](int op, const std::vector<double> &up, const std::vector<double> &lo) {
+        blocks[2 * op] = up;
+        blocks[2 * op + 1] = lo;
+    };
+    setop(SL_A, lin(b, cc, Sup), lin(b, cc, Slo));
+    setop(SL_ADAG, lin(b, cc, Slo), lin(b, cc, Sup));
+    setop(SL_MOOEE, lin(d, e, Sup), lin(d, e, Slo));
+    setop(SL_MOOEEDAG, lin(d, e, Slo), lin(d, e, Sup));
+    setop(SL_MINV, Minv, tr(Minv));
+    setop(SL_MINVDAG, tr(Minv), Minv);
+    setop(SL_E1, mul(blocks[2 * SL_A], blocks[2 * SL_MINV]), mul(blocks[2 * SL_A + 1], blocks[2 * SL_MINV + 1]));
+    setop(SL_E2, mul(blocks[2 * SL_MINVDAG], blocks[2 * SL_ADAG]),
+          mul(blocks[2 * SL_MINVDAG + 1], blocks[2 * SL_ADAG + 1]));
+    std::vector<double> h64;
+    std::vector<float> h32;
+    for (auto &bl : blocks)
+        for (double v : bl) {
+            h64.push_back(v);
+            h32.push_back((float)v);
+        }
+    if (!c.slmat64) HIPCHECK(hipMalloc(&c.slmat64, h64.size() * sizeof(double)));
+    if (!c.slmat32) HIPCHECK(hipMalloc(&c.slmat32, h32.size() * sizeof(float)));
+    HIPCHECK(hipMemcpy(c.slmat64, h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(c.slmat32, h32.data(), h32.size() * sizeof(float), hipMemcpyHostToDevice));
+}
+
+static void upload_gauge(Context &c, const double *gauge, int on_device)
+{
+    const size_t bytes = (size_t)c.V4 * 4 * 9 * 16;
+    if (!c.gauge_canon) HIPCHECK(hipMalloc(&c.gauge_canon, bytes));
+    HIPCHECK(hipMemcpyAsync(c.gauge_canon, gauge, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                            c.stream));
+    for (int prec = 0; prec < 4; prec++)
+        if (prec == P_F64 || c.links[prec][0]) prepare_links(c, prec);
+    HIPCHECK(hipStreamSynchronize(c.stream));
+}
+
+void ensure_links(Context &c, int prec)
+{
+    if (!c.links[prec][0]) prepare_links(c, prec);
+}
+
+// ---------------------------------------------------------------- Mpc
+
+int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduce, bool in_is_A_applied, Field pa)
+{
+    ensure_links(c, prec);
+    Field y = ws_field(c, "mpc_y", prec);
+    if (!dagger) {
+        Field ta = pa;
+        if (!in_is_A_applied) {
+            ta = ws_field(c, "mpc_ta", prec);
+            launch_slocal(c, prec, SL_A, in, ta);
+        }
+        StencilSpec s1;
+        s1.out_parity = 0;
+        s1.epi = EPI_DENSE;
+        s1.epi_op = SL_E1;
+        launch_stencil(c, prec, s1, ta, Field{}, y);
+        StencilSpec s2;
+        s2.out_parity = 1;
+        s2.self = true;
+        s2.s0 = c.d;
+        s2.s1 = c.e;
+        s2.tau = -0.25;
+        s2.reduce = reduce;
+        return launch_stencil(c, prec, s2, y, in, out);
+    }
+    StencilSpec s1;
+    s1.out_parity = 0;
+    s1.dagger = true;
+    s1.epi = EPI_DENSE;
+    s1.epi_op = SL_E2;
+    launch_stencil(c, prec, s1, in, Field{}, y);
+    StencilSpec s2;
+    s2.out_parity = 1;
+    s2.dagger = true;
+    s2.epi = EPI_SHIFT;
+    s2.e0 = c.p.b;
+    s2.e1 = c.p.c;
+    s2.edag = true;
+    s2.self = true;
+    s2.s0 = c.d;
+    s2.s1 = c.e;
+    s2.sdag = true;
+    s2.tau = -0.25;
+    s2.reduce = reduce;
+    return launch_stencil(c, prec, s2, y, in, out);
+}
+
+int launch_stencil_f64(Context &, const StencilSpec &, Field, Field, Field);
+int launch_stencil_f32(Context &, const StencilSpec &, Field, Field, Field);
+int launch_stencil_f16(Context &, const StencilSpec &, Field, Field, Field);
+int launch_stencil_bf16(Context &, const StencilSpec &, Field, Field, Field);
+void launch_slocal_f64(Context &, int, Field, Field);
+void launch_slocal_f32(Context &, int, Field, Field);
+void launch_slocal_f16(Context &, int, Field, Field);
+void launch_slocal_bf16(Context &, int, Field, Field);
+
+int launch_stencil(Context &c, int prec, const StencilSpec &sp, Field in, Field self, Field out)
+{
+    ensure_links(c, prec);
+    switch (prec) {
+    case P_F64: return launch_stencil_f64(c, sp, in, self, out);
+    case P_F32: return launch_stencil_f32(c, sp, in, self, out);
+    case P_F16: return launch_stencil_f16(c, sp, in, self, out);
+    default: return launch_stencil_bf16(c, sp, in, self, out);
+    }
+}
+
+void launch_slocal(Context &c, int prec, int op, Field in, Field out)
+{
+    switch (prec) {
+    case P_F64: launch_slocal_f64(c, op, in, out); break;
+    case P_F32: launch_slocal_f32(c, op, in, out); break;
+    case P_F16: launch_slocal_f16(c, op, in, out); break;
+    default: launch_slocal_bf16(c, op, in, out); break;
+    }
+}
+
+}  // namespace dwf
+
+// ================================================================ C ABI
+
+#define DWF_API_BEGIN try {
+#define DWF_API_END                              \
+    return DWF_OK;                               \
+    }                                            \
+    catch (const dwf::Error &e)                  \
+    {                                            \
+        dwf::set_error(e.msg);                   \
+        return e.code;                           \
+    }                                            \
+    catch (const std::exception &e)              \
+    {                                            \
+        dwf::set_error(e.what());                \
+        return DWF_ENOMEM;                       \
+    }
+
+static void check_prec(int prec)
+{
+    if (prec < 0 || prec > 3) fail(DWF_EINVAL, "unknown precision");
+}
+
+static dwf::Context &C_(dwf_ctx ctx)
+{
+    if (!ctx) fail(DWF_EINVAL, "null context");
+    return *ctx;
+}
+
+static void require(const void *p, const char *what)
+{
+    if (!p) fail(DWF_EINVAL, std::string("null pointer: ") + what);
+}
+
+extern "C" {
+
+int dwf_abi_version(void) { return 1; }
+
+const char *dwf_last_error(void) { return dwf::g_err.c_str(); }
+
+dwf_status dwf_create(const dwf_params *p, const double *gauge, int gauge_on_device, void *stream, dwf_ctx *out)
+{
+    DWF_API_BEGIN
+    require(p, "params");
+    require(gauge, "gauge");
+    require(out, "out");
+    *out = nullptr;
+    for (int mu = 0; mu < 4; mu++)
+        if (p->dims[mu] < 2 || (p->dims[mu] & 1)) fail(DWF_EINVAL, "every lattice extent must be even and >= 2");
+    if (p->Ls < 1) fail(DWF_EINVAL, "Ls must be >= 1");
+    if (p->Ls > 64) fail(DWF_ENOTSUP, "Ls > 64 is not supported");
+    if (!std::isfinite(p->b) || !std::isfinite(p->c) || !std::isfinite(p->M5) || !std::isfinite(p->mf))
+        fail(DWF_EINVAL, "non-finite operator parameter");
+    const double dd = p->b * (4.0 - p->M5) + 1.0;
+    if (dd == 0.0) fail(DWF_EINVAL, "b(4-M5)+1 = 0: Mooee is singular");
+    long V4 = (long)p->dims[0] * p->dims[1] * p->dims[2] * p->dims[3];
+    if (V4 * p->Ls / 2 > (1L << 30)) fail(DWF_ENOTSUP, "lattice too large for 32-bit neighbour indices");
+    auto *c = new dwf_context();
+    try {
+        c->p = *p;
+        for (int mu = 0; mu < 4; mu++) c->L[mu] = p->dims[mu];
+        c->Ls = p->Ls;
+        c->V4 = V4;
+        c->vh = V4 / 2;
+        c->n5h = c->vh * c->Ls;
+        c->d = dd;
+        c->e = p->c * (4.0 - p->M5) - 1.0;
+        c->stream = (hipStream_t)stream;
+        HIPCHECK(hipGetDevice(&c->device));
+        HIPCHECK(hipMalloc(&c->nbr, (size_t)2 * 8 * c->vh * sizeof(int)));
+        build_neighbours(*c);
+        build_slocal(*c);
+        c->partials_len = 2 * (c->n5h / 64 + c->vh + 1024);
+        HIPCHECK(hipMalloc(&c->partials, c->partials_len * sizeof(double)));
+        HIPCHECK(hipMalloc(&c->dscal, 64 * sizeof(double)));
+        HIPCHECK(hipMemset(c->dscal, 0, 64 * sizeof(double)));
+        HIPCHECK(hipHostMalloc(&c->hscal, 64 * sizeof(double), hipHostMallocDefault));
+        upload_gauge(*c, gauge, gauge_on_device);
+    } catch (...) {
+        dwf_destroy(c);
+        throw;
+    }
+    *out = c;
+    DWF_API_END
+}
+
+dwf_status dwf_destroy(dwf_ctx ctx)
+{
+    if (!ctx) return DWF_OK;
+    dwf::Context &c = *ctx;
+    (void)hipStreamSynchronize(c.stream);
+    for (auto &t : c.pending) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : c.event_pool) (void)hipEventDestroy(e);
+    for (auto &kv : c.ws) (void)hipFree(kv.second.data);
+    for (int pr = 0; pr < 4; pr++)
+        for (int p = 0; p < 2; p++)
+            if (c.links[pr][p]) (void)hipFree(c.links[pr][p]);
+    if (c.nbr) (void)hipFree(c.nbr);
+    if (c.slmat64) (void)hipFree(c.slmat64);
+    if (c.slmat32) (void)hipFree(c.slmat32);
+    if (c.gauge_canon) (void)hipFree(c.gauge_canon);
+    if (c.partials) (void)hipFree(c.partials);
+    if (c.dscal) (void)hipFree(c.dscal);
+    if (c.hscal) (void)hipHostFree(c.hscal);
+    delete ctx;
+    return DWF_OK;
+}
+
+dwf_status dwf_set_gauge(dwf_ctx ctx, const double *gauge, int on_device)
+{
+    DWF_API_BEGIN
+    require(gauge, "gauge");
+    upload_gauge(C_(ctx), gauge, on_device);
+    DWF_API_END
+}
+
+dwf_status dwf_set_stream(dwf_ctx ctx, void *stream)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    drain_timing(c);
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    c.stream = (hipStream_t)stream;
+    DWF_API_END
+}
+
+dwf_status dwf_field_bytes(dwf_ctx ctx, int full, int prec, size_t *bytes)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    check_prec(prec);
+    require(bytes, "bytes");
+    *bytes = field_bytes(c, c.n5h, prec) * (full ? 2 : 1);
+    DWF_API_END
+}
+
+static void import_any(dwf::Context &c, int full, int prec, const double *canon, void *internal)
+{
+    if (full) {
+        const size_t hb = field_bytes(c, c.n5h, prec);
+        launch_import(c, prec, canon, make_field(c, internal, prec), 1, 0);
+        launch_import(c, prec, canon, make_field(c, (char *)internal + hb, prec), 1, 1);
+    } else {
+        launch_import(c, prec, canon, make_field(c, internal, prec), 0, 0);
+    }
+}
+
+dwf_status dwf_import(dwf_ctx ctx, int full, int prec, const double *canon, void *internal)
+{
+    DWF_API_BEGIN
+    check_prec(prec);
+    require(canon, "canon");
+    require(internal, "internal");
+    import_any(C_(ctx), full, prec, canon, internal);
+    DWF_API_END
+}
+
+dwf_status dwf_export(dwf_ctx ctx, int full, int prec, const void *internal, double *canon)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    check_prec(prec);
+    require(canon, "canon");
+    require(internal, "internal");
+    if (full) {
+        const size_t hb = field_bytes(c, c.n5h, prec);
+        launch_export(c, prec, make_field(c, (void *)internal, prec), canon, 1, 0);
+        launch_export(c, prec, make_field(c, (char *)internal + hb, prec), canon, 1, 1);
+    } else {
+        launch_export(c, prec, make_field(c, (void *)internal, prec), canon, 0, 0);
+    }
+    DWF_API_END
+}
+
+dwf_status dwf_dhop(dwf_ctx ctx, int out_parity, int dagger, const double *in_half, double *out_half)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    require(in_half, "in");
+    require(out_half, "out");
+    if (out_parity != 0 && out_parity != 1) fail(DWF_EINVAL, "parity must be 0 or 1");
+    Field a = ws_field(c, "io_a", P_F64), b = ws_field(c, "io_b", P_F64);
+    launch_import(c, P_F64, in_half, a, 0, 0);
+    StencilSpec sp;
+    sp.out_parity = out_parity;
+    sp.dagger = dagger != 0;
+    sp.kclass = DWF_K_DHOP;
+    launch_stencil(c, P_F64, sp, a, Field{}, b);
+    launch_export(c, P_F64, b, out_half, 0, 0);
+    DWF_API_END
+}
+
+dwf_status dwf_dhop_internal(dwf_ctx ctx, int prec, int out_parity, int dagger, const void *in, void *out)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    check_prec(prec);
+    require(in, "in");
+    require(out, "out");
+    if (in == out) fail(DWF_EINVAL, "in and out must differ");
+    if (out_parity != 0 && out_parity != 1) fail(DWF_EINVAL, "parity must be 0 or 1");
+    StencilSpec sp;
+    sp.out_parity = out_parity;
+    sp.dagger = dagger != 0;
+    sp.kclass = DWF_K_DHOP;
+    launch_stencil(c, prec, sp, make_field(c, (void *)in, prec), Field{}, make_field(c, out, prec));
+    DWF_API_END
+}
+
+static dwf_status slocal_api(dwf_ctx ctx, int op, const double *in_half, double *out_half)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    require(in_half, "in");
+    require(out_half, "out");
+    Field a = ws_field(c, "io_a", P_F64);
+    launch_import(c, P_F64, in_half, a, 0, 0);
+    launch_slocal(c, P_F64, op, a, a);
+    launch_export(c, P_F64, a, out_half, 0, 0);
+    DWF_API_END
+}
+
+dwf_status dwf_mooee(dwf_ctx ctx, int dagger, const double *in_half, double *out_half)
+{
+    return slocal_api(ctx, dagger ? SL_MOOEEDAG : SL_MOOEE, in_half, out_half);
+}
+
+dwf_status dwf_mooeeinv(dwf_ctx ctx, int dagger, const double *in_half, double *out_half)
+{
+    return slocal_api(ctx, dagger ? SL_MINVDAG : SL_MINV, in_half, out_half);
+}
+
+dwf_status dwf_schur_apply(dwf_ctx ctx, int dagger, const double *in_odd, double *out_odd)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    require(in_odd, "in");
+    require(out_odd, "out");
+    Field a = ws_field(c, "io_a", P_F64), b = ws_field(c, "io_b", P_F64);
+    launch_import(c, P_F64, in_odd, a, 0, 0);
+    apply_mpc(c, P_F64, dagger != 0, a, b, false);
+    launch_export(c, P_F64, b, out_odd, 0, 0);
+    DWF_API_END
+}
+
+dwf_status dwf_schur_apply_internal(dwf_ctx ctx, int prec, int dagger, const void *in, void *out)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    check_prec(prec);
+    require(in, "in");
+    require(out, "out");
+    if (in == out) fail(DWF_EINVAL, "in and out must differ");
+    apply_mpc(c, prec, dagger != 0, make_field(c, (void *)in, prec), make_field(c, out, prec), false);
+    DWF_API_END
+}
+
+dwf_status dwf_kernel_timing(dwf_ctx ctx, int enable)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    drain_timing(c);
+    c.timing = enable != 0;
+    DWF_API_END
+}
+
+dwf_status dwf_kernel_timing_reset(dwf_ctx ctx)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    drain_timing(c);
+    for (auto &s : c.stats) s = KStats{};
+    DWF_API_END
+}
+
+dwf_status dwf_kernel_stats(dwf_ctx ctx, int kclass, long *launches, double *ms, double *bytes, double *flops)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    if (kclass < 0 || kclass >= DWF_K_NCLASS) fail(DWF_EINVAL, "unknown kernel class");
+    drain_timing(c);
+    const KStats &s = c.stats[kclass];
+    if (launches) *launches = s.launches;
+    if (ms) *ms = s.ms;
+    if (bytes) *bytes = s.bytes;
+    if (flops) *flops = s.flops;
+    DWF_API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,242 @@
+// Internal types shared by the gfx950 kernels: complex arithmetic, storage
+// precisions and the internal field layouts.
+//
+// Internal spinor layout (one parity, "half field"): structure of arrays over
+// the 12 spin-colour components,
+//     data[c][i],  c = spin*3 + colour,  i = cb*Ls + s
+// so that the lanes of a wavefront, which walk i with s fastest, read one
+// component contiguously.  FP16 fields carry one float scale per 5D site
+// (norm[i] = max |re|,|im| over the site's 24 reals; data holds value/scale).
+//
+// Internal gauge layout: per output parity p and direction d = 0..7
+// (+x,+y,+z,+t,-x,-y,-z,-t) the link the hop multiplies with, already
+// conjugated for the backward directions:
+//     link[p][d][k][cb], k = row*3 + col,  U_mu(x) for d < 4, U_mu(x-mu)^+ for d >= 4
+// and the checkerboard index of the neighbour, nbr[p][d][cb].
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dwf {
+
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+// i*a and -i*a
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> timesI(cx<T> a) { return {-a.im, a.re}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> timesMinusI(cx<T> a) { return {a.im, -a.re}; }
+// acc += a*b
+template <typename T>
+__host__ __device__ __forceinline__ void cmac(cx<T> &acc, cx<T> a, cx<T> b)
+{
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// ------------------------------------------------------------ storage types
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
+
+// epilogue kinds of the fused stencil
+enum EpiKind { EPI_NONE = 0, EPI_DENSE = 1, EPI_SHIFT = 2 };
+
+struct F64 {
+    using elem = double2;
+    using real = double;
+    static constexpr bool has_norm = false;
+    static constexpr int prec = P_F64;
+};
+struct F32 {
+    using elem = float2;
+    using real = float;
+    static constexpr bool has_norm = false;
+    static constexpr int prec = P_F32;
+};
+struct F16 {
+    using elem = __half2;
+    using real = float;
+    static constexpr bool has_norm = true;
+    static constexpr int prec = P_F16;
+};
+struct BF16 {
+    using elem = __hip_bfloat162;
+    using real = float;
+    static constexpr bool has_norm = false;
+    static constexpr int prec = P_BF16;
+};
+
+template <typename C>
+__device__ __forceinline__ cx<C> unpack(double2 v) { return {C(v.x), C(v.y)}; }
+template <typename C>
+__device__ __forceinline__ cx<C> unpack(float2 v) { return {C(v.x), C(v.y)}; }
+template <typename C>
+__device__ __forceinline__ cx<C> unpack(__half2 v)
+{
+    float2 f = __half22float2(v);
+    return {C(f.x), C(f.y)};
+}
+template <typename C>
+__device__ __forceinline__ cx<C> unpack(__hip_bfloat162 v)
+{
+    float2 f = __bfloat1622float2(v);
+    return {C(f.x), C(f.y)};
+}
+
+template <typename S, typename C>
+__device__ __forceinline__ typename S::elem pack(cx<C> v);
+template <>
+__device__ __forceinline__ double2 pack<F64, double>(cx<double> v) { return make_double2(v.re, v.im); }
+template <>
+__device__ __forceinline__ double2 pack<F64, float>(cx<float> v) { return make_double2(v.re, v.im); }
+template <>
+__device__ __forceinline__ float2 pack<F32, float>(cx<float> v) { return make_float2(v.re, v.im); }
+template <>
+__device__ __forceinline__ float2 pack<F32, double>(cx<double> v) { return make_float2(float(v.re), float(v.im)); }
+template <>
+__device__ __forceinline__ __half2 pack<F16, float>(cx<float> v) { return __float22half2_rn(make_float2(v.re, v.im)); }
+template <>
+__device__ __forceinline__ __half2 pack<F16, double>(cx<double> v)
+{
+    return __float22half2_rn(make_float2(float(v.re), float(v.im)));
+}
+template <>
+__device__ __forceinline__ __hip_bfloat162 pack<BF16, float>(cx<float> v)
+{
+    return __float22bfloat162_rn(make_float2(v.re, v.im));
+}
+template <>
+__device__ __forceinline__ __hip_bfloat162 pack<BF16, double>(cx<double> v)
+{
+    return __float22bfloat162_rn(make_float2(float(v.re), float(v.im)));
+}
+
+// A half field in internal layout: 12 component planes of n 5D sites.
+struct Field {
+    void *data;
+    float *norm;  // FP16 only
+    long n;       // 5D sites in the field (Vh * Ls)
+};
+
+template <typename S, typename C>
+__device__ __forceinline__ void load_spinor(const Field &f, long i, cx<C> v[12])
+{
+    const typename S::elem *d = (const typename S::elem *)f.data;
+    C scale = C(1);
+    if constexpr (S::has_norm) scale = C(f.norm[i]);
+#pragma unroll
+    for (int c = 0; c < 12; c++) {
+        cx<C> t = unpack<C>(d[c * f.n + i]);
+        if constexpr (S::has_norm) t = scale * t;
+        v[c] = t;
+    }
+}
+
+template <typename S, typename C>
+__device__ __forceinline__ void store_spinor(const Field &f, long i, const cx<C> v[12])
+{
+    typename S::elem *d = (typename S::elem *)f.data;
+    if constexpr (S::has_norm) {
+        C m = C(0);
+#pragma unroll
+        for (int c = 0; c < 12; c++) m = fmax(m, fmax(fabs(v[c].re), fabs(v[c].im)));
+        C inv = (m > C(0)) ? C(1) / m : C(0);
+        f.norm[i] = float(m);
+#pragma unroll
+        for (int c = 0; c < 12; c++) d[c * f.n + i] = pack<S, C>(inv * v[c]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 12; c++) d[c * f.n + i] = pack<S, C>(v[c]);
+    }
+}
+
+// Links of one output parity: 8 directions x 9 complex entries x vh sites.
+struct Links {
+    const void *data;
+    long vh;
+};
+
+template <typename S, typename C>
+__device__ __forceinline__ void load_link(const Links &l, int d, long cb, cx<C> u[9])
+{
+    const typename S::elem *p = (const typename S::elem *)l.data + (long)d * 9 * l.vh + cb;
+#pragma unroll
+    for (int k = 0; k < 9; k++) u[k] = unpack<C>(p[k * l.vh]);
+}
+
+// Value of (P5 psi) (dag = false) or (P5^+ psi) (dag = true) at slice s for
+// spin-colour component c, read from the Ls x 12 block of one 4D site:
+//   P5 psi_s = P_- psi_{s+1} + P_+ psi_{s-1},  P5^+ psi_s = P_+ psi_{s+1} + P_- psi_{s-1},
+// with psi_Ls = -mf psi_0 and psi_-1 = -mf psi_{Ls-1}.  Components c < 6 are
+// the P_+ spins (0, 1), c >= 6 the P_- spins (2, 3).
+template <typename C>
+__device__ __forceinline__ cx<C> shift5(const cx<C> *blk, int c, int s, int Ls, bool dag, C mf)
+{
+    const bool up = c < 6;
+    int src = (up != dag) ? s - 1 : s + 1;
+    C f = C(1);
+    if (src < 0) {
+        src = Ls - 1;
+        f = -mf;
+    } else if (src >= Ls) {
+        src = 0;
+        f = -mf;
+    }
+    return f * blk[src * 12 + c];
+}
+
+// Sum of v over the workgroup (fixed order: wavefront tree, then waves in
+// order); the result is valid in thread 0.  Every thread must call it.
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double red[16];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0;
+    if (tid == 0)
+        for (int w = 0; w < nw; w++) t += red[w];
+    __syncthreads();
+    return t;
+}
+
+// Workgroup -> tile mapping that keeps each XCD on contiguous runs of `run`
+// tiles.  Workgroups are dealt to the 8 XCDs round-robin; without the remap
+// neighbouring tiles land in different L2 caches.  Bijective on [0, nblk).
+__device__ __forceinline__ int xcd_swizzle(int b, int nblk, int run)
+{
+    if (run <= 1) return b;
+    const int chunk = 8 * run;
+    const int full = (nblk / chunk) * chunk;
+    if (b >= full) return b;
+    const int k = b >> 3, x = b & 7;
+    return (k / run) * chunk + x * run + (k % run);
+}
+
+}  // namespace dwf

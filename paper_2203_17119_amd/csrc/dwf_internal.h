@@ -1,0 +1,203 @@
+// Host-side internals of the library: the context, workspaces, launch
+// configuration, kernel timing and the kernel launchers implemented in the
+// .hip translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/dwf.h"
+#include "dwf_common.h"
+
+namespace dwf {
+
+// ---------------------------------------------------------------- errors
+
+struct Error {
+    dwf_status code;
+    std::string msg;
+};
+
+void set_error(const std::string &m);
+[[noreturn]] void fail(dwf_status code, const std::string &m);
+void hip_check(hipError_t e, const char *what);
+#define HIPCHECK(x) ::dwf::hip_check((x), #x)
+
+// ------------------------------------------------------- s-local operators
+
+// Every operator acting on the fifth dimension only is a pair of real Ls x Ls
+// matrices, one for the P+ spins (0,1) and one for the P- spins (2,3).
+enum SlocalOp {
+    SL_A = 0,       // b + c P5
+    SL_ADAG,        // b + c P5^+
+    SL_MOOEE,       // d + e P5
+    SL_MOOEEDAG,    // d + e P5^+
+    SL_MINV,        // (d + e P5)^-1
+    SL_MINVDAG,     // (d + e P5^+)^-1
+    SL_E1,          // A Mee^-1           (epilogue of the first Mpc stage)
+    SL_E2,          // Mee^-+ A^+         (epilogue of the first Mpc^+ stage)
+    SL_NOP
+};
+
+// ------------------------------------------------------------ launch shape
+
+struct LaunchCfg {
+    int sb = 0;   // 4D sites per workgroup (workgroup = Ls x sb threads)
+    int run = 1;  // XCD swizzle run length in workgroups
+};
+
+// ------------------------------------------------------------ timing
+
+struct TimedLaunch {
+    int kclass;
+    hipEvent_t a, b;
+    double bytes, flops;
+};
+
+struct KStats {
+    long launches = 0;
+    double ms = 0, bytes = 0, flops = 0;
+};
+
+// ------------------------------------------------------------ context
+
+struct Context {
+    dwf_params p;
+    int L[4];
+    int Ls;
+    long V4, vh, n5h;  // 4D sites, sites per parity, 5D sites per parity
+    double d, e;       // Mooee = d + e P5
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    int *nbr = nullptr;          // [2][8][vh]
+    void *links[4][2] = {};      // [prec][parity] -> [8][9][vh] elements
+    double *slmat64 = nullptr;   // [SL_NOP][2][Ls][Ls]
+    float *slmat32 = nullptr;
+    double *gauge_canon = nullptr;  // canonical FP64 gauge, kept to rebuild low-precision links
+
+    // reduction buffers
+    double *partials = nullptr;  // device, nblk_max * 2
+    long partials_len = 0;
+    double *dscal = nullptr;     // device scalars (see solvers)
+    double *hscal = nullptr;     // pinned host mirror
+
+    // workspaces keyed by name
+    struct Buf {
+        void *data = nullptr;
+        float *norm = nullptr;
+        size_t bytes = 0;
+        int prec = -1;
+    };
+    std::map<std::string, Buf> ws;
+
+    LaunchCfg cfg_stencil, cfg_slocal, cfg_blas;
+
+    bool timing = false;
+    std::vector<TimedLaunch> pending;
+    std::vector<hipEvent_t> event_pool;
+    KStats stats[DWF_K_NCLASS];
+};
+
+// sizes
+size_t elem_bytes(int prec);
+size_t field_bytes(const Context &c, long n5, int prec);
+
+// workspace field of one parity in precision prec (allocated on first use)
+Field ws_field(Context &c, const std::string &name, int prec);
+Field make_field(const Context &c, void *data, int prec);  // caller memory (FP16: norm follows data)
+
+const void *slmat(const Context &c, int op, bool f64);
+
+// timing helpers
+struct Timer {
+    Context &c;
+    int kclass;
+    double bytes, flops;
+    hipEvent_t a = nullptr;
+    Timer(Context &c_, int k, double by, double fl);
+    ~Timer();
+};
+
+// --------------------------------------------------------- kernel launchers
+
+// build the neighbour table on the host and upload; prepare links in prec
+void build_neighbours(Context &c);
+void prepare_links(Context &c, int prec);
+
+// canonical FP64 <-> internal (one parity); full canonical fields are read at
+// the sites of parity `parity` when full != 0
+void launch_import(Context &c, int prec, const double *canon, Field out, int full, int parity);
+void launch_export(Context &c, int prec, Field in, double *canon, int full, int parity);
+void launch_convert(Context &c, int pin, Field in, int pout, Field out);
+
+// Fused stencil: out = sigma * Self(self) + tau * Epi(H_{p,1-p} in)
+struct StencilSpec {
+    int out_parity = 0;
+    bool dagger = false;
+    int epi = EPI_NONE;
+    int epi_op = -1;          // SlocalOp for EPI_DENSE
+    double e0 = 0, e1 = 0;    // EPI_SHIFT: e0 + e1 P5 (edag: P5^+)
+    bool edag = false;
+    bool self = false;        // add sigma * (s0 + s1 P5) self
+    double s0 = 0, s1 = 0;
+    bool sdag = false;
+    double sigma = 1.0, tau = 1.0;
+    bool reduce = false;      // per-workgroup |out|^2 partials into c.partials
+    int kclass = DWF_K_STENCIL;
+};
+// prec: storage precision of in/out/self; FP64 uses double arithmetic, the
+// others float.  Returns the number of partials written when reduce is set.
+int launch_stencil(Context &c, int prec, const StencilSpec &sp, Field in, Field self, Field out);
+
+// s-local dense operator out = M in (M one of SlocalOp); in and out may alias
+void launch_slocal(Context &c, int prec, int op, Field in, Field out);
+
+// reductions: partial sums (2 doubles per workgroup for dots) then a fixed-order
+// finish on the device that writes dscal[slot] (and dscal[slot+1] for dots)
+int launch_norm2(Context &c, int prec, Field a);
+int launch_dot(Context &c, int prec, Field a, Field b);
+void launch_finish(Context &c, int nparts, int width, int slot);
+
+// generic vector ops with host scalars: z = a*x + b*y (real a, b)
+void launch_axpby(Context &c, int prec, double a, Field x, double b, Field y, Field z);
+// complex caxpy with host scalar: y += a * x
+void launch_caxpy(Context &c, int prec, double are, double aim, Field x, Field y);
+void launch_zero(Context &c, int prec, Field a);
+void launch_copy(Context &c, int prec, Field a, Field b);
+
+// precision of the low-precision solution accumulator for a sloppy precision
+inline int accum_prec(int prec) { return (prec == P_F16 || prec == P_BF16) ? P_F32 : prec; }
+
+// CG building blocks with device scalars
+// x += alpha p ; r -= alpha ap ; partials of |r|^2        (alpha = dscal[ia];
+// x in accum_prec(prec), the others in prec)
+int launch_cg_update_xr(Context &c, int prec, Field x, Field r, Field p, Field ap, int ia);
+// p = r + beta p ; pa = A p (A = b + c P5)                 (beta = dscal[ib])
+void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pa, int ib);
+// device scalar arithmetic: dscal[out] = dscal[num] / dscal[den]
+void launch_scalar_div(Context &c, int out, int num, int den);
+// r_h = b - ax (FP64), partials of |r_h|^2
+int launch_residual(Context &c, Field b, Field ax, Field r);
+// xh += xl (FP64 += prec), xl = 0
+void launch_accumulate_low(Context &c, int prec, Field xh, Field xl);
+// multi-shift: for shifts k with coef[k] active: x_k += a_k p_k ; p_k = z_k r + b_k p_k
+void launch_ms_update(Context &c, int prec, int nshift, Field *x, Field *p, Field r, const double *coef_dev,
+                      const int *active_host);
+
+void read_scalars(Context &c, int first, int count);  // dscal -> hscal, synchronising
+
+// ---------------------------------------------------------------- Mpc helpers
+
+// out = Mpc in (dagger: Mpc^+) in precision prec, using workspaces of that
+// precision; if reduce, partials of |out|^2 are written and their count returned
+int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduce, bool in_is_A_applied = false,
+              Field pa = Field{});
+
+}  // namespace dwf
+
+// the opaque handle of the C ABI
+struct dwf_context : public dwf::Context {};

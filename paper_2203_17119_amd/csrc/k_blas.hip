@@ -1,0 +1,374 @@
+// Vector kernels: reductions with deterministic FP64 accumulation, linear
+// combinations, precision conversions and the fused conjugate-gradient updates.
+// One lane per 5D site (12 complex components); scalars that the Krylov loops
+// produce on the device are read from device memory so no host round trip sits
+// between dependent kernels.
+#include "dwf_internal.h"
+
+namespace dwf {
+
+static constexpr int BS = 256;
+
+static dim3 g1(long n) { return dim3((unsigned)((n + BS - 1) / BS)); }
+
+template <typename S>
+using Cof = typename S::real;
+
+template <typename S>
+__global__ void __launch_bounds__(BS) k_norm2(Field a, double *partial)
+{
+    using C = Cof<S>;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    double t = 0;
+    if (i < a.n) {
+        cx<C> v[12];
+        load_spinor<S, C>(a, i, v);
+        for (int c = 0; c < 12; c++) t += double(v[c].re) * double(v[c].re) + double(v[c].im) * double(v[c].im);
+    }
+    t = block_sum(t);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// <a, b> = sum conj(a) b
+template <typename S>
+__global__ void __launch_bounds__(BS) k_dot(Field a, Field b, double *partial)
+{
+    using C = Cof<S>;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    double re = 0, im = 0;
+    if (i < a.n) {
+        cx<C> u[12], v[12];
+        load_spinor<S, C>(a, i, u);
+        load_spinor<S, C>(b, i, v);
+        for (int c = 0; c < 12; c++) {
+            re += double(u[c].re) * double(v[c].re) + double(u[c].im) * double(v[c].im);
+            im += double(u[c].re) * double(v[c].im) - double(u[c].im) * double(v[c].re);
+        }
+    }
+    re = block_sum(re);
+    im = block_sum(im);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = re;
+        partial[2 * blockIdx.x + 1] = im;
+    }
+}
+
+// fixed-order sum of nparts partials of `width` doubles -> dscal[slot + w]
+__global__ void __launch_bounds__(BS) k_finish(const double *partial, int nparts, int width, double *dscal, int slot)
+{
+    for (int w = 0; w < width; w++) {
+        double t = 0;
+        for (int k = threadIdx.x; k < nparts; k += BS) t += partial[(long)k * width + w];
+        t = block_sum(t);
+        if (threadIdx.x == 0) dscal[slot + w] = t;
+    }
+}
+
+__global__ void k_scalar_div(double *dscal, int out, int num, int den)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) dscal[out] = dscal[num] / dscal[den];
+}
+
+template <typename S>
+__global__ void __launch_bounds__(BS) k_axpby(double a, Field x, double b, Field y, Field z)
+{
+    using C = Cof<S>;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    if (i >= x.n) return;
+    cx<C> u[12], v[12];
+    load_spinor<S, C>(x, i, u);
+    load_spinor<S, C>(y, i, v);
+    for (int c = 0; c < 12; c++) u[c] = C(a) * u[c] + C(b) * v[c];
+    store_spinor<S, C>(z, i, u);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(BS) k_caxpy(double are, double aim, Field x, Field y)
+{
+    using C = Cof<S>;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    if (i >= x.n) return;
+    cx<C> u[12], v[12];
+    load_spinor<S, C>(x, i, u);
+    load_spinor<S, C>(y, i, v);
+    const cx<C> a = mk(C(are), C(aim));
+    for (int c = 0; c < 12; c++) cmac(v[c], a, u[c]);
+    store_spinor<S, C>(y, i, v);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(BS) k_zero(Field a)
+{
+    using C = Cof<S>;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    if (i >= a.n) return;
+    cx<C> v[12];
+    for (int c = 0; c < 12; c++) v[c] = mk(C(0), C(0));
+    store_spinor<S, C>(a, i, v);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(BS) k_copy(Field a, Field b)
+{
+    using C = Cof<S>;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    if (i >= a.n) return;
+    cx<C> v[12];
+    load_spinor<S, C>(a, i, v);
+    store_spinor<S, C>(b, i, v);
+}
+
+// x += alpha p ; r -= alpha ap ; partial |r|^2.  x is kept in SX, which is
+// wider than S for the 16-bit formats: the solution accumulates many
+// increments and its rounding error is amplified by the condition number.
+template <typename S, typename SX>
+__global__ void __launch_bounds__(BS) k_cg_update_xr(Field x, Field r, Field p, Field ap, const double *dscal, int ia,
+                                                      double *partial)
+{
+    using C = Cof<S>;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    const C alpha = C(dscal[ia]);
+    double t = 0;
+    if (i < x.n) {
+        cx<C> xv[12], pv[12];
+        load_spinor<SX, C>(x, i, xv);
+        load_spinor<S, C>(p, i, pv);
+        for (int c = 0; c < 12; c++) xv[c] = xv[c] + alpha * pv[c];
+        store_spinor<SX, C>(x, i, xv);
+        cx<C> rv[12], av[12];
+        load_spinor<S, C>(r, i, rv);
+        load_spinor<S, C>(ap, i, av);
+        for (int c = 0; c < 12; c++) {
+            rv[c] = rv[c] - alpha * av[c];
+            t += double(rv[c].re) * double(rv[c].re) + double(rv[c].im) * double(rv[c].im);
+        }
+        store_spinor<S, C>(r, i, rv);
+    }
+    t = block_sum(t);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// p = r + beta p ; pa = (b + c P5) p   (workgroup = Ls x sb lanes, one 4D site per row)
+template <typename S>
+__global__ void __launch_bounds__(256) k_cg_update_p(Field r, Field p, Field pa, const double *dscal, int ib, long vh,
+                                                     int Ls, double bb, double cc, double mf)
+{
+    using C = Cof<S>;
+    const int s = threadIdx.x, j = threadIdx.y, sb = blockDim.y;
+    const long cb = (long)blockIdx.x * sb + j;
+    const bool valid = cb < vh;
+    const long i = cb * Ls + s;
+    const C beta = C(dscal[ib]);
+    extern __shared__ unsigned char smem[];
+    cx<C> *lds = (cx<C> *)smem;
+    cx<C> pv[12];
+    if (valid) {
+        cx<C> rv[12];
+        load_spinor<S, C>(r, i, rv);
+        load_spinor<S, C>(p, i, pv);
+        for (int c = 0; c < 12; c++) pv[c] = rv[c] + beta * pv[c];
+        store_spinor<S, C>(p, i, pv);
+    } else {
+        for (int c = 0; c < 12; c++) pv[c] = mk(C(0), C(0));
+    }
+    for (int c = 0; c < 12; c++) lds[(j * Ls + s) * 12 + c] = pv[c];
+    __syncthreads();
+    if (!valid) return;
+    const cx<C> *blk = lds + j * Ls * 12;
+    cx<C> out[12];
+    for (int c = 0; c < 12; c++) out[c] = C(bb) * pv[c] + C(cc) * shift5<C>(blk, c, s, Ls, false, C(mf));
+    store_spinor<S, C>(pa, i, out);
+}
+
+// r = b - ax in FP64 ; partial |r|^2
+__global__ void __launch_bounds__(BS) k_residual(Field b, Field ax, Field r, double *partial)
+{
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    double t = 0;
+    if (i < b.n) {
+        cx<double> u[12], v[12];
+        load_spinor<F64, double>(b, i, u);
+        load_spinor<F64, double>(ax, i, v);
+        for (int c = 0; c < 12; c++) {
+            u[c] = u[c] - v[c];
+            t += u[c].re * u[c].re + u[c].im * u[c].im;
+        }
+        store_spinor<F64, double>(r, i, u);
+    }
+    t = block_sum(t);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// xh += xl ; xl = 0
+template <typename S>
+__global__ void __launch_bounds__(BS) k_accumulate_low(Field xh, Field xl)
+{
+    using C = Cof<S>;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    if (i >= xh.n) return;
+    cx<double> h[12];
+    cx<C> l[12];
+    load_spinor<F64, double>(xh, i, h);
+    load_spinor<S, C>(xl, i, l);
+    for (int c = 0; c < 12; c++) {
+        h[c] = h[c] + mk(double(l[c].re), double(l[c].im));
+        l[c] = mk(C(0), C(0));
+    }
+    store_spinor<F64, double>(xh, i, h);
+    store_spinor<S, C>(xl, i, l);
+}
+
+// multi-shift update for every active shift k:
+//   x_k += a_k p_k ; p_k = z_k r + b_k p_k      coef[4k..4k+3] = (a_k, z_k, b_k, active)
+template <typename S>
+__global__ void __launch_bounds__(BS) k_ms_update(int nshift, const Field *x, const Field *p, Field r,
+                                                   const double *coef)
+{
+    using C = Cof<S>;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    if (i >= r.n) return;
+    cx<C> rv[12];
+    load_spinor<S, C>(r, i, rv);
+    for (int k = 0; k < nshift; k++) {
+        if (coef[4 * k + 3] == 0.0) continue;
+        const C a = C(coef[4 * k]), z = C(coef[4 * k + 1]), b = C(coef[4 * k + 2]);
+        cx<C> xv[12], pv[12];
+        load_spinor<S, C>(x[k], i, xv);
+        load_spinor<S, C>(p[k], i, pv);
+        for (int c = 0; c < 12; c++) {
+            xv[c] = xv[c] + a * pv[c];
+            pv[c] = z * rv[c] + b * pv[c];
+        }
+        store_spinor<S, C>(x[k], i, xv);
+        store_spinor<S, C>(p[k], i, pv);
+    }
+}
+
+// ------------------------------------------------------------ launchers
+
+static double sbytes(int prec) { return 12.0 * elem_bytes(prec) + (prec == P_F16 ? 4.0 : 0.0); }
+
+#define DWF_DISPATCH(prec, KERNEL, grid, blk, lds, ...)                                                    \
+    switch (prec) {                                                                                        \
+    case P_F64: hipLaunchKernelGGL(KERNEL<F64>, grid, blk, lds, c.stream, __VA_ARGS__); break;             \
+    case P_F32: hipLaunchKernelGGL(KERNEL<F32>, grid, blk, lds, c.stream, __VA_ARGS__); break;             \
+    case P_F16: hipLaunchKernelGGL(KERNEL<F16>, grid, blk, lds, c.stream, __VA_ARGS__); break;             \
+    default: hipLaunchKernelGGL(KERNEL<BF16>, grid, blk, lds, c.stream, __VA_ARGS__); break;               \
+    }                                                                                                      \
+    HIPCHECK(hipGetLastError())
+
+static void need_partials(Context &c, long n, int width)
+{
+    if (n * width > c.partials_len) fail(DWF_EINVAL, "reduction buffer too small");
+}
+
+int launch_norm2(Context &c, int prec, Field a)
+{
+    const long nb = (a.n + BS - 1) / BS;
+    need_partials(c, nb, 1);
+    Timer tm(c, DWF_K_BLAS, sbytes(prec) * a.n, 4.0 * 12 * a.n);
+    DWF_DISPATCH(prec, k_norm2, g1(a.n), dim3(BS), 0, a, c.partials);
+    return (int)nb;
+}
+
+int launch_dot(Context &c, int prec, Field a, Field b)
+{
+    const long nb = (a.n + BS - 1) / BS;
+    need_partials(c, nb, 2);
+    Timer tm(c, DWF_K_BLAS, 2 * sbytes(prec) * a.n, 8.0 * 12 * a.n);
+    DWF_DISPATCH(prec, k_dot, g1(a.n), dim3(BS), 0, a, b, c.partials);
+    return (int)nb;
+}
+
+void launch_finish(Context &c, int nparts, int width, int slot)
+{
+    Timer tm(c, DWF_K_BLAS, 8.0 * nparts * width, 0);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(BS), 0, c.stream, c.partials, nparts, width, c.dscal, slot);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_scalar_div(Context &c, int out, int num, int den)
+{
+    hipLaunchKernelGGL(k_scalar_div, dim3(1), dim3(64), 0, c.stream, c.dscal, out, num, den);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_axpby(Context &c, int prec, double a, Field x, double b, Field y, Field z)
+{
+    Timer tm(c, DWF_K_BLAS, 3 * sbytes(prec) * x.n, 36.0 * x.n);
+    DWF_DISPATCH(prec, k_axpby, g1(x.n), dim3(BS), 0, a, x, b, y, z);
+}
+
+void launch_caxpy(Context &c, int prec, double are, double aim, Field x, Field y)
+{
+    Timer tm(c, DWF_K_BLAS, 3 * sbytes(prec) * x.n, 96.0 * x.n);
+    DWF_DISPATCH(prec, k_caxpy, g1(x.n), dim3(BS), 0, are, aim, x, y);
+}
+
+void launch_zero(Context &c, int prec, Field a)
+{
+    Timer tm(c, DWF_K_BLAS, sbytes(prec) * a.n, 0);
+    DWF_DISPATCH(prec, k_zero, g1(a.n), dim3(BS), 0, a);
+}
+
+void launch_copy(Context &c, int prec, Field a, Field b)
+{
+    Timer tm(c, DWF_K_BLAS, 2 * sbytes(prec) * a.n, 0);
+    DWF_DISPATCH(prec, k_copy, g1(a.n), dim3(BS), 0, a, b);
+}
+
+int launch_cg_update_xr(Context &c, int prec, Field x, Field r, Field p, Field ap, int ia)
+{
+    const long nb = (x.n + BS - 1) / BS;
+    need_partials(c, nb, 1);
+    const int xp = accum_prec(prec);
+    Timer tm(c, DWF_K_BLAS, (4 * sbytes(prec) + 2 * sbytes(xp)) * x.n, 120.0 * x.n);
+    const dim3 grid = g1(x.n), blk(BS);
+    switch (prec) {
+    case P_F64: hipLaunchKernelGGL((k_cg_update_xr<F64, F64>), grid, blk, 0, c.stream, x, r, p, ap, c.dscal, ia, c.partials); break;
+    case P_F32: hipLaunchKernelGGL((k_cg_update_xr<F32, F32>), grid, blk, 0, c.stream, x, r, p, ap, c.dscal, ia, c.partials); break;
+    case P_F16: hipLaunchKernelGGL((k_cg_update_xr<F16, F32>), grid, blk, 0, c.stream, x, r, p, ap, c.dscal, ia, c.partials); break;
+    default: hipLaunchKernelGGL((k_cg_update_xr<BF16, F32>), grid, blk, 0, c.stream, x, r, p, ap, c.dscal, ia, c.partials); break;
+    }
+    HIPCHECK(hipGetLastError());
+    return (int)nb;
+}
+
+void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pa, int ib)
+{
+    const int Ls = c.Ls;
+    const int sb = Ls >= 192 ? 1 : 192 / Ls;
+    const long nblk = (c.vh + sb - 1) / sb;
+    const size_t csz = (prec == P_F64) ? 16 : 8;
+    const size_t lds = (size_t)sb * Ls * 12 * csz;
+    Timer tm(c, DWF_K_BLAS, 4 * sbytes(prec) * c.n5h, 96.0 * c.n5h);
+    DWF_DISPATCH(prec, k_cg_update_p, dim3((unsigned)nblk), dim3(Ls, sb), lds, r, p, pa, c.dscal, ib, c.vh, Ls,
+                 c.p.b, c.p.c, c.p.mf);
+}
+
+int launch_residual(Context &c, Field b, Field ax, Field r)
+{
+    const long nb = (b.n + BS - 1) / BS;
+    need_partials(c, nb, 1);
+    Timer tm(c, DWF_K_BLAS, 3 * sbytes(P_F64) * b.n, 72.0 * b.n);
+    hipLaunchKernelGGL(k_residual, g1(b.n), dim3(BS), 0, c.stream, b, ax, r, c.partials);
+    HIPCHECK(hipGetLastError());
+    return (int)nb;
+}
+
+void launch_accumulate_low(Context &c, int prec, Field xh, Field xl)
+{
+    Timer tm(c, DWF_K_BLAS, (3 * sbytes(P_F64) / 1.5 + 2 * sbytes(prec)) * xh.n, 24.0 * xh.n);
+    DWF_DISPATCH(prec, k_accumulate_low, g1(xh.n), dim3(BS), 0, xh, xl);
+}
+
+void launch_ms_update(Context &c, int prec, int nshift, Field *x, Field *p, Field r, const double *coef_dev,
+                      const int *active_host)
+{
+    int nact = 0;
+    for (int k = 0; k < nshift; k++) nact += active_host[k] ? 1 : 0;
+    Timer tm(c, DWF_K_BLAS, (1 + 4.0 * nact) * sbytes(prec) * r.n, 96.0 * nact * r.n);
+    DWF_DISPATCH(prec, k_ms_update, g1(r.n), dim3(BS), 0, nshift, (const Field *)x, (const Field *)p, r, coef_dev);
+}
+
+}  // namespace dwf

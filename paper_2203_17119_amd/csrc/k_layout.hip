@@ -1,0 +1,216 @@
+// Layout kernels: neighbour table, Dirichlet link preparation, and the
+// conversions between the canonical FP64 layouts of the C ABI and the internal
+// structure-of-arrays layouts in every storage precision.
+#include <vector>
+
+#include "dwf_internal.h"
+
+namespace dwf {
+
+struct Geo {
+    int L[4];
+    long vh;
+    int Ls;
+};
+
+// lexicographic site of checkerboard index cb in parity p (Lx is even, so
+// sites 2cb and 2cb+1 differ only in x and exactly one has parity p)
+__host__ __device__ __forceinline__ long site_of_cb(const int L[4], long cb, int p, int x[4])
+{
+    long n = 2 * cb, r = n;
+    for (int mu = 0; mu < 4; mu++) {
+        x[mu] = (int)(r % L[mu]);
+        r /= L[mu];
+    }
+    if (((x[0] + x[1] + x[2] + x[3]) & 1) != p) {
+        n += 1;
+        x[0] += 1;
+    }
+    return n;
+}
+
+__host__ __device__ __forceinline__ long lex(const int L[4], const int x[4])
+{
+    return x[0] + (long)L[0] * (x[1] + (long)L[1] * (x[2] + (long)L[2] * x[3]));
+}
+
+void build_neighbours(Context &c)
+{
+    std::vector<int> h((size_t)2 * 8 * c.vh);
+    for (int p = 0; p < 2; p++)
+        for (long cb = 0; cb < c.vh; cb++) {
+            int x[4];
+            site_of_cb(c.L, cb, p, x);
+            for (int d = 0; d < 8; d++) {
+                const int mu = d & 3, step = d < 4 ? 1 : -1;
+                int y[4] = {x[0], x[1], x[2], x[3]};
+                y[mu] = (y[mu] + step + c.L[mu]) % c.L[mu];
+                h[((size_t)p * 8 + d) * c.vh + cb] = (int)(lex(c.L, y) >> 1);
+            }
+        }
+    HIPCHECK(hipMemcpy(c.nbr, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice));
+}
+
+// link[d][k][cb] of output parity p: U_mu(x) (d < 4) or U_mu(x-mu)^+ (d >= 4),
+// zero when the link crosses a Dirichlet face (leaves through x_mu = L_mu - 1)
+template <typename S>
+__global__ void k_prepare_links(Geo g, const double2 *gauge, int p, int4 dir, typename S::elem *out)
+{
+    const long cb = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (cb >= g.vh) return;
+    int x[4];
+    const long n = site_of_cb(g.L, cb, p, x);
+    const int dm[4] = {dir.x, dir.y, dir.z, dir.w};
+    for (int d = 0; d < 8; d++) {
+        const int mu = d & 3;
+        long m = n;
+        bool zero;
+        if (d < 4) {
+            zero = dm[mu] && x[mu] == g.L[mu] - 1;
+        } else {
+            int y[4] = {x[0], x[1], x[2], x[3]};
+            y[mu] = (y[mu] - 1 + g.L[mu]) % g.L[mu];
+            m = lex(g.L, y);
+            zero = dm[mu] && y[mu] == g.L[mu] - 1;
+        }
+        const double2 *U = gauge + (m * 4 + mu) * 9;
+        for (int r = 0; r < 3; r++)
+            for (int col = 0; col < 3; col++) {
+                cx<double> v;
+                if (d < 4) v = mk(U[r * 3 + col].x, U[r * 3 + col].y);
+                else v = mk(U[col * 3 + r].x, -U[col * 3 + r].y);
+                if (zero) v = mk(0.0, 0.0);
+                out[((long)d * 9 + r * 3 + col) * g.vh + cb] = pack<S, double>(v);
+            }
+    }
+}
+
+static Geo geo(const Context &c)
+{
+    Geo g;
+    for (int mu = 0; mu < 4; mu++) g.L[mu] = c.L[mu];
+    g.vh = c.vh;
+    g.Ls = c.Ls;
+    return g;
+}
+
+void prepare_links(Context &c, int prec)
+{
+    const Geo g = geo(c);
+    const int4 dir = make_int4(c.p.dirichlet[0], c.p.dirichlet[1], c.p.dirichlet[2], c.p.dirichlet[3]);
+    const size_t bytes = (size_t)8 * 9 * c.vh * elem_bytes(prec);
+    for (int p = 0; p < 2; p++) {
+        if (!c.links[prec][p]) HIPCHECK(hipMalloc(&c.links[prec][p], bytes));
+        const dim3 grid((unsigned)((c.vh + 255) / 256)), blk(256);
+        const double2 *U = (const double2 *)c.gauge_canon;
+        switch (prec) {
+        case P_F64: hipLaunchKernelGGL(k_prepare_links<F64>, grid, blk, 0, c.stream, g, U, p, dir, (double2 *)c.links[prec][p]); break;
+        case P_F32: hipLaunchKernelGGL(k_prepare_links<F32>, grid, blk, 0, c.stream, g, U, p, dir, (float2 *)c.links[prec][p]); break;
+        case P_F16: hipLaunchKernelGGL(k_prepare_links<F16>, grid, blk, 0, c.stream, g, U, p, dir, (__half2 *)c.links[prec][p]); break;
+        default: hipLaunchKernelGGL(k_prepare_links<BF16>, grid, blk, 0, c.stream, g, U, p, dir, (__hip_bfloat162 *)c.links[prec][p]); break;
+        }
+        HIPCHECK(hipGetLastError());
+    }
+}
+
+// canonical [n or cb][s][12] FP64 -> internal, one parity
+template <typename S>
+__global__ void k_import(Geo g, const double2 *canon, Field out, int full, int parity)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= g.vh * g.Ls) return;
+    const long cb = i / g.Ls;
+    const int s = (int)(i - cb * g.Ls);
+    long site = cb;
+    if (full) {
+        int x[4];
+        site = site_of_cb(g.L, cb, parity, x);
+    }
+    const double2 *src = canon + (site * g.Ls + s) * 12;
+    cx<double> v[12];
+    for (int c = 0; c < 12; c++) v[c] = mk(src[c].x, src[c].y);
+    store_spinor<S, double>(out, i, v);
+}
+
+template <typename S>
+__global__ void k_export(Geo g, Field in, double2 *canon, int full, int parity)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= g.vh * g.Ls) return;
+    const long cb = i / g.Ls;
+    const int s = (int)(i - cb * g.Ls);
+    long site = cb;
+    if (full) {
+        int x[4];
+        site = site_of_cb(g.L, cb, parity, x);
+    }
+    double2 *dst = canon + (site * g.Ls + s) * 12;
+    cx<double> v[12];
+    load_spinor<S, double>(in, i, v);
+    for (int c = 0; c < 12; c++) dst[c] = make_double2(v[c].re, v[c].im);
+}
+
+template <typename SI, typename SO>
+__global__ void k_convert(Field in, Field out)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= in.n) return;
+    cx<double> v[12];
+    load_spinor<SI, double>(in, i, v);
+    store_spinor<SO, double>(out, i, v);
+}
+
+static dim3 grid1(long n) { return dim3((unsigned)((n + 255) / 256)); }
+
+void launch_import(Context &c, int prec, const double *canon, Field out, int full, int parity)
+{
+    const Geo g = geo(c);
+    const double2 *src = (const double2 *)canon;
+    Timer tm(c, DWF_K_BLAS, (double)c.n5h * (192.0 + 12 * elem_bytes(prec)), 0);
+    switch (prec) {
+    case P_F64: hipLaunchKernelGGL(k_import<F64>, grid1(c.n5h), dim3(256), 0, c.stream, g, src, out, full, parity); break;
+    case P_F32: hipLaunchKernelGGL(k_import<F32>, grid1(c.n5h), dim3(256), 0, c.stream, g, src, out, full, parity); break;
+    case P_F16: hipLaunchKernelGGL(k_import<F16>, grid1(c.n5h), dim3(256), 0, c.stream, g, src, out, full, parity); break;
+    default: hipLaunchKernelGGL(k_import<BF16>, grid1(c.n5h), dim3(256), 0, c.stream, g, src, out, full, parity); break;
+    }
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_export(Context &c, int prec, Field in, double *canon, int full, int parity)
+{
+    const Geo g = geo(c);
+    double2 *dst = (double2 *)canon;
+    Timer tm(c, DWF_K_BLAS, (double)c.n5h * (192.0 + 12 * elem_bytes(prec)), 0);
+    switch (prec) {
+    case P_F64: hipLaunchKernelGGL(k_export<F64>, grid1(c.n5h), dim3(256), 0, c.stream, g, in, dst, full, parity); break;
+    case P_F32: hipLaunchKernelGGL(k_export<F32>, grid1(c.n5h), dim3(256), 0, c.stream, g, in, dst, full, parity); break;
+    case P_F16: hipLaunchKernelGGL(k_export<F16>, grid1(c.n5h), dim3(256), 0, c.stream, g, in, dst, full, parity); break;
+    default: hipLaunchKernelGGL(k_export<BF16>, grid1(c.n5h), dim3(256), 0, c.stream, g, in, dst, full, parity); break;
+    }
+    HIPCHECK(hipGetLastError());
+}
+
+template <typename SI>
+static void convert_to(Context &c, int pout, Field in, Field out)
+{
+    switch (pout) {
+    case P_F64: hipLaunchKernelGGL((k_convert<SI, F64>), grid1(in.n), dim3(256), 0, c.stream, in, out); break;
+    case P_F32: hipLaunchKernelGGL((k_convert<SI, F32>), grid1(in.n), dim3(256), 0, c.stream, in, out); break;
+    case P_F16: hipLaunchKernelGGL((k_convert<SI, F16>), grid1(in.n), dim3(256), 0, c.stream, in, out); break;
+    default: hipLaunchKernelGGL((k_convert<SI, BF16>), grid1(in.n), dim3(256), 0, c.stream, in, out); break;
+    }
+}
+
+void launch_convert(Context &c, int pin, Field in, int pout, Field out)
+{
+    Timer tm(c, DWF_K_BLAS, (double)in.n * 12 * (elem_bytes(pin) + elem_bytes(pout)), 0);
+    switch (pin) {
+    case P_F64: convert_to<F64>(c, pout, in, out); break;
+    case P_F32: convert_to<F32>(c, pout, in, out); break;
+    case P_F16: convert_to<F16>(c, pout, in, out); break;
+    default: convert_to<BF16>(c, pout, in, out); break;
+    }
+    HIPCHECK(hipGetLastError());
+}
+
+}  // namespace dwf

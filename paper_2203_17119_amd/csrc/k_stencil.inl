@@ -1,0 +1,355 @@
+// Fused domain-wall stencil for gfx950, included once per storage precision.
+//
+//   out(x,s) = sigma * Self(self)(x,s) + tau * Epi( H_{p,1-p} in )(x,s)
+//
+// H is the Wilson hop on every fifth-dimension slice: eight directions, the
+// neighbour spinor projected to a half spinor (two colour vectors) with the
+// chiral-basis identities
+//   (1 + P g_k) psi = (h, P i sigma_k h),  h = u - P i sigma_k l   (k = x,y,z)
+//   (1 + P g_t) psi = (h, P h),            h = u + P l
+// (u, l = upper and lower spin pairs), the two colour vectors multiplied by the
+// link and the lower pair rebuilt from the upper one.  P = -1 for the forward
+// and +1 for the backward hop, both flipped for H^+ = g5 H g5.
+//
+// Work mapping: a workgroup is an (Ls x sb) grid of lanes, lane (s, j) owns the
+// 5D site (cb, s) of 4D site cb = tile*sb + j.  The Ls lanes of one 4D site
+// load the same link addresses, so each link is fetched from memory once per
+// workgroup and reused for every s.  Fifth-dimension operators (Epi, Self)
+// need every s of a site and run from LDS after one barrier:
+//   Epi  = dense Ls x Ls matrix per chirality, or e0 + e1 P5 (P5^+)
+//   Self = s0 + s1 P5 (P5^+) on a second input at the output site.
+#include "dwf_common.h"
+
+namespace dwf {
+
+struct StencilKArgs {
+    Field in, self, out;
+    const void *links;  // output-parity links [8][9][vh]
+    const int *nbr;     // output-parity neighbours [8][vh]
+    long vh;
+    int Ls;
+    int run;
+    const void *emat;   // [2][Ls][Ls] in the arithmetic type (dense epilogue)
+    double e0, e1, s0, s1, mf, sigma, tau;
+    int edag, sdag;
+    double *partial;
+};
+
+template <typename C, int MU, int P>
+__device__ __forceinline__ void hop_dir(cx<C> acc[12], const cx<C> v[12], const cx<C> u[9], bool first)
+{
+    cx<C> h[6];
+#pragma unroll
+    for (int col = 0; col < 3; col++) {
+        const cx<C> u0 = v[col], u1 = v[3 + col], l0 = v[6 + col], l1 = v[9 + col];
+        if constexpr (MU == 0) {
+            h[col] = (P > 0) ? u0 - timesI(l1) : u0 + timesI(l1);
+            h[3 + col] = (P > 0) ? u1 - timesI(l0) : u1 + timesI(l0);
+        } else if constexpr (MU == 1) {
+            h[col] = (P > 0) ? u0 - l1 : u0 + l1;
+            h[3 + col] = (P > 0) ? u1 + l0 : u1 - l0;
+        } else if constexpr (MU == 2) {
+            h[col] = (P > 0) ? u0 - timesI(l0) : u0 + timesI(l0);
+            h[3 + col] = (P > 0) ? u1 + timesI(l1) : u1 - timesI(l1);
+        } else {
+            h[col] = (P > 0) ? u0 + l0 : u0 - l0;
+            h[3 + col] = (P > 0) ? u1 + l1 : u1 - l1;
+        }
+    }
+    cx<C> g[6];
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+            cx<C> t = cmul(u[r * 3 + 0], h[j * 3 + 0]);
+            cmac(t, u[r * 3 + 1], h[j * 3 + 1]);
+            cmac(t, u[r * 3 + 2], h[j * 3 + 2]);
+            g[j * 3 + r] = t;
+        }
+    // lower pair: P i sigma_k g (k = x,y,z) or P g (t)
+    cx<C> lo0[3], lo1[3];
+#pragma unroll
+    for (int col = 0; col < 3; col++) {
+        const cx<C> g0 = g[col], g1 = g[3 + col];
+        if constexpr (MU == 0) {
+            lo0[col] = (P > 0) ? timesI(g1) : timesMinusI(g1);
+            lo1[col] = (P > 0) ? timesI(g0) : timesMinusI(g0);
+        } else if constexpr (MU == 1) {
+            lo0[col] = (P > 0) ? g1 : -g1;
+            lo1[col] = (P > 0) ? -g0 : g0;
+        } else if constexpr (MU == 2) {
+            lo0[col] = (P > 0) ? timesI(g0) : timesMinusI(g0);
+            lo1[col] = (P > 0) ? timesMinusI(g1) : timesI(g1);
+        } else {
+            lo0[col] = (P > 0) ? g0 : -g0;
+            lo1[col] = (P > 0) ? g1 : -g1;
+        }
+    }
+    if (first) {
+#pragma unroll
+        for (int col = 0; col < 3; col++) {
+            acc[col] = g[col];
+            acc[3 + col] = g[3 + col];
+            acc[6 + col] = lo0[col];
+            acc[9 + col] = lo1[col];
+        }
+    } else {
+#pragma unroll
+        for (int col = 0; col < 3; col++) {
+            acc[col] = acc[col] + g[col];
+            acc[3 + col] = acc[3 + col] + g[3 + col];
+            acc[6 + col] = acc[6 + col] + lo0[col];
+            acc[9 + col] = acc[9 + col] + lo1[col];
+        }
+    }
+}
+
+template <typename S, typename C, int D, bool DAG>
+__device__ __forceinline__ void hop_step(cx<C> acc[12], const StencilKArgs &a, long cb, int s)
+{
+    constexpr int MU = D & 3;
+    constexpr int P0 = (D < 4) ? -1 : +1;
+    constexpr int P = DAG ? -P0 : P0;
+    const long nb = a.nbr[(long)D * a.vh + cb];
+    cx<C> v[12];
+    load_spinor<S, C>(a.in, nb * a.Ls + s, v);
+    cx<C> u[9];
+    Links l{a.links, a.vh};
+    load_link<S, C>(l, D, cb, u);
+    hop_dir<C, MU, P>(acc, v, u, D == 0);
+}
+
+template <typename S, typename C, int EPI, bool SELF, bool DAG, bool RED>
+__global__ void __launch_bounds__(256) k_stencil(const StencilKArgs a)
+{
+    const int Ls = a.Ls;
+    const int s = threadIdx.x;
+    const int j = threadIdx.y;
+    const int sb = blockDim.y;
+    const int tile = xcd_swizzle(blockIdx.x, gridDim.x, a.run);
+    const long cb = (long)tile * sb + j;
+    const bool valid = cb < a.vh;
+    const long i = cb * Ls + s;
+
+    extern __shared__ unsigned char smem[];
+    cx<C> *lds_h = (cx<C> *)smem;
+    cx<C> *lds_s = lds_h + ((EPI != EPI_NONE) ? sb * Ls * 12 : 0);
+    C *lds_e = (C *)(lds_s + (SELF ? sb * Ls * 12 : 0));
+
+    cx<C> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) acc[c] = mk(C(0), C(0));
+    if (valid) {
+        hop_step<S, C, 0, DAG>(acc, a, cb, s);
+        hop_step<S, C, 1, DAG>(acc, a, cb, s);
+        hop_step<S, C, 2, DAG>(acc, a, cb, s);
+        hop_step<S, C, 3, DAG>(acc, a, cb, s);
+        hop_step<S, C, 4, DAG>(acc, a, cb, s);
+        hop_step<S, C, 5, DAG>(acc, a, cb, s);
+        hop_step<S, C, 6, DAG>(acc, a, cb, s);
+        hop_step<S, C, 7, DAG>(acc, a, cb, s);
+    }
+    const C mf = C(a.mf);
+    cx<C> own[12];
+    if constexpr (SELF) {
+        if (valid) {
+            load_spinor<S, C>(a.self, i, own);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; c++) own[c] = mk(C(0), C(0));
+        }
+    }
+    if constexpr (EPI != EPI_NONE || SELF) {
+        cx<C> *bh = lds_h + (j * Ls + s) * 12;
+        cx<C> *bs = lds_s + (j * Ls + s) * 12;
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            if constexpr (EPI != EPI_NONE) bh[c] = acc[c];
+            if constexpr (SELF) bs[c] = own[c];
+        }
+        if constexpr (EPI == EPI_DENSE) {
+            const C *em = (const C *)a.emat;
+            const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+            for (int k = tid; k < 2 * Ls * Ls; k += blockDim.x * blockDim.y) lds_e[k] = em[k];
+        }
+        __syncthreads();
+    }
+    cx<C> res[12];
+    const C tau = C(a.tau);
+    if constexpr (EPI == EPI_NONE) {
+#pragma unroll
+        for (int c = 0; c < 12; c++) res[c] = tau * acc[c];
+    } else if constexpr (EPI == EPI_DENSE) {
+        const cx<C> *blk = lds_h + j * Ls * 12;
+        const C *Mu = lds_e + s * Ls;            // P+ block row s
+        const C *Ml = lds_e + Ls * Ls + s * Ls;  // P- block row s
+#pragma unroll
+        for (int c = 0; c < 12; c++) res[c] = mk(C(0), C(0));
+        for (int t = 0; t < Ls; t++) {
+            const C mu = Mu[t], ml = Ml[t];
+#pragma unroll
+            for (int c = 0; c < 12; c++) {
+                const C m = (c < 6) ? mu : ml;
+                const cx<C> v = blk[t * 12 + c];
+                res[c].re = fma(m, v.re, res[c].re);
+                res[c].im = fma(m, v.im, res[c].im);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 12; c++) res[c] = tau * res[c];
+    } else {
+        const cx<C> *blk = lds_h + j * Ls * 12;
+        const C e0 = C(a.e0), e1 = C(a.e1);
+#pragma unroll
+        for (int c = 0; c < 12; c++) res[c] = tau * (e0 * acc[c] + e1 * shift5<C>(blk, c, s, Ls, a.edag, mf));
+    }
+    if constexpr (SELF) {
+        const cx<C> *blk = lds_s + j * Ls * 12;
+        const C s0 = C(a.s0), s1 = C(a.s1), sg = C(a.sigma);
+#pragma unroll
+        for (int c = 0; c < 12; c++) res[c] = res[c] + sg * (s0 * own[c] + s1 * shift5<C>(blk, c, s, Ls, a.sdag, mf));
+    }
+    if (valid) store_spinor<S, C>(a.out, i, res);
+    if constexpr (RED) {
+        double n2 = 0;
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < 12; c++) n2 += double(res[c].re) * double(res[c].re) + double(res[c].im) * double(res[c].im);
+        }
+        const double t = block_sum(n2);
+        if (threadIdx.x == 0 && threadIdx.y == 0) a.partial[blockIdx.x] = t;
+    }
+}
+
+// s-local dense operator out = M in, M = [2][Ls][Ls] (P+ block, P- block)
+template <typename S, typename C>
+__global__ void __launch_bounds__(256) k_slocal(Field in, Field out, const C *mat, long vh, int Ls, int run)
+{
+    const int s = threadIdx.x, j = threadIdx.y, sb = blockDim.y;
+    const long cb = (long)xcd_swizzle(blockIdx.x, gridDim.x, run) * sb + j;
+    const bool valid = cb < vh;
+    const long i = cb * Ls + s;
+    extern __shared__ unsigned char smem[];
+    cx<C> *lds = (cx<C> *)smem;
+    C *lm = (C *)(lds + sb * Ls * 12);
+    cx<C> v[12];
+    if (valid) {
+        load_spinor<S, C>(in, i, v);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 12; c++) v[c] = mk(C(0), C(0));
+    }
+#pragma unroll
+    for (int c = 0; c < 12; c++) lds[(j * Ls + s) * 12 + c] = v[c];
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    for (int k = tid; k < 2 * Ls * Ls; k += blockDim.x * blockDim.y) lm[k] = mat[k];
+    __syncthreads();
+    cx<C> res[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) res[c] = mk(C(0), C(0));
+    const cx<C> *blk = lds + j * Ls * 12;
+    for (int t = 0; t < Ls; t++) {
+        const C mu = lm[s * Ls + t], ml = lm[Ls * Ls + s * Ls + t];
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            const C m = (c < 6) ? mu : ml;
+            res[c].re = fma(m, blk[t * 12 + c].re, res[c].re);
+            res[c].im = fma(m, blk[t * 12 + c].im, res[c].im);
+        }
+    }
+    if (valid) store_spinor<S, C>(out, i, res);
+}
+
+}  // namespace dwf
+
+// ------------------------------------------------------------ host launchers
+#include "dwf_internal.h"
+
+namespace dwf {
+
+template <typename S, typename C>
+static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field self, Field out)
+{
+    const int Ls = c.Ls;
+    const int sb = c.cfg_stencil.sb > 0 ? c.cfg_stencil.sb : (Ls >= 192 ? 1 : 192 / Ls);
+    const long nblk = (c.vh + sb - 1) / sb;
+    if (sp.reduce && nblk > c.partials_len) fail(DWF_EINVAL, "reduction buffer too small");
+    StencilKArgs a;
+    a.in = in;
+    a.self = self;
+    a.out = out;
+    a.links = c.links[S::prec][sp.out_parity];
+    a.nbr = c.nbr + (long)sp.out_parity * 8 * c.vh;
+    a.vh = c.vh;
+    a.Ls = Ls;
+    a.run = c.cfg_stencil.run;
+    a.emat = (sp.epi == EPI_DENSE) ? slmat(c, sp.epi_op, sizeof(C) == 8) : nullptr;
+    a.e0 = sp.e0;
+    a.e1 = sp.e1;
+    a.s0 = sp.s0;
+    a.s1 = sp.s1;
+    a.mf = c.p.mf;
+    a.sigma = sp.sigma;
+    a.tau = sp.tau;
+    a.edag = sp.edag;
+    a.sdag = sp.sdag;
+    a.partial = c.partials;
+    size_t lds = 0;
+    if (sp.epi != EPI_NONE) lds += (size_t)sb * Ls * 12 * sizeof(cx<C>);
+    if (sp.self) lds += (size_t)sb * Ls * 12 * sizeof(cx<C>);
+    if (sp.epi == EPI_DENSE) lds += 2 * (size_t)Ls * Ls * sizeof(C);
+    dim3 blk(Ls, sb), grid((unsigned)nblk);
+    // algorithmic traffic: neighbour spinor, 8 links shared by the Ls slices, output, self input
+    const double sbytes = 12.0 * sizeof(typename S::elem) + (S::has_norm ? 4.0 : 0.0);
+    const double bytes = (double)c.n5h * (2 * sbytes + (sp.self ? sbytes : 0.0)) +
+                         (double)c.vh * 8 * 9 * sizeof(typename S::elem);
+    double flops = (double)c.n5h * 1320.0;
+    if (sp.epi == EPI_DENSE) flops += (double)c.n5h * 24.0 * 2.0 * Ls;
+    Timer tm(c, sp.kclass, bytes, flops);
+#define DWF_LAUNCH(E, SF, DG, RD) \
+    hipLaunchKernelGGL((k_stencil<S, C, E, SF, DG, RD>), grid, blk, lds, c.stream, a)
+#define DWF_RD(E, SF, DG)            \
+    if (sp.reduce)                    \
+        DWF_LAUNCH(E, SF, DG, true);  \
+    else                              \
+        DWF_LAUNCH(E, SF, DG, false);
+#define DWF_DG(E, SF)             \
+    if (sp.dagger) {              \
+        DWF_RD(E, SF, true)       \
+    } else {                      \
+        DWF_RD(E, SF, false)      \
+    }
+#define DWF_SF(E)            \
+    if (sp.self) {           \
+        DWF_DG(E, true)      \
+    } else {                 \
+        DWF_DG(E, false)     \
+    }
+    switch (sp.epi) {
+    case EPI_NONE: DWF_SF(EPI_NONE) break;
+    case EPI_DENSE: DWF_SF(EPI_DENSE) break;
+    default: DWF_SF(EPI_SHIFT) break;
+    }
+#undef DWF_SF
+#undef DWF_DG
+#undef DWF_RD
+#undef DWF_LAUNCH
+    HIPCHECK(hipGetLastError());
+    return sp.reduce ? (int)nblk : 0;
+}
+
+template <typename S, typename C>
+static void launch_slocal_t(Context &c, int op, Field in, Field out)
+{
+    const int Ls = c.Ls;
+    const int sb = c.cfg_slocal.sb > 0 ? c.cfg_slocal.sb : (Ls >= 192 ? 1 : 192 / Ls);
+    const long nblk = (c.vh + sb - 1) / sb;
+    const size_t lds = (size_t)sb * Ls * 12 * sizeof(cx<C>) + 2 * (size_t)Ls * Ls * sizeof(C);
+    const double sbytes = 12.0 * sizeof(typename S::elem) + (S::has_norm ? 4.0 : 0.0);
+    Timer tm(c, DWF_K_SLOCAL, 2.0 * sbytes * c.n5h, (double)c.n5h * 48.0 * Ls);
+    hipLaunchKernelGGL((k_slocal<S, C>), dim3((unsigned)nblk), dim3(Ls, sb), lds, c.stream, in, out,
+                       (const C *)slmat(c, op, sizeof(C) == 8), c.vh, Ls, c.cfg_slocal.run);
+    HIPCHECK(hipGetLastError());
+}
+
+}  // namespace dwf

@@ -1,0 +1,462 @@
+// Krylov solvers on the odd-site Schur complement.
+//
+//   cg_core      CG on (Mpc^+ Mpc + sigma) x = rhs in FP64, or in a low storage
+//                precision with FP64 reliable updates (Sleijpen & van der Vorst;
+//                mixed precision as in Clark et al.)
+//   dwf_cg       red-black solve of D5 x = b: Schur source, CGNE, reconstruction
+//   dwf_multishift_cg   shifted systems from one Krylov space (Jegerlehner)
+//
+// Scalars that the loop needs are produced on the device (fixed-order FP64
+// reductions) and consumed there; the host reads back |r|^2 once per
+// iteration for the stopping and reliable-update decisions.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "dwf_internal.h"
+
+using namespace dwf;
+
+namespace dwf {
+
+// device scalar slots
+enum { S_RHO = 0, S_RHONEW = 1, S_PAP = 2, S_ALPHA = 3, S_BETA = 4, S_ONE = 5, S_TMP = 6, S_DOT = 8 };
+
+static double now()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static int prec_of_mode(int mode)
+{
+    switch (mode) {
+    case DWF_SOLVE_F64: return P_F64;
+    case DWF_SOLVE_MIXED_F32: return P_F32;
+    case DWF_SOLVE_MIXED_F16: return P_F16;
+    case DWF_SOLVE_MIXED_BF16: return P_BF16;
+    default: fail(DWF_EINVAL, "unknown solver mode");
+    }
+}
+
+static void set_scalar(Context &c, int slot, double v)
+{
+    c.hscal[slot] = v;
+    HIPCHECK(hipMemcpyAsync(c.dscal + slot, c.hscal + slot, sizeof(double), hipMemcpyHostToDevice, c.stream));
+    HIPCHECK(hipStreamSynchronize(c.stream));
+}
+
+static double norm2(Context &c, int prec, Field a, int slot = S_TMP)
+{
+    const int np = launch_norm2(c, prec, a);
+    launch_finish(c, np, 1, slot);
+    read_scalars(c, slot, 1);
+    return c.hscal[slot];
+}
+
+// ap = (Mpc^+ Mpc + sigma) p ; dscal[S_PAP] = <p, ap>.  pa = A p when given.
+static void normal_op(Context &c, int prec, double sigma, Field p, Field ap, Field m, bool have_pa, Field pa)
+{
+    if (sigma == 0.0) {
+        const int np = apply_mpc(c, prec, false, p, m, true, have_pa, pa);
+        launch_finish(c, np, 1, S_PAP);  // <p, Mpc^+ Mpc p> = |Mpc p|^2
+        apply_mpc(c, prec, true, m, ap, false);
+    } else {
+        apply_mpc(c, prec, false, p, m, false, have_pa, pa);
+        apply_mpc(c, prec, true, m, ap, false);
+        launch_axpby(c, prec, 1.0, ap, sigma, p, ap);
+        const int np = launch_dot(c, prec, p, ap);
+        launch_finish(c, np, 2, S_DOT);
+        launch_scalar_div(c, S_PAP, S_DOT, S_ONE);
+    }
+}
+
+struct CoreStats {
+    int iters = 0, reliable = 0, converged = 0;
+    double rel_res = 0;
+};
+
+// Solve (Mpc^+ Mpc + sigma) x = rhs.  rhs and x are FP64 fields; x holds the
+// initial guess when guess is set.  Stops when |r| <= tol |rhs| in FP64.
+static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x, double tol, int maxit,
+                         double delta, bool guess)
+{
+    CoreStats st;
+    const int lp = prec_of_mode(mode);
+    const bool mixed = lp != P_F64;
+    set_scalar(c, S_ONE, 1.0);
+    const double rhs2 = norm2(c, P_F64, rhs);
+    if (rhs2 == 0.0) {
+        launch_zero(c, P_F64, x);
+        st.converged = 1;
+        return st;
+    }
+    const double target = tol * std::sqrt(rhs2);
+    Field m64 = ws_field(c, "cg_m64", P_F64), ap64 = ws_field(c, "cg_ap64", P_F64);
+    Field rh = ws_field(c, "cg_rh", P_F64);
+
+    // r_h = rhs - A x
+    auto true_residual = [&]() {
+        if (!guess && st.iters == 0 && st.reliable == 0) {
+            launch_copy(c, P_F64, rhs, rh);
+            const int np = launch_norm2(c, P_F64, rh);
+            launch_finish(c, np, 1, S_RHONEW);
+        } else {
+            apply_mpc(c, P_F64, false, x, m64, false);
+            apply_mpc(c, P_F64, true, m64, ap64, false);
+            if (sigma != 0.0) launch_axpby(c, P_F64, 1.0, ap64, sigma, x, ap64);
+            const int np = launch_residual(c, rhs, ap64, rh);
+            launch_finish(c, np, 1, S_RHONEW);
+        }
+        read_scalars(c, S_RHONEW, 1);
+        return c.hscal[S_RHONEW];
+    };
+    if (!guess) launch_zero(c, P_F64, x);
+
+    const int xp = accum_prec(lp);
+    Field r = mixed ? ws_field(c, "cg_rl", lp) : rh;
+    Field xl = mixed ? ws_field(c, "cg_xl", xp) : x;
+    Field p = ws_field(c, "cg_p", lp), pa = ws_field(c, "cg_pa", lp);
+    Field m = mixed ? ws_field(c, "cg_m", lp) : m64, ap = mixed ? ws_field(c, "cg_ap", lp) : ap64;
+
+    double rho = true_residual();
+    if (mixed) {
+        launch_convert(c, P_F64, rh, lp, r);
+        launch_zero(c, xp, xl);
+    }
+    // p = r, pa = A p  (via p = r + 0 p)
+    set_scalar(c, S_BETA, 0.0);
+    launch_zero(c, lp, p);
+    launch_cg_update_p(c, lp, r, p, pa, S_BETA);
+    set_scalar(c, S_RHO, rho);
+    double rmax = std::sqrt(rho);
+    if (std::sqrt(rho) <= target) {
+        st.converged = 1;
+        st.rel_res = std::sqrt(rho / rhs2);
+        return st;
+    }
+    const int maxi = maxit > 0 ? maxit : 100000;
+    while (st.iters < maxi) {
+        normal_op(c, lp, sigma, p, ap, m, true, pa);
+        launch_scalar_div(c, S_ALPHA, S_RHO, S_PAP);
+        const int np = launch_cg_update_xr(c, lp, xl, r, p, ap, S_ALPHA);
+        launch_finish(c, np, 1, S_RHONEW);
+        read_scalars(c, S_RHONEW, 1);
+        double rho1 = c.hscal[S_RHONEW];
+        st.iters++;
+        if (!std::isfinite(rho1)) fail(DWF_ENOCONV, "CG breakdown: non-finite residual");
+        const double rn = std::sqrt(rho1);
+        bool done = false;
+        if (mixed && (rn < delta * rmax || rn <= target)) {
+            // reliable update: fold the low-precision solution into x and
+            // recompute the residual exactly
+            launch_accumulate_low(c, xp, x, xl);
+            rho1 = true_residual();
+            launch_convert(c, P_F64, rh, lp, r);
+            rmax = std::sqrt(rho1);
+            st.reliable++;
+            if (std::sqrt(rho1) <= target) done = true;
+        } else if (!mixed && rn <= target) {
+            done = true;
+        }
+        if (done) {
+            st.converged = 1;
+            break;
+        }
+        launch_scalar_div(c, S_BETA, S_RHONEW, S_RHO);
+        launch_scalar_div(c, S_RHO, S_RHONEW, S_ONE);
+        launch_cg_update_p(c, lp, r, p, pa, S_BETA);
+    }
+    if (mixed && !st.converged) launch_accumulate_low(c, xp, x, xl);
+    // final FP64 check
+    guess = true;
+    const double rf = true_residual();
+    st.rel_res = std::sqrt(rf / rhs2);
+    st.converged = st.rel_res <= tol * 1.0000001 ? 1 : 0;
+    return st;
+}
+
+static void fill_opts(const dwf_solver_opts *o, double &tol, int &maxit, int &mode, double &delta, bool &guess)
+{
+    tol = (o && o->tol > 0) ? o->tol : 1e-8;
+    maxit = (o && o->maxit > 0) ? o->maxit : 100000;
+    mode = o ? o->mode : DWF_SOLVE_F64;
+    delta = (o && o->delta > 0) ? o->delta : 0.1;
+    guess = o && o->x0_is_guess;
+    prec_of_mode(mode);
+}
+
+}  // namespace dwf
+
+#define DWF_API_BEGIN try {
+#define DWF_API_END                              \
+    }                                            \
+    catch (const dwf::Error &e)                  \
+    {                                            \
+        dwf::set_error(e.msg);                   \
+        return e.code;                           \
+    }                                            \
+    catch (const std::exception &e)              \
+    {                                            \
+        dwf::set_error(e.what());                \
+        return DWF_ENOMEM;                       \
+    }
+
+extern "C" {
+
+dwf_status dwf_cg(dwf_ctx ctx, const double *b_full, double *x_full, const dwf_solver_opts *o, dwf_solver_stats *st)
+{
+    DWF_API_BEGIN
+    if (!ctx) fail(DWF_EINVAL, "null context");
+    if (!b_full || !x_full) fail(DWF_EINVAL, "null field pointer");
+    dwf::Context &c = *ctx;
+    double tol, delta;
+    int maxit, mode;
+    bool guess;
+    fill_opts(o, tol, maxit, mode, delta, guess);
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    const double t0 = now();
+    Field be = ws_field(c, "sv_be", P_F64), bo = ws_field(c, "sv_bo", P_F64);
+    Field bt = ws_field(c, "sv_bt", P_F64), rhs = ws_field(c, "sv_rhs", P_F64);
+    Field xo = ws_field(c, "sv_xo", P_F64), xe = ws_field(c, "sv_xe", P_F64);
+    Field t1 = ws_field(c, "sv_t1", P_F64), t2 = ws_field(c, "sv_t2", P_F64);
+    launch_import(c, P_F64, b_full, be, 1, 0);
+    launch_import(c, P_F64, b_full, bo, 1, 1);
+    if (guess) launch_import(c, P_F64, x_full, xo, 1, 1);
+    // b~_o = b_o - Moe Mee^-1 b_e = b_o + (1/2) H_oe A Mee^-1 b_e
+    launch_slocal(c, P_F64, SL_E1, be, t1);
+    StencilSpec sp;
+    sp.out_parity = 1;
+    sp.self = true;
+    sp.s0 = 1.0;
+    sp.s1 = 0.0;
+    sp.tau = 0.5;
+    launch_stencil(c, P_F64, sp, t1, bo, bt);
+    // normal-equation right-hand side Mpc^+ b~
+    apply_mpc(c, P_F64, true, bt, rhs, false);
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    const double t1w = now();
+    CoreStats cs = cg_core(c, mode, 0.0, rhs, xo, tol, maxit, delta, guess);
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    const double t2w = now();
+    // x_e = Mee^-1 (b_e - Meo x_o) = Mee^-1 (b_e + (1/2) H_eo A x_o)
+    launch_slocal(c, P_F64, SL_A, xo, t1);
+    sp = StencilSpec{};
+    sp.out_parity = 0;
+    sp.self = true;
+    sp.s0 = 1.0;
+    sp.tau = 0.5;
+    launch_stencil(c, P_F64, sp, t1, be, t2);
+    launch_slocal(c, P_F64, SL_MINV, t2, xe);
+    launch_export(c, P_F64, xe, x_full, 1, 0);
+    launch_export(c, P_F64, xo, x_full, 1, 1);
+    // residuals in FP64
+    apply_mpc(c, P_F64, false, xo, t1, false);
+    launch_axpby(c, P_F64, 1.0, bt, -1.0, t1, t1);  // b~ - Mpc x
+    const double bt2 = dwf::norm2(c, P_F64, bt, S_TMP);
+    const double rs2 = dwf::norm2(c, P_F64, t1, S_TMP);
+    apply_mpc(c, P_F64, true, t1, t2, false);
+    const double rn2 = dwf::norm2(c, P_F64, t2, S_TMP);
+    const double rhs2 = dwf::norm2(c, P_F64, rhs, S_TMP);
+    // D5 x on both parities: Mooee x_p - (1/2) H_{p,1-p} A x_{1-p}
+    Field ax = ws_field(c, "sv_ax", P_F64);
+    double r2 = 0, b2 = 0;
+    for (int par = 0; par < 2; par++) {
+        Field xp = par ? xo : xe, xq = par ? xe : xo, bp = par ? bo : be;
+        launch_slocal(c, P_F64, SL_A, xq, ax);
+        StencilSpec d5;
+        d5.out_parity = par;
+        d5.self = true;
+        d5.s0 = c.d;
+        d5.s1 = c.e;
+        d5.tau = -0.5;
+        launch_stencil(c, P_F64, d5, ax, xp, t2);
+        launch_axpby(c, P_F64, 1.0, bp, -1.0, t2, t2);
+        r2 += dwf::norm2(c, P_F64, t2, S_TMP);
+        b2 += dwf::norm2(c, P_F64, bp, S_TMP);
+    }
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    const double t3w = now();
+    if (st) {
+        st->iters = cs.iters;
+        st->reliable_updates = cs.reliable;
+        st->converged = cs.converged;
+        st->fell_back = 0;
+        st->res_normal = rhs2 > 0 ? std::sqrt(rn2 / rhs2) : 0.0;
+        st->res_schur = bt2 > 0 ? std::sqrt(rs2 / bt2) : 0.0;
+        st->res_full = b2 > 0 ? std::sqrt(r2 / b2) : 0.0;
+        st->seconds = t3w - t0;
+        st->t_prep = t1w - t0;
+        st->t_solve = t2w - t1w;
+        st->t_final = t3w - t2w;
+    }
+    return cs.converged ? DWF_OK : DWF_ENOCONV;
+    DWF_API_END
+}
+
+dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *const *b_odd, int nshift, const double *shifts,
+                             double *const *x_odd, const dwf_solver_opts *o, dwf_solver_stats *st)
+{
+    DWF_API_BEGIN
+    if (!ctx) fail(DWF_EINVAL, "null context");
+    if (nrhs < 1 || nshift < 1 || nshift > 64) fail(DWF_EINVAL, "need 1 <= nrhs and 1 <= nshift <= 64");
+    if (!b_odd || !x_odd || !shifts) fail(DWF_EINVAL, "null pointer");
+    for (int k = 0; k < nshift; k++)
+        if (!(shifts[k] >= 0.0) || !std::isfinite(shifts[k])) fail(DWF_EINVAL, "shifts must be finite and >= 0");
+    for (int j = 0; j < nrhs; j++) {
+        if (!b_odd[j]) fail(DWF_EINVAL, "null right-hand side");
+        for (int k = 0; k < nshift; k++)
+            if (!x_odd[j * nshift + k]) fail(DWF_EINVAL, "null solution pointer");
+    }
+    dwf::Context &c = *ctx;
+    double tol, delta;
+    int maxit, mode;
+    bool guess;
+    fill_opts(o, tol, maxit, mode, delta, guess);
+    if (mode != DWF_SOLVE_F64 && mode != DWF_SOLVE_MIXED_F32) fail(DWF_ENOTSUP, "multi-shift mode must be F64 or MIXED_F32");
+    const int lp = prec_of_mode(mode);
+    const bool mixed = lp != P_F64;
+    set_scalar(c, S_ONE, 1.0);
+    int kmin = 0;
+    for (int k = 1; k < nshift; k++)
+        if (shifts[k] < shifts[kmin]) kmin = k;
+    const double s0 = shifts[kmin];
+    // per-shift fields of the Krylov precision, and their device descriptor arrays
+    std::vector<Field> X(nshift), P(nshift);
+    for (int k = 0; k < nshift; k++) {
+        X[k] = ws_field(c, "ms_x" + std::to_string(k), lp);
+        P[k] = ws_field(c, "ms_p" + std::to_string(k), lp);
+    }
+    Field *dX = nullptr, *dP = nullptr;
+    double *dcoef = nullptr, *hcoef = nullptr;
+    HIPCHECK(hipMalloc(&dX, nshift * sizeof(Field)));
+    HIPCHECK(hipMalloc(&dP, nshift * sizeof(Field)));
+    HIPCHECK(hipMalloc(&dcoef, 4 * nshift * sizeof(double)));
+    HIPCHECK(hipHostMalloc(&hcoef, 4 * nshift * sizeof(double), hipHostMallocDefault));
+    struct Guard {
+        Field *a, *b;
+        double *c, *h;
+        ~Guard()
+        {
+            (void)hipFree(a);
+            (void)hipFree(b);
+            (void)hipFree(c);
+            (void)hipHostFree(h);
+        }
+    } guard{dX, dP, dcoef, hcoef};
+    HIPCHECK(hipMemcpy(dX, X.data(), nshift * sizeof(Field), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(dP, P.data(), nshift * sizeof(Field), hipMemcpyHostToDevice));
+    Field b64 = ws_field(c, "ms_b", P_F64), x64 = ws_field(c, "ms_x64", P_F64);
+    Field r = ws_field(c, "ms_r", lp), ap = ws_field(c, "ms_ap", lp), m = ws_field(c, "ms_m", lp);
+    Field bl = mixed ? ws_field(c, "ms_bl", lp) : b64;
+    bool all_ok = true;
+    const int maxi = maxit > 0 ? maxit : 100000;
+    for (int j = 0; j < nrhs; j++) {
+        const double t0 = now();
+        launch_import(c, P_F64, b_odd[j], b64, 0, 0);
+        if (mixed) launch_convert(c, P_F64, b64, lp, bl);
+        const double b2 = dwf::norm2(c, P_F64, b64);
+        launch_copy(c, lp, bl, r);
+        for (int k = 0; k < nshift; k++) {
+            launch_zero(c, lp, X[k]);
+            launch_copy(c, lp, bl, P[k]);
+        }
+        std::vector<double> zeta(nshift, 1.0), zeta_old(nshift, 1.0);
+        std::vector<int> active(nshift, 1), iters(nshift, 0);
+        double rho = dwf::norm2(c, lp, r);
+        double alpha_old = 1.0, beta_old = 0.0;
+        int it = 0, nact = nshift;
+        // the Krylov space of the lowest shift; its direction is P[kmin]
+        const double target = tol * std::sqrt(b2);
+        while (nact > 0 && it < maxi && rho > 0) {
+            Field p = P[kmin];
+            apply_mpc(c, lp, false, p, m, false);
+            apply_mpc(c, lp, true, m, ap, false);
+            launch_axpby(c, lp, 1.0, ap, s0, p, ap);
+            const int np = launch_dot(c, lp, p, ap);
+            launch_finish(c, np, 2, S_DOT);
+            read_scalars(c, S_DOT, 1);
+            const double alpha = rho / c.hscal[S_DOT];
+            launch_axpby(c, lp, 1.0, r, -alpha, ap, r);
+            const double rho1 = dwf::norm2(c, lp, r);
+            if (!std::isfinite(rho1)) fail(DWF_ENOCONV, "multi-shift breakdown: non-finite residual");
+            const double beta = rho1 / rho;
+            it++;
+            for (int k = 0; k < nshift; k++) {
+                hcoef[4 * k + 3] = active[k] ? 1.0 : 0.0;
+                if (!active[k]) continue;
+                const double ds = shifts[k] - s0;
+                const double z = zeta[k], zo = zeta_old[k];
+                const double zn =
+                    z * zo * alpha_old / (alpha * beta_old * (zo - z) + zo * alpha_old * (1.0 + ds * alpha));
+                hcoef[4 * k + 0] = alpha * zn / z;
+                hcoef[4 * k + 1] = zn;
+                hcoef[4 * k + 2] = beta * (zn / z) * (zn / z);
+                zeta_old[k] = z;
+                zeta[k] = zn;
+            }
+            HIPCHECK(hipMemcpyAsync(dcoef, hcoef, 4 * nshift * sizeof(double), hipMemcpyHostToDevice, c.stream));
+            launch_ms_update(c, lp, nshift, dX, dP, r, dcoef, active.data());
+            // the lowest shift carries the Krylov space and is frozen last
+            for (int k = 0; k < nshift; k++)
+                if (active[k] && (k != kmin || nact == 1) && std::fabs(zeta[k]) * std::sqrt(rho1) <= target) {
+                    active[k] = 0;
+                    iters[k] = it;
+                    nact--;
+                }
+            rho = rho1;
+            alpha_old = alpha;
+            beta_old = beta;
+            HIPCHECK(hipStreamSynchronize(c.stream));
+        }
+        const double t1 = now();
+        // FP64 check (and refinement of the low-precision solutions)
+        for (int k = 0; k < nshift; k++) {
+            Field xk = X[k];
+            if (mixed) {
+                launch_convert(c, lp, xk, P_F64, x64);
+                CoreStats cs = cg_core(c, DWF_SOLVE_MIXED_F32, shifts[k], b64, x64, tol, maxi, delta, true);
+                (void)cs;
+                iters[k] += cs.iters;
+            } else {
+                launch_copy(c, P_F64, xk, x64);
+            }
+            apply_mpc(c, P_F64, false, x64, ws_field(c, "ms_t1", P_F64), false);
+            Field t2 = ws_field(c, "ms_t2", P_F64);
+            apply_mpc(c, P_F64, true, ws_field(c, "ms_t1", P_F64), t2, false);
+            launch_axpby(c, P_F64, 1.0, t2, shifts[k], x64, t2);
+            launch_axpby(c, P_F64, 1.0, b64, -1.0, t2, t2);
+            const double res = std::sqrt(dwf::norm2(c, P_F64, t2) / b2);
+            launch_export(c, P_F64, x64, x_odd[j * nshift + k], 0, 0);
+            const bool ok = res <= tol * 1.5;
+            all_ok = all_ok && ok;
+            if (st) {
+                dwf_solver_stats &s = st[j * nshift + k];
+                s.iters = iters[k] ? iters[k] : it;
+                s.reliable_updates = 0;
+                s.converged = ok;
+                s.fell_back = 0;
+                s.res_normal = res;
+                s.res_schur = 0;
+                s.res_full = 0;
+                s.t_prep = 0;
+                s.t_solve = t1 - t0;
+                s.t_final = 0;
+                s.seconds = 0;
+            }
+        }
+        HIPCHECK(hipStreamSynchronize(c.stream));
+        const double t2 = now();
+        if (st)
+            for (int k = 0; k < nshift; k++) {
+                st[j * nshift + k].t_final = t2 - t1;
+                st[j * nshift + k].seconds = t2 - t0;
+            }
+    }
+    return all_ok ? DWF_OK : DWF_ENOCONV;
+    DWF_API_END
+}
+
+}  // extern "C"
