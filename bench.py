@@ -72,6 +72,63 @@ def dhop_table(lat, dwf, torch, reps=20):
     return out
 
 
+def schedule_sweep(lat, dwf, torch, precs=(1, 2), reps=5):
+    """Standalone Dhop GB/s over site orders and (sites per workgroup, XCD run) schedules."""
+    res = {}
+    src = torch.view_as_complex(torch.randn(lat.half_shape() + (2,), dtype=torch.float64, device="cuda"))
+    L = lat.dims
+    orders = [(0, 0, 0), (L[0], L[1], L[2]), (16, 8, 8), (8, 16, 8), (8, 8, 8), (16, 16, 8), (8, 8, 16), (4, 8, 8)]
+    for order in orders:
+        dwf.dwf_set_site_order(lat.ctx, *order)
+        got = dwf.dwf_get_site_order(lat.ctx)
+        base = dwf.dwf_get_tile_schedule(lat.ctx, dwf.DWF_K_STENCIL)
+        col_sites = got[0] // 2 * got[1] * got[2] * L[3]
+        for prec in precs:
+            a = lat.internal(prec)
+            b = lat.internal(prec)
+            dwf.dwf_import(lat.ctx, 0, prec, src, a)
+            rows = []
+            for sb in sorted({max(1, n // lat.Ls) for n in (128, 192, 256)}):
+                runs = {1, 64}
+                if col_sites % sb == 0:
+                    runs.add(col_sites // sb)
+                for run in sorted(runs):
+                    dwf.dwf_set_tile_schedule(lat.ctx, dwf.DWF_K_STENCIL, sb, run)
+                    dwf.dwf_dhop_internal(lat.ctx, prec, 1, 0, a, b)
+                    dwf.dwf_kernel_timing_reset(lat.ctx)
+                    dwf.dwf_kernel_timing(lat.ctx, 1)
+                    for _ in range(reps):
+                        dwf.dwf_dhop_internal(lat.ctx, prec, 1, 0, a, b)
+                    st = dwf.dwf_kernel_stats(lat.ctx, dwf.DWF_K_DHOP)
+                    dwf.dwf_kernel_timing(lat.ctx, 0)
+                    rows.append((sb, run, round(st["ms"] / st["launches"], 4),
+                                 round(st["bytes"] / st["ms"] / 1e6, 1)))
+            res[f"{got}/{PREC_NAMES[prec]}"] = rows
+            del a, b
+            torch.cuda.empty_cache()
+        dwf.dwf_set_tile_schedule(lat.ctx, dwf.DWF_K_STENCIL, *base)
+    dwf.dwf_set_site_order(lat.ctx, 0, 0, 0)
+    return res
+
+
+def copy_bandwidth(lat, dwf, torch, nbytes=1 << 31, reps=5):
+    """Achievable HBM bandwidth of a plain streaming copy (read + write counted)."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    dwf.dwf_stream_copy(lat.ctx, a, b, nbytes)
+    dwf.dwf_kernel_timing_reset(lat.ctx)
+    dwf.dwf_kernel_timing(lat.ctx, 1)
+    for _ in range(reps):
+        dwf.dwf_stream_copy(lat.ctx, a, b, nbytes)
+    st = dwf.dwf_kernel_stats(lat.ctx, dwf.DWF_K_BLAS)
+    dwf.dwf_kernel_timing(lat.ctx, 0)
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_launch": 2 * nbytes, "ms": round(st["ms"] / st["launches"], 4),
+            "GB/s": round(st["bytes"] / st["ms"] / 1e6, 1)}
+
+
 def cpu_baseline(w, U, b_full):
     """FP64 oracle Wilson hop (both parities, all s) on the same lattice and field."""
     import oracle
@@ -105,6 +162,9 @@ def main():
     ap.add_argument("--mode", type=int, default=2, help="0 f64, 1 mixed f32, 2 mixed f16, 3 mixed bf16")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-table", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the stream copy and the standalone Dhop per precision (for counter runs)")
+    ap.add_argument("--sweep", action="store_true", help="with --kernels-only: Dhop time over tile schedules")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the hot path is one GPU's Dirichlet block and needs no "
@@ -121,6 +181,13 @@ def main():
     U = synth.gauge_field(w.dims, w.eps, w.gauge_seed)
     log(f"gauge field {w.dims} generated in {time.time() - t0:.1f}s")
     lat = dwf.Lattice(w.dims, w.Ls, w.b, w.c, w.M5, w.mf, w.dirichlet, gauge=U)
+    if args.kernels_only:
+        out = {"copy": copy_bandwidth(lat, dwf, torch), "dhop": dhop_table(lat, dwf, torch, reps=5)}
+        if args.sweep:
+            out["sweep"] = schedule_sweep(lat, dwf, torch)
+        print(json.dumps(out), flush=True)
+        lat.close()
+        return
     srcs = []
     b0_host = None
     for k, seed in enumerate(w.source_seeds):

@@ -171,6 +171,98 @@ dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *const *b_odd, 
                              const double *shifts, double *const *x_odd, const dwf_solver_opts *o,
                              dwf_solver_stats *st);
 
+/* ---------------------------------------------- learned preconditioner */
+
+/* A gauge-equivariant network of parallel-transport convolution layers
+ * (Lehner & Wettig; not part of the paper, whose plan for faster local solves
+ * is multigrid).  Layer l maps chans[l] colour-vector channels to chans[l+1]:
+ *   out_a(x,s) = sum_pi sum_b W_l[pi][a][b] (T_pi phi_b)(x,s)
+ * over 11 paths pi: 0 identity; 1+mu: U_mu(x) phi(x+mu); 5+mu: U_mu(x-mu)^+
+ * phi(x-mu) (mu = x,y,z,t); 9: phi(x,s+1); 10: phi(x,s-1) (zero outside
+ * 0 <= s < Ls).  Links are the context's (Dirichlet faces included).  The first
+ * and last layers have 4 channels, the spin components of a fermion; as a
+ * preconditioner of the odd Schur system the network acts on the odd field
+ * embedded in the full lattice (zero on even sites) and its output is
+ * restricted to odd sites.  Weights are stored in BF16 with FP32 masters;
+ * arithmetic is FP32.  Channel counts must be 4, 8 or 12. */
+typedef struct dwf_net_s *dwf_net;
+
+typedef struct {
+    double lr, beta1, beta2, eps;  /* Adam step size and moments */
+} dwf_adam;
+
+dwf_status dwf_net_create(dwf_ctx ctx, int nlayer, const int *chans, dwf_net *out);
+dwf_status dwf_net_destroy(dwf_net net);
+/* number of complex weights: sum_l 11 chans[l+1] chans[l] (-1 for a null net) */
+int dwf_net_num_weights(dwf_net net);
+/* weights in host memory: FP32 (re, im) pairs, layer blocks back to back,
+ * each block [pi][a][b] (a output, b input channel); setting resets Adam */
+dwf_status dwf_net_set_weights(dwf_net net, const float *w);
+dwf_status dwf_net_get_weights(dwf_net net, float *w);
+/* out = restrict_odd(N(embed_odd(in))); canonical FP64 odd half fields */
+dwf_status dwf_precond_apply(dwf_ctx ctx, dwf_net net, const double *in_odd, double *out_odd);
+/* Gradients of a real loss L through y = precond(in), given grad_out =
+ * dL/dRe(y) + i dL/dIm(y): grad_in the same for the input (may be NULL) and
+ * grad_w (host, FP32 pairs in the weight layout, may be NULL). */
+dwf_status dwf_net_backward(dwf_net net, const double *in_odd, const double *grad_out_odd, double *grad_in_odd,
+                            float *grad_w);
+/* One training step on nbatch pairs (b_j, x_j), canonical FP64 odd fields on
+ * the device: loss = (1/nbatch) sum_j |N(b_j) - x_j|^2 / |x_j|^2, gradients by
+ * the network's own backward kernels, then one Adam update of the FP32 masters
+ * (skipped when opt is NULL, which evaluates the loss only). */
+dwf_status dwf_net_train_step(dwf_net net, int nbatch, const double *const *b_odd, const double *const *x_odd,
+                              const dwf_adam *opt, double *loss);
+
+/* Flexible GCR(m) on the odd Schur system Mpc x_o = b~_o (o->normal = 0) or on
+ * Mpc^+ Mpc x_o = Mpc^+ b~_o (o->normal = 1), right-preconditioned by net
+ * (NULL: plain GCR; normal equations use N N^+), FP64 vectors, restart every
+ * o->restart steps with the residual recomputed.  On stagnation or a
+ * non-finite residual it falls back to dwf_cg in FP64 when o->fallback (the
+ * statistics then say fell_back = 1).  Same source preparation and
+ * reconstruction as dwf_cg; canonical FP64 full fields. */
+dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, double *x_full, const dwf_solver_opts *o,
+                    dwf_solver_stats *st);
+
+/* ------------------------------------------------------ tile schedules */
+
+/* Launch shape of a kernel family (DWF_K_STENCIL covers the hop and every
+ * fused stencil stage, DWF_K_SLOCAL the fifth-dimension kernels):
+ * sites_per_group 4D sites per workgroup (workgroup = Ls x sites_per_group
+ * lanes, at most 256; 0 = default) and xcd_run, the number of consecutive
+ * tiles each of the 8 XCDs processes before the next XCD takes over (1 = the
+ * hardware's round-robin).  Results do not depend on the schedule except for
+ * the order of the FP64 partial sums of fused reductions. */
+dwf_status dwf_set_tile_schedule(dwf_ctx ctx, int kclass, int sites_per_group, int xcd_run);
+dwf_status dwf_get_tile_schedule(dwf_ctx ctx, int kclass, int *sites_per_group, int *xcd_run);
+
+/* Internal site order.  Internal fields store the 4D sites of a parity in
+ * columns of cx x cy x cz sites (x, y, z extents; cx even) that run along t,
+ * so that a sweep over one column keeps its +-t neighbours in the XCD's L2.
+ * dwf_create picks a column for the lattice size (the whole 3D slice for small
+ * lattices); dwf_set_site_order(ctx, 0, 0, 0) restores that choice.  Changing
+ * the order invalidates every field held in the internal layout (re-import
+ * them); canonical-layout calls are unaffected.  The order is the same for
+ * both parities, so a half field's internal layout does not depend on its
+ * parity. */
+dwf_status dwf_set_site_order(dwf_ctx ctx, int cx, int cy, int cz);
+dwf_status dwf_get_site_order(dwf_ctx ctx, int *cx, int *cy, int *cz);
+
+/* Autotuner: times candidate schedules of the fused stencil in storage
+ * precision prec on this context's lattice (scratch fields allocated and freed
+ * by the call), applies the fastest and, when cache_path is not NULL, stores
+ * it in a JSON cache keyed by lattice, Ls, precision and device; a later call
+ * with the same key reads the cache instead of timing.  Synchronises the
+ * stream.  best_ms (may be NULL) returns the time of the chosen schedule. */
+dwf_status dwf_tune(dwf_ctx ctx, int prec, const char *cache_path, double *best_ms);
+
+/* ------------------------------------------------------ measurement */
+
+/* Plain streaming copy of `bytes` bytes (a multiple of 16; 16-byte aligned
+ * device pointers, non-overlapping) on the context's stream.  It reads and
+ * writes each byte once and serves as the achievable-bandwidth reference of
+ * the roofline and as the calibration kernel for memory counters. */
+dwf_status dwf_stream_copy(dwf_ctx ctx, const void *src, void *dst, size_t bytes);
+
 /* ------------------------------------------------------ kernel statistics */
 
 enum {

@@ -212,6 +212,15 @@ void ensure_links(Context &c, int prec)
     if (!c.links[prec][0]) prepare_links(c, prec);
 }
 
+// default stencil schedule: each XCD sweeps whole columns of the site order
+void default_schedule(Context &c)
+{
+    const int sb = default_sb(c);
+    const long col = column_sites(c);
+    c.cfg_stencil.sb = 0;
+    c.cfg_stencil.run = (col < c.vh && col % sb == 0) ? (int)std::min<long>(col / sb, 1 << 20) : 1;
+}
+
 // ---------------------------------------------------------------- Mpc
 
 int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduce, bool in_is_A_applied, Field pa)
@@ -361,7 +370,9 @@ dwf_status dwf_create(const dwf_params *p, const double *gauge, int gauge_on_dev
         c->stream = (hipStream_t)stream;
         HIPCHECK(hipGetDevice(&c->device));
         HIPCHECK(hipMalloc(&c->nbr, (size_t)2 * 8 * c->vh * sizeof(int)));
+        build_order(*c, 0, 0, 0);
         build_neighbours(*c);
+        default_schedule(*c);
         build_slocal(*c);
         c->partials_len = 2 * (c->n5h / 64 + c->vh + 1024);
         HIPCHECK(hipMalloc(&c->partials, c->partials_len * sizeof(double)));
@@ -392,6 +403,7 @@ dwf_status dwf_destroy(dwf_ctx ctx)
         for (int p = 0; p < 2; p++)
             if (c.links[pr][p]) (void)hipFree(c.links[pr][p]);
     if (c.nbr) (void)hipFree(c.nbr);
+    if (c.perm_inv) (void)hipFree(c.perm_inv);
     if (c.slmat64) (void)hipFree(c.slmat64);
     if (c.slmat32) (void)hipFree(c.slmat32);
     if (c.gauge_canon) (void)hipFree(c.gauge_canon);
@@ -548,6 +560,80 @@ dwf_status dwf_schur_apply_internal(dwf_ctx ctx, int prec, int dagger, const voi
     require(out, "out");
     if (in == out) fail(DWF_EINVAL, "in and out must differ");
     apply_mpc(c, prec, dagger != 0, make_field(c, (void *)in, prec), make_field(c, out, prec), false);
+    DWF_API_END
+}
+
+static LaunchCfg &cfg_of(dwf::Context &c, int kclass)
+{
+    switch (kclass) {
+    case DWF_K_DHOP:
+    case DWF_K_STENCIL: return c.cfg_stencil;
+    case DWF_K_SLOCAL: return c.cfg_slocal;
+    default: fail(DWF_EINVAL, "tile schedules exist for DWF_K_STENCIL and DWF_K_SLOCAL");
+    }
+}
+
+dwf_status dwf_set_tile_schedule(dwf_ctx ctx, int kclass, int sites_per_group, int xcd_run)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    if (sites_per_group < 0 || (long)sites_per_group * c.Ls > 256)
+        fail(DWF_EINVAL, "sites_per_group * Ls must be <= 256");
+    if (xcd_run < 1 || xcd_run > (1 << 20)) fail(DWF_EINVAL, "xcd_run must be in [1, 2^20]");
+    LaunchCfg &g = cfg_of(c, kclass);
+    g.sb = sites_per_group;
+    g.run = xcd_run;
+    DWF_API_END
+}
+
+dwf_status dwf_get_tile_schedule(dwf_ctx ctx, int kclass, int *sites_per_group, int *xcd_run)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    LaunchCfg &g = cfg_of(c, kclass);
+    if (sites_per_group) *sites_per_group = g.sb > 0 ? g.sb : default_sb(c);
+    if (xcd_run) *xcd_run = g.run;
+    DWF_API_END
+}
+
+dwf_status dwf_set_site_order(dwf_ctx ctx, int cx, int cy, int cz)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    const bool dflt = cx == 0 && cy == 0 && cz == 0;
+    if (!dflt) {
+        if (cx < 2 || (cx & 1) || cy < 1 || cz < 1) fail(DWF_EINVAL, "column extents: cx even >= 2, cy, cz >= 1");
+        if (c.L[0] % cx || c.L[1] % cy || c.L[2] % cz) fail(DWF_EINVAL, "column extents must divide Lx, Ly, Lz");
+    }
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    build_order(c, dflt ? 0 : cx / 2, cy, cz);
+    build_neighbours(c);
+    for (int prec = 0; prec < 4; prec++)
+        if (c.links[prec][0]) prepare_links(c, prec);
+    default_schedule(c);
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    DWF_API_END
+}
+
+dwf_status dwf_get_site_order(dwf_ctx ctx, int *cx, int *cy, int *cz)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    if (cx) *cx = 2 * c.order[0];
+    if (cy) *cy = c.order[1];
+    if (cz) *cz = c.order[2];
+    DWF_API_END
+}
+
+dwf_status dwf_stream_copy(dwf_ctx ctx, const void *src, void *dst, size_t bytes)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    require(src, "src");
+    require(dst, "dst");
+    if (bytes % 16 || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16))
+        fail(DWF_EINVAL, "stream copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+    if (bytes) launch_stream_copy(c, src, dst, bytes);
     DWF_API_END
 }
 

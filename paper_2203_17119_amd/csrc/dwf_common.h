@@ -1,12 +1,14 @@
 // Internal types shared by the gfx950 kernels: complex arithmetic, storage
 // precisions and the internal field layouts.
 //
-// Internal spinor layout (one parity, "half field"): structure of arrays over
-// the 12 spin-colour components,
-//     data[c][i],  c = spin*3 + colour,  i = cb*Ls + s
-// so that the lanes of a wavefront, which walk i with s fastest, read one
-// component contiguously.  FP16 fields carry one float scale per 5D site
-// (norm[i] = max |re|,|im| over the site's 24 reals; data holds value/scale).
+// Internal spinor layout (one parity, "half field"): structure of 16-byte
+// planes over the 12 spin-colour components c = spin*3 + colour,
+//     data[q][i] = components (q*CPP .. q*CPP + CPP-1) of 5D site i,
+//     i = j*Ls + s,  j the site's internal 4D index,  CPP = 16/sizeof(complex)
+// so that the lanes of a wavefront, which walk i with s fastest, each load 16
+// contiguous bytes of one plane.  FP16 fields carry one float scale per 5D
+// site (norm[i] = max |re|,|im| over the site's 24 reals; data holds
+// value/scale).
 //
 // Internal gauge layout: per output parity p and direction d = 0..7
 // (+x,+y,+z,+t,-x,-y,-z,-t) the link the hop multiplies with, already
@@ -141,35 +143,83 @@ struct Field {
     long n;       // 5D sites in the field (Vh * Ls)
 };
 
+// Spinor planes are 16 bytes wide: plane q of site i holds the CPP = 16 /
+// sizeof(elem) consecutive components CPP*q .. CPP*q + CPP - 1, so that one
+// lane moves 16 bytes per load and a wavefront 1 KiB of one plane.
+template <typename S>
+struct Planes {
+    static constexpr int cpp = 16 / sizeof(typename S::elem);  // components per plane
+    static constexpr int n = 12 / cpp;                           // planes per spinor
+};
+
+union Vec16 {
+    uint4 u;
+    double2 d[1];
+    float2 f[2];
+    __half2 h[4];
+    __hip_bfloat162 b[4];
+};
+
+template <typename S>
+__device__ __forceinline__ typename S::elem vec_get(const Vec16 &v, int k)
+{
+    if constexpr (sizeof(typename S::elem) == 16) return v.d[0];
+    else if constexpr (sizeof(typename S::elem) == 8) return v.f[k];
+    else if constexpr (S::prec == P_F16) return v.h[k];
+    else return v.b[k];
+}
+
+template <typename S>
+__device__ __forceinline__ void vec_set(Vec16 &v, int k, typename S::elem e)
+{
+    if constexpr (sizeof(typename S::elem) == 16) v.d[0] = e;
+    else if constexpr (sizeof(typename S::elem) == 8) v.f[k] = e;
+    else if constexpr (S::prec == P_F16) v.h[k] = e;
+    else v.b[k] = e;
+}
+
 template <typename S, typename C>
 __device__ __forceinline__ void load_spinor(const Field &f, long i, cx<C> v[12])
 {
-    const typename S::elem *d = (const typename S::elem *)f.data;
+    using P = Planes<S>;
+    const uint4 *d = (const uint4 *)f.data;
     C scale = C(1);
     if constexpr (S::has_norm) scale = C(f.norm[i]);
 #pragma unroll
-    for (int c = 0; c < 12; c++) {
-        cx<C> t = unpack<C>(d[c * f.n + i]);
-        if constexpr (S::has_norm) t = scale * t;
-        v[c] = t;
+    for (int q = 0; q < P::n; q++) {
+        Vec16 w;
+        w.u = d[q * f.n + i];
+#pragma unroll
+        for (int k = 0; k < P::cpp; k++) {
+            cx<C> t = unpack<C>(vec_get<S>(w, k));
+            if constexpr (S::has_norm) t = scale * t;
+            v[q * P::cpp + k] = t;
+        }
     }
 }
 
 template <typename S, typename C>
 __device__ __forceinline__ void store_spinor(const Field &f, long i, const cx<C> v[12])
 {
-    typename S::elem *d = (typename S::elem *)f.data;
+    using P = Planes<S>;
+    uint4 *d = (uint4 *)f.data;
+    C inv = C(1);
     if constexpr (S::has_norm) {
         C m = C(0);
 #pragma unroll
         for (int c = 0; c < 12; c++) m = fmax(m, fmax(fabs(v[c].re), fabs(v[c].im)));
-        C inv = (m > C(0)) ? C(1) / m : C(0);
+        inv = (m > C(0)) ? C(1) / m : C(0);
         f.norm[i] = float(m);
+    }
 #pragma unroll
-        for (int c = 0; c < 12; c++) d[c * f.n + i] = pack<S, C>(inv * v[c]);
-    } else {
+    for (int q = 0; q < P::n; q++) {
+        Vec16 w;
 #pragma unroll
-        for (int c = 0; c < 12; c++) d[c * f.n + i] = pack<S, C>(v[c]);
+        for (int k = 0; k < P::cpp; k++) {
+            const cx<C> t = S::has_norm ? inv * v[q * P::cpp + k] : v[q * P::cpp + k];
+            vec_set<S>(w, k, pack<S, C>(t));
+        }
+        d[q * f.n + i] = w.u;
     }
 }
 

@@ -74,6 +74,13 @@ struct Context {
     int device = 0;
 
     int *nbr = nullptr;          // [2][8][vh]
+    // Internal 4D site order, the same for both parities: internal index j of
+    // the site with checkerboard index cb is perm[cb]; perm_inv[j] = cb.
+    // Sites are grouped in columns of (order[0] x order[1] x order[2]) sites in
+    // (x/2, y, z) that run along t, columns in lexicographic order.
+    int *perm_inv = nullptr;     // device [vh]
+    std::vector<int> perm_h, perm_inv_h;
+    int order[3] = {0, 0, 0};
     void *links[4][2] = {};      // [prec][parity] -> [8][9][vh] elements
     double *slmat64 = nullptr;   // [SL_NOP][2][Ls][Ls]
     float *slmat32 = nullptr;
@@ -102,6 +109,10 @@ struct Context {
     KStats stats[DWF_K_NCLASS];
 };
 
+// default 4D sites per workgroup: about 192 lanes
+inline int default_sb(const Context &c) { return c.Ls >= 192 ? 1 : 192 / c.Ls; }
+inline int cfg_sb(const Context &c, const LaunchCfg &g) { return g.sb > 0 ? g.sb : default_sb(c); }
+
 // sizes
 size_t elem_bytes(int prec);
 size_t field_bytes(const Context &c, long n5, int prec);
@@ -124,6 +135,12 @@ struct Timer {
 
 // --------------------------------------------------------- kernel launchers
 
+// choose the column cross-section (in x/2, y, z) of the internal site order;
+// zeros pick the default for the lattice size
+void build_order(Context &c, int cxh, int cy, int cz);
+long column_sites(const Context &c);
+void ensure_links(Context &c, int prec);
+void default_schedule(Context &c);
 // build the neighbour table on the host and upload; prepare links in prec
 void build_neighbours(Context &c);
 void prepare_links(Context &c, int prec);
@@ -189,6 +206,7 @@ void launch_ms_update(Context &c, int prec, int nshift, Field *x, Field *p, Fiel
                       const int *active_host);
 
 void read_scalars(Context &c, int first, int count);  // dscal -> hscal, synchronising
+void launch_stream_copy(Context &c, const void *src, void *dst, size_t bytes);
 
 // ---------------------------------------------------------------- Mpc helpers
 

@@ -244,6 +244,22 @@ __global__ void __launch_bounds__(BS) k_ms_update(int nshift, const Field *x, co
     }
 }
 
+// plain 16-byte streaming copy, grid-stride
+__global__ void __launch_bounds__(BS) k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, long n)
+{
+    for (long i = blockIdx.x * (long)BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) dst[i] = src[i];
+}
+
+void launch_stream_copy(Context &c, const void *src, void *dst, size_t bytes)
+{
+    const long n = (long)(bytes / 16);
+    const long nblk = std::min<long>((n + BS - 1) / BS, 65536L);
+    Timer tm(c, DWF_K_BLAS, 2.0 * bytes, 0);
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)std::max<long>(nblk, 1)), dim3(BS), 0, c.stream,
+                       (const uint4 *)src, (uint4 *)dst, n);
+    HIPCHECK(hipGetLastError());
+}
+
 // ------------------------------------------------------------ launchers
 
 static double sbytes(int prec) { return 12.0 * elem_bytes(prec) + (prec == P_F16 ? 4.0 : 0.0); }
@@ -337,7 +353,7 @@ int launch_cg_update_xr(Context &c, int prec, Field x, Field r, Field p, Field a
 void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pa, int ib)
 {
     const int Ls = c.Ls;
-    const int sb = Ls >= 192 ? 1 : 192 / Ls;
+    const int sb = default_sb(c);
     const long nblk = (c.vh + sb - 1) / sb;
     const size_t csz = (prec == P_F64) ? 16 : 8;
     const size_t lds = (size_t)sb * Ls * 12 * csz;

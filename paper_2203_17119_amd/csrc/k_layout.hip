@@ -11,6 +11,7 @@ struct Geo {
     int L[4];
     long vh;
     int Ls;
+    const int *perm_inv;  // internal site j -> checkerboard index cb
 };
 
 // lexicographic site of checkerboard index cb in parity p (Lx is even, so
@@ -34,18 +35,85 @@ __host__ __device__ __forceinline__ long lex(const int L[4], const int x[4])
     return x[0] + (long)L[0] * (x[1] + (long)L[1] * (x[2] + (long)L[2] * x[3]));
 }
 
+// Cache-blocked site order.  A workgroup's neighbours in +-x, +-y, +-z and
+// +-t must still be in the L2 of its XCD when they are read again; in
+// lexicographic order the +-t neighbours lie a whole 3D slice away.  Sites are
+// therefore grouped in columns with a small (x/2, y, z) cross-section that run
+// along t; a column's t-planes are consecutive, so a sweep along one column
+// keeps about three planes live.  The order is a permutation of the
+// checkerboard index cb = (x/2, y, z, t) and hence identical for both parities.
+static long divisor_at_most(long n, long cap)
+{
+    for (long d = std::min(n, std::max(1L, cap)); d >= 1; d--)
+        if (n % d == 0) return d;
+    return 1;
+}
+
+void build_order(Context &c, int cxh, int cy, int cz)
+{
+    const int Lxh = c.L[0] / 2, Ly = c.L[1], Lz = c.L[2], Lt = c.L[3];
+    if (cxh <= 0 || cy <= 0 || cz <= 0) {
+        // target: one t-plane of a column about 0.6 MB in FP32 storage
+        const long target = std::max(64L, 600000L / (96L * c.Ls));
+        if ((long)Lxh * Ly * Lz <= 2 * target) {
+            cxh = Lxh, cy = Ly, cz = Lz;
+        } else {
+            long best = -1;
+            double best_face = 1e9;
+            for (long dx = 1; dx <= Lxh; dx++) {
+                if (Lxh % dx) continue;
+                for (long dy = 1; dy <= Ly; dy++) {
+                    if (Ly % dy) continue;
+                    const long dz = divisor_at_most(Lz, target / (dx * dy));
+                    const long plane = dx * dy * dz;
+                    if (plane > target) continue;
+                    // neighbour reads leaving the column per site
+                    const double face = 1.0 / (2 * dx) + 1.0 / dy + 1.0 / dz;
+                    if (plane > best || (plane == best && face < best_face)) {
+                        best = plane;
+                        best_face = face;
+                        cxh = (int)dx, cy = (int)dy, cz = (int)dz;
+                    }
+                }
+            }
+        }
+    }
+    if (Lxh % cxh || Ly % cy || Lz % cz) fail(DWF_EINVAL, "column cross-section must divide (Lx/2, Ly, Lz)");
+    c.order[0] = cxh, c.order[1] = cy, c.order[2] = cz;
+    c.perm_h.assign(c.vh, 0);
+    c.perm_inv_h.assign(c.vh, 0);
+    long j = 0;
+    for (int Z = 0; Z < Lz / cz; Z++)
+        for (int Y = 0; Y < Ly / cy; Y++)
+            for (int X = 0; X < Lxh / cxh; X++)
+                for (int t = 0; t < Lt; t++)
+                    for (int z = Z * cz; z < (Z + 1) * cz; z++)
+                        for (int y = Y * cy; y < (Y + 1) * cy; y++)
+                            for (int xh = X * cxh; xh < (X + 1) * cxh; xh++) {
+                                const long cb = xh + (long)Lxh * (y + (long)Ly * (z + (long)Lz * t));
+                                c.perm_h[cb] = (int)j;
+                                c.perm_inv_h[j] = (int)cb;
+                                j++;
+                            }
+    if (!c.perm_inv) HIPCHECK(hipMalloc(&c.perm_inv, c.vh * sizeof(int)));
+    HIPCHECK(hipMemcpy(c.perm_inv, c.perm_inv_h.data(), c.vh * sizeof(int), hipMemcpyHostToDevice));
+}
+
+// sites in one column (one parity)
+long column_sites(const Context &c) { return (long)c.order[0] * c.order[1] * c.order[2] * c.L[3]; }
+
 void build_neighbours(Context &c)
 {
     std::vector<int> h((size_t)2 * 8 * c.vh);
     for (int p = 0; p < 2; p++)
-        for (long cb = 0; cb < c.vh; cb++) {
+        for (long j = 0; j < c.vh; j++) {
             int x[4];
-            site_of_cb(c.L, cb, p, x);
+            site_of_cb(c.L, c.perm_inv_h[j], p, x);
             for (int d = 0; d < 8; d++) {
                 const int mu = d & 3, step = d < 4 ? 1 : -1;
                 int y[4] = {x[0], x[1], x[2], x[3]};
                 y[mu] = (y[mu] + step + c.L[mu]) % c.L[mu];
-                h[((size_t)p * 8 + d) * c.vh + cb] = (int)(lex(c.L, y) >> 1);
+                h[((size_t)p * 8 + d) * c.vh + j] = c.perm_h[lex(c.L, y) >> 1];
             }
         }
     HIPCHECK(hipMemcpy(c.nbr, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -56,10 +124,10 @@ void build_neighbours(Context &c)
 template <typename S>
 __global__ void k_prepare_links(Geo g, const double2 *gauge, int p, int4 dir, typename S::elem *out)
 {
-    const long cb = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (cb >= g.vh) return;
+    const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (j >= g.vh) return;
     int x[4];
-    const long n = site_of_cb(g.L, cb, p, x);
+    const long n = site_of_cb(g.L, g.perm_inv[j], p, x);
     const int dm[4] = {dir.x, dir.y, dir.z, dir.w};
     for (int d = 0; d < 8; d++) {
         const int mu = d & 3;
@@ -80,7 +148,7 @@ __global__ void k_prepare_links(Geo g, const double2 *gauge, int p, int4 dir, ty
                 if (d < 4) v = mk(U[r * 3 + col].x, U[r * 3 + col].y);
                 else v = mk(U[col * 3 + r].x, -U[col * 3 + r].y);
                 if (zero) v = mk(0.0, 0.0);
-                out[((long)d * 9 + r * 3 + col) * g.vh + cb] = pack<S, double>(v);
+                out[((long)d * 9 + r * 3 + col) * g.vh + j] = pack<S, double>(v);
             }
     }
 }
@@ -90,6 +158,7 @@ static Geo geo(const Context &c)
     Geo g;
     for (int mu = 0; mu < 4; mu++) g.L[mu] = c.L[mu];
     g.vh = c.vh;
+    g.perm_inv = c.perm_inv;
     g.Ls = c.Ls;
     return g;
 }
@@ -119,8 +188,9 @@ __global__ void k_import(Geo g, const double2 *canon, Field out, int full, int p
 {
     const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (i >= g.vh * g.Ls) return;
-    const long cb = i / g.Ls;
-    const int s = (int)(i - cb * g.Ls);
+    const long j = i / g.Ls;
+    const int s = (int)(i - j * g.Ls);
+    const long cb = g.perm_inv[j];
     long site = cb;
     if (full) {
         int x[4];
@@ -137,8 +207,9 @@ __global__ void k_export(Geo g, Field in, double2 *canon, int full, int parity)
 {
     const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (i >= g.vh * g.Ls) return;
-    const long cb = i / g.Ls;
-    const int s = (int)(i - cb * g.Ls);
+    const long j = i / g.Ls;
+    const int s = (int)(i - j * g.Ls);
+    const long cb = g.perm_inv[j];
     long site = cb;
     if (full) {
         int x[4];

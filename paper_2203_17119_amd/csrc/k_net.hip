@@ -1,0 +1,429 @@
+// Gauge-equivariant parallel-transport convolution (PTC) network kernels.
+//
+// A layer maps Cin colour-vector channels to Cout:
+//   out_a(x,s) = sum_pi sum_b W[pi][a][b] (T_pi phi_b)(x,s)
+// over 11 paths pi: 0 identity; 1+mu: U_mu(x) phi(x+mu); 5+mu: U_mu(x-mu)^+ phi(x-mu);
+// 9: phi(x,s+1) and 10: phi(x,s-1), zero outside 0 <= s < Ls.  The map is
+// linear, commutes with local SU(3) rotations, and its adjoint is the same
+// layer with W[pi]^+ on the adjoint path (T_{+mu}^+ = T_{-mu}, T_{+s}^+ = T_{-s}).
+//
+// Features are FP32 complex planes over both parities:
+//   f[p][ch*3 + colour][i],  i = j*Ls + s (internal site order)
+// Weights are BF16 (re, im) pairs converted to FP32 in LDS; all arithmetic FP32,
+// weight-gradient partial sums FP64.
+#include "dwf_internal.h"
+
+namespace dwf {
+
+struct NetGeo {
+    const int *nbr;        // [2][8][vh]
+    const float2 *links0;  // FP32 links, output parity 0: [8][9][vh]
+    const float2 *links1;  // output parity 1
+    long vh;
+    int Ls;
+};
+
+__device__ __forceinline__ cx<float> c2(float2 v) { return mk(v.x, v.y); }
+
+// path source for output site (j, s) of parity p: returns the 5D index in the
+// source parity and whether the site exists (s-paths have open ends)
+__device__ __forceinline__ bool path_source(const NetGeo &g, int p, int pi, long j, int s, long &src, int &sp)
+{
+    if (pi == 0) {
+        src = j * g.Ls + s;
+        sp = p;
+        return true;
+    }
+    if (pi <= 8) {
+        const int d = (pi <= 4) ? pi - 1 : pi - 1;  // 1..4 -> 0..3 (+mu), 5..8 -> 4..7 (-mu)
+        src = (long)g.nbr[((long)p * 8 + d) * g.vh + j] * g.Ls + s;
+        sp = 1 - p;
+        return true;
+    }
+    const int s2 = (pi == 9) ? s + 1 : s - 1;
+    src = j * g.Ls + s2;
+    sp = p;
+    return s2 >= 0 && s2 < g.Ls;
+}
+
+template <int CIN>
+__device__ __forceinline__ void transported(const NetGeo &g, const float2 *in, long n, int p, int pi, long j, int s,
+                                            cx<float> t[CIN][3])
+{
+    long src;
+    int sp;
+    const bool ok = path_source(g, p, pi, j, s, src, sp);
+    const float2 *base = in + (long)sp * CIN * 3 * n;
+    if (!ok) {
+#pragma unroll
+        for (int b = 0; b < CIN; b++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) t[b][c] = mk(0.f, 0.f);
+        return;
+    }
+#pragma unroll
+    for (int b = 0; b < CIN; b++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) t[b][c] = c2(base[(b * 3 + c) * n + src]);
+    if (pi >= 1 && pi <= 8) {
+        const int d = pi - 1;
+        const float2 *L = (p ? g.links1 : g.links0) + (long)d * 9 * g.vh + j;
+        cx<float> u[9];
+#pragma unroll
+        for (int k = 0; k < 9; k++) u[k] = c2(L[k * g.vh]);
+#pragma unroll
+        for (int b = 0; b < CIN; b++) {
+            cx<float> v0 = t[b][0], v1 = t[b][1], v2 = t[b][2];
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                cx<float> a = cmul(u[r * 3 + 0], v0);
+                cmac(a, u[r * 3 + 1], v1);
+                cmac(a, u[r * 3 + 2], v2);
+                t[b][r] = a;
+            }
+        }
+    }
+}
+
+// one layer, output parity p.  w: [11][COUT][CIN] BF16 pairs
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) k_ptc_fwd(NetGeo g, const float2 *in, float2 *out, const __hip_bfloat162 *w, int p,
+                                                 long n)
+{
+    __shared__ cx<float> W[11 * COUT * CIN];
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    for (int k = tid; k < 11 * COUT * CIN; k += blockDim.x * blockDim.y) {
+        const float2 f = __bfloat1622float2(w[k]);
+        W[k] = mk(f.x, f.y);
+    }
+    __syncthreads();
+    const int s = threadIdx.x;
+    const long j = (long)blockIdx.x * blockDim.y + threadIdx.y;
+    if (j >= g.vh) return;
+    cx<float> acc[COUT][3];
+#pragma unroll
+    for (int a = 0; a < COUT; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) acc[a][c] = mk(0.f, 0.f);
+    for (int pi = 0; pi < 11; pi++) {
+        cx<float> t[CIN][3];
+        transported<CIN>(g, in, n, p, pi, j, s, t);
+        const cx<float> *Wp = W + pi * COUT * CIN;
+#pragma unroll
+        for (int a = 0; a < COUT; a++)
+#pragma unroll
+            for (int b = 0; b < CIN; b++) {
+                const cx<float> wab = Wp[a * CIN + b];
+#pragma unroll
+                for (int c = 0; c < 3; c++) cmac(acc[a][c], wab, t[b][c]);
+            }
+    }
+    float2 *o = out + (long)p * COUT * 3 * n;
+    const long i = j * g.Ls + s;
+#pragma unroll
+    for (int a = 0; a < COUT; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) o[(a * 3 + c) * n + i] = make_float2(acc[a][c].re, acc[a][c].im);
+}
+
+// Weight gradient of one layer over the output sites of parity p:
+//   gW[pi][a][b] += sum_{sites, colour} g_a conj(T_pi phi_b)
+// Each workgroup reduces its sites through LDS; partial[blk][pi][a][b] (re, im) in FP64.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) k_ptc_wgrad(NetGeo g, const float2 *in, const float2 *gout, int p, long n,
+                                                   double *partial)
+{
+    extern __shared__ unsigned char smem[];
+    const int nt = blockDim.x * blockDim.y;
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    cx<float> *T = (cx<float> *)smem;   // [nt][CIN*3]
+    cx<float> *G = T + nt * CIN * 3;   // [nt][COUT*3]
+    const int s = threadIdx.x;
+    const long j = (long)blockIdx.x * blockDim.y + threadIdx.y;
+    const bool valid = j < g.vh;
+    const float2 *go = gout + (long)p * COUT * 3 * n;
+    for (int a = 0; a < COUT; a++)
+        for (int c = 0; c < 3; c++)
+            G[tid * COUT * 3 + a * 3 + c] = valid ? c2(go[(a * 3 + c) * n + j * g.Ls + s]) : mk(0.f, 0.f);
+    for (int pi = 0; pi < 11; pi++) {
+        cx<float> t[CIN][3];
+        if (valid) {
+            transported<CIN>(g, in, n, p, pi, j, s, t);
+        } else {
+            for (int b = 0; b < CIN; b++)
+                for (int c = 0; c < 3; c++) t[b][c] = mk(0.f, 0.f);
+        }
+        __syncthreads();
+        for (int b = 0; b < CIN; b++)
+            for (int c = 0; c < 3; c++) T[tid * CIN * 3 + b * 3 + c] = t[b][c];
+        __syncthreads();
+        for (int q = tid; q < COUT * CIN; q += nt) {
+            const int a = q / CIN, b = q % CIN;
+            double re = 0, im = 0;
+            for (int r = 0; r < nt; r++)
+                for (int c = 0; c < 3; c++) {
+                    const cx<float> gg = G[r * COUT * 3 + a * 3 + c], tt = T[r * CIN * 3 + b * 3 + c];
+                    // g * conj(t)
+                    re += double(gg.re) * tt.re + double(gg.im) * tt.im;
+                    im += double(gg.im) * tt.re - double(gg.re) * tt.im;
+                }
+            double *dst = partial + (((long)blockIdx.x * 11 + pi) * COUT * CIN + q) * 2;
+            dst[0] = re;
+            dst[1] = im;
+        }
+    }
+}
+
+// gw[k] (FP32, re/im interleaved) = sum over nblk partials (fixed order) [+ gw[k] when accumulate]
+__global__ void k_wgrad_finish(const double *partial, int nblk, int nw, float *gw, int accumulate)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 2 * nw) return;
+    double t = 0;
+    for (int b = 0; b < nblk; b++) t += partial[(long)b * 2 * nw + k];
+    gw[k] = accumulate ? float(double(gw[k]) + t) : float(t);
+}
+
+// adjoint weights for the input gradient: wt[adj(pi)][b][a] = conj(w[pi][a][b])
+__global__ void k_adjoint_weights(const __hip_bfloat162 *w, __hip_bfloat162 *wt, int cin, int cout)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 11 * cout * cin) return;
+    const int pi = k / (cout * cin), a = (k / cin) % cout, b = k % cin;
+    const int adj = (pi == 0) ? 0 : (pi <= 4) ? pi + 4 : (pi <= 8) ? pi - 4 : (pi == 9 ? 10 : 9);
+    const float2 f = __bfloat1622float2(w[k]);
+    wt[(adj * cin + b) * cout + a] = __float22bfloat162_rn(make_float2(f.x, -f.y));
+}
+
+// FP32 master -> BF16 working copy
+__global__ void k_to_bf16(const float2 *w, __hip_bfloat162 *o, int nw)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nw) o[k] = __float22bfloat162_rn(w[k]);
+}
+
+// Adam on FP32 masters with the real-pair gradient g (= dL/dRe + i dL/dIm)
+__global__ void k_adam(float *w, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float gk = g[k];
+    const float mk_ = b1 * m[k] + (1.f - b1) * gk;
+    const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+    m[k] = mk_;
+    v[k] = vk;
+    w[k] -= lr * (mk_ / c1) / (sqrtf(vk / c2) + eps);
+}
+
+// ------------------------------------------------------ spinor <-> features
+
+// half spinor (internal layout, precision S) -> 4-channel features of parity p
+// (channel = spin), the other parity zero when zero_other
+template <typename S>
+__global__ void __launch_bounds__(256) k_spinor_to_feat(Field f, float2 *feat, int p, long n, int zero_other)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cx<float> v[12];
+    load_spinor<S, float>(f, i, v);
+    float2 *dst = feat + (long)p * 12 * n;
+    for (int c = 0; c < 12; c++) dst[c * n + i] = make_float2(v[c].re, v[c].im);
+    if (zero_other) {
+        float2 *o = feat + (long)(1 - p) * 12 * n;
+        for (int c = 0; c < 12; c++) o[c * n + i] = make_float2(0.f, 0.f);
+    }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_feat_to_spinor(const float2 *feat, Field f, int p, long n)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cx<float> v[12];
+    const float2 *src = feat + (long)p * 12 * n;
+    for (int c = 0; c < 12; c++) v[c] = c2(src[c * n + i]);
+    store_spinor<S, float>(f, i, v);
+}
+
+// loss of one sample on parity p: r = y - x (FP32 features vs FP64 spinor x),
+// partial |r|^2 and |x|^2; writes r into grad (scaled later on the host)
+__global__ void __launch_bounds__(256) k_loss_residual(const float2 *y, Field x, float2 *grad, int p, long n,
+                                                       double *partial)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    double r2 = 0, x2 = 0;
+    if (i < n) {
+        cx<double> xv[12];
+        load_spinor<F64, double>(x, i, xv);
+        const float2 *yy = y + (long)p * 12 * n;
+        float2 *gg = grad + (long)p * 12 * n;
+        for (int c = 0; c < 12; c++) {
+            const double dr = double(yy[c * n + i].x) - xv[c].re, di = double(yy[c * n + i].y) - xv[c].im;
+            r2 += dr * dr + di * di;
+            x2 += xv[c].re * xv[c].re + xv[c].im * xv[c].im;
+            gg[c * n + i] = make_float2(float(dr), float(di));
+        }
+    }
+    r2 = block_sum(r2);
+    x2 = block_sum(x2);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = r2;
+        partial[2 * blockIdx.x + 1] = x2;
+    }
+}
+
+__global__ void k_scale_feat(float2 *f, long n, float a)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) f[i] = make_float2(a * f[i].x, a * f[i].y);
+}
+
+__global__ void k_zero_feat(float2 *f, long n)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) f[i] = make_float2(0.f, 0.f);
+}
+
+// ------------------------------------------------------------ launchers
+
+static NetGeo net_geo(Context &c)
+{
+    NetGeo g;
+    g.nbr = c.nbr;
+    g.links0 = (const float2 *)c.links[P_F32][0];
+    g.links1 = (const float2 *)c.links[P_F32][1];
+    g.vh = c.vh;
+    g.Ls = c.Ls;
+    return g;
+}
+
+static int net_sb(const Context &c) { return std::max(1, std::min(64, 128 / c.Ls)); }
+
+void launch_ptc_layer(Context &c, int cin, int cout, const float2 *in, float2 *out, const void *w_bf16, int p)
+{
+    const NetGeo g = net_geo(c);
+    const int sb = net_sb(c);
+    const dim3 grid((unsigned)((c.vh + sb - 1) / sb)), blk(c.Ls, sb);
+    const __hip_bfloat162 *w = (const __hip_bfloat162 *)w_bf16;
+    const double flops = (double)c.n5h * (11.0 * cout * cin * 3 * 8 + 8.0 * cin * 66);
+    Timer tm(c, DWF_K_NET, (double)c.n5h * 8.0 * 3 * (11 * cin + cout), flops);
+#define NETL(CI, CO) hipLaunchKernelGGL((k_ptc_fwd<CI, CO>), grid, blk, 0, c.stream, g, in, out, w, p, c.n5h)
+    if (cin == 4 && cout == 12) NETL(4, 12);
+    else if (cin == 12 && cout == 12) NETL(12, 12);
+    else if (cin == 12 && cout == 4) NETL(12, 4);
+    else if (cin == 4 && cout == 4) NETL(4, 4);
+    else if (cin == 4 && cout == 8) NETL(4, 8);
+    else if (cin == 8 && cout == 8) NETL(8, 8);
+    else if (cin == 8 && cout == 4) NETL(8, 4);
+    else if (cin == 12 && cout == 8) NETL(12, 8);
+    else if (cin == 8 && cout == 12) NETL(8, 12);
+    else fail(DWF_ENOTSUP, "layer channel counts must be 4, 8 or 12");
+#undef NETL
+    HIPCHECK(hipGetLastError());
+}
+
+int launch_ptc_wgrad(Context &c, int cin, int cout, const float2 *in, const float2 *gout, int p, double *partial,
+                     long partial_len)
+{
+    const NetGeo g = net_geo(c);
+    const int sb = net_sb(c);
+    const long nblk = (c.vh + sb - 1) / sb;
+    if (nblk * 11 * cin * cout * 2 > partial_len) fail(DWF_EINVAL, "weight-gradient buffer too small");
+    const dim3 grid((unsigned)nblk), blk(c.Ls, sb);
+    const size_t lds = (size_t)c.Ls * sb * (cin + cout) * 3 * sizeof(cx<float>);
+    if (lds > 160 * 1024) fail(DWF_ENOTSUP, "weight-gradient tile does not fit in LDS");
+    Timer tm(c, DWF_K_NET, (double)c.n5h * 8.0 * 3 * (11 * cin + cout), (double)c.n5h * 11.0 * cin * cout * 3 * 8);
+#define NETW(CI, CO) hipLaunchKernelGGL((k_ptc_wgrad<CI, CO>), grid, blk, lds, c.stream, g, in, gout, p, c.n5h, partial)
+    if (cin == 4 && cout == 12) NETW(4, 12);
+    else if (cin == 12 && cout == 12) NETW(12, 12);
+    else if (cin == 12 && cout == 4) NETW(12, 4);
+    else if (cin == 4 && cout == 4) NETW(4, 4);
+    else if (cin == 4 && cout == 8) NETW(4, 8);
+    else if (cin == 8 && cout == 8) NETW(8, 8);
+    else if (cin == 8 && cout == 4) NETW(8, 4);
+    else if (cin == 12 && cout == 8) NETW(12, 8);
+    else if (cin == 8 && cout == 12) NETW(8, 12);
+    else fail(DWF_ENOTSUP, "layer channel counts must be 4, 8 or 12");
+#undef NETW
+    HIPCHECK(hipGetLastError());
+    return (int)nblk;
+}
+
+void launch_wgrad_finish(Context &c, const double *partial, int nblk, int nw, float *gw, bool accumulate)
+{
+    hipLaunchKernelGGL(k_wgrad_finish, dim3((2 * nw + 255) / 256), dim3(256), 0, c.stream, partial, nblk, nw, gw,
+                       accumulate ? 1 : 0);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_adjoint_weights(Context &c, const void *w, void *wt, int cin, int cout)
+{
+    const int n = 11 * cin * cout;
+    hipLaunchKernelGGL(k_adjoint_weights, dim3((n + 255) / 256), dim3(256), 0, c.stream, (const __hip_bfloat162 *)w,
+                       (__hip_bfloat162 *)wt, cin, cout);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_to_bf16(Context &c, const float *w, void *o, int nw)
+{
+    hipLaunchKernelGGL(k_to_bf16, dim3((nw + 255) / 256), dim3(256), 0, c.stream, (const float2 *)w,
+                       (__hip_bfloat162 *)o, nw);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_adam(Context &c, float *w, const float *g, float *m, float *v, int n, float lr, float b1, float b2,
+                 float eps, int step)
+{
+    const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, c.stream, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_spinor_to_feat(Context &c, int prec, Field f, float2 *feat, int p, bool zero_other)
+{
+    const dim3 grid((unsigned)((c.n5h + 255) / 256));
+    switch (prec) {
+    case P_F64: hipLaunchKernelGGL(k_spinor_to_feat<F64>, grid, dim3(256), 0, c.stream, f, feat, p, c.n5h, (int)zero_other); break;
+    case P_F32: hipLaunchKernelGGL(k_spinor_to_feat<F32>, grid, dim3(256), 0, c.stream, f, feat, p, c.n5h, (int)zero_other); break;
+    case P_F16: hipLaunchKernelGGL(k_spinor_to_feat<F16>, grid, dim3(256), 0, c.stream, f, feat, p, c.n5h, (int)zero_other); break;
+    default: hipLaunchKernelGGL(k_spinor_to_feat<BF16>, grid, dim3(256), 0, c.stream, f, feat, p, c.n5h, (int)zero_other); break;
+    }
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_feat_to_spinor(Context &c, int prec, const float2 *feat, Field f, int p)
+{
+    const dim3 grid((unsigned)((c.n5h + 255) / 256));
+    switch (prec) {
+    case P_F64: hipLaunchKernelGGL(k_feat_to_spinor<F64>, grid, dim3(256), 0, c.stream, feat, f, p, c.n5h); break;
+    case P_F32: hipLaunchKernelGGL(k_feat_to_spinor<F32>, grid, dim3(256), 0, c.stream, feat, f, p, c.n5h); break;
+    case P_F16: hipLaunchKernelGGL(k_feat_to_spinor<F16>, grid, dim3(256), 0, c.stream, feat, f, p, c.n5h); break;
+    default: hipLaunchKernelGGL(k_feat_to_spinor<BF16>, grid, dim3(256), 0, c.stream, feat, f, p, c.n5h); break;
+    }
+    HIPCHECK(hipGetLastError());
+}
+
+int launch_loss_residual(Context &c, const float2 *y, Field x, float2 *grad, int p)
+{
+    const long nb = (c.n5h + 255) / 256;
+    if (2 * nb > c.partials_len) fail(DWF_EINVAL, "reduction buffer too small");
+    hipLaunchKernelGGL(k_loss_residual, dim3((unsigned)nb), dim3(256), 0, c.stream, y, x, grad, p, c.n5h,
+                       c.partials);
+    HIPCHECK(hipGetLastError());
+    return (int)nb;
+}
+
+void launch_scale_feat(Context &c, float2 *f, long n, float a)
+{
+    hipLaunchKernelGGL(k_scale_feat, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, f, n, a);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_zero_feat(Context &c, float2 *f, long n)
+{
+    hipLaunchKernelGGL(k_zero_feat, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, f, n);
+    HIPCHECK(hipGetLastError());
+}
+
+}  // namespace dwf

@@ -271,7 +271,7 @@ template <typename S, typename C>
 static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field self, Field out)
 {
     const int Ls = c.Ls;
-    const int sb = c.cfg_stencil.sb > 0 ? c.cfg_stencil.sb : (Ls >= 192 ? 1 : 192 / Ls);
+    const int sb = cfg_sb(c, c.cfg_stencil);
     const long nblk = (c.vh + sb - 1) / sb;
     if (sp.reduce && nblk > c.partials_len) fail(DWF_EINVAL, "reduction buffer too small");
     StencilKArgs a;
@@ -342,7 +342,7 @@ template <typename S, typename C>
 static void launch_slocal_t(Context &c, int op, Field in, Field out)
 {
     const int Ls = c.Ls;
-    const int sb = c.cfg_slocal.sb > 0 ? c.cfg_slocal.sb : (Ls >= 192 ? 1 : 192 / Ls);
+    const int sb = cfg_sb(c, c.cfg_slocal);
     const long nblk = (c.vh + sb - 1) / sb;
     const size_t lds = (size_t)sb * Ls * 12 * sizeof(cx<C>) + 2 * (size_t)Ls * Ls * sizeof(C);
     const double sbytes = 12.0 * sizeof(typename S::elem) + (S::has_norm ? 4.0 : 0.0);

@@ -1,0 +1,534 @@
+// Learned preconditioner: network lifecycle, forward / backward / training
+// step on the device, the preconditioner application and flexible GCR.
+//
+// Weights: per layer l a block W_l[pi][a][b] of 11 x Cout x Cin complex
+// numbers, layers back to back.  The host-facing format is FP32 (re, im)
+// pairs; the device keeps FP32 masters (Adam) and the BF16 copies the kernels
+// use.  Gradients follow the real-pair convention dL/dRe + i dL/dIm.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "dwf_internal.h"
+
+using namespace dwf;
+
+namespace dwf {
+void launch_ptc_layer(Context &c, int cin, int cout, const float2 *in, float2 *out, const void *w_bf16, int p);
+int launch_ptc_wgrad(Context &c, int cin, int cout, const float2 *in, const float2 *gout, int p, double *partial,
+                     long partial_len);
+void launch_wgrad_finish(Context &c, const double *partial, int nblk, int nw, float *gw, bool accumulate);
+void launch_adjoint_weights(Context &c, const void *w, void *wt, int cin, int cout);
+void launch_to_bf16(Context &c, const float *w, void *o, int nw);
+void launch_adam(Context &c, float *w, const float *g, float *m, float *v, int n, float lr, float b1, float b2,
+                 float eps, int step);
+void launch_spinor_to_feat(Context &c, int prec, Field f, float2 *feat, int p, bool zero_other);
+void launch_feat_to_spinor(Context &c, int prec, const float2 *feat, Field f, int p);
+int launch_loss_residual(Context &c, const float2 *y, Field x, float2 *grad, int p);
+void launch_scale_feat(Context &c, float2 *f, long n, float a);
+void launch_zero_feat(Context &c, float2 *f, long n);
+}  // namespace dwf
+
+struct dwf_net_s {
+    Context *c = nullptr;
+    int nlayer = 0;
+    std::vector<int> chans;
+    std::vector<int> woff;  // complex offset of each layer's block
+    int nw = 0;             // complex weights in total
+    float *w32 = nullptr, *gw = nullptr, *m = nullptr, *v = nullptr;
+    void *wbf = nullptr, *wadj = nullptr;
+    int step = 0;
+    std::vector<float2 *> acts;  // layer inputs (both parities), acts[nlayer] = output
+    float2 *g0 = nullptr, *g1 = nullptr;  // gradient ping-pong (max channels)
+    double *wpart = nullptr;
+    long wpart_len = 0;
+    int cmax = 0;
+};
+
+namespace dwf {
+
+static double wall()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static size_t feat_elems(const Context &c, int C) { return (size_t)2 * C * 3 * c.n5h; }
+
+static void net_free(dwf_net_s *n)
+{
+    for (void *p : {(void *)n->w32, (void *)n->gw, (void *)n->m, (void *)n->v, n->wbf, n->wadj, (void *)n->g0,
+                    (void *)n->g1, (void *)n->wpart})
+        if (p) (void)hipFree(p);
+    for (auto *a : n->acts)
+        if (a) (void)hipFree(a);
+    delete n;
+}
+
+static void refresh_bf16(dwf_net_s *n)
+{
+    Context &c = *n->c;
+    launch_to_bf16(c, n->w32, n->wbf, n->nw);
+    for (int l = 0; l < n->nlayer; l++)
+        launch_adjoint_weights(c, (const __hip_bfloat162 *)n->wbf + n->woff[l], (__hip_bfloat162 *)n->wadj + n->woff[l],
+                               n->chans[l], n->chans[l + 1]);
+}
+
+// forward of one sample whose input is acts[0] (4 channels); the last layer
+// is evaluated on odd sites only (the preconditioner's range)
+static void net_forward(dwf_net_s *n, bool all_parities)
+{
+    Context &c = *n->c;
+    for (int l = 0; l < n->nlayer; l++) {
+        const bool last = l == n->nlayer - 1;
+        for (int p = (last && !all_parities) ? 1 : 0; p < 2; p++)
+            launch_ptc_layer(c, n->chans[l], n->chans[l + 1], n->acts[l], n->acts[l + 1],
+                             (const __hip_bfloat162 *)n->wbf + n->woff[l], p);
+    }
+}
+
+// adjoint network applied to features g (4 channels, both parities, not g0/g1);
+// returns the buffer (g0 or g1) holding the 4-channel result
+static float2 *net_adjoint(dwf_net_s *n, const float2 *g)
+{
+    Context &c = *n->c;
+    const float2 *cur = g;
+    float2 *dst = nullptr;
+    for (int l = n->nlayer - 1; l >= 0; l--) {
+        dst = (cur == n->g0) ? n->g1 : n->g0;
+        for (int p = 0; p < 2; p++)
+            launch_ptc_layer(c, n->chans[l + 1], n->chans[l], cur, dst, (const __hip_bfloat162 *)n->wadj + n->woff[l], p);
+        cur = dst;
+    }
+    return dst;
+}
+
+// backward from the gradient in g0 (4 output channels, both parities, even part
+// zero): accumulates the weight gradient into gw and leaves the input gradient in
+// the returned buffer
+static float2 *net_backward(dwf_net_s *n)
+{
+    Context &c = *n->c;
+    float2 *g = n->g0, *o = n->g1;
+    for (int l = n->nlayer - 1; l >= 0; l--) {
+        const int cin = n->chans[l], cout = n->chans[l + 1];
+        const int nwl = 11 * cin * cout;
+        for (int p = (l == n->nlayer - 1) ? 1 : 0; p < 2; p++) {
+            const int nb = launch_ptc_wgrad(c, cin, cout, n->acts[l], g, p, n->wpart, n->wpart_len);
+            launch_wgrad_finish(c, n->wpart, nb, nwl, n->gw + 2 * (size_t)n->woff[l], true);
+        }
+        for (int p = 0; p < 2; p++)
+            launch_ptc_layer(c, cout, cin, g, o, (const __hip_bfloat162 *)n->wadj + n->woff[l], p);
+        std::swap(g, o);
+    }
+    return g;
+}
+
+}  // namespace dwf
+
+// ================================================================ C ABI
+
+#define DWF_API_BEGIN try {
+#define DWF_API_END                              \
+    return DWF_OK;                               \
+    }                                            \
+    catch (const dwf::Error &e)                  \
+    {                                            \
+        dwf::set_error(e.msg);                   \
+        return e.code;                           \
+    }                                            \
+    catch (const std::exception &e)              \
+    {                                            \
+        dwf::set_error(e.what());                \
+        return DWF_ENOMEM;                       \
+    }
+
+static dwf_net_s &N_(dwf_net n)
+{
+    if (!n) fail(DWF_EINVAL, "null network");
+    return *n;
+}
+
+extern "C" {
+
+dwf_status dwf_net_create(dwf_ctx ctx, int nlayer, const int *chans, dwf_net *out)
+{
+    DWF_API_BEGIN
+    if (!ctx || !chans || !out) fail(DWF_EINVAL, "null pointer");
+    *out = nullptr;
+    if (nlayer < 1 || nlayer > 16) fail(DWF_EINVAL, "1 <= nlayer <= 16");
+    if (chans[0] != 4 || chans[nlayer] != 4) fail(DWF_EINVAL, "the first and last channel counts must be 4 (spins)");
+    for (int l = 0; l <= nlayer; l++)
+        if (chans[l] != 4 && chans[l] != 8 && chans[l] != 12) fail(DWF_ENOTSUP, "channel counts must be 4, 8 or 12");
+    Context &c = *ctx;
+    auto *n = new dwf_net_s();
+    try {
+        n->c = &c;
+        n->nlayer = nlayer;
+        n->chans.assign(chans, chans + nlayer + 1);
+        for (int l = 0; l < nlayer; l++) {
+            n->woff.push_back(n->nw);
+            n->nw += 11 * chans[l] * chans[l + 1];
+        }
+        for (int ch : n->chans) n->cmax = std::max(n->cmax, ch);
+        ensure_links(c, P_F32);
+        HIPCHECK(hipMalloc(&n->w32, 2 * sizeof(float) * n->nw));
+        HIPCHECK(hipMalloc(&n->gw, 2 * sizeof(float) * n->nw));
+        HIPCHECK(hipMalloc(&n->m, 2 * sizeof(float) * n->nw));
+        HIPCHECK(hipMalloc(&n->v, 2 * sizeof(float) * n->nw));
+        HIPCHECK(hipMalloc(&n->wbf, 4 * (size_t)n->nw));
+        HIPCHECK(hipMalloc(&n->wadj, 4 * (size_t)n->nw));
+        for (void *p : {(void *)n->w32, (void *)n->gw, (void *)n->m, (void *)n->v})
+            HIPCHECK(hipMemset(p, 0, 2 * sizeof(float) * n->nw));
+        for (int l = 0; l <= nlayer; l++) {
+            float2 *a = nullptr;
+            HIPCHECK(hipMalloc(&a, feat_elems(c, chans[l]) * sizeof(float2)));
+            n->acts.push_back(a);
+        }
+        HIPCHECK(hipMalloc(&n->g0, feat_elems(c, n->cmax) * sizeof(float2)));
+        HIPCHECK(hipMalloc(&n->g1, feat_elems(c, n->cmax) * sizeof(float2)));
+        const int sbn = std::max(1, std::min(64, 128 / c.Ls));
+        const long nblk = (c.vh + sbn - 1) / sbn;
+        n->wpart_len = nblk * 11 * (long)n->cmax * n->cmax * 2;
+        HIPCHECK(hipMalloc(&n->wpart, n->wpart_len * sizeof(double)));
+        refresh_bf16(n);
+        HIPCHECK(hipStreamSynchronize(c.stream));
+    } catch (...) {
+        net_free(n);
+        throw;
+    }
+    *out = n;
+    DWF_API_END
+}
+
+dwf_status dwf_net_destroy(dwf_net net)
+{
+    if (!net) return DWF_OK;
+    (void)hipStreamSynchronize(net->c->stream);
+    net_free(net);
+    return DWF_OK;
+}
+
+int dwf_net_num_weights(dwf_net net) { return net ? net->nw : -1; }
+
+dwf_status dwf_net_set_weights(dwf_net net, const float *w)
+{
+    DWF_API_BEGIN
+    dwf_net_s &n = N_(net);
+    if (!w) fail(DWF_EINVAL, "null weights");
+    HIPCHECK(hipMemcpy(n.w32, w, 2 * sizeof(float) * n.nw, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemset(n.m, 0, 2 * sizeof(float) * n.nw));
+    HIPCHECK(hipMemset(n.v, 0, 2 * sizeof(float) * n.nw));
+    n.step = 0;
+    refresh_bf16(&n);
+    HIPCHECK(hipStreamSynchronize(n.c->stream));
+    DWF_API_END
+}
+
+dwf_status dwf_net_get_weights(dwf_net net, float *w)
+{
+    DWF_API_BEGIN
+    dwf_net_s &n = N_(net);
+    if (!w) fail(DWF_EINVAL, "null weights");
+    HIPCHECK(hipStreamSynchronize(n.c->stream));
+    HIPCHECK(hipMemcpy(w, n.w32, 2 * sizeof(float) * n.nw, hipMemcpyDeviceToHost));
+    DWF_API_END
+}
+
+dwf_status dwf_precond_apply(dwf_ctx ctx, dwf_net net, const double *in_odd, double *out_odd)
+{
+    DWF_API_BEGIN
+    if (!ctx) fail(DWF_EINVAL, "null context");
+    dwf_net_s &n = N_(net);
+    if (n.c != ctx) fail(DWF_EINVAL, "network belongs to another context");
+    if (!in_odd || !out_odd) fail(DWF_EINVAL, "null field");
+    Context &c = *ctx;
+    Field a = ws_field(c, "net_io", P_F64);
+    launch_import(c, P_F64, in_odd, a, 0, 0);
+    launch_spinor_to_feat(c, P_F64, a, n.acts[0], 1, true);
+    net_forward(&n, false);
+    launch_feat_to_spinor(c, P_F64, n.acts[n.nlayer], a, 1);
+    launch_export(c, P_F64, a, out_odd, 0, 0);
+    DWF_API_END
+}
+
+dwf_status dwf_net_backward(dwf_net net, const double *in_odd, const double *grad_out_odd, double *grad_in_odd,
+                            float *grad_w)
+{
+    DWF_API_BEGIN
+    dwf_net_s &n = N_(net);
+    if (!in_odd || !grad_out_odd) fail(DWF_EINVAL, "null field");
+    Context &c = *n.c;
+    Field a = ws_field(c, "net_io", P_F64);
+    launch_import(c, P_F64, in_odd, a, 0, 0);
+    launch_spinor_to_feat(c, P_F64, a, n.acts[0], 1, true);
+    net_forward(&n, false);
+    launch_import(c, P_F64, grad_out_odd, a, 0, 0);
+    launch_spinor_to_feat(c, P_F64, a, n.g0, 1, true);
+    HIPCHECK(hipMemsetAsync(n.gw, 0, 2 * sizeof(float) * n.nw, c.stream));
+    float2 *gin = net_backward(&n);
+    if (grad_in_odd) {
+        launch_feat_to_spinor(c, P_F64, gin, a, 1);
+        launch_export(c, P_F64, a, grad_in_odd, 0, 0);
+    }
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    if (grad_w) HIPCHECK(hipMemcpy(grad_w, n.gw, 2 * sizeof(float) * n.nw, hipMemcpyDeviceToHost));
+    DWF_API_END
+}
+
+dwf_status dwf_net_train_step(dwf_net net, int nbatch, const double *const *b_odd, const double *const *x_odd,
+                              const dwf_adam *opt, double *loss)
+{
+    DWF_API_BEGIN
+    dwf_net_s &n = N_(net);
+    if (nbatch < 1 || !b_odd || !x_odd) fail(DWF_EINVAL, "need nbatch >= 1 and field arrays");
+    Context &c = *n.c;
+    Field a = ws_field(c, "net_io", P_F64), xt = ws_field(c, "net_x", P_F64);
+    HIPCHECK(hipMemsetAsync(n.gw, 0, 2 * sizeof(float) * n.nw, c.stream));
+    double total = 0;
+    for (int k = 0; k < nbatch; k++) {
+        if (!b_odd[k] || !x_odd[k]) fail(DWF_EINVAL, "null field in batch");
+        launch_import(c, P_F64, b_odd[k], a, 0, 0);
+        launch_import(c, P_F64, x_odd[k], xt, 0, 0);
+        launch_spinor_to_feat(c, P_F64, a, n.acts[0], 1, true);
+        net_forward(&n, false);
+        // loss_k = |y - x|^2 / |x|^2 on odd sites; gradient 2 (y - x) / (|x|^2 B)
+        launch_zero_feat(c, n.g0, (long)2 * 12 * c.n5h);
+        const int nb = launch_loss_residual(c, n.acts[n.nlayer], xt, n.g0, 1);
+        launch_finish(c, nb, 2, 10);
+        read_scalars(c, 10, 2);
+        const double r2 = c.hscal[10], x2 = c.hscal[11];
+        if (!(x2 > 0)) fail(DWF_EINVAL, "zero target field");
+        total += r2 / x2;
+        launch_scale_feat(c, n.g0 + 12 * c.n5h, 12 * c.n5h, (float)(2.0 / (x2 * nbatch)));
+        net_backward(&n);
+    }
+    if (loss) *loss = total / nbatch;
+    if (opt) {
+        n.step++;
+        launch_adam(c, n.w32, n.gw, n.m, n.v, 2 * n.nw, (float)opt->lr, (float)opt->beta1, (float)opt->beta2,
+                    (float)opt->eps, n.step);
+        refresh_bf16(&n);
+    }
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    DWF_API_END
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- FGCR
+
+namespace dwf {
+
+// z = N(r) (normal = false) or N N^+ r (normal = true), FP64 odd fields
+static void precondition(dwf_net_s *n, Field r, Field z, bool normal)
+{
+    Context &c = *n->c;
+    launch_spinor_to_feat(c, P_F64, r, n->acts[0], 1, true);
+    if (normal) {
+        // N^+ r: adjoint network on the embedded residual, then N on its result
+        const float2 *adj = net_adjoint(n, n->acts[0]);
+        launch_feat_to_spinor(c, P_F64, adj, z, 1);  // keep odd part only
+        launch_spinor_to_feat(c, P_F64, z, n->acts[0], 1, true);
+    }
+    net_forward(n, false);
+    launch_feat_to_spinor(c, P_F64, n->acts[n->nlayer], z, 1);
+}
+
+static double dnorm2(Context &c, Field a)
+{
+    const int np = launch_norm2(c, P_F64, a);
+    launch_finish(c, np, 1, 12);
+    read_scalars(c, 12, 1);
+    return c.hscal[12];
+}
+
+static void ddot(Context &c, Field a, Field b, double &re, double &im)
+{
+    const int np = launch_dot(c, P_F64, a, b);
+    launch_finish(c, np, 2, 14);
+    read_scalars(c, 14, 2);
+    re = c.hscal[14];
+    im = c.hscal[15];
+}
+
+static void fgcr_op(Context &c, Field in, Field out, bool normal)
+{
+    if (normal) {
+        Field t = ws_field(c, "fg_t", P_F64);
+        apply_mpc(c, P_F64, false, in, t, false);
+        apply_mpc(c, P_F64, true, t, out, false);
+    } else {
+        apply_mpc(c, P_F64, false, in, out, false);
+    }
+}
+
+}  // namespace dwf
+
+extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, double *x_full,
+                               const dwf_solver_opts *o, dwf_solver_stats *st)
+{
+    DWF_API_BEGIN
+    if (!ctx || !b_full || !x_full) fail(DWF_EINVAL, "null pointer");
+    Context &c = *ctx;
+    if (net && net->c != ctx) fail(DWF_EINVAL, "network belongs to another context");
+    const double tol = (o && o->tol > 0) ? o->tol : 1e-8;
+    const int maxit = (o && o->maxit > 0) ? o->maxit : 20000;
+    const int m = (o && o->restart > 0) ? std::min(o->restart, 64) : 16;
+    const bool normal = o && o->normal;
+    const bool fallback = !o || o->fallback;
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    const double t0 = wall();
+    Field be = ws_field(c, "sv_be", P_F64), bo = ws_field(c, "sv_bo", P_F64), bt = ws_field(c, "sv_bt", P_F64);
+    Field rhs = ws_field(c, "fg_rhs", P_F64), x = ws_field(c, "sv_xo", P_F64), r = ws_field(c, "fg_r", P_F64);
+    Field t1 = ws_field(c, "sv_t1", P_F64);
+    launch_import(c, P_F64, b_full, be, 1, 0);
+    launch_import(c, P_F64, b_full, bo, 1, 1);
+    launch_slocal(c, P_F64, SL_E1, be, t1);
+    StencilSpec sp;
+    sp.out_parity = 1;
+    sp.self = true;
+    sp.s0 = 1.0;
+    sp.tau = 0.5;
+    launch_stencil(c, P_F64, sp, t1, bo, bt);
+    if (normal) apply_mpc(c, P_F64, true, bt, rhs, false);
+    else launch_copy(c, P_F64, bt, rhs);
+    std::vector<Field> Z, Q;
+    for (int k = 0; k < m; k++) {
+        Z.push_back(ws_field(c, "fg_z" + std::to_string(k), P_F64));
+        Q.push_back(ws_field(c, "fg_q" + std::to_string(k), P_F64));
+    }
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    const double t1w = wall();
+    const double bn = std::sqrt(dnorm2(c, rhs));
+    launch_zero(c, P_F64, x);
+    launch_copy(c, P_F64, rhs, r);
+    int it = 0;
+    bool conv = bn == 0.0, stalled = false;
+    double best = bn;
+    int since_best = 0;
+    while (!conv && !stalled && it < maxit) {
+        int k = 0;
+        for (; k < m && it < maxit; k++) {
+            if (net) precondition(net, r, Z[k], normal);
+            else launch_copy(c, P_F64, r, Z[k]);
+            fgcr_op(c, Z[k], Q[k], normal);
+            for (int j = 0; j < k; j++) {
+                double re, im;
+                ddot(c, Q[j], Q[k], re, im);
+                launch_caxpy(c, P_F64, -re, -im, Q[j], Q[k]);
+                launch_caxpy(c, P_F64, -re, -im, Z[j], Z[k]);
+            }
+            const double qn = std::sqrt(dnorm2(c, Q[k]));
+            if (!(qn > 0) || !std::isfinite(qn)) {
+                stalled = true;
+                break;
+            }
+            launch_axpby(c, P_F64, 1.0 / qn, Q[k], 0.0, Q[k], Q[k]);
+            launch_axpby(c, P_F64, 1.0 / qn, Z[k], 0.0, Z[k], Z[k]);
+            double are, aim;
+            ddot(c, Q[k], r, are, aim);
+            launch_caxpy(c, P_F64, are, aim, Z[k], x);
+            launch_caxpy(c, P_F64, -are, -aim, Q[k], r);
+            it++;
+            const double rn = std::sqrt(dnorm2(c, r));
+            if (!std::isfinite(rn)) {
+                stalled = true;
+                break;
+            }
+            if (rn < 0.9 * best) {
+                best = rn;
+                since_best = 0;
+            } else if (++since_best > 8 * m) {
+                stalled = true;  // no progress over many restart cycles
+                break;
+            }
+            if (rn <= tol * bn) break;
+        }
+        // restart: true residual
+        fgcr_op(c, x, t1, normal);
+        launch_axpby(c, P_F64, 1.0, rhs, -1.0, t1, r);
+        const double rn = std::sqrt(dnorm2(c, r));
+        if (!std::isfinite(rn)) stalled = true;
+        if (rn <= tol * bn) conv = true;
+    }
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    const double t2w = wall();
+    int fell = 0;
+    dwf_status status = DWF_OK;
+    if (!conv) {
+        if (!fallback) {
+            status = DWF_ENOCONV;
+        } else {
+            fell = 1;
+        }
+    }
+    if (fell) {
+        dwf_solver_opts co{};
+        co.tol = tol;
+        co.maxit = o && o->maxit > 0 ? o->maxit : 0;
+        co.mode = DWF_SOLVE_F64;
+        dwf_solver_stats cs{};
+        status = dwf_cg(ctx, b_full, x_full, &co, &cs);
+        if (st) {
+            *st = cs;
+            st->fell_back = 1;
+            st->iters += it;
+            st->seconds = wall() - t0;
+        }
+        return status;
+    }
+    // reconstruct, residuals (shared with the CG path's final stage)
+    Field t2 = ws_field(c, "sv_t2", P_F64), xe = ws_field(c, "sv_xe", P_F64), ax = ws_field(c, "sv_ax", P_F64);
+    launch_slocal(c, P_F64, SL_A, x, t1);
+    sp = StencilSpec{};
+    sp.out_parity = 0;
+    sp.self = true;
+    sp.s0 = 1.0;
+    sp.tau = 0.5;
+    launch_stencil(c, P_F64, sp, t1, be, t2);
+    launch_slocal(c, P_F64, SL_MINV, t2, xe);
+    launch_export(c, P_F64, xe, x_full, 1, 0);
+    launch_export(c, P_F64, x, x_full, 1, 1);
+    apply_mpc(c, P_F64, false, x, t1, false);
+    launch_axpby(c, P_F64, 1.0, bt, -1.0, t1, t1);
+    const double bt2 = dnorm2(c, bt), rs2 = dnorm2(c, t1);
+    apply_mpc(c, P_F64, true, t1, t2, false);
+    Field nrm = ws_field(c, "fg_nrm", P_F64);
+    apply_mpc(c, P_F64, true, bt, nrm, false);
+    const double rn2 = dnorm2(c, t2), nb2 = dnorm2(c, nrm);
+    double r2 = 0, b2 = 0;
+    for (int par = 0; par < 2; par++) {
+        Field xp = par ? x : xe, xq = par ? xe : x, bp = par ? bo : be;
+        launch_slocal(c, P_F64, SL_A, xq, ax);
+        StencilSpec d5;
+        d5.out_parity = par;
+        d5.self = true;
+        d5.s0 = c.d;
+        d5.s1 = c.e;
+        d5.tau = -0.5;
+        launch_stencil(c, P_F64, d5, ax, xp, t2);
+        launch_axpby(c, P_F64, 1.0, bp, -1.0, t2, t2);
+        r2 += dnorm2(c, t2);
+        b2 += dnorm2(c, bp);
+    }
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    const double t3w = wall();
+    if (st) {
+        st->iters = it;
+        st->reliable_updates = 0;
+        st->converged = conv ? 1 : 0;
+        st->fell_back = 0;
+        st->res_normal = nb2 > 0 ? std::sqrt(rn2 / nb2) : 0;
+        st->res_schur = bt2 > 0 ? std::sqrt(rs2 / bt2) : 0;
+        st->res_full = b2 > 0 ? std::sqrt(r2 / b2) : 0;
+        st->seconds = t3w - t0;
+        st->t_prep = t1w - t0;
+        st->t_solve = t2w - t1w;
+        st->t_final = t3w - t2w;
+    }
+    return status;
+    DWF_API_END
+}

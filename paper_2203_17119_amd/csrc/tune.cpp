@@ -1,0 +1,163 @@
+// Autotuner of the fused stencil's tile schedule.
+//
+// A candidate schedule is (4D sites per workgroup, XCD run length).  Each is
+// timed with HIP events on the context's stream over the normal operator
+// Mpc^+ Mpc in the requested storage precision; the fastest is applied.  The
+// choice is cached as one JSON object per line:
+//   {"key": "<arch>/<Lx>x<Ly>x<Lz>x<Lt>/Ls<n>/p<prec>/d<dirichlet>", "sb": s, "run": r, "ms": t}
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "dwf_internal.h"
+
+using namespace dwf;
+
+namespace dwf {
+
+static std::string tune_key(const Context &c, int prec)
+{
+    hipDeviceProp_t prop;
+    HIPCHECK(hipGetDeviceProperties(&prop, c.device));
+    std::ostringstream k;
+    k << prop.gcnArchName << "/" << c.L[0] << "x" << c.L[1] << "x" << c.L[2] << "x" << c.L[3] << "/Ls" << c.Ls
+      << "/p" << prec << "/d" << c.p.dirichlet[0] << c.p.dirichlet[1] << c.p.dirichlet[2] << c.p.dirichlet[3];
+    return k.str();
+}
+
+static bool cache_lookup(const char *path, const std::string &key, int &sb, int &run, double &ms)
+{
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    bool found = false;
+    const std::string tag = "\"key\": \"" + key + "\"";
+    while (std::getline(f, line)) {
+        if (line.find(tag) == std::string::npos) continue;
+        int s = 0, r = 0;
+        double t = 0;
+        const size_t ps = line.find("\"sb\":"), pr = line.find("\"run\":"), pm = line.find("\"ms\":");
+        if (ps == std::string::npos || pr == std::string::npos || pm == std::string::npos) continue;
+        if (std::sscanf(line.c_str() + ps + 5, "%d", &s) != 1 || std::sscanf(line.c_str() + pr + 6, "%d", &r) != 1 ||
+            std::sscanf(line.c_str() + pm + 5, "%lf", &t) != 1)
+            continue;
+        sb = s;
+        run = r;
+        ms = t;
+        found = true;  // the last matching line wins
+    }
+    return found;
+}
+
+static void cache_store(const char *path, const std::string &key, int sb, int run, double ms)
+{
+    std::ofstream f(path, std::ios::app);
+    if (!f) fail(DWF_EINVAL, std::string("cannot write tune cache ") + path);
+    f << "{\"key\": \"" << key << "\", \"sb\": " << sb << ", \"run\": " << run << ", \"ms\": " << ms << "}\n";
+}
+
+double time_normal_op(Context &c, int prec, Field a, Field b, Field m, int reps)
+{
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    for (int i = 0; i < 2; i++) {
+        apply_mpc(c, prec, false, a, m, false);
+        apply_mpc(c, prec, true, m, b, false);
+    }
+    HIPCHECK(hipEventRecord(e0, c.stream));
+    for (int i = 0; i < reps; i++) {
+        apply_mpc(c, prec, false, a, m, false);
+        apply_mpc(c, prec, true, m, b, false);
+    }
+    HIPCHECK(hipEventRecord(e1, c.stream));
+    HIPCHECK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms / reps;
+}
+
+}  // namespace dwf
+
+#define DWF_API_BEGIN try {
+#define DWF_API_END                              \
+    return DWF_OK;                               \
+    }                                            \
+    catch (const dwf::Error &e)                  \
+    {                                            \
+        dwf::set_error(e.msg);                   \
+        return e.code;                           \
+    }                                            \
+    catch (const std::exception &e)              \
+    {                                            \
+        dwf::set_error(e.what());                \
+        return DWF_ENOMEM;                       \
+    }
+
+extern "C" dwf_status dwf_tune(dwf_ctx ctx, int prec, const char *cache_path, double *best_ms)
+{
+    DWF_API_BEGIN
+    if (!ctx) fail(DWF_EINVAL, "null context");
+    if (prec < 0 || prec > 3) fail(DWF_EINVAL, "unknown precision");
+    Context &c = *ctx;
+    const std::string key = tune_key(c, prec);
+    int sb = 0, run = 1;
+    double ms = 0;
+    if (cache_path && cache_lookup(cache_path, key, sb, run, ms)) {
+        if (sb < 0 || (long)sb * c.Ls > 256 || run < 1) fail(DWF_EINVAL, "corrupt tune cache entry for " + key);
+        c.cfg_stencil.sb = sb;
+        c.cfg_stencil.run = run;
+        if (best_ms) *best_ms = ms;
+        return DWF_OK;
+    }
+    // scratch fields, filled with a finite bit pattern
+    const size_t bytes = field_bytes(c, c.n5h, prec);
+    std::vector<void *> bufs(3, nullptr);
+    struct Free {
+        std::vector<void *> &b;
+        ~Free()
+        {
+            for (void *p : b)
+                if (p) (void)hipFree(p);
+        }
+    } guard{bufs};
+    for (auto &p : bufs) {
+        HIPCHECK(hipMalloc(&p, bytes));
+        HIPCHECK(hipMemsetAsync(p, 0x3c, bytes, c.stream));
+    }
+    Field a = make_field(c, bufs[0], prec), b = make_field(c, bufs[1], prec), m = make_field(c, bufs[2], prec);
+    std::vector<int> sbs;
+    for (int lanes : {64, 128, 192, 256}) {
+        const int s = std::max(1, lanes / c.Ls);
+        if ((long)s * c.Ls <= 256 && std::find(sbs.begin(), sbs.end(), s) == sbs.end()) sbs.push_back(s);
+    }
+    const long work = c.vh;
+    const LaunchCfg saved = c.cfg_stencil;
+    double best = 1e30;
+    LaunchCfg best_cfg = saved;
+    const int reps = work > 100000 ? 5 : 20;
+    const long col = column_sites(c);
+    for (int s : sbs)
+        for (int r : {1, 8, 32, 128, 512, (col < c.vh && col % s == 0) ? (int)(col / s) : 1}) {
+            const long nblk = (work + s - 1) / s;
+            if (r > 1 && nblk < 16L * r) continue;  // run longer than the grid allows
+            c.cfg_stencil.sb = s;
+            c.cfg_stencil.run = r;
+            const double t = time_normal_op(c, prec, a, b, m, reps);
+            if (t < best) {
+                best = t;
+                best_cfg = c.cfg_stencil;
+            }
+        }
+    c.cfg_stencil = best_cfg;
+    if (cache_path) cache_store(cache_path, key, best_cfg.sb, best_cfg.run, best);
+    if (best_ms) *best_ms = best;
+    DWF_API_END
+}

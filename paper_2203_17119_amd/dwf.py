@@ -50,10 +50,15 @@ class DWFError(RuntimeError):
         self.status = status
 
 
+class dwf_adam(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
+
+
 _P = C.c_void_p
 _I = C.c_int
 _D = C.c_double
 _CTX = C.c_void_p
+_NET = C.c_void_p
 
 # name -> (argtypes, restype); mirrors include/dwf.h
 SIGNATURES = {
@@ -75,6 +80,21 @@ SIGNATURES = {
     "dwf_cg": ([_CTX, _P, _P, C.POINTER(dwf_solver_opts), C.POINTER(dwf_solver_stats)], C.c_int32),
     "dwf_multishift_cg": ([_CTX, _I, C.POINTER(_P), _I, C.POINTER(_D), C.POINTER(_P),
                            C.POINTER(dwf_solver_opts), C.POINTER(dwf_solver_stats)], C.c_int32),
+    "dwf_net_create": ([_CTX, _I, C.POINTER(_I), C.POINTER(_NET)], C.c_int32),
+    "dwf_net_destroy": ([_NET], C.c_int32),
+    "dwf_net_num_weights": ([_NET], C.c_int),
+    "dwf_net_set_weights": ([_NET, _P], C.c_int32),
+    "dwf_net_get_weights": ([_NET, _P], C.c_int32),
+    "dwf_precond_apply": ([_CTX, _NET, _P, _P], C.c_int32),
+    "dwf_net_backward": ([_NET, _P, _P, _P, _P], C.c_int32),
+    "dwf_net_train_step": ([_NET, _I, C.POINTER(_P), C.POINTER(_P), C.POINTER(dwf_adam), C.POINTER(_D)], C.c_int32),
+    "dwf_fgcr": ([_CTX, _NET, _P, _P, C.POINTER(dwf_solver_opts), C.POINTER(dwf_solver_stats)], C.c_int32),
+    "dwf_set_site_order": ([_CTX, _I, _I, _I], C.c_int32),
+    "dwf_get_site_order": ([_CTX, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)], C.c_int32),
+    "dwf_set_tile_schedule": ([_CTX, _I, _I, _I], C.c_int32),
+    "dwf_get_tile_schedule": ([_CTX, _I, C.POINTER(_I), C.POINTER(_I)], C.c_int32),
+    "dwf_tune": ([_CTX, _I, C.c_char_p, C.POINTER(_D)], C.c_int32),
+    "dwf_stream_copy": ([_CTX, _P, _P, C.c_size_t], C.c_int32),
     "dwf_kernel_timing": ([_CTX, _I], C.c_int32),
     "dwf_kernel_timing_reset": ([_CTX], C.c_int32),
     "dwf_kernel_stats": ([_CTX, _I, C.POINTER(C.c_long), C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)], C.c_int32),
@@ -230,6 +250,95 @@ def dwf_multishift_cg(ctx, b_odd, shifts, x_odd, **opts):
     st = (dwf_solver_stats * (nrhs * ns))()
     s = _check(load().dwf_multishift_cg(ctx, nrhs, bp, ns, sh, xp, C.byref(o), st), allow=(DWF_ENOCONV,))
     return s, [x.asdict() for x in st]
+
+
+def dwf_net_create(ctx, chans):
+    arr = (C.c_int * len(chans))(*chans)
+    net = _NET()
+    _check(load().dwf_net_create(ctx, len(chans) - 1, arr, C.byref(net)))
+    return net
+
+
+def dwf_net_destroy(net):
+    _check(load().dwf_net_destroy(net))
+
+
+def dwf_net_num_weights(net) -> int:
+    return load().dwf_net_num_weights(net)
+
+
+def dwf_net_set_weights(net, w):
+    """w: complex array of dwf_net_num_weights(net) weights, layer blocks [pi][a][b]."""
+    a = np.ascontiguousarray(np.asarray(w).ravel(), dtype=np.complex64)
+    if a.size != dwf_net_num_weights(net):
+        raise ValueError("wrong number of weights")
+    _check(load().dwf_net_set_weights(net, a.ctypes.data))
+
+
+def dwf_net_get_weights(net):
+    a = np.empty(dwf_net_num_weights(net), dtype=np.complex64)
+    _check(load().dwf_net_get_weights(net, a.ctypes.data))
+    return a
+
+
+def dwf_precond_apply(ctx, net, in_odd, out_odd):
+    _check(load().dwf_precond_apply(ctx, net, _ptr(in_odd), _ptr(out_odd)))
+
+
+def dwf_net_backward(net, in_odd, grad_out_odd, grad_in_odd=None, want_w=True):
+    gw = np.empty(dwf_net_num_weights(net), dtype=np.complex64) if want_w else None
+    _check(load().dwf_net_backward(net, _ptr(in_odd), _ptr(grad_out_odd), _ptr(grad_in_odd),
+                                   gw.ctypes.data if gw is not None else None))
+    return gw
+
+
+def dwf_net_train_step(net, b_odd, x_odd, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, update=True):
+    n = len(b_odd)
+    bp = (_P * n)(*[_ptr(t) for t in b_odd])
+    xp = (_P * n)(*[_ptr(t) for t in x_odd])
+    opt = dwf_adam(lr, beta1, beta2, eps)
+    loss = C.c_double()
+    _check(load().dwf_net_train_step(net, n, bp, xp, C.byref(opt) if update else None, C.byref(loss)))
+    return loss.value
+
+
+def dwf_fgcr(ctx, net, b_full, x_full, **opts):
+    o = _opts(**opts)
+    st = dwf_solver_stats()
+    s = _check(load().dwf_fgcr(ctx, net, _ptr(b_full), _ptr(x_full), C.byref(o), C.byref(st)),
+               allow=(DWF_ENOCONV,))
+    return s, st.asdict()
+
+
+def dwf_set_site_order(ctx, cx, cy, cz):
+    _check(load().dwf_set_site_order(ctx, int(cx), int(cy), int(cz)))
+
+
+def dwf_get_site_order(ctx):
+    a, b, c = C.c_int(), C.c_int(), C.c_int()
+    _check(load().dwf_get_site_order(ctx, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def dwf_set_tile_schedule(ctx, kclass, sites_per_group, xcd_run):
+    _check(load().dwf_set_tile_schedule(ctx, int(kclass), int(sites_per_group), int(xcd_run)))
+
+
+def dwf_get_tile_schedule(ctx, kclass):
+    s, r = C.c_int(), C.c_int()
+    _check(load().dwf_get_tile_schedule(ctx, int(kclass), C.byref(s), C.byref(r)))
+    return s.value, r.value
+
+
+def dwf_tune(ctx, prec, cache_path=None):
+    """Autotune the stencil schedule for prec; returns the chosen schedule's time (ms)."""
+    ms = C.c_double()
+    _check(load().dwf_tune(ctx, int(prec), cache_path.encode() if cache_path else None, C.byref(ms)))
+    return ms.value
+
+
+def dwf_stream_copy(ctx, src, dst, nbytes):
+    _check(load().dwf_stream_copy(ctx, _ptr(src), _ptr(dst), int(nbytes)))
 
 
 def dwf_kernel_timing(ctx, enable):

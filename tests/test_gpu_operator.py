@@ -96,6 +96,43 @@ def test_dhop_16x16x16x16_ls12_dirichlet():
         c.close()
 
 
+@pytest.mark.parametrize("order", [(2, 2, 2), (4, 4, 2), (2, 1, 4), (8, 4, 4), (0, 0, 0)])
+def test_site_orders(order):
+    """Results do not depend on the internal (cache-blocked) site order or schedule."""
+    print(f"\n[site order {order}]", flush=True)
+    c = Case((8, 4, 4, 6), 4, mf=0.05, dirichlet=(1, 0, 0, 1), seed=41)
+    try:
+        dwf.dwf_set_site_order(c.ctx, *order)
+        got = dwf.dwf_get_site_order(c.ctx)
+        if order != (0, 0, 0):
+            assert got == order
+        x = c.half(12)
+        xg = to_gpu(x)
+        out = torch().empty_like(xg)
+        for out_parity, dagger in [(0, 0), (1, 1)]:
+            dwf.dwf_dhop(c.ctx, out_parity, dagger, xg, out)
+            assert relerr(to_host(out), c.oracle_dhop(x, out_parity, bool(dagger))) < 1e-12
+        for sb, run in [(3, 1), (5, 2), (8, 1)]:
+            dwf.dwf_set_tile_schedule(c.ctx, dwf.DWF_K_STENCIL, sb, run)
+            dwf.dwf_schur_apply(c.ctx, 1, xg, out)
+            assert relerr(to_host(out), oracle.mpc(c.P, c.Ud, x, True)) < 1e-12
+        # internal-layout round trip in every precision
+        for prec in (dwf.DWF_F64, dwf.DWF_F16):
+            buf = c.lat.internal(prec)
+            dwf.dwf_import(c.ctx, 0, prec, xg, buf)
+            dwf.dwf_dhop_internal(c.ctx, prec, 1, 0, buf, c.lat.internal(prec))
+            dwf.dwf_export(c.ctx, 0, prec, buf, out)
+            assert relerr(to_host(out), x) < (1e-16 if prec == dwf.DWF_F64 else 1e-3)
+        b = c.full(13)
+        xs = torch().zeros_like(to_gpu(b))
+        status, st = dwf.dwf_cg(c.ctx, to_gpu(b), xs, tol=1e-10, mode=dwf.DWF_SOLVE_MIXED_F16)
+        assert status == dwf.DWF_OK
+        r = b - oracle.d5(c.P, c.Ud, to_host(xs))
+        assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-8
+    finally:
+        c.close()
+
+
 def test_repeated_calls_are_bitwise_identical(case):
     x = to_gpu(case.half(11))
     a = torch().empty_like(x)
