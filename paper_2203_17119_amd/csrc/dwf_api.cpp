@@ -223,20 +223,46 @@ void default_schedule(Context &c)
 
 // ---------------------------------------------------------------- Mpc
 
-int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduce, bool in_is_A_applied, Field pa)
+long batch_stride(const Context &c, int prec) { return (long)((field_bytes(c, c.n5h, prec) + 255) / 256 * 256); }
+
+Field ws_batch(Context &c, const std::string &name, int prec, int nbatch)
+{
+    if (nbatch <= 1) return ws_field(c, name, prec);
+    const std::string key = name + "#" + std::to_string(prec) + "x" + std::to_string(nbatch);
+    auto it = c.ws.find(key);
+    if (it == c.ws.end()) {
+        Context::Buf b;
+        b.bytes = (size_t)batch_stride(c, prec) * nbatch;
+        HIPCHECK(hipMalloc(&b.data, b.bytes));
+        HIPCHECK(hipMemsetAsync(b.data, 0, b.bytes, c.stream));
+        b.prec = prec;
+        it = c.ws.emplace(key, b).first;
+    }
+    return make_field(c, it->second.data, prec);
+}
+
+int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduce, bool in_is_A_applied, Field pa,
+              int nbatch, long bstride)
 {
     ensure_links(c, prec);
-    Field y = ws_field(c, "mpc_y", prec);
+    const int nb = std::max(1, nbatch);
+    Field y = ws_batch(c, "mpc_y", prec, nb);
+    if (nb > 1 && bstride != batch_stride(c, prec)) fail(DWF_EINVAL, "batched fields must use the batch stride");
+    auto batched = [&](StencilSpec &s) {
+        s.nbatch = nb;
+        s.bstride = bstride;
+    };
     if (!dagger) {
         Field ta = pa;
         if (!in_is_A_applied) {
-            ta = ws_field(c, "mpc_ta", prec);
-            launch_slocal(c, prec, SL_A, in, ta);
+            ta = ws_batch(c, "mpc_ta", prec, nb);
+            launch_slocal(c, prec, SL_A, in, ta, nb, bstride);
         }
         StencilSpec s1;
         s1.out_parity = 0;
         s1.epi = EPI_DENSE;
         s1.epi_op = SL_E1;
+        batched(s1);
         launch_stencil(c, prec, s1, ta, Field{}, y);
         StencilSpec s2;
         s2.out_parity = 1;
@@ -245,6 +271,7 @@ int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduc
         s2.s1 = c.e;
         s2.tau = -0.25;
         s2.reduce = reduce;
+        batched(s2);
         return launch_stencil(c, prec, s2, y, in, out);
     }
     StencilSpec s1;
@@ -252,6 +279,7 @@ int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduc
     s1.dagger = true;
     s1.epi = EPI_DENSE;
     s1.epi_op = SL_E2;
+    batched(s1);
     launch_stencil(c, prec, s1, in, Field{}, y);
     StencilSpec s2;
     s2.out_parity = 1;
@@ -266,6 +294,7 @@ int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduc
     s2.sdag = true;
     s2.tau = -0.25;
     s2.reduce = reduce;
+    batched(s2);
     return launch_stencil(c, prec, s2, y, in, out);
 }
 
@@ -273,10 +302,10 @@ int launch_stencil_f64(Context &, const StencilSpec &, Field, Field, Field);
 int launch_stencil_f32(Context &, const StencilSpec &, Field, Field, Field);
 int launch_stencil_f16(Context &, const StencilSpec &, Field, Field, Field);
 int launch_stencil_bf16(Context &, const StencilSpec &, Field, Field, Field);
-void launch_slocal_f64(Context &, int, Field, Field);
-void launch_slocal_f32(Context &, int, Field, Field);
-void launch_slocal_f16(Context &, int, Field, Field);
-void launch_slocal_bf16(Context &, int, Field, Field);
+void launch_slocal_f64(Context &, int, Field, Field, int, long);
+void launch_slocal_f32(Context &, int, Field, Field, int, long);
+void launch_slocal_f16(Context &, int, Field, Field, int, long);
+void launch_slocal_bf16(Context &, int, Field, Field, int, long);
 
 int launch_stencil(Context &c, int prec, const StencilSpec &sp, Field in, Field self, Field out)
 {
@@ -289,13 +318,13 @@ int launch_stencil(Context &c, int prec, const StencilSpec &sp, Field in, Field 
     }
 }
 
-void launch_slocal(Context &c, int prec, int op, Field in, Field out)
+void launch_slocal(Context &c, int prec, int op, Field in, Field out, int nbatch, long bstride)
 {
     switch (prec) {
-    case P_F64: launch_slocal_f64(c, op, in, out); break;
-    case P_F32: launch_slocal_f32(c, op, in, out); break;
-    case P_F16: launch_slocal_f16(c, op, in, out); break;
-    default: launch_slocal_bf16(c, op, in, out); break;
+    case P_F64: launch_slocal_f64(c, op, in, out, nbatch, bstride); break;
+    case P_F32: launch_slocal_f32(c, op, in, out, nbatch, bstride); break;
+    case P_F16: launch_slocal_f16(c, op, in, out, nbatch, bstride); break;
+    default: launch_slocal_bf16(c, op, in, out, nbatch, bstride); break;
     }
 }
 
@@ -376,9 +405,9 @@ dwf_status dwf_create(const dwf_params *p, const double *gauge, int gauge_on_dev
         build_slocal(*c);
         c->partials_len = 2 * (c->n5h / 64 + c->vh + 1024);
         HIPCHECK(hipMalloc(&c->partials, c->partials_len * sizeof(double)));
-        HIPCHECK(hipMalloc(&c->dscal, 64 * sizeof(double)));
-        HIPCHECK(hipMemset(c->dscal, 0, 64 * sizeof(double)));
-        HIPCHECK(hipHostMalloc(&c->hscal, 64 * sizeof(double), hipHostMallocDefault));
+        HIPCHECK(hipMalloc(&c->dscal, 256 * sizeof(double)));
+        HIPCHECK(hipMemset(c->dscal, 0, 256 * sizeof(double)));
+        HIPCHECK(hipHostMalloc(&c->hscal, 256 * sizeof(double), hipHostMallocDefault));
         upload_gauge(*c, gauge, gauge_on_device);
     } catch (...) {
         dwf_destroy(c);

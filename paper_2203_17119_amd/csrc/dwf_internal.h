@@ -165,13 +165,40 @@ struct StencilSpec {
     double sigma = 1.0, tau = 1.0;
     bool reduce = false;      // per-workgroup |out|^2 partials into c.partials
     int kclass = DWF_K_STENCIL;
+    int nbatch = 1;           // fields processed in one launch (blockIdx.y), member k of
+    long bstride = 0;         // in/self/out at data + k*bstride bytes; partials [k][block]
 };
 // prec: storage precision of in/out/self; FP64 uses double arithmetic, the
 // others float.  Returns the number of partials written when reduce is set.
 int launch_stencil(Context &c, int prec, const StencilSpec &sp, Field in, Field self, Field out);
 
 // s-local dense operator out = M in (M one of SlocalOp); in and out may alias
-void launch_slocal(Context &c, int prec, int op, Field in, Field out);
+void launch_slocal(Context &c, int prec, int op, Field in, Field out, int nbatch = 1, long bstride = 0);
+
+// batches of fields: member k of a batch starting at field f lies k*batch_stride
+// bytes after it (field bytes rounded up to 256)
+long batch_stride(const Context &c, int prec);
+Field ws_batch(Context &c, const std::string &name, int prec, int nbatch);
+__host__ __device__ inline Field member(Field f, int k, long stride)
+{
+    f.data = (char *)f.data + (long)k * stride;
+    if (f.norm) f.norm = (float *)((char *)f.norm + (long)k * stride);
+    return f;
+}
+
+// device state of the batched multi-shift solver
+struct MsState {
+    double *rho, *pap, *alpha, *alpha_old, *beta_old, *target;  // [nrhs]
+    double *zeta, *zeta_old;                                      // [nshift*nrhs]
+    int *active, *iters;                                          // [nshift*nrhs]
+    double *coef;                                                 // [nshift*nrhs][4] (a, z, b, on)
+    double *shifts;                                               // [nshift]
+};
+void ms_launch_norm2(Context &c, int prec, Field a, int nb, long stride, double *out);
+void ms_launch_redot(Context &c, int prec, Field a, Field b, int nb, long stride, double *out);
+void ms_launch_axpy(Context &c, int prec, double a, Field x, Field y, int nb, long stride);
+void ms_launch_step(Context &c, int prec, const MsState &s, Field r, Field ap, Field X, Field P, int nrhs, int nshift,
+                    int kmin, long stride, double *rho_new, int it);
 
 // reductions: partial sums (2 doubles per workgroup for dots) then a fixed-order
 // finish on the device that writes dscal[slot] (and dscal[slot+1] for dots)
@@ -213,7 +240,7 @@ void launch_stream_copy(Context &c, const void *src, void *dst, size_t bytes);
 // out = Mpc in (dagger: Mpc^+) in precision prec, using workspaces of that
 // precision; if reduce, partials of |out|^2 are written and their count returned
 int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduce, bool in_is_A_applied = false,
-              Field pa = Field{});
+              Field pa = Field{}, int nbatch = 1, long bstride = 0);
 
 }  // namespace dwf
 

@@ -11,6 +11,15 @@ static constexpr int BS = 256;
 
 static dim3 g1(long n) { return dim3((unsigned)((n + BS - 1) / BS)); }
 
+#define DWF_DISPATCH(prec, KERNEL, grid, blk, lds, ...)                                                    \
+    switch (prec) {                                                                                        \
+    case P_F64: hipLaunchKernelGGL(KERNEL<F64>, grid, blk, lds, c.stream, __VA_ARGS__); break;             \
+    case P_F32: hipLaunchKernelGGL(KERNEL<F32>, grid, blk, lds, c.stream, __VA_ARGS__); break;             \
+    case P_F16: hipLaunchKernelGGL(KERNEL<F16>, grid, blk, lds, c.stream, __VA_ARGS__); break;             \
+    default: hipLaunchKernelGGL(KERNEL<BF16>, grid, blk, lds, c.stream, __VA_ARGS__); break;               \
+    }                                                                                                      \
+    HIPCHECK(hipGetLastError())
+
 template <typename S>
 using Cof = typename S::real;
 
@@ -244,6 +253,229 @@ __global__ void __launch_bounds__(BS) k_ms_update(int nshift, const Field *x, co
     }
 }
 
+// ------------------------------------------------ batched multi-shift CG
+//
+// All right-hand sides j advance together; shift k of rhs j is batch member
+// k*nrhs + j of the solution and direction batches.  The shifted recurrences
+// (Jegerlehner) run on the device, one workgroup per right-hand side:
+//   zeta_{n+1} = zeta_n zeta_{n-1} a_{n-1} / (a_n b_{n-1} (zeta_{n-1} - zeta_n)
+//                + zeta_{n-1} a_{n-1} (1 + ds a_n))
+//   a^s = a zeta_{n+1}/zeta_n,  b^s = b (zeta_{n+1}/zeta_n)^2
+// A shift freezes once |zeta| |r| <= tol |b| and its zeta is not updated
+// further; the lowest shift carries the Krylov space and freezes last.
+
+// batched |a_j|^2 and <a_j, b_j>: member blockIdx.y, partial[j][block]
+template <typename S>
+__global__ void __launch_bounds__(BS) k_norm2_b(Field a, long stride, double *partial)
+{
+    a = member(a, blockIdx.y, stride);
+    using C = Cof<S>;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    double t = 0;
+    if (i < a.n) {
+        cx<C> v[12];
+        load_spinor<S, C>(a, i, v);
+        for (int c = 0; c < 12; c++) t += double(v[c].re) * double(v[c].re) + double(v[c].im) * double(v[c].im);
+    }
+    t = block_sum(t);
+    if (threadIdx.x == 0) partial[(long)blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(BS) k_redot_b(Field a, Field b, long stride, double *partial)
+{
+    a = member(a, blockIdx.y, stride);
+    b = member(b, blockIdx.y, stride);
+    using C = Cof<S>;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    double t = 0;
+    if (i < a.n) {
+        cx<C> u[12], v[12];
+        load_spinor<S, C>(a, i, u);
+        load_spinor<S, C>(b, i, v);
+        for (int c = 0; c < 12; c++) t += double(u[c].re) * double(v[c].re) + double(u[c].im) * double(v[c].im);
+    }
+    t = block_sum(t);
+    if (threadIdx.x == 0) partial[(long)blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
+// out[j] = sum of nparts partials of member j (fixed order)
+__global__ void __launch_bounds__(BS) k_finish_b(const double *partial, int nparts, double *out)
+{
+    double t = 0;
+    for (int k = threadIdx.x; k < nparts; k += BS) t += partial[(long)blockIdx.x * nparts + k];
+    t = block_sum(t);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+// y_j += a x_j (host scalar), batched
+template <typename S>
+__global__ void __launch_bounds__(BS) k_axpy_b(double a, Field x, Field y, long stride)
+{
+    x = member(x, blockIdx.y, stride);
+    y = member(y, blockIdx.y, stride);
+    using C = Cof<S>;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    if (i >= x.n) return;
+    cx<C> u[12], v[12];
+    load_spinor<S, C>(x, i, u);
+    load_spinor<S, C>(y, i, v);
+    for (int c = 0; c < 12; c++) v[c] = v[c] + C(a) * u[c];
+    store_spinor<S, C>(y, i, v);
+}
+
+// r_j -= alpha_j ap_j with alpha_j from the device, partial |r_j|^2
+template <typename S>
+__global__ void __launch_bounds__(BS) k_ms_residual(Field r, Field ap, long stride, const double *alpha, double *partial)
+{
+    r = member(r, blockIdx.y, stride);
+    ap = member(ap, blockIdx.y, stride);
+    using C = Cof<S>;
+    const C al = C(alpha[blockIdx.y]);
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    double t = 0;
+    if (i < r.n) {
+        cx<C> u[12], v[12];
+        load_spinor<S, C>(r, i, u);
+        load_spinor<S, C>(ap, i, v);
+        for (int c = 0; c < 12; c++) {
+            u[c] = u[c] - al * v[c];
+            t += double(u[c].re) * double(u[c].re) + double(u[c].im) * double(u[c].im);
+        }
+        store_spinor<S, C>(r, i, u);
+    }
+    t = block_sum(t);
+    if (threadIdx.x == 0) partial[(long)blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
+// alpha_j = rho_j / <p_j, A p_j>; zero once every shift of rhs j is frozen
+__global__ void k_ms_alpha(MsState s, int nrhs, int nshift)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nrhs) return;
+    int on = 0;
+    for (int k = 0; k < nshift; k++) on |= s.active[k * nrhs + j];
+    s.alpha[j] = (on && s.pap[j] > 0) ? s.rho[j] / s.pap[j] : 0.0;
+}
+
+// one workgroup per rhs j, one lane per shift; rho_new[j] holds |r_j|^2 after the update
+__global__ void k_ms_recur(MsState s, const double *rho_new, int nrhs, int nshift, int kmin, int it)
+{
+    const int j = blockIdx.x, k = threadIdx.x;
+    __shared__ int nact;
+    if (k == 0) nact = 0;
+    __syncthreads();
+    const double al = s.alpha[j], alo = s.alpha_old[j], bo = s.beta_old[j];
+    const double rho = s.rho[j], rn = rho_new[j];
+    const double beta = (rho > 0 && al != 0.0) ? rn / rho : 0.0;
+    if (k < nshift) {
+        const int q = k * nrhs + j;
+        double *cf = s.coef + 4 * (long)q;
+        if (s.active[q] && al != 0.0) {
+            const double ds = s.shifts[k] - s.shifts[kmin];
+            const double z = s.zeta[q], zo = s.zeta_old[q];
+            const double zn = z * zo * alo / (al * bo * (zo - z) + zo * alo * (1.0 + ds * al));
+            cf[0] = al * zn / z;
+            cf[1] = zn;
+            cf[2] = beta * (zn / z) * (zn / z);
+            cf[3] = 1.0;
+            s.zeta_old[q] = z;
+            s.zeta[q] = zn;
+            s.iters[q] = it;
+            atomicAdd(&nact, 1);
+        } else {
+            cf[3] = 0.0;
+        }
+    }
+    __syncthreads();
+    if (k < nshift) {
+        const int q = k * nrhs + j;
+        // freeze converged shifts; the Krylov carrier kmin only when it is the last one
+        if (s.active[q] && s.coef[4 * (long)q + 3] != 0.0 && (k != kmin || nact == 1) &&
+            fabs(s.zeta[q]) * sqrt(rn) <= s.target[j])
+            s.active[q] = 0;
+        if (!(rn == rn)) s.active[q] = 0;  // non-finite residual: stop this rhs
+    }
+    __syncthreads();
+    if (k == 0 && al != 0.0) {
+        s.rho[j] = rn;
+        s.alpha_old[j] = al;
+        s.beta_old[j] = beta;
+    }
+}
+
+// x_kj += a p_kj ; p_kj = z r_j + b p_kj for the active shifts (member k*nrhs + j)
+template <typename S>
+__global__ void __launch_bounds__(BS) k_ms_update_b(int nrhs, int nshift, Field X, Field P, Field r, long stride,
+                                                     const double *coef)
+{
+    using C = Cof<S>;
+    const int j = blockIdx.y;
+    r = member(r, j, stride);
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    if (i >= r.n) return;
+    cx<C> rv[12];
+    load_spinor<S, C>(r, i, rv);
+    for (int k = 0; k < nshift; k++) {
+        const double *cf = coef + 4 * (long)(k * nrhs + j);
+        if (cf[3] == 0.0) continue;
+        const C a = C(cf[0]), z = C(cf[1]), b = C(cf[2]);
+        const Field x = member(X, k * nrhs + j, stride), p = member(P, k * nrhs + j, stride);
+        cx<C> xv[12], pv[12];
+        load_spinor<S, C>(x, i, xv);
+        load_spinor<S, C>(p, i, pv);
+        for (int c = 0; c < 12; c++) {
+            xv[c] = xv[c] + a * pv[c];
+            pv[c] = z * rv[c] + b * pv[c];
+        }
+        store_spinor<S, C>(x, i, xv);
+        store_spinor<S, C>(p, i, pv);
+    }
+}
+
+void ms_launch_norm2(Context &c, int prec, Field a, int nb, long stride, double *out)
+{
+    const long np = (a.n + BS - 1) / BS;
+    if (np * nb > c.partials_len) fail(DWF_EINVAL, "reduction buffer too small");
+    Timer tm(c, DWF_K_BLAS, nb * (12.0 * elem_bytes(prec)) * a.n, 0);
+    DWF_DISPATCH(prec, k_norm2_b, dim3((unsigned)np, nb), dim3(BS), 0, a, stride, c.partials);
+    hipLaunchKernelGGL(k_finish_b, dim3(nb), dim3(BS), 0, c.stream, c.partials, (int)np, out);
+    HIPCHECK(hipGetLastError());
+}
+
+void ms_launch_redot(Context &c, int prec, Field a, Field b, int nb, long stride, double *out)
+{
+    const long np = (a.n + BS - 1) / BS;
+    if (np * nb > c.partials_len) fail(DWF_EINVAL, "reduction buffer too small");
+    Timer tm(c, DWF_K_BLAS, nb * 2 * (12.0 * elem_bytes(prec)) * a.n, 0);
+    DWF_DISPATCH(prec, k_redot_b, dim3((unsigned)np, nb), dim3(BS), 0, a, b, stride, c.partials);
+    hipLaunchKernelGGL(k_finish_b, dim3(nb), dim3(BS), 0, c.stream, c.partials, (int)np, out);
+    HIPCHECK(hipGetLastError());
+}
+
+void ms_launch_axpy(Context &c, int prec, double a, Field x, Field y, int nb, long stride)
+{
+    Timer tm(c, DWF_K_BLAS, nb * 3 * (12.0 * elem_bytes(prec)) * x.n, 0);
+    DWF_DISPATCH(prec, k_axpy_b, dim3((unsigned)((x.n + BS - 1) / BS), nb), dim3(BS), 0, a, x, y, stride);
+}
+
+void ms_launch_step(Context &c, int prec, const MsState &s, Field r, Field ap, Field X, Field P, int nrhs, int nshift,
+                    int kmin, long stride, double *rho_new, int it)
+{
+    const long np = (r.n + BS - 1) / BS;
+    if (np * nrhs > c.partials_len) fail(DWF_EINVAL, "reduction buffer too small");
+    hipLaunchKernelGGL(k_ms_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, c.stream, s, nrhs, nshift);
+    {
+        Timer tm(c, DWF_K_BLAS, nrhs * 3 * (12.0 * elem_bytes(prec)) * r.n, 0);
+        DWF_DISPATCH(prec, k_ms_residual, dim3((unsigned)np, nrhs), dim3(BS), 0, r, ap, stride, s.alpha, c.partials);
+    }
+    hipLaunchKernelGGL(k_finish_b, dim3(nrhs), dim3(BS), 0, c.stream, c.partials, (int)np, rho_new);
+    hipLaunchKernelGGL(k_ms_recur, dim3(nrhs), dim3(64), 0, c.stream, s, rho_new, nrhs, nshift, kmin, it);
+    HIPCHECK(hipGetLastError());
+    Timer tm(c, DWF_K_BLAS, nrhs * (1 + 4.0 * nshift) * (12.0 * elem_bytes(prec)) * r.n, 0);
+    DWF_DISPATCH(prec, k_ms_update_b, dim3((unsigned)np, nrhs), dim3(BS), 0, nrhs, nshift, X, P, r, stride, s.coef);
+}
+
 // plain 16-byte streaming copy, grid-stride
 __global__ void __launch_bounds__(BS) k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, long n)
 {
@@ -263,15 +495,6 @@ void launch_stream_copy(Context &c, const void *src, void *dst, size_t bytes)
 // ------------------------------------------------------------ launchers
 
 static double sbytes(int prec) { return 12.0 * elem_bytes(prec) + (prec == P_F16 ? 4.0 : 0.0); }
-
-#define DWF_DISPATCH(prec, KERNEL, grid, blk, lds, ...)                                                    \
-    switch (prec) {                                                                                        \
-    case P_F64: hipLaunchKernelGGL(KERNEL<F64>, grid, blk, lds, c.stream, __VA_ARGS__); break;             \
-    case P_F32: hipLaunchKernelGGL(KERNEL<F32>, grid, blk, lds, c.stream, __VA_ARGS__); break;             \
-    case P_F16: hipLaunchKernelGGL(KERNEL<F16>, grid, blk, lds, c.stream, __VA_ARGS__); break;             \
-    default: hipLaunchKernelGGL(KERNEL<BF16>, grid, blk, lds, c.stream, __VA_ARGS__); break;               \
-    }                                                                                                      \
-    HIPCHECK(hipGetLastError())
 
 static void need_partials(Context &c, long n, int width)
 {

@@ -33,6 +33,7 @@ struct StencilKArgs {
     double e0, e1, s0, s1, mf, sigma, tau;
     int edag, sdag;
     double *partial;
+    long bstride;  // bytes between batch members (blockIdx.y), 0 for one field
 };
 
 template <typename C, int MU, int P>
@@ -119,9 +120,23 @@ __device__ __forceinline__ void hop_step(cx<C> acc[12], const StencilKArgs &a, l
     hop_dir<C, MU, P>(acc, v, u, D == 0);
 }
 
-template <typename S, typename C, int EPI, bool SELF, bool DAG, bool RED>
-__global__ void __launch_bounds__(256) k_stencil(const StencilKArgs a)
+// batch member blockIdx.y of fields laid out `stride` bytes apart
+__device__ __forceinline__ Field batch_member(Field f, long stride)
 {
+    if (stride) {
+        const long off = (long)blockIdx.y * stride;
+        f.data = (char *)f.data + off;
+        if (f.norm) f.norm = (float *)((char *)f.norm + off);
+    }
+    return f;
+}
+
+template <typename S, typename C, int EPI, bool SELF, bool DAG, bool RED>
+__global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
+{
+    a.in = batch_member(a.in, a.bstride);
+    a.out = batch_member(a.out, a.bstride);
+    if constexpr (SELF) a.self = batch_member(a.self, a.bstride);
     const int Ls = a.Ls;
     const int s = threadIdx.x;
     const int j = threadIdx.y;
@@ -217,14 +232,16 @@ __global__ void __launch_bounds__(256) k_stencil(const StencilKArgs a)
             for (int c = 0; c < 12; c++) n2 += double(res[c].re) * double(res[c].re) + double(res[c].im) * double(res[c].im);
         }
         const double t = block_sum(n2);
-        if (threadIdx.x == 0 && threadIdx.y == 0) a.partial[blockIdx.x] = t;
+        if (threadIdx.x == 0 && threadIdx.y == 0) a.partial[(long)blockIdx.y * gridDim.x + blockIdx.x] = t;
     }
 }
 
 // s-local dense operator out = M in, M = [2][Ls][Ls] (P+ block, P- block)
 template <typename S, typename C>
-__global__ void __launch_bounds__(256) k_slocal(Field in, Field out, const C *mat, long vh, int Ls, int run)
+__global__ void __launch_bounds__(256) k_slocal(Field in, Field out, const C *mat, long vh, int Ls, int run, long bstride)
 {
+    in = batch_member(in, bstride);
+    out = batch_member(out, bstride);
     const int s = threadIdx.x, j = threadIdx.y, sb = blockDim.y;
     const long cb = (long)xcd_swizzle(blockIdx.x, gridDim.x, run) * sb + j;
     const bool valid = cb < vh;
@@ -273,8 +290,10 @@ static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field s
     const int Ls = c.Ls;
     const int sb = cfg_sb(c, c.cfg_stencil);
     const long nblk = (c.vh + sb - 1) / sb;
-    if (sp.reduce && nblk > c.partials_len) fail(DWF_EINVAL, "reduction buffer too small");
+    const int nb = std::max(1, sp.nbatch);
+    if (sp.reduce && nblk * nb > c.partials_len) fail(DWF_EINVAL, "reduction buffer too small");
     StencilKArgs a;
+    a.bstride = nb > 1 ? sp.bstride : 0;
     a.in = in;
     a.self = self;
     a.out = out;
@@ -298,13 +317,13 @@ static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field s
     if (sp.epi != EPI_NONE) lds += (size_t)sb * Ls * 12 * sizeof(cx<C>);
     if (sp.self) lds += (size_t)sb * Ls * 12 * sizeof(cx<C>);
     if (sp.epi == EPI_DENSE) lds += 2 * (size_t)Ls * Ls * sizeof(C);
-    dim3 blk(Ls, sb), grid((unsigned)nblk);
+    dim3 blk(Ls, sb), grid((unsigned)nblk, (unsigned)nb);
     // algorithmic traffic: neighbour spinor, 8 links shared by the Ls slices, output, self input
     const double sbytes = 12.0 * sizeof(typename S::elem) + (S::has_norm ? 4.0 : 0.0);
-    const double bytes = (double)c.n5h * (2 * sbytes + (sp.self ? sbytes : 0.0)) +
-                         (double)c.vh * 8 * 9 * sizeof(typename S::elem);
-    double flops = (double)c.n5h * 1320.0;
-    if (sp.epi == EPI_DENSE) flops += (double)c.n5h * 24.0 * 2.0 * Ls;
+    const double bytes = nb * ((double)c.n5h * (2 * sbytes + (sp.self ? sbytes : 0.0)) +
+                               (double)c.vh * 8 * 9 * sizeof(typename S::elem));
+    double flops = nb * (double)c.n5h * 1320.0;
+    if (sp.epi == EPI_DENSE) flops += nb * (double)c.n5h * 24.0 * 2.0 * Ls;
     Timer tm(c, sp.kclass, bytes, flops);
 #define DWF_LAUNCH(E, SF, DG, RD) \
     hipLaunchKernelGGL((k_stencil<S, C, E, SF, DG, RD>), grid, blk, lds, c.stream, a)
@@ -339,16 +358,17 @@ static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field s
 }
 
 template <typename S, typename C>
-static void launch_slocal_t(Context &c, int op, Field in, Field out)
+static void launch_slocal_t(Context &c, int op, Field in, Field out, int nbatch, long bstride)
 {
     const int Ls = c.Ls;
     const int sb = cfg_sb(c, c.cfg_slocal);
     const long nblk = (c.vh + sb - 1) / sb;
+    const int nb = std::max(1, nbatch);
     const size_t lds = (size_t)sb * Ls * 12 * sizeof(cx<C>) + 2 * (size_t)Ls * Ls * sizeof(C);
     const double sbytes = 12.0 * sizeof(typename S::elem) + (S::has_norm ? 4.0 : 0.0);
-    Timer tm(c, DWF_K_SLOCAL, 2.0 * sbytes * c.n5h, (double)c.n5h * 48.0 * Ls);
-    hipLaunchKernelGGL((k_slocal<S, C>), dim3((unsigned)nblk), dim3(Ls, sb), lds, c.stream, in, out,
-                       (const C *)slmat(c, op, sizeof(C) == 8), c.vh, Ls, c.cfg_slocal.run);
+    Timer tm(c, DWF_K_SLOCAL, nb * 2.0 * sbytes * c.n5h, nb * (double)c.n5h * 48.0 * Ls);
+    hipLaunchKernelGGL((k_slocal<S, C>), dim3((unsigned)nblk, (unsigned)nb), dim3(Ls, sb), lds, c.stream, in, out,
+                       (const C *)slmat(c, op, sizeof(C) == 8), c.vh, Ls, c.cfg_slocal.run, nb > 1 ? bstride : 0L);
     HIPCHECK(hipGetLastError());
 }
 

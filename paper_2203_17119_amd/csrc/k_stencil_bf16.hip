@@ -6,5 +6,8 @@ int launch_stencil_bf16(Context &c, const StencilSpec &sp, Field in, Field self,
 {
     return launch_stencil_t<BF16, float>(c, sp, in, self, out);
 }
-void launch_slocal_bf16(Context &c, int op, Field in, Field out) { launch_slocal_t<BF16, float>(c, op, in, out); }
+void launch_slocal_bf16(Context &c, int op, Field in, Field out, int nbatch, long bstride)
+{
+    launch_slocal_t<BF16, float>(c, op, in, out, nbatch, bstride);
+}
 }  // namespace dwf

@@ -296,12 +296,35 @@ dwf_status dwf_cg(dwf_ctx ctx, const double *b_full, double *x_full, const dwf_s
     DWF_API_END
 }
 
-dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *const *b_odd, int nshift, const double *shifts,
-                             double *const *x_odd, const dwf_solver_opts *o, dwf_solver_stats *st)
+}  // extern "C"
+
+// ---------------------------------------------------------- multi-shift CG
+
+namespace dwf {
+
+struct DevBuf {
+    void *p = nullptr;
+    DevBuf(size_t bytes) { HIPCHECK(hipMalloc(&p, bytes)); }
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+    template <typename T>
+    T *as() const
+    {
+        return (T *)p;
+    }
+};
+
+}  // namespace dwf
+
+extern "C" dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *const *b_odd, int nshift,
+                                        const double *shifts, double *const *x_odd, const dwf_solver_opts *o,
+                                        dwf_solver_stats *st)
 {
     DWF_API_BEGIN
     if (!ctx) fail(DWF_EINVAL, "null context");
-    if (nrhs < 1 || nshift < 1 || nshift > 64) fail(DWF_EINVAL, "need 1 <= nrhs and 1 <= nshift <= 64");
+    if (nrhs < 1 || nrhs > 64 || nshift < 1 || nshift > 64) fail(DWF_EINVAL, "need 1 <= nrhs, nshift <= 64");
     if (!b_odd || !x_odd || !shifts) fail(DWF_EINVAL, "null pointer");
     for (int k = 0; k < nshift; k++)
         if (!(shifts[k] >= 0.0) || !std::isfinite(shifts[k])) fail(DWF_EINVAL, "shifts must be finite and >= 0");
@@ -315,148 +338,134 @@ dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *const *b_odd, 
     int maxit, mode;
     bool guess;
     fill_opts(o, tol, maxit, mode, delta, guess);
-    if (mode != DWF_SOLVE_F64 && mode != DWF_SOLVE_MIXED_F32) fail(DWF_ENOTSUP, "multi-shift mode must be F64 or MIXED_F32");
+    if (mode != DWF_SOLVE_F64 && mode != DWF_SOLVE_MIXED_F32)
+        fail(DWF_ENOTSUP, "multi-shift mode must be F64 or MIXED_F32");
     const int lp = prec_of_mode(mode);
     const bool mixed = lp != P_F64;
-    set_scalar(c, S_ONE, 1.0);
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    const double t0 = now();
     int kmin = 0;
     for (int k = 1; k < nshift; k++)
         if (shifts[k] < shifts[kmin]) kmin = k;
-    const double s0 = shifts[kmin];
-    // per-shift fields of the Krylov precision, and their device descriptor arrays
-    std::vector<Field> X(nshift), P(nshift);
-    for (int k = 0; k < nshift; k++) {
-        X[k] = ws_field(c, "ms_x" + std::to_string(k), lp);
-        P[k] = ws_field(c, "ms_p" + std::to_string(k), lp);
-    }
-    Field *dX = nullptr, *dP = nullptr;
-    double *dcoef = nullptr, *hcoef = nullptr;
-    HIPCHECK(hipMalloc(&dX, nshift * sizeof(Field)));
-    HIPCHECK(hipMalloc(&dP, nshift * sizeof(Field)));
-    HIPCHECK(hipMalloc(&dcoef, 4 * nshift * sizeof(double)));
-    HIPCHECK(hipHostMalloc(&hcoef, 4 * nshift * sizeof(double), hipHostMallocDefault));
-    struct Guard {
-        Field *a, *b;
-        double *c, *h;
-        ~Guard()
-        {
-            (void)hipFree(a);
-            (void)hipFree(b);
-            (void)hipFree(c);
-            (void)hipHostFree(h);
-        }
-    } guard{dX, dP, dcoef, hcoef};
-    HIPCHECK(hipMemcpy(dX, X.data(), nshift * sizeof(Field), hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(dP, P.data(), nshift * sizeof(Field), hipMemcpyHostToDevice));
-    Field b64 = ws_field(c, "ms_b", P_F64), x64 = ws_field(c, "ms_x64", P_F64);
-    Field r = ws_field(c, "ms_r", lp), ap = ws_field(c, "ms_ap", lp), m = ws_field(c, "ms_m", lp);
-    Field bl = mixed ? ws_field(c, "ms_bl", lp) : b64;
-    bool all_ok = true;
-    const int maxi = maxit > 0 ? maxit : 100000;
+    const long stride = batch_stride(c, lp);
+    const int nq = nrhs * nshift;
+    // batches: B, R, AP, M over rhs; X, P over (shift, rhs), member k*nrhs + j
+    Field B = ws_batch(c, "ms_B", lp, nrhs), R = ws_batch(c, "ms_R", lp, nrhs);
+    Field AP = ws_batch(c, "ms_AP", lp, nrhs), M = ws_batch(c, "ms_M", lp, nrhs);
+    Field X = ws_batch(c, "ms_X", lp, nq), P = ws_batch(c, "ms_P", lp, nq);
+    Field b64 = ws_field(c, "ms_b64", P_F64), x64 = ws_field(c, "ms_x64", P_F64);
     for (int j = 0; j < nrhs; j++) {
-        const double t0 = now();
         launch_import(c, P_F64, b_odd[j], b64, 0, 0);
-        if (mixed) launch_convert(c, P_F64, b64, lp, bl);
-        const double b2 = dwf::norm2(c, P_F64, b64);
-        launch_copy(c, lp, bl, r);
-        for (int k = 0; k < nshift; k++) {
-            launch_zero(c, lp, X[k]);
-            launch_copy(c, lp, bl, P[k]);
+        launch_convert(c, P_F64, b64, lp, member(B, j, stride));
+    }
+    // device state
+    DevBuf dstate(sizeof(double) * (7 * nrhs + 2 * nq + 4 * nq + nshift) + sizeof(int) * 2 * nq);
+    double *db = dstate.as<double>();
+    MsState s;
+    s.rho = db;
+    s.pap = db + nrhs;
+    s.alpha = db + 2 * nrhs;
+    s.alpha_old = db + 3 * nrhs;
+    s.beta_old = db + 4 * nrhs;
+    s.target = db + 5 * nrhs;
+    double *rho_new = db + 6 * nrhs;
+    s.zeta = db + 7 * nrhs;
+    s.zeta_old = s.zeta + nq;
+    s.coef = s.zeta_old + nq;
+    s.shifts = s.coef + 4 * nq;
+    s.active = (int *)(s.shifts + nshift);
+    s.iters = s.active + nq;
+    {
+        std::vector<double> h(7 * nrhs + 6 * nq + nshift, 0.0);
+        std::vector<int> hi(2 * nq, 0);
+        ms_launch_norm2(c, lp, B, nrhs, stride, c.dscal + 16);
+        read_scalars(c, 16, nrhs);
+        for (int j = 0; j < nrhs; j++) {
+            h[j] = c.hscal[16 + j];                         // rho
+            h[3 * nrhs + j] = 1.0;                          // alpha_old
+            h[5 * nrhs + j] = tol * std::sqrt(c.hscal[16 + j]);  // target
         }
-        std::vector<double> zeta(nshift, 1.0), zeta_old(nshift, 1.0);
-        std::vector<int> active(nshift, 1), iters(nshift, 0);
-        double rho = dwf::norm2(c, lp, r);
-        double alpha_old = 1.0, beta_old = 0.0;
-        int it = 0, nact = nshift;
-        // the Krylov space of the lowest shift; its direction is P[kmin]
-        const double target = tol * std::sqrt(b2);
-        while (nact > 0 && it < maxi && rho > 0) {
-            Field p = P[kmin];
-            apply_mpc(c, lp, false, p, m, false);
-            apply_mpc(c, lp, true, m, ap, false);
-            launch_axpby(c, lp, 1.0, ap, s0, p, ap);
-            const int np = launch_dot(c, lp, p, ap);
-            launch_finish(c, np, 2, S_DOT);
-            read_scalars(c, S_DOT, 1);
-            const double alpha = rho / c.hscal[S_DOT];
-            launch_axpby(c, lp, 1.0, r, -alpha, ap, r);
-            const double rho1 = dwf::norm2(c, lp, r);
-            if (!std::isfinite(rho1)) fail(DWF_ENOCONV, "multi-shift breakdown: non-finite residual");
-            const double beta = rho1 / rho;
-            it++;
-            for (int k = 0; k < nshift; k++) {
-                hcoef[4 * k + 3] = active[k] ? 1.0 : 0.0;
-                if (!active[k]) continue;
-                const double ds = shifts[k] - s0;
-                const double z = zeta[k], zo = zeta_old[k];
-                const double zn =
-                    z * zo * alpha_old / (alpha * beta_old * (zo - z) + zo * alpha_old * (1.0 + ds * alpha));
-                hcoef[4 * k + 0] = alpha * zn / z;
-                hcoef[4 * k + 1] = zn;
-                hcoef[4 * k + 2] = beta * (zn / z) * (zn / z);
-                zeta_old[k] = z;
-                zeta[k] = zn;
-            }
-            HIPCHECK(hipMemcpyAsync(dcoef, hcoef, 4 * nshift * sizeof(double), hipMemcpyHostToDevice, c.stream));
-            launch_ms_update(c, lp, nshift, dX, dP, r, dcoef, active.data());
-            // the lowest shift carries the Krylov space and is frozen last
-            for (int k = 0; k < nshift; k++)
-                if (active[k] && (k != kmin || nact == 1) && std::fabs(zeta[k]) * std::sqrt(rho1) <= target) {
-                    active[k] = 0;
-                    iters[k] = it;
-                    nact--;
-                }
-            rho = rho1;
-            alpha_old = alpha;
-            beta_old = beta;
+        for (int q = 0; q < nq; q++) h[7 * nrhs + q] = h[7 * nrhs + nq + q] = 1.0;  // zeta, zeta_old
+        for (int k = 0; k < nshift; k++) h[7 * nrhs + 6 * nq + k] = shifts[k];
+        for (int q = 0; q < nq; q++) hi[q] = 1;
+        HIPCHECK(hipMemcpy(db, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(s.active, hi.data(), hi.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    for (int j = 0; j < nrhs; j++) launch_copy(c, lp, member(B, j, stride), member(R, j, stride));
+    for (int q = 0; q < nq; q++) {
+        launch_zero(c, lp, member(X, q, stride));
+        launch_copy(c, lp, member(B, q % nrhs, stride), member(P, q, stride));
+    }
+    const Field Pbase = member(P, kmin * nrhs, stride);
+    const int maxi = maxit > 0 ? maxit : 100000;
+    std::vector<int> act(nq);
+    int it = 0;
+    while (it < maxi) {
+        apply_mpc(c, lp, false, Pbase, M, false, false, Field{}, nrhs, stride);
+        apply_mpc(c, lp, true, M, AP, false, false, Field{}, nrhs, stride);
+        if (shifts[kmin] != 0.0) ms_launch_axpy(c, lp, shifts[kmin], Pbase, AP, nrhs, stride);
+        ms_launch_redot(c, lp, Pbase, AP, nrhs, stride, s.pap);
+        it++;
+        ms_launch_step(c, lp, s, R, AP, X, P, nrhs, nshift, kmin, stride, rho_new, it);
+        if (it % 8 == 0 || it == maxi) {
+            HIPCHECK(hipMemcpyAsync(act.data(), s.active, nq * sizeof(int), hipMemcpyDeviceToHost, c.stream));
             HIPCHECK(hipStreamSynchronize(c.stream));
+            int n = 0;
+            for (int a : act) n += a;
+            if (n == 0) break;
         }
-        const double t1 = now();
-        // FP64 check (and refinement of the low-precision solutions)
+    }
+    std::vector<int> its(nq);
+    HIPCHECK(hipMemcpy(its.data(), s.iters, nq * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(act.data(), s.active, nq * sizeof(int), hipMemcpyDeviceToHost));
+    const double t1 = now();
+    // FP64 true residual of every (rhs, shift); low-precision solutions are refined
+    bool all_ok = true;
+    Field t1f = ws_field(c, "ms_t1", P_F64), t2f = ws_field(c, "ms_t2", P_F64);
+    for (int j = 0; j < nrhs; j++) {
+        launch_import(c, P_F64, b_odd[j], b64, 0, 0);
+        const double b2 = norm2(c, P_F64, b64);
         for (int k = 0; k < nshift; k++) {
-            Field xk = X[k];
-            if (mixed) {
-                launch_convert(c, lp, xk, P_F64, x64);
-                CoreStats cs = cg_core(c, DWF_SOLVE_MIXED_F32, shifts[k], b64, x64, tol, maxi, delta, true);
-                (void)cs;
-                iters[k] += cs.iters;
-            } else {
-                launch_copy(c, P_F64, xk, x64);
+            const int q = k * nrhs + j;
+            launch_convert(c, lp, member(X, q, stride), P_F64, x64);
+            int extra = 0;
+            auto residual = [&]() {
+                apply_mpc(c, P_F64, false, x64, t1f, false);
+                apply_mpc(c, P_F64, true, t1f, t2f, false);
+                launch_axpby(c, P_F64, 1.0, t2f, shifts[k], x64, t2f);
+                launch_axpby(c, P_F64, 1.0, b64, -1.0, t2f, t2f);
+                return std::sqrt(norm2(c, P_F64, t2f) / b2);
+            };
+            double res = b2 > 0 ? residual() : 0.0;
+            if (b2 > 0 && (mixed || res > tol)) {
+                if (res > tol) {
+                    CoreStats cs = cg_core(c, mixed ? DWF_SOLVE_MIXED_F32 : DWF_SOLVE_F64, shifts[k], b64, x64, tol,
+                                           maxi, delta, true);
+                    extra = cs.iters;
+                    res = cs.rel_res;
+                }
             }
-            apply_mpc(c, P_F64, false, x64, ws_field(c, "ms_t1", P_F64), false);
-            Field t2 = ws_field(c, "ms_t2", P_F64);
-            apply_mpc(c, P_F64, true, ws_field(c, "ms_t1", P_F64), t2, false);
-            launch_axpby(c, P_F64, 1.0, t2, shifts[k], x64, t2);
-            launch_axpby(c, P_F64, 1.0, b64, -1.0, t2, t2);
-            const double res = std::sqrt(dwf::norm2(c, P_F64, t2) / b2);
             launch_export(c, P_F64, x64, x_odd[j * nshift + k], 0, 0);
-            const bool ok = res <= tol * 1.5;
+            const bool ok = res <= tol * 1.0000001;
             all_ok = all_ok && ok;
             if (st) {
-                dwf_solver_stats &s = st[j * nshift + k];
-                s.iters = iters[k] ? iters[k] : it;
-                s.reliable_updates = 0;
-                s.converged = ok;
-                s.fell_back = 0;
-                s.res_normal = res;
-                s.res_schur = 0;
-                s.res_full = 0;
-                s.t_prep = 0;
-                s.t_solve = t1 - t0;
-                s.t_final = 0;
-                s.seconds = 0;
+                dwf_solver_stats &sv = st[j * nshift + k];
+                sv = dwf_solver_stats{};
+                sv.iters = (act[q] ? it : its[q]) + extra;
+                sv.reliable_updates = extra;
+                sv.converged = ok;
+                sv.res_normal = res;
+                sv.t_solve = t1 - t0;
             }
         }
-        HIPCHECK(hipStreamSynchronize(c.stream));
-        const double t2 = now();
-        if (st)
-            for (int k = 0; k < nshift; k++) {
-                st[j * nshift + k].t_final = t2 - t1;
-                st[j * nshift + k].seconds = t2 - t0;
-            }
     }
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    const double t2 = now();
+    if (st)
+        for (int q = 0; q < nq; q++) {
+            st[q].t_final = t2 - t1;
+            st[q].seconds = t2 - t0;
+        }
     return all_ok ? DWF_OK : DWF_ENOCONV;
     DWF_API_END
 }
-
-}  // extern "C"
