@@ -271,6 +271,82 @@ void or_d5(const int *L, int Ls, double b, double c, double M5, double mf, const
     free(t2);
 }
 
+/* ------------------------------------------------------------ sampled sites */
+
+/* The same operators evaluated only at a list of 4D sites (all s), for checks
+ * at lattice sizes where the full operator is too expensive for the CPU.  Each
+ * sample gathers its 9-site neighbourhood into a small periodic-free buffer and
+ * applies the definitions above to it. */
+
+/* (H in)(n) or (H^+ in)(n) for n in sites; out[k][s][spin][colour] */
+void or_hop_sites(const int *L, int Ls, const double *Uin, const double *in_, const long *sites, long nsite,
+                  double *out_, int dagger)
+{
+    init_gamma();
+    const cplx *U = (const cplx *)Uin;
+    const cplx *in = (const cplx *)in_;
+    cplx *out = (cplx *)out_;
+    double sf = dagger ? +1.0 : -1.0;
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < nsite; k++) {
+        long n = sites[k];
+        for (int s = 0; s < Ls; s++) {
+            cplx acc[4][3];
+            memset(acc, 0, sizeof(acc));
+            for (int mu = 0; mu < 4; mu++) {
+                long nf = shifted(L, n, mu, +1), nb = shifted(L, n, mu, -1);
+                for (int al = 0; al < 4; al++)
+                    for (int a = 0; a < 3; a++) {
+                        cplx t = 0;
+                        for (int be = 0; be < 4; be++) {
+                            cplx id = (al == be) ? 1.0 : 0.0;
+                            cplx v = 0, w = 0;
+                            for (int b = 0; b < 3; b++) {
+                                v += U[UIDX(n, mu, a, b)] * in[FIDX(nf, s, be, b, Ls)];
+                                w += conj(U[UIDX(nb, mu, b, a)]) * in[FIDX(nb, s, be, b, Ls)];
+                            }
+                            t += (id + sf * G[mu][al][be]) * v + (id - sf * G[mu][al][be]) * w;
+                        }
+                        acc[al][a] += t;
+                    }
+            }
+            for (int sp = 0; sp < 4; sp++)
+                for (int a = 0; a < 3; a++) out[((k * Ls + s) * 4 + sp) * 3 + a] = acc[sp][a];
+        }
+    }
+}
+
+/* (D5 in)(n) for n in sites (non-dagger), from
+ * D5 = (b D_W + 1) + (c D_W - 1) P5 with D_W = (4 - M5) - H/2 */
+void or_d5_sites(const int *L, int Ls, double b, double c, double M5, double mf, const double *U, const double *in_,
+                 const long *sites, long nsite, double *out_)
+{
+    const cplx *in = (const cplx *)in_;
+    cplx *out = (cplx *)out_;
+    long per = (long)Ls * 12;
+    /* P5 in at the 9 sites of each neighbourhood, then the hops at the centre */
+    cplx *hop_in = malloc(nsite * per * sizeof(cplx));
+    cplx *hop_p5 = malloc(nsite * per * sizeof(cplx));
+    or_hop_sites(L, Ls, U, in_, sites, nsite, (double *)hop_in, 0);
+    long V = vol(L);
+    /* P5 applied on the full field is s-local; evaluate it on the whole field once */
+    cplx *p5in = malloc(V * per * sizeof(cplx));
+    p5(V, Ls, mf, in, p5in, 0);
+    or_hop_sites(L, Ls, U, (const double *)p5in, sites, nsite, (double *)hop_p5, 0);
+    for (long k = 0; k < nsite; k++) {
+        long n = sites[k];
+        for (long e = 0; e < per; e++) {
+            cplx x = in[n * per + e], px = p5in[n * per + e];
+            cplx dw = (4.0 - M5) * x - 0.5 * hop_in[k * per + e];
+            cplx dwp = (4.0 - M5) * px - 0.5 * hop_p5[k * per + e];
+            out[k * per + e] = b * dw + x + c * dwp - px;
+        }
+    }
+    free(hop_in);
+    free(hop_p5);
+    free(p5in);
+}
+
 /* ------------------------------------------------------------ parity */
 
 static long site_of_cb(const int *L, long cb, int p)

@@ -59,6 +59,8 @@ def lib():
             "or_ptc_layer_backward": [_p, _i, _p, _i, _i, _p, _p, _p, _p, _p],
             "or_net_apply": [_p, _i, _p, _i, _p, _p, _p, _p],
             "or_fgcr": [_p, _i, _d, _d, _d, _d, _p, _i, _p, _p, _p, _p, _d, _i, _i, _i, _p],
+            "or_hop_sites": [_p, _i, _p, _p, _p, _l, _p, _i],
+            "or_d5_sites": [_p, _i, _d, _d, _d, _d, _p, _p, _p, _l, _p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -141,6 +143,24 @@ def d5(P: Params, U, psi, dagger=False) -> np.ndarray:
     U, psi = _c128(U), _c128(psi)
     out = np.empty_like(psi)
     lib().or_d5(_ptr(P._L), P.Ls, *P.args(), _ptr(U), _ptr(psi), _ptr(out), int(dagger))
+    return out
+
+
+def hop_sites(P: Params, U, psi, sites, dagger=False) -> np.ndarray:
+    """(H psi)(n) for the listed lexicographic 4D sites n; shape (len(sites), Ls, 4, 3)."""
+    U, psi = _c128(U), _c128(psi)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.empty((len(sites), P.Ls, 4, 3), dtype=np.complex128)
+    lib().or_hop_sites(_ptr(P._L), P.Ls, _ptr(U), _ptr(psi), _ptr(sites), len(sites), _ptr(out), int(dagger))
+    return out
+
+
+def d5_sites(P: Params, U, psi, sites) -> np.ndarray:
+    """(D5 psi)(n) for the listed lexicographic 4D sites n; shape (len(sites), Ls, 4, 3)."""
+    U, psi = _c128(U), _c128(psi)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.empty((len(sites), P.Ls, 4, 3), dtype=np.complex128)
+    lib().or_d5_sites(_ptr(P._L), P.Ls, *P.args(), _ptr(U), _ptr(psi), _ptr(sites), len(sites), _ptr(out))
     return out
 
 

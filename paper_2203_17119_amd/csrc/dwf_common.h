@@ -198,6 +198,24 @@ __device__ __forceinline__ void load_spinor(const Field &f, long i, cx<C> v[12])
     }
 }
 
+// the stored components without the FP16 site scale, and the scale (1 for
+// formats without one); value = scale * v
+template <typename S, typename C>
+__device__ __forceinline__ void load_spinor_unscaled(const Field &f, long i, cx<C> v[12], C &scale)
+{
+    using P = Planes<S>;
+    const uint4 *d = (const uint4 *)f.data;
+    scale = C(1);
+    if constexpr (S::has_norm) scale = C(f.norm[i]);
+#pragma unroll
+    for (int q = 0; q < P::n; q++) {
+        Vec16 w;
+        w.u = d[q * f.n + i];
+#pragma unroll
+        for (int k = 0; k < P::cpp; k++) v[q * P::cpp + k] = unpack<C>(vec_get<S>(w, k));
+    }
+}
+
 template <typename S, typename C>
 __device__ __forceinline__ void store_spinor(const Field &f, long i, const cx<C> v[12])
 {

@@ -36,10 +36,10 @@ struct StencilKArgs {
     long bstride;  // bytes between batch members (blockIdx.y), 0 for one field
 };
 
+// half-spinor projection h = upper pair of (1 + P g_MU) v
 template <typename C, int MU, int P>
-__device__ __forceinline__ void hop_dir(cx<C> acc[12], const cx<C> v[12], const cx<C> u[9], bool first)
+__device__ __forceinline__ void project(const cx<C> v[12], cx<C> h[6])
 {
-    cx<C> h[6];
 #pragma unroll
     for (int col = 0; col < 3; col++) {
         const cx<C> u0 = v[col], u1 = v[3 + col], l0 = v[6 + col], l1 = v[9 + col];
@@ -57,6 +57,60 @@ __device__ __forceinline__ void hop_dir(cx<C> acc[12], const cx<C> v[12], const 
             h[3 + col] = (P > 0) ? u1 + l1 : u1 - l1;
         }
     }
+}
+
+// f = sign(NEG) a.half[SA] + b.half[SB] in FP32 from two packed FP16 pairs,
+// one v_fma_mix_f32 (a * 1.0 + b with both operands read as FP16); the sum of
+// two FP16 numbers is formed exactly as in FP32 after conversion
+template <int SA, int SB, bool NEG>
+__device__ __forceinline__ float mix_add(uint32_t a, uint32_t b)
+{
+    float r;
+#define DWF_MIX(STR) asm volatile(STR : "=v"(r) : "v"(a), "v"(b))
+    if constexpr (!NEG && SA == 0 && SB == 0) DWF_MIX("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[0,0,0] op_sel_hi:[1,0,1]");
+    else if constexpr (!NEG && SA == 0 && SB == 1) DWF_MIX("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[0,0,1] op_sel_hi:[1,0,1]");
+    else if constexpr (!NEG && SA == 1 && SB == 0) DWF_MIX("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,1]");
+    else if constexpr (!NEG && SA == 1 && SB == 1) DWF_MIX("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]");
+    else if constexpr (NEG && SA == 0 && SB == 0) DWF_MIX("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[0,0,0] op_sel_hi:[1,0,1]");
+    else if constexpr (NEG && SA == 0 && SB == 1) DWF_MIX("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[0,0,1] op_sel_hi:[1,0,1]");
+    else if constexpr (NEG && SA == 1 && SB == 0) DWF_MIX("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,1]");
+    else DWF_MIX("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]");
+#undef DWF_MIX
+    return r;
+}
+
+// the same projection on raw FP16 pairs (re in the low, im in the high half):
+// with x = u + s l (s = +-1) or u + s i l, componentwise
+//   u + s l   : (u.re + s l.re, u.im + s l.im)
+//   u + s i l : (u.re - s l.im, u.im + s l.re)
+template <int MU, int P>
+__device__ __forceinline__ void project_f16(const uint32_t r[12], cx<float> h[6])
+{
+#pragma unroll
+    for (int col = 0; col < 3; col++) {
+        const uint32_t u0 = r[col], u1 = r[3 + col], l0 = r[6 + col], l1 = r[9 + col];
+        if constexpr (MU == 0) {  // h0 = u0 - P i l1, h1 = u1 - P i l0
+            h[col] = mk(mix_add<1, 0, (P < 0)>(l1, u0), mix_add<0, 1, (P > 0)>(l1, u0));
+            h[3 + col] = mk(mix_add<1, 0, (P < 0)>(l0, u1), mix_add<0, 1, (P > 0)>(l0, u1));
+        } else if constexpr (MU == 1) {  // h0 = u0 - P l1, h1 = u1 + P l0
+            h[col] = mk(mix_add<0, 0, (P > 0)>(l1, u0), mix_add<1, 1, (P > 0)>(l1, u0));
+            h[3 + col] = mk(mix_add<0, 0, (P < 0)>(l0, u1), mix_add<1, 1, (P < 0)>(l0, u1));
+        } else if constexpr (MU == 2) {  // h0 = u0 - P i l0, h1 = u1 + P i l1
+            h[col] = mk(mix_add<1, 0, (P < 0)>(l0, u0), mix_add<0, 1, (P > 0)>(l0, u0));
+            h[3 + col] = mk(mix_add<1, 0, (P > 0)>(l1, u1), mix_add<0, 1, (P < 0)>(l1, u1));
+        } else {  // h0 = u0 + P l0, h1 = u1 + P l1
+            h[col] = mk(mix_add<0, 0, (P < 0)>(l0, u0), mix_add<1, 1, (P < 0)>(l0, u0));
+            h[3 + col] = mk(mix_add<0, 0, (P < 0)>(l1, u1), mix_add<1, 1, (P < 0)>(l1, u1));
+        }
+    }
+}
+
+// acc += scale * (1 + P g_MU) U (projected h): the two colour vectors of h are
+// multiplied by the link, the lower spin pair rebuilt from the upper one; the
+// neighbour's FP16 site scale is applied in the accumulation
+template <typename C, int MU, int P>
+__device__ __forceinline__ void link_accumulate(cx<C> acc[12], const cx<C> h[6], const cx<C> u[9], bool first, C scale)
+{
     cx<C> g[6];
 #pragma unroll
     for (int j = 0; j < 2; j++)
@@ -86,38 +140,80 @@ __device__ __forceinline__ void hop_dir(cx<C> acc[12], const cx<C> v[12], const 
             lo1[col] = (P > 0) ? g1 : -g1;
         }
     }
+    auto acc_add = [&](cx<C> &a, cx<C> b) {
+        a.re = fma(scale, b.re, a.re);
+        a.im = fma(scale, b.im, a.im);
+    };
     if (first) {
 #pragma unroll
         for (int col = 0; col < 3; col++) {
-            acc[col] = g[col];
-            acc[3 + col] = g[3 + col];
-            acc[6 + col] = lo0[col];
-            acc[9 + col] = lo1[col];
+            acc[col] = scale * g[col];
+            acc[3 + col] = scale * g[3 + col];
+            acc[6 + col] = scale * lo0[col];
+            acc[9 + col] = scale * lo1[col];
         }
     } else {
 #pragma unroll
         for (int col = 0; col < 3; col++) {
-            acc[col] = acc[col] + g[col];
-            acc[3 + col] = acc[3 + col] + g[3 + col];
-            acc[6 + col] = acc[6 + col] + lo0[col];
-            acc[9 + col] = acc[9 + col] + lo1[col];
+            acc_add(acc[col], g[col]);
+            acc_add(acc[3 + col], g[3 + col]);
+            acc_add(acc[6 + col], lo0[col]);
+            acc_add(acc[9 + col], lo1[col]);
         }
     }
 }
 
+// one direction of the hop; the workgroup's links and neighbour indices are in
+// LDS: lk[(d*9 + k)*sb + j], nb[d*sb + j]
 template <typename S, typename C, int D, bool DAG>
-__device__ __forceinline__ void hop_step(cx<C> acc[12], const StencilKArgs &a, long cb, int s)
+__device__ __forceinline__ void hop_step(cx<C> acc[12], const StencilKArgs &a, const cx<C> *lk, const int *nbs, int j,
+                                         int sb, int s)
 {
     constexpr int MU = D & 3;
     constexpr int P0 = (D < 4) ? -1 : +1;
     constexpr int P = DAG ? -P0 : P0;
-    const long nb = a.nbr[(long)D * a.vh + cb];
-    cx<C> v[12];
-    load_spinor<S, C>(a.in, nb * a.Ls + s, v);
+    const long nb = nbs[D * sb + j];
+    const long i = nb * a.Ls + s;
+    cx<C> h[6];
+    C scale;
+    if constexpr (S::prec == P_F16) {
+        const uint4 *d = (const uint4 *)a.in.data;
+        uint32_t r[12];
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            const uint4 w = d[q * a.in.n + i];
+            r[4 * q] = w.x;
+            r[4 * q + 1] = w.y;
+            r[4 * q + 2] = w.z;
+            r[4 * q + 3] = w.w;
+        }
+        scale = C(a.in.norm[i]);
+        project_f16<MU, P>(r, h);
+    } else {
+        cx<C> v[12];
+        load_spinor_unscaled<S, C>(a.in, i, v, scale);
+        project<C, MU, P>(v, h);
+    }
     cx<C> u[9];
-    Links l{a.links, a.vh};
-    load_link<S, C>(l, D, cb, u);
-    hop_dir<C, MU, P>(acc, v, u, D == 0);
+#pragma unroll
+    for (int k = 0; k < 9; k++) u[k] = lk[(D * 9 + k) * sb + j];
+    link_accumulate<C, MU, P>(acc, h, u, D == 0, scale);
+}
+
+// cooperative load of the links and neighbour indices of sb consecutive
+// internal sites starting at tile*sb into LDS (each link read once per
+// workgroup instead of once per lane)
+template <typename S, typename C>
+__device__ __forceinline__ void stage_links(const StencilKArgs &a, long base, int sb, cx<C> *lk, int *nbs)
+{
+    // the Ls lanes of site j = threadIdx.y share its 72 link entries and 8 indices
+    const int jj = threadIdx.y;
+    const long site = base + jj;
+    const bool ok = site < a.vh;
+    const typename S::elem *L = (const typename S::elem *)a.links;
+    for (int dk = threadIdx.x; dk < 72; dk += blockDim.x)
+        lk[dk * sb + jj] = ok ? unpack<C>(L[(long)dk * a.vh + site]) : mk(C(0), C(0));
+    for (int d = threadIdx.x; d < 8; d += blockDim.x) nbs[d * sb + jj] = ok ? a.nbr[(long)d * a.vh + site] : 0;
 }
 
 // batch member blockIdx.y of fields laid out `stride` bytes apart
@@ -146,24 +242,31 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
     const bool valid = cb < a.vh;
     const long i = cb * Ls + s;
 
+    // LDS: staged links + neighbour indices during the hop, then reused for the
+    // fifth-dimension epilogue (hop results, self input, dense matrix)
     extern __shared__ unsigned char smem[];
+    cx<C> *lk = (cx<C> *)smem;
+    int *nbs = (int *)(lk + 72 * sb);
     cx<C> *lds_h = (cx<C> *)smem;
     cx<C> *lds_s = lds_h + ((EPI != EPI_NONE) ? sb * Ls * 12 : 0);
     C *lds_e = (C *)(lds_s + (SELF ? sb * Ls * 12 : 0));
 
+    stage_links<S, C>(a, (long)tile * sb, sb, lk, nbs);
+    __syncthreads();
     cx<C> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; c++) acc[c] = mk(C(0), C(0));
     if (valid) {
-        hop_step<S, C, 0, DAG>(acc, a, cb, s);
-        hop_step<S, C, 1, DAG>(acc, a, cb, s);
-        hop_step<S, C, 2, DAG>(acc, a, cb, s);
-        hop_step<S, C, 3, DAG>(acc, a, cb, s);
-        hop_step<S, C, 4, DAG>(acc, a, cb, s);
-        hop_step<S, C, 5, DAG>(acc, a, cb, s);
-        hop_step<S, C, 6, DAG>(acc, a, cb, s);
-        hop_step<S, C, 7, DAG>(acc, a, cb, s);
+        hop_step<S, C, 0, DAG>(acc, a, lk, nbs, j, sb, s);
+        hop_step<S, C, 1, DAG>(acc, a, lk, nbs, j, sb, s);
+        hop_step<S, C, 2, DAG>(acc, a, lk, nbs, j, sb, s);
+        hop_step<S, C, 3, DAG>(acc, a, lk, nbs, j, sb, s);
+        hop_step<S, C, 4, DAG>(acc, a, lk, nbs, j, sb, s);
+        hop_step<S, C, 5, DAG>(acc, a, lk, nbs, j, sb, s);
+        hop_step<S, C, 6, DAG>(acc, a, lk, nbs, j, sb, s);
+        hop_step<S, C, 7, DAG>(acc, a, lk, nbs, j, sb, s);
     }
+    if constexpr (EPI != EPI_NONE || SELF) __syncthreads();  // the staged links are dead from here
     const C mf = C(a.mf);
     cx<C> own[12];
     if constexpr (SELF) {
@@ -317,6 +420,7 @@ static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field s
     if (sp.epi != EPI_NONE) lds += (size_t)sb * Ls * 12 * sizeof(cx<C>);
     if (sp.self) lds += (size_t)sb * Ls * 12 * sizeof(cx<C>);
     if (sp.epi == EPI_DENSE) lds += 2 * (size_t)Ls * Ls * sizeof(C);
+    lds = std::max(lds, (size_t)sb * (72 * sizeof(cx<C>) + 8 * sizeof(int)));
     dim3 blk(Ls, sb), grid((unsigned)nblk, (unsigned)nb);
     // algorithmic traffic: neighbour spinor, 8 links shared by the Ls slices, output, self input
     const double sbytes = 12.0 * sizeof(typename S::elem) + (S::has_norm ? 4.0 : 0.0);

@@ -210,3 +210,14 @@ def test_dirichlet_mask_zeroes_only_face_links():
         face = (x[:, mu] == L[mu] - 1) & (mu in (0, 2))
         assert np.all(Ud[face, mu] == 0)
         assert np.array_equal(Ud[~face, mu], U[~face, mu])
+
+
+def test_sampled_site_evaluation_matches_full_operators():
+    """The per-site versions used for full-size GPU checks agree with the pinned full operators."""
+    L, Ls = (4, 2, 6, 4), 3
+    P = Params(L, Ls, **MOB, mf=0.04)
+    U, x, _ = _fields(L, Ls, 71)
+    sites = np.array([0, 5, 17, 40, P.V - 1])
+    for dag in (False, True):
+        assert relerr(oracle.hop_sites(P, U, x, sites, dag), oracle.hop(P, U, x, dag)[sites]) < 1e-15
+    assert relerr(oracle.d5_sites(P, U, x, sites), oracle.d5(P, U, x)[sites]) < 1e-14
