@@ -249,7 +249,10 @@ dwf_status dwf_get_site_order(dwf_ctx ctx, int *cx, int *cy, int *cz);
 
 /* Autotuner: times candidate schedules of the fused stencil in storage
  * precision prec on this context's lattice (scratch fields allocated and freed
- * by the call), applies the fastest and, when cache_path is not NULL, stores
+ * by the call): every candidate once, then the four fastest and the current
+ * schedule best-of-three with longer runs.  It applies the fastest, but keeps
+ * the current schedule unless the winner beats it by more than 2% (timing
+ * noise), and, when cache_path is not NULL, stores
  * it in a JSON cache keyed by lattice, Ls, precision and device; a later call
  * with the same key reads the cache instead of timing.  Synchronises the
  * stream.  best_ms (may be NULL) returns the time of the chosen schedule. */
@@ -279,8 +282,10 @@ enum {
 dwf_status dwf_kernel_timing(dwf_ctx ctx, int enable);
 dwf_status dwf_kernel_timing_reset(dwf_ctx ctx);
 /* Per kernel class: launches, summed device time (ms), summed algorithmic
- * bytes and flops.  Synchronises the stream. */
-dwf_status dwf_kernel_stats(dwf_ctx ctx, int kclass, long *launches, double *ms, double *bytes,
+ * bytes and flops, over launches whose fields have storage precision prec
+ * (DWF_F64 .. DWF_BF16), or over all launches of the class (prec = -1).
+ * Synchronises the stream. */
+dwf_status dwf_kernel_stats(dwf_ctx ctx, int kclass, int prec, long *launches, double *ms, double *bytes,
                             double *flops);
 
 #ifdef __cplusplus

@@ -74,7 +74,7 @@ const void *slmat(const Context &c, int op, bool f64)
     return f64 ? (const void *)(c.slmat64 + off) : (const void *)(c.slmat32 + off);
 }
 
-Timer::Timer(Context &c_, int k, double by, double fl) : c(c_), kclass(k), bytes(by), flops(fl)
+Timer::Timer(Context &c_, int k, double by, double fl, int pr) : c(c_), kclass(k), prec(pr), bytes(by), flops(fl)
 {
     if (!c.timing) return;
     if (c.event_pool.empty()) {
@@ -98,7 +98,7 @@ Timer::~Timer()
     hipEvent_t b = c.event_pool.back();
     c.event_pool.pop_back();
     if (hipEventRecord(b, c.stream) != hipSuccess) return;
-    c.pending.push_back(TimedLaunch{kclass, a, b, bytes, flops});
+    c.pending.push_back(TimedLaunch{kclass, prec, a, b, bytes, flops});
 }
 
 static void drain_timing(Context &c)
@@ -108,11 +108,14 @@ static void drain_timing(Context &c)
     for (auto &t : c.pending) {
         float ms = 0;
         HIPCHECK(hipEventElapsedTime(&ms, t.a, t.b));
-        KStats &s = c.stats[t.kclass];
-        s.launches++;
-        s.ms += ms;
-        s.bytes += t.bytes;
-        s.flops += t.flops;
+        for (int k = 0; k < 2; k++) {
+            if (k == 1 && (t.prec < 0 || t.prec > 3)) break;
+            KStats &s = k == 0 ? c.stats[t.kclass] : c.stats_prec[t.kclass][t.prec];
+            s.launches++;
+            s.ms += ms;
+            s.bytes += t.bytes;
+            s.flops += t.flops;
+        }
         c.event_pool.push_back(t.a);
         c.event_pool.push_back(t.b);
     }
@@ -681,16 +684,20 @@ dwf_status dwf_kernel_timing_reset(dwf_ctx ctx)
     dwf::Context &c = C_(ctx);
     drain_timing(c);
     for (auto &s : c.stats) s = KStats{};
+    for (auto &r : c.stats_prec)
+        for (auto &s : r) s = KStats{};
     DWF_API_END
 }
 
-dwf_status dwf_kernel_stats(dwf_ctx ctx, int kclass, long *launches, double *ms, double *bytes, double *flops)
+dwf_status dwf_kernel_stats(dwf_ctx ctx, int kclass, int prec, long *launches, double *ms, double *bytes,
+                            double *flops)
 {
     DWF_API_BEGIN
     dwf::Context &c = C_(ctx);
     if (kclass < 0 || kclass >= DWF_K_NCLASS) fail(DWF_EINVAL, "unknown kernel class");
+    if (prec < -1 || prec > 3) fail(DWF_EINVAL, "unknown precision");
     drain_timing(c);
-    const KStats &s = c.stats[kclass];
+    const KStats &s = prec < 0 ? c.stats[kclass] : c.stats_prec[kclass][prec];
     if (launches) *launches = s.launches;
     if (ms) *ms = s.ms;
     if (bytes) *bytes = s.bytes;

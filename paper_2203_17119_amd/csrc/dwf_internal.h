@@ -52,7 +52,7 @@ struct LaunchCfg {
 // ------------------------------------------------------------ timing
 
 struct TimedLaunch {
-    int kclass;
+    int kclass, prec;
     hipEvent_t a, b;
     double bytes, flops;
 };
@@ -107,6 +107,7 @@ struct Context {
     std::vector<TimedLaunch> pending;
     std::vector<hipEvent_t> event_pool;
     KStats stats[DWF_K_NCLASS];
+    KStats stats_prec[DWF_K_NCLASS][4];
 };
 
 // default 4D sites per workgroup: about 192 lanes
@@ -126,10 +127,11 @@ const void *slmat(const Context &c, int op, bool f64);
 // timing helpers
 struct Timer {
     Context &c;
-    int kclass;
+    int kclass, prec;
     double bytes, flops;
     hipEvent_t a = nullptr;
-    Timer(Context &c_, int k, double by, double fl);
+    // prec: storage precision of the launch's fields, -1 when not specific
+    Timer(Context &c_, int k, double by, double fl, int pr = -1);
     ~Timer();
 };
 

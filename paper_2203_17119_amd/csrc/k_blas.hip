@@ -62,13 +62,23 @@ __global__ void __launch_bounds__(BS) k_dot(Field a, Field b, double *partial)
     }
 }
 
-// fixed-order sum of nparts partials of `width` doubles -> dscal[slot + w]
-__global__ void __launch_bounds__(BS) k_finish(const double *partial, int nparts, int width, double *dscal, int slot)
+// fixed-order sum of nparts partials of `width` doubles -> dscal[slot + w].
+// One workgroup of FBS threads; thread t sums partials t, t + FBS, ... in four
+// interleaved running sums, so the order depends only on nparts.
+static constexpr int FBS = 1024;
+__global__ void __launch_bounds__(FBS) k_finish(const double *partial, int nparts, int width, double *dscal, int slot)
 {
     for (int w = 0; w < width; w++) {
-        double t = 0;
-        for (int k = threadIdx.x; k < nparts; k += BS) t += partial[(long)k * width + w];
-        t = block_sum(t);
+        double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+        int k = threadIdx.x;
+        for (; k + 3 * FBS < nparts; k += 4 * FBS) {
+            t0 += partial[(long)k * width + w];
+            t1 += partial[(long)(k + FBS) * width + w];
+            t2 += partial[(long)(k + 2 * FBS) * width + w];
+            t3 += partial[(long)(k + 3 * FBS) * width + w];
+        }
+        for (; k < nparts; k += FBS) t0 += partial[(long)k * width + w];
+        const double t = block_sum((t0 + t1) + (t2 + t3));
         if (threadIdx.x == 0) dscal[slot + w] = t;
     }
 }
@@ -522,7 +532,7 @@ int launch_dot(Context &c, int prec, Field a, Field b)
 void launch_finish(Context &c, int nparts, int width, int slot)
 {
     Timer tm(c, DWF_K_BLAS, 8.0 * nparts * width, 0);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(BS), 0, c.stream, c.partials, nparts, width, c.dscal, slot);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(FBS), 0, c.stream, c.partials, nparts, width, c.dscal, slot);
     HIPCHECK(hipGetLastError());
 }
 

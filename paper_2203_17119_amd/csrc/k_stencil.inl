@@ -428,7 +428,7 @@ static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field s
                                (double)c.vh * 8 * 9 * sizeof(typename S::elem));
     double flops = nb * (double)c.n5h * 1320.0;
     if (sp.epi == EPI_DENSE) flops += nb * (double)c.n5h * 24.0 * 2.0 * Ls;
-    Timer tm(c, sp.kclass, bytes, flops);
+    Timer tm(c, sp.kclass, bytes, flops, S::prec);
 #define DWF_LAUNCH(E, SF, DG, RD) \
     hipLaunchKernelGGL((k_stencil<S, C, E, SF, DG, RD>), grid, blk, lds, c.stream, a)
 #define DWF_RD(E, SF, DG)            \
@@ -470,7 +470,7 @@ static void launch_slocal_t(Context &c, int op, Field in, Field out, int nbatch,
     const int nb = std::max(1, nbatch);
     const size_t lds = (size_t)sb * Ls * 12 * sizeof(cx<C>) + 2 * (size_t)Ls * Ls * sizeof(C);
     const double sbytes = 12.0 * sizeof(typename S::elem) + (S::has_norm ? 4.0 : 0.0);
-    Timer tm(c, DWF_K_SLOCAL, nb * 2.0 * sbytes * c.n5h, nb * (double)c.n5h * 48.0 * Ls);
+    Timer tm(c, DWF_K_SLOCAL, nb * 2.0 * sbytes * c.n5h, nb * (double)c.n5h * 48.0 * Ls, S::prec);
     hipLaunchKernelGGL((k_slocal<S, C>), dim3((unsigned)nblk, (unsigned)nb), dim3(Ls, sb), lds, c.stream, in, out,
                        (const C *)slmat(c, op, sizeof(C) == 8), c.vh, Ls, c.cfg_slocal.run, nb > 1 ? bstride : 0L);
     HIPCHECK(hipGetLastError());

@@ -97,7 +97,7 @@ SIGNATURES = {
     "dwf_stream_copy": ([_CTX, _P, _P, C.c_size_t], C.c_int32),
     "dwf_kernel_timing": ([_CTX, _I], C.c_int32),
     "dwf_kernel_timing_reset": ([_CTX], C.c_int32),
-    "dwf_kernel_stats": ([_CTX, _I, C.POINTER(C.c_long), C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)], C.c_int32),
+    "dwf_kernel_stats": ([_CTX, _I, _I, C.POINTER(C.c_long), C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)], C.c_int32),
 }
 
 _lib = None
@@ -349,9 +349,10 @@ def dwf_kernel_timing_reset(ctx):
     _check(load().dwf_kernel_timing_reset(ctx))
 
 
-def dwf_kernel_stats(ctx, kclass):
+def dwf_kernel_stats(ctx, kclass, prec=-1):
     n, ms, by, fl = C.c_long(), C.c_double(), C.c_double(), C.c_double()
-    _check(load().dwf_kernel_stats(ctx, int(kclass), C.byref(n), C.byref(ms), C.byref(by), C.byref(fl)))
+    _check(load().dwf_kernel_stats(ctx, int(kclass), int(prec), C.byref(n), C.byref(ms), C.byref(by),
+                                   C.byref(fl)))
     return {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
 
 
