@@ -216,8 +216,10 @@ dwf_status dwf_net_train_step(dwf_net net, int nbatch, const double *const *b_od
 /* Flexible GCR(m) on the odd Schur system Mpc x_o = b~_o (o->normal = 0) or on
  * Mpc^+ Mpc x_o = Mpc^+ b~_o (o->normal = 1), right-preconditioned by net
  * (NULL: plain GCR; normal equations use N N^+), FP64 vectors, restart every
- * o->restart steps with the residual recomputed.  On stagnation or a
- * non-finite residual it falls back to dwf_cg in FP64 when o->fallback (the
+ * o->restart steps (default 16, at most 64) with the residual recomputed.
+ * Stagnation means no 10% reduction of the residual norm over max(8 m, 256)
+ * steps.  On stagnation or a non-finite residual it falls back to dwf_cg in
+ * FP64 when o->fallback (the
  * statistics then say fell_back = 1).  Same source preparation and
  * reconstruction as dwf_cg; canonical FP64 full fields. */
 dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, double *x_full, const dwf_solver_opts *o,

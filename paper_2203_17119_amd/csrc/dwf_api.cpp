@@ -186,6 +186,32 @@ static void build_slocal(Context &c)
     setop(SL_E1, mul(blocks[2 * SL_A], blocks[2 * SL_MINV]), mul(blocks[2 * SL_A + 1], blocks[2 * SL_MINV + 1]));
     setop(SL_E2, mul(blocks[2 * SL_MINVDAG], blocks[2 * SL_ADAG]),
           mul(blocks[2 * SL_MINVDAG + 1], blocks[2 * SL_ADAG + 1]));
+    // twisted-circulant operators (polynomials in the shift, per chirality):
+    // T[t][s] = f_{t-s} (t >= s), -mf f_{t-s+n} (t < s), the other block T^T
+    auto twisted = [&](const std::vector<double> &T, const std::vector<double> &O, double *f) {
+        double scale = 0;
+        for (double v : T) scale = std::max(scale, std::fabs(v));
+        if (scale == 0) return false;
+        for (int k = 0; k < n; k++) f[k] = T[idx(k, 0)];
+        for (int t = 0; t < n; t++)
+            for (int col = 0; col < n; col++) {
+                const double want = t >= col ? f[t - col] : -mf * f[t - col + n];
+                if (std::fabs(T[idx(t, col)] - want) > 1e-12 * scale) return false;
+                if (std::fabs(O[idx(col, t)] - T[idx(t, col)]) > 1e-12 * scale) return false;
+            }
+        return true;
+    };
+    for (int op = 0; op < SL_NOP; op++) {
+        c.toep_ok[op] = false;
+        c.toep_rev[op] = 0;
+        if (n > 16) continue;
+        if (twisted(blocks[2 * op], blocks[2 * op + 1], c.toep_f[op])) {
+            c.toep_ok[op] = true;
+        } else if (twisted(blocks[2 * op + 1], blocks[2 * op], c.toep_f[op])) {
+            c.toep_ok[op] = true;
+            c.toep_rev[op] = 1;
+        }
+    }
     std::vector<double> h64;
     std::vector<float> h32;
     for (auto &bl : blocks)
@@ -245,8 +271,9 @@ Field ws_batch(Context &c, const std::string &name, int prec, int nbatch)
 }
 
 int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduce, bool in_is_A_applied, Field pa,
-              int nbatch, long bstride)
+              int nbatch, long bstride, int alpha_slot)
 {
+    if (alpha_slot >= 0 && (!dagger || nbatch > 1)) fail(DWF_EINVAL, "fused residual update needs Mpc^+, one field");
     ensure_links(c, prec);
     const int nb = std::max(1, nbatch);
     Field y = ws_batch(c, "mpc_y", prec, nb);
@@ -296,7 +323,9 @@ int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduc
     s2.s1 = c.e;
     s2.sdag = true;
     s2.tau = -0.25;
-    s2.reduce = reduce;
+    s2.reduce = reduce || alpha_slot >= 0;
+    s2.cg_update = alpha_slot >= 0;
+    s2.alpha_slot = alpha_slot;
     batched(s2);
     return launch_stencil(c, prec, s2, y, in, out);
 }

@@ -64,7 +64,7 @@ __host__ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
 enum Prec { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
 
 // epilogue kinds of the fused stencil
-enum EpiKind { EPI_NONE = 0, EPI_DENSE = 1, EPI_SHIFT = 2 };
+enum EpiKind { EPI_NONE = 0, EPI_DENSE = 1, EPI_SHIFT = 2, EPI_TOEP = 3 };
 
 struct F64 {
     using elem = double2;

@@ -83,6 +83,11 @@ struct Context {
     int order[3] = {0, 0, 0};
     void *links[4][2] = {};      // [prec][parity] -> [8][9][vh] elements
     double *slmat64 = nullptr;   // [SL_NOP][2][Ls][Ls]
+    // operators that are twisted-circulant on one chirality block (first column
+    // toep_f) and its transpose on the other; toep_rev: the P+ block is the transpose
+    bool toep_ok[SL_NOP] = {};
+    int toep_rev[SL_NOP] = {};
+    double toep_f[SL_NOP][16] = {};
     float *slmat32 = nullptr;
     double *gauge_canon = nullptr;  // canonical FP64 gauge, kept to rebuild low-precision links
 
@@ -166,6 +171,8 @@ struct StencilSpec {
     bool sdag = false;
     double sigma = 1.0, tau = 1.0;
     bool reduce = false;      // per-workgroup |out|^2 partials into c.partials
+    bool cg_update = false;   // out = out - dscal[alpha_slot] * result (needs reduce)
+    int alpha_slot = -1;
     int kclass = DWF_K_STENCIL;
     int nbatch = 1;           // fields processed in one launch (blockIdx.y), member k of
     long bstride = 0;         // in/self/out at data + k*bstride bytes; partials [k][block]
@@ -223,7 +230,11 @@ inline int accum_prec(int prec) { return (prec == P_F16 || prec == P_BF16) ? P_F
 // x in accum_prec(prec), the others in prec)
 int launch_cg_update_xr(Context &c, int prec, Field x, Field r, Field p, Field ap, int ia);
 // p = r + beta p ; pa = A p (A = b + c P5)                 (beta = dscal[ib])
-void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pa, int ib);
+// p = r + beta p, pa = A p (beta = dscal[ib]); with ia >= 0 first x += alpha p
+// (alpha = dscal[ia], x in the accumulator precision of prec)
+void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pa, int ib, Field x = Field{}, int ia = -1);
+// x += dscal[ia] p, x in the accumulator precision of prec
+void launch_axpy_dev(Context &c, int prec, Field x, Field p, int ia);
 // device scalar arithmetic: dscal[out] = dscal[num] / dscal[den]
 void launch_scalar_div(Context &c, int out, int num, int den);
 // r_h = b - ax (FP64), partials of |r_h|^2
@@ -240,9 +251,12 @@ void launch_stream_copy(Context &c, const void *src, void *dst, size_t bytes);
 // ---------------------------------------------------------------- Mpc helpers
 
 // out = Mpc in (dagger: Mpc^+) in precision prec, using workspaces of that
-// precision; if reduce, partials of |out|^2 are written and their count returned
+// precision; if reduce, partials of |out|^2 are written and their count returned.
+// With dagger and alpha_slot >= 0 the result is not stored: out holds a
+// residual r on entry and becomes r - dscal[alpha_slot] Mpc^+ in, with the
+// partials of its |r|^2 (reduce implied).
 int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduce, bool in_is_A_applied = false,
-              Field pa = Field{}, int nbatch = 1, long bstride = 0);
+              Field pa = Field{}, int nbatch = 1, long bstride = 0, int alpha_slot = -1);
 
 }  // namespace dwf
 

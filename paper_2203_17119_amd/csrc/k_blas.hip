@@ -167,10 +167,12 @@ __global__ void __launch_bounds__(BS) k_cg_update_xr(Field x, Field r, Field p, 
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// p = r + beta p ; pa = (b + c P5) p   (workgroup = Ls x sb lanes, one 4D site per row)
-template <typename S>
-__global__ void __launch_bounds__(256) k_cg_update_p(Field r, Field p, Field pa, const double *dscal, int ib, long vh,
-                                                     int Ls, double bb, double cc, double mf)
+// p = r + beta p ; pa = (b + c P5) p   (workgroup = Ls x sb lanes, one 4D site per row).
+// With ia >= 0 the solution update of the same iteration is folded in first:
+// x += alpha p (old p), x in storage precision SX.
+template <typename S, typename SX>
+__global__ void __launch_bounds__(256) k_cg_update_p(Field r, Field p, Field pa, Field x, const double *dscal, int ib,
+                                                     int ia, long vh, int Ls, double bb, double cc, double mf)
 {
     using C = Cof<S>;
     const int s = threadIdx.x, j = threadIdx.y, sb = blockDim.y;
@@ -183,8 +185,15 @@ __global__ void __launch_bounds__(256) k_cg_update_p(Field r, Field p, Field pa,
     cx<C> pv[12];
     if (valid) {
         cx<C> rv[12];
-        load_spinor<S, C>(r, i, rv);
         load_spinor<S, C>(p, i, pv);
+        if (ia >= 0) {
+            const C alpha = C(dscal[ia]);
+            cx<C> xv[12];
+            load_spinor<SX, C>(x, i, xv);
+            for (int c = 0; c < 12; c++) xv[c] = xv[c] + alpha * pv[c];
+            store_spinor<SX, C>(x, i, xv);
+        }
+        load_spinor<S, C>(r, i, rv);
         for (int c = 0; c < 12; c++) pv[c] = rv[c] + beta * pv[c];
         store_spinor<S, C>(p, i, pv);
     } else {
@@ -197,6 +206,21 @@ __global__ void __launch_bounds__(256) k_cg_update_p(Field r, Field p, Field pa,
     cx<C> out[12];
     for (int c = 0; c < 12; c++) out[c] = C(bb) * pv[c] + C(cc) * shift5<C>(blk, c, s, Ls, false, C(mf));
     store_spinor<S, C>(pa, i, out);
+}
+
+// x += alpha p with alpha = dscal[ia]; x in storage precision SX
+template <typename S, typename SX>
+__global__ void __launch_bounds__(BS) k_axpy_dev(Field x, Field p, const double *dscal, int ia)
+{
+    using C = Cof<S>;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    if (i >= x.n) return;
+    const C alpha = C(dscal[ia]);
+    cx<C> xv[12], pv[12];
+    load_spinor<SX, C>(x, i, xv);
+    load_spinor<S, C>(p, i, pv);
+    for (int c = 0; c < 12; c++) xv[c] = xv[c] + alpha * pv[c];
+    store_spinor<SX, C>(x, i, xv);
 }
 
 // r = b - ax in FP64 ; partial |r|^2
@@ -583,16 +607,35 @@ int launch_cg_update_xr(Context &c, int prec, Field x, Field r, Field p, Field a
     return (int)nb;
 }
 
-void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pa, int ib)
+// the low-precision vector kernels pair storage precision S with the
+// accumulator precision of the solution (FP64 with FP64, FP32 otherwise)
+#define DWF_DISPATCH_X(prec, KERNEL, grid, blk, lds, ...)                                                      \
+    switch (prec) {                                                                                            \
+    case P_F64: hipLaunchKernelGGL((KERNEL<F64, F64>), grid, blk, lds, c.stream, __VA_ARGS__); break;          \
+    case P_F32: hipLaunchKernelGGL((KERNEL<F32, F32>), grid, blk, lds, c.stream, __VA_ARGS__); break;          \
+    case P_F16: hipLaunchKernelGGL((KERNEL<F16, F32>), grid, blk, lds, c.stream, __VA_ARGS__); break;          \
+    default: hipLaunchKernelGGL((KERNEL<BF16, F32>), grid, blk, lds, c.stream, __VA_ARGS__); break;            \
+    }                                                                                                          \
+    HIPCHECK(hipGetLastError())
+
+void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pa, int ib, Field x, int ia)
 {
     const int Ls = c.Ls;
     const int sb = default_sb(c);
     const long nblk = (c.vh + sb - 1) / sb;
     const size_t csz = (prec == P_F64) ? 16 : 8;
     const size_t lds = (size_t)sb * Ls * 12 * csz;
-    Timer tm(c, DWF_K_BLAS, 4 * sbytes(prec) * c.n5h, 96.0 * c.n5h);
-    DWF_DISPATCH(prec, k_cg_update_p, dim3((unsigned)nblk), dim3(Ls, sb), lds, r, p, pa, c.dscal, ib, c.vh, Ls,
-                 c.p.b, c.p.c, c.p.mf);
+    if (ia >= 0 && !x.data) fail(DWF_EINVAL, "solution update needs x");
+    const double xb = ia >= 0 ? 2 * sbytes(accum_prec(prec)) : 0.0;
+    Timer tm(c, DWF_K_BLAS, (4 * sbytes(prec) + xb) * c.n5h, 96.0 * c.n5h, prec);
+    DWF_DISPATCH_X(prec, k_cg_update_p, dim3((unsigned)nblk), dim3(Ls, sb), lds, r, p, pa, x, c.dscal, ib, ia, c.vh,
+                   Ls, c.p.b, c.p.c, c.p.mf);
+}
+
+void launch_axpy_dev(Context &c, int prec, Field x, Field p, int ia)
+{
+    Timer tm(c, DWF_K_BLAS, (sbytes(prec) + 2 * sbytes(accum_prec(prec))) * x.n, 48.0 * x.n, prec);
+    DWF_DISPATCH_X(prec, k_axpy_dev, g1(x.n), dim3(BS), 0, x, p, c.dscal, ia);
 }
 
 int launch_residual(Context &c, Field b, Field ax, Field r)

@@ -16,8 +16,22 @@
 // load the same link addresses, so each link is fetched from memory once per
 // workgroup and reused for every s.  Fifth-dimension operators (Epi, Self)
 // need every s of a site and run from LDS after one barrier:
-//   Epi  = dense Ls x Ls matrix per chirality, or e0 + e1 P5 (P5^+)
+//   Epi  = dense Ls x Ls matrix per chirality, or e0 + e1 P5 (P5^+), or a
+//          Toeplitz operator (see below)
 //   Self = s0 + s1 P5 (P5^+) on a second input at the output site.
+//
+// Toeplitz epilogue.  A A Mee^-1-type operator is, on each chirality, a
+// polynomial in the twisted shift S (row s takes s-1, S^Ls = -mf): with first
+// column f_k it is  T[t][s'] = f_{t-s'} (t >= s'),  -mf f_{t-s'+Ls} (t < s'),
+// and the other chirality is T^T = J T J (J reverses s).  The hop results are
+// transposed through LDS so that one lane holds one spin-colour component of
+// a site for every s (components of the transposed chirality stored in
+// reversed s order), applies T from registers with uniform coefficients, and
+// transposes back: four LDS passes of one spinor per lane instead of Ls.
+//
+// Reductions: RED = 1 writes per-workgroup partials of |out|^2; RED = 2 is the
+// conjugate-gradient residual update out = out - alpha * result (alpha read
+// from device memory) with partials of the updated |out|^2.
 #include "dwf_common.h"
 
 namespace dwf {
@@ -34,6 +48,9 @@ struct StencilKArgs {
     int edag, sdag;
     double *partial;
     long bstride;  // bytes between batch members (blockIdx.y), 0 for one field
+    double tcoef[32];      // Toeplitz epilogue: f_k (k < Ls), then -mf f_k
+    int trev;              // Toeplitz epilogue: P+ components use reversed s order
+    const double *alpha;   // RED = 2: device pointer to alpha
 };
 
 // half-spinor projection h = upper pair of (1 + P g_MU) v
@@ -227,7 +244,25 @@ __device__ __forceinline__ Field batch_member(Field f, long stride)
     return f;
 }
 
-template <typename S, typename C, int EPI, bool SELF, bool DAG, bool RED>
+// o = T a for the twisted-circulant T of first column f (g = -mf f)
+template <typename C, int LSC>
+__device__ __forceinline__ void toeplitz_apply(const cx<C> av[LSC], cx<C> o[LSC], const C f[LSC], const C g[LSC])
+{
+#pragma unroll
+    for (int t = 0; t < LSC; t++) {
+        cx<C> v = mk(C(0), C(0));
+#pragma unroll
+        for (int k = 0; k < LSC; k++) {
+            const C w = (k <= t) ? f[k] : g[k];
+            const cx<C> x = (k <= t) ? av[t - k] : av[t - k + LSC];
+            v.re = fma(w, x.re, v.re);
+            v.im = fma(w, x.im, v.im);
+        }
+        o[t] = v;
+    }
+}
+
+template <typename S, typename C, int EPI, bool SELF, bool DAG, int RED, int LSC>
 __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
 {
     a.in = batch_member(a.in, a.bstride);
@@ -277,58 +312,103 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
             for (int c = 0; c < 12; c++) own[c] = mk(C(0), C(0));
         }
     }
-    if constexpr (EPI != EPI_NONE || SELF) {
-        cx<C> *bh = lds_h + (j * Ls + s) * 12;
-        cx<C> *bs = lds_s + (j * Ls + s) * 12;
-#pragma unroll
-        for (int c = 0; c < 12; c++) {
-            if constexpr (EPI != EPI_NONE) bh[c] = acc[c];
-            if constexpr (SELF) bs[c] = own[c];
-        }
-        if constexpr (EPI == EPI_DENSE) {
-            const C *em = (const C *)a.emat;
-            const int tid = threadIdx.x + blockDim.x * threadIdx.y;
-            for (int k = tid; k < 2 * Ls * Ls; k += blockDim.x * blockDim.y) lds_e[k] = em[k];
-        }
-        __syncthreads();
-    }
     cx<C> res[12];
     const C tau = C(a.tau);
-    if constexpr (EPI == EPI_NONE) {
+    if constexpr (EPI == EPI_TOEP) {
+        static_assert(!SELF && LSC > 0 && LSC <= 16, "Toeplitz epilogue: no self term, 1 <= Ls <= 16");
+        // rows [site j][component c] of LSC values, padded by 16 bytes against bank conflicts
+        constexpr int RS = LSC + 16 / (int)sizeof(cx<C>);
+        cx<C> *rows = lds_h + j * 12 * RS;
+        const bool rp = a.trev != 0;
 #pragma unroll
-        for (int c = 0; c < 12; c++) res[c] = tau * acc[c];
-    } else if constexpr (EPI == EPI_DENSE) {
-        const cx<C> *blk = lds_h + j * Ls * 12;
-        const C *Mu = lds_e + s * Ls;            // P+ block row s
-        const C *Ml = lds_e + Ls * Ls + s * Ls;  // P- block row s
+        for (int c = 0; c < 12; c++) {
+            const bool rev = (c < 6) ? rp : !rp;
+            rows[c * RS + (rev ? LSC - 1 - s : s)] = acc[c];
+        }
+        __syncthreads();
+        C f[LSC], g[LSC];
 #pragma unroll
-        for (int c = 0; c < 12; c++) res[c] = mk(C(0), C(0));
-        for (int t = 0; t < Ls; t++) {
-            const C mu = Mu[t], ml = Ml[t];
+        for (int k = 0; k < LSC; k++) {
+            f[k] = C(a.tcoef[k]);
+            g[k] = C(a.tcoef[16 + k]);
+        }
+        for (int c = s; c < 12; c += LSC) {
+            cx<C> av[LSC], o[LSC];
+#pragma unroll
+            for (int t = 0; t < LSC; t++) av[t] = rows[c * RS + t];
+            toeplitz_apply<C, LSC>(av, o, f, g);
+#pragma unroll
+            for (int t = 0; t < LSC; t++) rows[c * RS + t] = o[t];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            const bool rev = (c < 6) ? rp : !rp;
+            res[c] = tau * rows[c * RS + (rev ? LSC - 1 - s : s)];
+        }
+    } else {
+        if constexpr (EPI != EPI_NONE || SELF) {
+            cx<C> *bh = lds_h + (j * Ls + s) * 12;
+            cx<C> *bs = lds_s + (j * Ls + s) * 12;
 #pragma unroll
             for (int c = 0; c < 12; c++) {
-                const C m = (c < 6) ? mu : ml;
-                const cx<C> v = blk[t * 12 + c];
-                res[c].re = fma(m, v.re, res[c].re);
-                res[c].im = fma(m, v.im, res[c].im);
+                if constexpr (EPI != EPI_NONE) bh[c] = acc[c];
+                if constexpr (SELF) bs[c] = own[c];
             }
+            if constexpr (EPI == EPI_DENSE) {
+                const C *em = (const C *)a.emat;
+                const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+                for (int k = tid; k < 2 * Ls * Ls; k += blockDim.x * blockDim.y) lds_e[k] = em[k];
+            }
+            __syncthreads();
         }
+        if constexpr (EPI == EPI_NONE) {
 #pragma unroll
-        for (int c = 0; c < 12; c++) res[c] = tau * res[c];
-    } else {
-        const cx<C> *blk = lds_h + j * Ls * 12;
-        const C e0 = C(a.e0), e1 = C(a.e1);
+            for (int c = 0; c < 12; c++) res[c] = tau * acc[c];
+        } else if constexpr (EPI == EPI_DENSE) {
+            const cx<C> *blk = lds_h + j * Ls * 12;
+            const C *Mu = lds_e + s * Ls;            // P+ block row s
+            const C *Ml = lds_e + Ls * Ls + s * Ls;  // P- block row s
 #pragma unroll
-        for (int c = 0; c < 12; c++) res[c] = tau * (e0 * acc[c] + e1 * shift5<C>(blk, c, s, Ls, a.edag, mf));
+            for (int c = 0; c < 12; c++) res[c] = mk(C(0), C(0));
+            for (int t = 0; t < Ls; t++) {
+                const C mu = Mu[t], ml = Ml[t];
+#pragma unroll
+                for (int c = 0; c < 12; c++) {
+                    const C m = (c < 6) ? mu : ml;
+                    const cx<C> v = blk[t * 12 + c];
+                    res[c].re = fma(m, v.re, res[c].re);
+                    res[c].im = fma(m, v.im, res[c].im);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 12; c++) res[c] = tau * res[c];
+        } else {
+            const cx<C> *blk = lds_h + j * Ls * 12;
+            const C e0 = C(a.e0), e1 = C(a.e1);
+#pragma unroll
+            for (int c = 0; c < 12; c++) res[c] = tau * (e0 * acc[c] + e1 * shift5<C>(blk, c, s, Ls, a.edag, mf));
+        }
+        if constexpr (SELF) {
+            const cx<C> *blk = lds_s + j * Ls * 12;
+            const C s0 = C(a.s0), s1 = C(a.s1), sg = C(a.sigma);
+#pragma unroll
+            for (int c = 0; c < 12; c++)
+                res[c] = res[c] + sg * (s0 * own[c] + s1 * shift5<C>(blk, c, s, Ls, a.sdag, mf));
+        }
     }
-    if constexpr (SELF) {
-        const cx<C> *blk = lds_s + j * Ls * 12;
-        const C s0 = C(a.s0), s1 = C(a.s1), sg = C(a.sigma);
+    if constexpr (RED == 2) {
+        // conjugate-gradient residual update: out holds r on entry
+        const C al = C(*a.alpha);
+        if (valid) {
+            cx<C> rv[12];
+            load_spinor<S, C>(a.out, i, rv);
 #pragma unroll
-        for (int c = 0; c < 12; c++) res[c] = res[c] + sg * (s0 * own[c] + s1 * shift5<C>(blk, c, s, Ls, a.sdag, mf));
+            for (int c = 0; c < 12; c++) res[c] = rv[c] - al * res[c];
+        }
     }
     if (valid) store_spinor<S, C>(a.out, i, res);
-    if constexpr (RED) {
+    if constexpr (RED != 0) {
         double n2 = 0;
         if (valid) {
 #pragma unroll
@@ -405,7 +485,24 @@ static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field s
     a.vh = c.vh;
     a.Ls = Ls;
     a.run = c.cfg_stencil.run;
-    a.emat = (sp.epi == EPI_DENSE) ? slmat(c, sp.epi_op, sizeof(C) == 8) : nullptr;
+    // a dense epilogue whose operator is twisted-circulant runs as the Toeplitz epilogue
+    int epi = sp.epi;
+    const bool toep = epi == EPI_DENSE && sp.epi_op >= 0 && sp.epi_op < SL_NOP && c.toep_ok[sp.epi_op] &&
+                      (Ls == 8 || Ls == 12 || Ls == 16) && !sp.self && !sp.reduce && !sp.cg_update;
+    if (toep) epi = EPI_TOEP;
+    a.emat = (epi == EPI_DENSE) ? slmat(c, sp.epi_op, sizeof(C) == 8) : nullptr;
+    if (toep) {
+        for (int k = 0; k < 16; k++) {
+            a.tcoef[k] = k < Ls ? c.toep_f[sp.epi_op][k] : 0.0;
+            a.tcoef[16 + k] = k < Ls ? -c.p.mf * c.toep_f[sp.epi_op][k] : 0.0;
+        }
+        a.trev = c.toep_rev[sp.epi_op];
+    } else {
+        for (double &t : a.tcoef) t = 0.0;
+        a.trev = 0;
+    }
+    a.alpha = sp.cg_update ? c.dscal + sp.alpha_slot : nullptr;
+    if (sp.cg_update && (sp.alpha_slot < 0 || !sp.reduce)) fail(DWF_EINVAL, "residual update needs alpha and reduce");
     a.e0 = sp.e0;
     a.e1 = sp.e1;
     a.s0 = sp.s0;
@@ -417,46 +514,75 @@ static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field s
     a.sdag = sp.sdag;
     a.partial = c.partials;
     size_t lds = 0;
-    if (sp.epi != EPI_NONE) lds += (size_t)sb * Ls * 12 * sizeof(cx<C>);
+    if (epi == EPI_TOEP) lds += (size_t)sb * 12 * (Ls * sizeof(cx<C>) + 16);
+    else if (epi != EPI_NONE) lds += (size_t)sb * Ls * 12 * sizeof(cx<C>);
     if (sp.self) lds += (size_t)sb * Ls * 12 * sizeof(cx<C>);
-    if (sp.epi == EPI_DENSE) lds += 2 * (size_t)Ls * Ls * sizeof(C);
+    if (epi == EPI_DENSE) lds += 2 * (size_t)Ls * Ls * sizeof(C);
     lds = std::max(lds, (size_t)sb * (72 * sizeof(cx<C>) + 8 * sizeof(int)));
     dim3 blk(Ls, sb), grid((unsigned)nblk, (unsigned)nb);
-    // algorithmic traffic: neighbour spinor, 8 links shared by the Ls slices, output, self input
+    // algorithmic traffic: neighbour spinor, 8 links shared by the Ls slices,
+    // output, self input, residual input of the fused update
     const double sbytes = 12.0 * sizeof(typename S::elem) + (S::has_norm ? 4.0 : 0.0);
-    const double bytes = nb * ((double)c.n5h * (2 * sbytes + (sp.self ? sbytes : 0.0)) +
-                               (double)c.vh * 8 * 9 * sizeof(typename S::elem));
+    const double bytes =
+        nb * ((double)c.n5h * (2 * sbytes + (sp.self ? sbytes : 0.0) + (sp.cg_update ? sbytes : 0.0)) +
+              (double)c.vh * 8 * 9 * sizeof(typename S::elem));
     double flops = nb * (double)c.n5h * 1320.0;
     if (sp.epi == EPI_DENSE) flops += nb * (double)c.n5h * 24.0 * 2.0 * Ls;
     Timer tm(c, sp.kclass, bytes, flops, S::prec);
-#define DWF_LAUNCH(E, SF, DG, RD) \
-    hipLaunchKernelGGL((k_stencil<S, C, E, SF, DG, RD>), grid, blk, lds, c.stream, a)
-#define DWF_RD(E, SF, DG)            \
-    if (sp.reduce)                    \
-        DWF_LAUNCH(E, SF, DG, true);  \
-    else                              \
-        DWF_LAUNCH(E, SF, DG, false);
-#define DWF_DG(E, SF)             \
-    if (sp.dagger) {              \
-        DWF_RD(E, SF, true)       \
-    } else {                      \
-        DWF_RD(E, SF, false)      \
+    const int red = sp.cg_update ? 2 : (sp.reduce ? 1 : 0);
+#define DWF_K(E, SF, DG, RD, LS) hipLaunchKernelGGL((k_stencil<S, C, E, SF, DG, RD, LS>), grid, blk, lds, c.stream, a)
+#define DWF_DG(E, SF, RD, LS)        \
+    if (sp.dagger)                   \
+        DWF_K(E, SF, true, RD, LS);  \
+    else                             \
+        DWF_K(E, SF, false, RD, LS);
+    bool done = true;
+    if (epi == EPI_TOEP) {
+        if (Ls == 8) {
+            DWF_DG(EPI_TOEP, false, 0, 8)
+        } else if (Ls == 12) {
+            DWF_DG(EPI_TOEP, false, 0, 12)
+        } else {
+            DWF_DG(EPI_TOEP, false, 0, 16)
+        }
+    } else if (epi == EPI_NONE) {
+        if (sp.self) {
+            if (red == 1) {
+                DWF_DG(EPI_NONE, true, 1, 0)
+            } else if (red == 0) {
+                DWF_DG(EPI_NONE, true, 0, 0)
+            } else {
+                done = false;
+            }
+        } else {
+            if (red == 1) {
+                DWF_DG(EPI_NONE, false, 1, 0)
+            } else if (red == 0) {
+                DWF_DG(EPI_NONE, false, 0, 0)
+            } else {
+                done = false;
+            }
+        }
+    } else if (epi == EPI_DENSE) {
+        if (!sp.self && red == 0) {
+            DWF_DG(EPI_DENSE, false, 0, 0)
+        } else {
+            done = false;
+        }
+    } else if (epi == EPI_SHIFT && sp.self) {
+        if (red == 2) {
+            DWF_DG(EPI_SHIFT, true, 2, 0)
+        } else if (red == 1) {
+            DWF_DG(EPI_SHIFT, true, 1, 0)
+        } else {
+            DWF_DG(EPI_SHIFT, true, 0, 0)
+        }
+    } else {
+        done = false;
     }
-#define DWF_SF(E)            \
-    if (sp.self) {           \
-        DWF_DG(E, true)      \
-    } else {                 \
-        DWF_DG(E, false)     \
-    }
-    switch (sp.epi) {
-    case EPI_NONE: DWF_SF(EPI_NONE) break;
-    case EPI_DENSE: DWF_SF(EPI_DENSE) break;
-    default: DWF_SF(EPI_SHIFT) break;
-    }
-#undef DWF_SF
 #undef DWF_DG
-#undef DWF_RD
-#undef DWF_LAUNCH
+#undef DWF_K
+    if (!done) fail(DWF_EINVAL, "unsupported fused stencil stage");
     HIPCHECK(hipGetLastError());
     return sp.reduce ? (int)nblk : 0;
 }

@@ -441,8 +441,8 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
             if (rn < 0.9 * best) {
                 best = rn;
                 since_best = 0;
-            } else if (++since_best > 8 * m) {
-                stalled = true;  // no progress over many restart cycles
+            } else if (++since_best > std::max(8 * m, 256)) {
+                stalled = true;  // no 10% progress over many restart cycles
                 break;
             }
             if (rn <= tol * bn) break;

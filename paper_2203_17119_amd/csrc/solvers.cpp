@@ -138,20 +138,36 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
         return st;
     }
     const int maxi = maxit > 0 ? maxit : 100000;
+    // Unshifted systems fuse the residual update into the last stencil stage
+    // (r -= alpha Mpc^+ Mpc p without storing the product) and defer the
+    // solution update x += alpha p to the next p-update kernel, which reads p
+    // anyway; before a reliable update or the exit it is applied on its own.
+    const bool fused = sigma == 0.0;
     while (st.iters < maxi) {
-        normal_op(c, lp, sigma, p, ap, m, true, pa);
-        launch_scalar_div(c, S_ALPHA, S_RHO, S_PAP);
-        const int np = launch_cg_update_xr(c, lp, xl, r, p, ap, S_ALPHA);
-        launch_finish(c, np, 1, S_RHONEW);
+        if (fused) {
+            const int npm = apply_mpc(c, lp, false, p, m, true, true, pa);
+            launch_finish(c, npm, 1, S_PAP);  // <p, Mpc^+ Mpc p> = |Mpc p|^2
+            launch_scalar_div(c, S_ALPHA, S_RHO, S_PAP);
+            const int np = apply_mpc(c, lp, true, m, r, false, false, Field{}, 1, 0, S_ALPHA);
+            launch_finish(c, np, 1, S_RHONEW);
+        } else {
+            normal_op(c, lp, sigma, p, ap, m, true, pa);
+            launch_scalar_div(c, S_ALPHA, S_RHO, S_PAP);
+            const int np = launch_cg_update_xr(c, lp, xl, r, p, ap, S_ALPHA);
+            launch_finish(c, np, 1, S_RHONEW);
+        }
         read_scalars(c, S_RHONEW, 1);
         double rho1 = c.hscal[S_RHONEW];
         st.iters++;
         if (!std::isfinite(rho1)) fail(DWF_ENOCONV, "CG breakdown: non-finite residual");
         const double rn = std::sqrt(rho1);
         bool done = false;
+        bool x_pending = fused;  // x += alpha p of this iteration not yet applied
         if (mixed && (rn < delta * rmax || rn <= target)) {
             // reliable update: fold the low-precision solution into x and
             // recompute the residual exactly
+            if (x_pending) launch_axpy_dev(c, lp, xl, p, S_ALPHA);
+            x_pending = false;
             launch_accumulate_low(c, xp, x, xl);
             rho1 = true_residual();
             launch_convert(c, P_F64, rh, lp, r);
@@ -161,13 +177,14 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
         } else if (!mixed && rn <= target) {
             done = true;
         }
-        if (done) {
-            st.converged = 1;
+        if (done || st.iters >= maxi) {
+            if (x_pending) launch_axpy_dev(c, lp, xl, p, S_ALPHA);
+            if (done) st.converged = 1;
             break;
         }
         launch_scalar_div(c, S_BETA, S_RHONEW, S_RHO);
         launch_scalar_div(c, S_RHO, S_RHONEW, S_ONE);
-        launch_cg_update_p(c, lp, r, p, pa, S_BETA);
+        launch_cg_update_p(c, lp, r, p, pa, S_BETA, xl, x_pending ? S_ALPHA : -1);
     }
     if (mixed && !st.converged) launch_accumulate_low(c, xp, x, xl);
     // final FP64 check

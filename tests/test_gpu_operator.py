@@ -15,8 +15,12 @@ from gpu_helpers import TOL, Case, relerr, to_gpu, to_host, torch
 
 pytestmark = pytest.mark.gpu
 
+# Ls = 8, 12 and 16 run the Toeplitz (twisted-circulant) form of the dense
+# fifth-dimension epilogue, the others the general dense form.
 CASES = {
     "4^4x8_periodic": dict(dims=(4, 4, 4, 4), Ls=8, eps=0.4, seed=1001),
+    "2x4x2x4_ls16_dirichlet": dict(dims=(2, 4, 2, 4), Ls=16, dirichlet=(0, 1, 0, 1), mf=0.03, seed=33),
+    "4x2x2x2_ls12": dict(dims=(4, 2, 2, 2), Ls=12, mf=0.2, seed=34),
     "4x6x2x8_ls5_dirichlet": dict(dims=(4, 6, 2, 8), Ls=5, dirichlet=(1, 0, 1, 1), mf=0.07, seed=31),
     "2x2x2x2_ls3": dict(dims=(2, 2, 2, 2), Ls=3, dirichlet=(0, 0, 0, 1), seed=32),
 }
