@@ -19,7 +19,8 @@ Printed JSON line:
                  counter-measured HBM bytes per launch from the committed
                  rocprofv3 summary, null once the kernel sources differ from the
                  ones the counters were taken on
-  time_to_1e-8   FP64 CG vs the chosen mixed form on the same source
+  time_to_1e-8   FP64 CG vs the chosen mixed form and vs FGCR with the trained
+                 network preconditioner, on the same source
   dhop           standalone Dhop GB/s and GFLOP/s per storage precision
   copy           stream-copy bandwidth, the achievable-HBM reference
   cpu_baseline   the FP64 oracle's Wilson hop on this lattice, host cores
@@ -166,6 +167,30 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
+WEIGHTS = os.path.join(ROOT, "paper_2203_17119_amd", "weights", "ptc_4-12-12-12-4_8x8x8x8_ls8.npz")
+
+
+def learned_precond(lat, dwf, torch, b, tol, restart=32, maxit=2000):
+    """FGCR(restart) on the Schur system, right-preconditioned by the trained
+    network, to tol in the FP64 full residual (CG fallback on stagnation)."""
+    data = np.load(WEIGHTS)
+    net = dwf.dwf_net_create(lat.ctx, [int(v) for v in data["chans"]])
+    try:
+        dwf.dwf_net_set_weights(net, data["weights"])
+        x = torch.zeros_like(b)
+        dwf.dwf_kernel_timing_reset(lat.ctx)
+        dwf.dwf_kernel_timing(lat.ctx, 1)
+        s, st = dwf.dwf_fgcr(lat.ctx, net, b, x, tol=tol, restart=restart, maxit=maxit, fallback=True)
+        kn = dwf.dwf_kernel_stats(lat.ctx, dwf.DWF_K_NET)
+        dwf.dwf_kernel_timing(lat.ctx, 0)
+    finally:
+        dwf.dwf_net_destroy(net)
+    return {"solver": f"FGCR({restart}) + PTC network 4-12-12-12-4 (trained on 8^4x8)", "status": s,
+            "iters": st["iters"], "seconds": round(st["seconds"], 3), "res_full": st["res_full"],
+            "converged": st["converged"], "fell_back": st["fell_back"],
+            "network_ms": round(kn["ms"], 1), "network_launches": kn["launches"]}
+
+
 def cpu_baseline(w, U, b_full):
     """FP64 oracle Wilson hop (both parities, all s) on the same lattice and field."""
     import oracle
@@ -202,6 +227,8 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the stream copy and the standalone Dhop per precision (for counter runs)")
     ap.add_argument("--sweep", action="store_true", help="with --kernels-only: Dhop time over tile schedules")
+    ap.add_argument("--no-precond", action="store_true",
+                    help="skip the FGCR solve with the trained network preconditioner")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the hot path is one GPU's Dirichlet block and needs no "
@@ -277,6 +304,10 @@ def main():
     kern_gbs = dom["bytes"] / dom["ms"] / 1e6
     traffic = measured_traffic()
 
+    lp = None
+    if not args.no_precond:
+        lp = learned_precond(lat, dwf, torch, srcs[0], w.tol)
+        log(f"learned preconditioner: {lp}")
     table = None if args.no_table else dhop_table(lat, dwf, torch)
     cpu = None if args.no_cpu else cpu_baseline(w, U, b0_host)
 
@@ -300,7 +331,8 @@ def main():
                    "solver": f"red-black CGNE, {MODE_NAMES[args.mode]} + FP64 reliable updates, tol 1e-8"},
         "gflops": round(whole_gflops, 1),
         "value_definition": "algorithmic bytes of all hop stencils of the timed solves / their wall time",
-        "time_to_1e-8_s": {"f64": round(st64["seconds"], 4), MODE_NAMES[args.mode]: round(tmixed, 4)},
+        "time_to_1e-8_s": {"f64": round(st64["seconds"], 4), MODE_NAMES[args.mode]: round(tmixed, 4),
+                           "fgcr_learned": lp["seconds"] if lp else None},
         "iters": {"f64": st64["iters"], MODE_NAMES[args.mode]: [s["iters"] for s in stats]},
         "res_full": {"f64": st64["res_full"], MODE_NAMES[args.mode]: max(s["res_full"] for s in stats)},
         "speedup_vs_f64": round(st64["seconds"] / tmixed, 3),
@@ -316,6 +348,7 @@ def main():
                      "bytes_per_launch": dom["bytes"] / dom["launches"],
                      "gflops": round(dom["flops"] / dom["ms"] / 1e6, 1),
                      "frac_of_copy": round(kern_gbs / copy["GB/s"], 4)},
+        "learned_precond": lp,
         "tile_schedule": sched,
         "copy": copy,
         "dhop": table,

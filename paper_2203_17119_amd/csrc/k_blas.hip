@@ -342,6 +342,115 @@ __global__ void __launch_bounds__(BS) k_finish_b(const double *partial, int npar
     if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
+// ---------------------------------------------------------------------------
+// Block Gram-Schmidt for flexible GCR.  FP64 fields are viewed as flat complex
+// arrays of m elements (the inner product does not depend on the layout).
+// Each thread owns GS_EPT elements of one chunk; partial sums are written per
+// workgroup, member-major ([member][block]), and summed in a fixed order.
+
+static constexpr int GS_EPT = 8;
+
+static long gs_blocks(long m) { return (m + (long)BS * GS_EPT - 1) / ((long)BS * GS_EPT); }
+
+// partial[(2j + {0,1}) nblk + blk] = Re, Im of sum conj(X_j) y over the chunk, j < nv
+__global__ void __launch_bounds__(BS) k_gs_dots(const double2 *const *X, int nv, const double2 *y, long m,
+                                                double *partial)
+{
+    const long nblk = gridDim.x;
+    const long base = (long)blockIdx.x * BS * GS_EPT + threadIdx.x;
+    double2 yv[GS_EPT];
+#pragma unroll
+    for (int e = 0; e < GS_EPT; e++) {
+        const long k = base + (long)e * BS;
+        yv[e] = k < m ? y[k] : make_double2(0.0, 0.0);
+    }
+    for (int j = 0; j < nv; j++) {
+        const double2 *x = X[j];
+        double re = 0, im = 0;
+#pragma unroll
+        for (int e = 0; e < GS_EPT; e++) {
+            const long k = base + (long)e * BS;
+            if (k < m) {
+                const double2 xv = x[k];
+                re += xv.x * yv[e].x + xv.y * yv[e].y;
+                im += xv.x * yv[e].y - xv.y * yv[e].x;
+            }
+        }
+        re = block_sum(re);
+        im = block_sum(im);
+        if (threadIdx.x == 0) {
+            partial[(2 * j) * nblk + blockIdx.x] = re;
+            partial[(2 * j + 1) * nblk + blockIdx.x] = im;
+        }
+    }
+}
+
+// y -= sum_j b_j X_j, w -= sum_j b_j W_j with b_j = dots_j / nq[3 j] (dots_j =
+// <X_j, y> as Re, Im pairs); partials of |y|^2 and <y, r> (new y) as members 0..2
+__global__ void __launch_bounds__(BS) k_gs_project(const double2 *const *X, const double2 *const *W, int nv,
+                                                   const double *dots, const double *nq, double2 *y, double2 *w,
+                                                   const double2 *r, long m, double *partial)
+{
+    const long nblk = gridDim.x;
+    const long base = (long)blockIdx.x * BS * GS_EPT + threadIdx.x;
+    double n2 = 0, dre = 0, dim_ = 0;
+#pragma unroll
+    for (int e = 0; e < GS_EPT; e++) {
+        const long k = base + (long)e * BS;
+        if (k >= m) continue;
+        double2 yv = y[k], wv = w[k];
+        for (int j = 0; j < nv; j++) {
+            const double inv = 1.0 / nq[3 * j];
+            const double bre = dots[2 * j] * inv, bim = dots[2 * j + 1] * inv;
+            const double2 xv = X[j][k], vv = W[j][k];
+            yv.x -= bre * xv.x - bim * xv.y;
+            yv.y -= bre * xv.y + bim * xv.x;
+            wv.x -= bre * vv.x - bim * vv.y;
+            wv.y -= bre * vv.y + bim * vv.x;
+        }
+        y[k] = yv;
+        w[k] = wv;
+        const double2 rv = r[k];
+        n2 += yv.x * yv.x + yv.y * yv.y;
+        dre += yv.x * rv.x + yv.y * rv.y;
+        dim_ += yv.x * rv.y - yv.y * rv.x;
+    }
+    n2 = block_sum(n2);
+    dre = block_sum(dre);
+    dim_ = block_sum(dim_);
+    if (threadIdx.x == 0) {
+        partial[0 * nblk + blockIdx.x] = n2;
+        partial[1 * nblk + blockIdx.x] = dre;
+        partial[2 * nblk + blockIdx.x] = dim_;
+    }
+}
+
+// a = <q, r> / |q|^2 (coef = {|q|^2, Re, Im}); x += a z, r -= a q; partials |r|^2
+__global__ void __launch_bounds__(BS) k_gs_update(double2 *x, const double2 *z, double2 *r, const double2 *q,
+                                                  const double *coef, long m, double *partial)
+{
+    const long base = (long)blockIdx.x * BS * GS_EPT + threadIdx.x;
+    const double inv = 1.0 / coef[0];
+    const double are = coef[1] * inv, aim = coef[2] * inv;
+    double n2 = 0;
+#pragma unroll
+    for (int e = 0; e < GS_EPT; e++) {
+        const long k = base + (long)e * BS;
+        if (k >= m) continue;
+        const double2 zv = z[k], qv = q[k];
+        double2 xv = x[k], rv = r[k];
+        xv.x += are * zv.x - aim * zv.y;
+        xv.y += are * zv.y + aim * zv.x;
+        rv.x -= are * qv.x - aim * qv.y;
+        rv.y -= are * qv.y + aim * qv.x;
+        x[k] = xv;
+        r[k] = rv;
+        n2 += rv.x * rv.x + rv.y * rv.y;
+    }
+    n2 = block_sum(n2);
+    if (threadIdx.x == 0) partial[blockIdx.x] = n2;
+}
+
 // y_j += a x_j (host scalar), batched
 template <typename S>
 __global__ void __launch_bounds__(BS) k_axpy_b(double a, Field x, Field y, long stride)
@@ -652,6 +761,42 @@ void launch_accumulate_low(Context &c, int prec, Field xh, Field xl)
 {
     Timer tm(c, DWF_K_BLAS, (3 * sbytes(P_F64) / 1.5 + 2 * sbytes(prec)) * xh.n, 24.0 * xh.n);
     DWF_DISPATCH(prec, k_accumulate_low, g1(xh.n), dim3(BS), 0, xh, xl);
+}
+
+long gs_partials_needed(const Context &c, int nv) { return gs_blocks(12 * c.n5h) * std::max(3, 2 * nv); }
+
+void launch_gs_dots(Context &c, const double2 *const *X_dev, int nv, Field y, double *partial, double *out)
+{
+    const long m = 12 * y.n, nblk = gs_blocks(m);
+    Timer tm(c, DWF_K_BLAS, (nv + 1.0) * 16.0 * m, 8.0 * nv * m);
+    hipLaunchKernelGGL(k_gs_dots, dim3((unsigned)nblk), dim3(BS), 0, c.stream, X_dev, nv, (const double2 *)y.data, m,
+                       partial);
+    HIPCHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_finish_b, dim3(2 * nv), dim3(BS), 0, c.stream, partial, (int)nblk, out);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_gs_project(Context &c, const double2 *const *X_dev, const double2 *const *W_dev, int nv,
+                       const double *dots, const double *nq, Field y, Field w, Field r, double *partial, double *out)
+{
+    const long m = 12 * y.n, nblk = gs_blocks(m);
+    Timer tm(c, DWF_K_BLAS, (2.0 * nv + 5.0) * 16.0 * m, (16.0 * nv + 12.0) * m);
+    hipLaunchKernelGGL(k_gs_project, dim3((unsigned)nblk), dim3(BS), 0, c.stream, X_dev, W_dev, nv, dots, nq,
+                       (double2 *)y.data, (double2 *)w.data, (const double2 *)r.data, m, partial);
+    HIPCHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_finish_b, dim3(3), dim3(BS), 0, c.stream, partial, (int)nblk, out);
+    HIPCHECK(hipGetLastError());
+}
+
+int launch_gs_update(Context &c, Field x, Field z, Field r, Field q, const double *coef)
+{
+    const long m = 12 * x.n, nblk = gs_blocks(m);
+    need_partials(c, nblk, 1);
+    Timer tm(c, DWF_K_BLAS, 6.0 * 16.0 * m, 18.0 * m);
+    hipLaunchKernelGGL(k_gs_update, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (double2 *)x.data,
+                       (const double2 *)z.data, (double2 *)r.data, (const double2 *)q.data, coef, m, c.partials);
+    HIPCHECK(hipGetLastError());
+    return (int)nblk;
 }
 
 void launch_ms_update(Context &c, int prec, int nshift, Field *x, Field *p, Field r, const double *coef_dev,

@@ -400,6 +400,30 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
         Z.push_back(ws_field(c, "fg_z" + std::to_string(k), P_F64));
         Q.push_back(ws_field(c, "fg_q" + std::to_string(k), P_F64));
     }
+    // device pointer tables of the Krylov vectors, Gram-Schmidt coefficients
+    // (dots[2m]; info[3k] = {|q_k|^2, <q_k, r>} per step) and partial sums
+    struct Dev {
+        void *p = nullptr;
+        ~Dev()
+        {
+            if (p) (void)hipFree(p);
+        }
+    } tab, coef, part;
+    HIPCHECK(hipMalloc(&tab.p, 2 * m * sizeof(void *)));
+    HIPCHECK(hipMalloc(&coef.p, (2 * m + 3 * m) * sizeof(double)));
+    HIPCHECK(hipMalloc(&part.p, gs_partials_needed(c, m) * sizeof(double)));
+    {
+        std::vector<const void *> h(2 * m);
+        for (int k = 0; k < m; k++) {
+            h[k] = Q[k].data;
+            h[m + k] = Z[k].data;
+        }
+        HIPCHECK(hipMemcpy(tab.p, h.data(), h.size() * sizeof(void *), hipMemcpyHostToDevice));
+    }
+    const double2 *const *qtab = (const double2 *const *)tab.p;
+    const double2 *const *ztab = qtab + m;
+    double *dots = (double *)coef.p, *info = dots + 2 * m;
+    double *partial = (double *)part.p;
     HIPCHECK(hipStreamSynchronize(c.stream));
     const double t1w = wall();
     const double bn = std::sqrt(dnorm2(c, rhs));
@@ -415,25 +439,15 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
             if (net) precondition(net, r, Z[k], normal);
             else launch_copy(c, P_F64, r, Z[k]);
             fgcr_op(c, Z[k], Q[k], normal);
-            for (int j = 0; j < k; j++) {
-                double re, im;
-                ddot(c, Q[j], Q[k], re, im);
-                launch_caxpy(c, P_F64, -re, -im, Q[j], Q[k]);
-                launch_caxpy(c, P_F64, -re, -im, Z[j], Z[k]);
-            }
-            const double qn = std::sqrt(dnorm2(c, Q[k]));
-            if (!(qn > 0) || !std::isfinite(qn)) {
-                stalled = true;
-                break;
-            }
-            launch_axpby(c, P_F64, 1.0 / qn, Q[k], 0.0, Q[k], Q[k]);
-            launch_axpby(c, P_F64, 1.0 / qn, Z[k], 0.0, Z[k], Z[k]);
-            double are, aim;
-            ddot(c, Q[k], r, are, aim);
-            launch_caxpy(c, P_F64, are, aim, Z[k], x);
-            launch_caxpy(c, P_F64, -are, -aim, Q[k], r);
+            // classical Gram-Schmidt against the cycle's earlier directions in
+            // one pass over the vectors; the residual stays orthogonal to them
+            if (k > 0) launch_gs_dots(c, qtab, k, Q[k], partial, dots);
+            launch_gs_project(c, qtab, ztab, k, dots, info, Q[k], Z[k], r, partial, info + 3 * k);
+            const int np = launch_gs_update(c, x, Z[k], r, Q[k], info + 3 * k);
+            launch_finish(c, np, 1, 12);
+            read_scalars(c, 12, 1);
             it++;
-            const double rn = std::sqrt(dnorm2(c, r));
+            const double rn = std::sqrt(c.hscal[12]);
             if (!std::isfinite(rn)) {
                 stalled = true;
                 break;

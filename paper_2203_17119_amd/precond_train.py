@@ -139,14 +139,15 @@ def train(lat, net, gauges, train_pairs, val_pairs, epochs: int, batch: int = 8,
     return hist
 
 
-def solve_table(lat, torch, nets: dict, b_full, tol: float, restart: int, maxit: int):
-    """Time-to-tol of plain CG, plain GCR and FGCR with each network on one source."""
+def solve_table(lat, torch, nets: dict, b_full, tol: float, restart: int, maxit: int, normal_too: bool = False):
+    """Time-to-tol of plain CG, plain GCR and FGCR with each network on one source
+    (Schur system; with normal_too also the normal equations)."""
     rows = {}
     x = torch.zeros_like(b_full)
     torch.cuda.synchronize()
     s, st = dwf.dwf_cg(lat.ctx, b_full, x, tol=tol, mode=dwf.DWF_SOLVE_F64)
     rows["cg_f64"] = {"status": s, "iters": st["iters"], "seconds": st["seconds"], "res_full": st["res_full"]}
-    for normal in (False, True):
+    for normal in ((False, True) if normal_too else (False,)):
         tag = "normal" if normal else "schur"
         for name, net in [("gcr", None)] + list(nets.items()):
             x.zero_()
@@ -172,16 +173,22 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--sources", default="operator", choices=("operator", "gaussian"))
     ap.add_argument("--out", default=None, help="write the trained weights (npz)")
+    ap.add_argument("--weights", default=None, help="skip training: evaluate these weights (npz)")
     ap.add_argument("--eval-workload", default="24^4x12_fgcr")
     ap.add_argument("--eval-sources", type=int, default=1)
     ap.add_argument("--restart", type=int, default=32)
     ap.add_argument("--maxit", type=int, default=3000)
+    ap.add_argument("--normal-too", action="store_true", help="also evaluate FGCR on the normal equations")
     args = ap.parse_args()
 
     import torch
 
-    w = synth.WORKLOADS["8^4x8_train"]
     torch.cuda.set_device(0)
+    if args.weights:
+        data = np.load(args.weights)
+        evaluate(args, torch, data["init"], data["weights"])
+        return
+    w = synth.WORKLOADS["8^4x8_train"]
     gauges = [torch.from_numpy(synth.gauge_field(w.dims, w.eps, w.gauge_seed + f)).cuda() for f in range(args.fields)]
     lat = dwf.Lattice(w.dims, w.Ls, w.b, w.c, w.M5, w.mf, w.dirichlet, gauge=gauges[0])
     d = w.b * (4 - w.M5) + 1
@@ -205,6 +212,10 @@ def main():
     if args.out:
         np.savez(args.out, weights=wt, chans=np.array(CHANS), init=w0)
 
+    evaluate(args, torch, w0, wt)
+
+
+def evaluate(args, torch, w0, wt):
     ev = synth.WORKLOADS[args.eval_workload]
     U = synth.gauge_field(ev.dims, ev.eps, ev.gauge_seed)
     lat = dwf.Lattice(ev.dims, ev.Ls, ev.b, ev.c, ev.M5, ev.mf, ev.dirichlet, gauge=U)
@@ -215,7 +226,7 @@ def main():
         dwf.dwf_net_set_weights(nets[name], wts)
     for k in range(args.eval_sources):
         b = torch.from_numpy(synth.gaussian_fermion(ev.dims, ev.Ls, ev.source_seeds[k])).cuda()
-        rows = solve_table(lat, torch, nets, b, ev.tol, args.restart, args.maxit)
+        rows = solve_table(lat, torch, nets, b, ev.tol, args.restart, args.maxit, args.normal_too)
         print(json.dumps({"phase": "eval", "workload": args.eval_workload, "source": ev.source_seeds[k],
                           "restart": args.restart, "rows": rows}), flush=True)
     for n in nets.values():
