@@ -170,13 +170,15 @@ def measured_traffic():
 WEIGHTS = os.path.join(ROOT, "paper_2203_17119_amd", "weights", "ptc_4-12-12-12-4_8x8x8x8_ls8.npz")
 
 
-def learned_precond(lat, dwf, torch, b, tol, restart=32, maxit=2000):
+def learned_precond(lat, dwf, torch, b, tol, restart=32, maxit=2000, mfma=True):
     """FGCR(restart) on the Schur system, right-preconditioned by the trained
-    network, to tol in the FP64 full residual (CG fallback on stagnation)."""
+    network (matrix-core or FP32 forward), to tol in the FP64 full residual
+    (CG fallback on stagnation)."""
     data = np.load(WEIGHTS)
     net = dwf.dwf_net_create(lat.ctx, [int(v) for v in data["chans"]])
     try:
         dwf.dwf_net_set_weights(net, data["weights"])
+        dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_MFMA_BF16 if mfma else dwf.DWF_NET_FWD_FP32)
         x = torch.zeros_like(b)
         dwf.dwf_kernel_timing_reset(lat.ctx)
         dwf.dwf_kernel_timing(lat.ctx, 1)
@@ -185,7 +187,8 @@ def learned_precond(lat, dwf, torch, b, tol, restart=32, maxit=2000):
         dwf.dwf_kernel_timing(lat.ctx, 0)
     finally:
         dwf.dwf_net_destroy(net)
-    return {"solver": f"FGCR({restart}) + PTC network 4-12-12-12-4 (trained on 8^4x8)", "status": s,
+    return {"solver": f"FGCR({restart}) + PTC network 4-12-12-12-4 (trained on 8^4x8), "
+                      f"{'matrix-core BF16' if mfma else 'FP32'} forward", "status": s,
             "iters": st["iters"], "seconds": round(st["seconds"], 3), "res_full": st["res_full"],
             "converged": st["converged"], "fell_back": st["fell_back"],
             "network_ms": round(kn["ms"], 1), "network_launches": kn["launches"]}
@@ -306,8 +309,10 @@ def main():
 
     lp = None
     if not args.no_precond:
-        lp = learned_precond(lat, dwf, torch, srcs[0], w.tol)
+        lp = learned_precond(lat, dwf, torch, srcs[0], w.tol, mfma=True)
         log(f"learned preconditioner: {lp}")
+        lp["fp32_forward"] = learned_precond(lat, dwf, torch, srcs[0], w.tol, mfma=False)
+        log(f"learned preconditioner, FP32 forward: {lp['fp32_forward']}")
     table = None if args.no_table else dhop_table(lat, dwf, torch)
     cpu = None if args.no_cpu else cpu_baseline(w, U, b0_host)
 

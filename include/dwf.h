@@ -199,6 +199,16 @@ int dwf_net_num_weights(dwf_net net);
  * each block [pi][a][b] (a output, b input channel); setting resets Adam */
 dwf_status dwf_net_set_weights(dwf_net net, const float *w);
 dwf_status dwf_net_get_weights(dwf_net net, float *w);
+/* Forward used when the network is applied as a preconditioner
+ * (dwf_precond_apply, dwf_fgcr):
+ *   DWF_NET_FWD_FP32       vector units, FP32 arithmetic (the default; training
+ *                          always uses it)
+ *   DWF_NET_FWD_MFMA_BF16  channel mixing on the matrix cores, the transported
+ *                          inputs rounded to BF16 (the weights are BF16 already),
+ *                          FP32 accumulation; relative deviation from the FP32
+ *                          forward of order 1e-2 over four layers */
+enum { DWF_NET_FWD_FP32 = 0, DWF_NET_FWD_MFMA_BF16 = 1 };
+dwf_status dwf_net_set_forward(dwf_net net, int mode);
 /* out = restrict_odd(N(embed_odd(in))); canonical FP64 odd half fields */
 dwf_status dwf_precond_apply(dwf_ctx ctx, dwf_net net, const double *in_odd, double *out_odd);
 /* Gradients of a real loss L through y = precond(in), given grad_out =

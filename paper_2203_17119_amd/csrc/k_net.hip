@@ -126,6 +126,117 @@ __global__ void __launch_bounds__(256) k_ptc_fwd(NetGeo g, const float2 *in, flo
         for (int c = 0; c < 3; c++) o[(a * 3 + c) * n + i] = make_float2(acc[a][c].re, acc[a][c].im);
 }
 
+// ------------------------------------------------- forward on the matrix cores
+//
+// For every output column (5D site, colour) a layer is out[a] = sum_q W_q[a] T_q
+// with q = (path, input channel) and T_q the transported input: a complex GEMM
+// of M = COUT, K = 11 CIN over all columns.  It runs in real form,
+//   [Re out; Im out] = [[Wr, -Wi], [Wi, Wr]] [Re T; Im T],
+// as 32 x 32 x 8 BF16 MFMA tiles with FP32 accumulation (rows m' = 2a + re/im,
+// K index k' = 2q + re/im).  A wavefront owns 32 columns; each lane builds the
+// transported values of its own column in FP32 on the vector units (one link
+// row per path) and rounds them to BF16 for the B operand.  The weights are
+// BF16 already, so the A operand is exact; it is packed once per weight update
+// in operand order [step][lane][4].
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ short bf16_bits(float f)
+{
+    const __hip_bfloat16 h = __float2bfloat16(f);
+    return *(const short *)&h;
+}
+
+// A operand of a CIN -> COUT layer: pk[(step * 64 + lane) * 4 + e] = A[m'][k'],
+// m' = lane % 32, k' = 8 step + 4 (lane / 32) + e
+template <int CIN, int COUT>
+__global__ void k_pack_mfma_weights(const __hip_bfloat162 *w, short *pk)
+{
+    constexpr int NSTEP = 11 * CIN / 4;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NSTEP * 64 * 4) return;
+    const int e = t & 3, lane = (t >> 2) & 63, step = t >> 8;
+    const int mr = lane & 31, kr = 8 * step + 4 * (lane >> 5) + e;
+    const int a = mr >> 1, rho = mr & 1, q = kr >> 1, sig = kr & 1;
+    float v = 0.f;
+    if (a < COUT) {
+        const int pi = q / CIN, b = q % CIN;
+        const float2 wf = __bfloat1622float2(w[(pi * COUT + a) * CIN + b]);
+        v = (rho == 0) ? (sig == 0 ? wf.x : -wf.y) : (sig == 0 ? wf.y : wf.x);
+    }
+    pk[t] = bf16_bits(v);
+}
+
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) k_ptc_fwd_mfma(NetGeo g, const float2 *in, float2 *out, const short *wpk, int p,
+                                                      long n)
+{
+    static_assert(CIN % 4 == 0 && 2 * COUT <= 32, "channel counts");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = lane >> 5;
+    const long col = ((long)blockIdx.x * 4 + wave) * 32 + (lane & 31);  // (5D site, colour)
+    const bool ok = col < 3 * n;
+    const long i = ok ? col / 3 : 0;
+    const int cc = ok ? (int)(col - 3 * i) : 0;
+    const long j = i / g.Ls;
+    const int s = (int)(i - j * g.Ls);
+    const bf16x4 *A = (const bf16x4 *)wpk + lane;
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; r++) acc[r] = 0.f;
+    for (int pi = 0; pi < 11; pi++) {
+        long src = 0;
+        int sp = p;
+        const bool have = ok && path_source(g, p, pi, j, s, src, sp);
+        const bool hop = pi >= 1 && pi <= 8;
+        cx<float> u0 = mk(0.f, 0.f), u1 = u0, u2 = u0;
+        if (have && hop) {
+            const float2 *L = (p ? g.links1 : g.links0) + ((long)(pi - 1) * 9 + 3 * cc) * g.vh + j;
+            u0 = c2(L[0]);
+            u1 = c2(L[g.vh]);
+            u2 = c2(L[2 * g.vh]);
+        }
+        const float2 *base = in + (long)sp * CIN * 3 * n + src;
+#pragma unroll
+        for (int u = 0; u < CIN / 4; u++) {
+            const int b0 = 4 * u + 2 * h;
+            cx<float> t0 = mk(0.f, 0.f), t1 = t0;
+            if (have) {
+                if (hop) {
+                    const float2 *f0 = base + (long)(b0 * 3) * n, *f1 = base + (long)((b0 + 1) * 3) * n;
+                    t0 = cmul(u0, c2(f0[0]));
+                    cmac(t0, u1, c2(f0[n]));
+                    cmac(t0, u2, c2(f0[2 * n]));
+                    t1 = cmul(u0, c2(f1[0]));
+                    cmac(t1, u1, c2(f1[n]));
+                    cmac(t1, u2, c2(f1[2 * n]));
+                } else {
+                    t0 = c2(base[(long)(b0 * 3 + cc) * n]);
+                    t1 = c2(base[(long)((b0 + 1) * 3 + cc) * n]);
+                }
+            }
+            bf16x4 bf;
+            bf[0] = bf16_bits(t0.re);
+            bf[1] = bf16_bits(t0.im);
+            bf[2] = bf16_bits(t1.re);
+            bf[3] = bf16_bits(t1.im);
+            const int step = pi * (CIN / 4) + u;
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A[step * 64], bf, acc, 0, 0, 0);
+        }
+    }
+    if (!ok) return;
+    // accumulator register r holds row m' = 8 (r / 4) + 4 h + r % 4 of this column
+    float2 *o = out + (long)p * COUT * 3 * n;
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+        for (int hh = 0; hh < 2; hh++) {
+            const int a = 4 * q + 2 * h + hh;
+            if (a < COUT) o[(long)(a * 3 + cc) * n + i] = make_float2(acc[4 * q + 2 * hh], acc[4 * q + 2 * hh + 1]);
+        }
+}
+
 // Weight gradient of one layer over the output sites of parity p:
 //   gW[pi][a][b] += sum_{sites, colour} g_a conj(T_pi phi_b)
 // Each workgroup reduces its sites through LDS; partial[blk][pi][a][b] (re, im) in FP64.
@@ -309,6 +420,50 @@ void launch_ptc_layer(Context &c, int cin, int cout, const float2 *in, float2 *o
     const double flops = (double)c.n5h * (11.0 * cout * cin * 3 * 8 + 8.0 * cin * 66);
     Timer tm(c, DWF_K_NET, (double)c.n5h * 8.0 * 3 * (11 * cin + cout), flops);
 #define NETL(CI, CO) hipLaunchKernelGGL((k_ptc_fwd<CI, CO>), grid, blk, 0, c.stream, g, in, out, w, p, c.n5h)
+    if (cin == 4 && cout == 12) NETL(4, 12);
+    else if (cin == 12 && cout == 12) NETL(12, 12);
+    else if (cin == 12 && cout == 4) NETL(12, 4);
+    else if (cin == 4 && cout == 4) NETL(4, 4);
+    else if (cin == 4 && cout == 8) NETL(4, 8);
+    else if (cin == 8 && cout == 8) NETL(8, 8);
+    else if (cin == 8 && cout == 4) NETL(8, 4);
+    else if (cin == 12 && cout == 8) NETL(12, 8);
+    else if (cin == 8 && cout == 12) NETL(8, 12);
+    else fail(DWF_ENOTSUP, "layer channel counts must be 4, 8 or 12");
+#undef NETL
+    HIPCHECK(hipGetLastError());
+}
+
+// operand-order weights of the matrix-core forward: 11 cin / 4 steps x 64 lanes x 4
+size_t mfma_weight_elems(int cin) { return (size_t)11 * cin / 4 * 64 * 4; }
+
+void launch_pack_mfma_weights(Context &c, int cin, int cout, const void *w_bf16, short *pk)
+{
+    const __hip_bfloat162 *w = (const __hip_bfloat162 *)w_bf16;
+    const dim3 grid((unsigned)((mfma_weight_elems(cin) + 255) / 256));
+#define PK(CI, CO) hipLaunchKernelGGL((k_pack_mfma_weights<CI, CO>), grid, dim3(256), 0, c.stream, w, pk)
+    if (cin == 4 && cout == 12) PK(4, 12);
+    else if (cin == 12 && cout == 12) PK(12, 12);
+    else if (cin == 12 && cout == 4) PK(12, 4);
+    else if (cin == 4 && cout == 4) PK(4, 4);
+    else if (cin == 4 && cout == 8) PK(4, 8);
+    else if (cin == 8 && cout == 8) PK(8, 8);
+    else if (cin == 8 && cout == 4) PK(8, 4);
+    else if (cin == 12 && cout == 8) PK(12, 8);
+    else if (cin == 8 && cout == 12) PK(8, 12);
+    else fail(DWF_ENOTSUP, "layer channel counts must be 4, 8 or 12");
+#undef PK
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_ptc_layer_mfma(Context &c, int cin, int cout, const float2 *in, float2 *out, const short *pk, int p)
+{
+    const NetGeo g = net_geo(c);
+    const long ncol = 3 * c.n5h;
+    const dim3 grid((unsigned)((ncol + 127) / 128)), blk(256);
+    const double flops = (double)c.n5h * (11.0 * cout * cin * 3 * 8 + 8.0 * cin * 66);
+    Timer tm(c, DWF_K_NET, (double)c.n5h * 8.0 * 3 * (11 * cin + cout), flops);
+#define NETL(CI, CO) hipLaunchKernelGGL((k_ptc_fwd_mfma<CI, CO>), grid, blk, 0, c.stream, g, in, out, pk, p, c.n5h)
     if (cin == 4 && cout == 12) NETL(4, 12);
     else if (cin == 12 && cout == 12) NETL(12, 12);
     else if (cin == 12 && cout == 4) NETL(12, 4);

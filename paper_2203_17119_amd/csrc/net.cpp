@@ -18,6 +18,9 @@ using namespace dwf;
 
 namespace dwf {
 void launch_ptc_layer(Context &c, int cin, int cout, const float2 *in, float2 *out, const void *w_bf16, int p);
+size_t mfma_weight_elems(int cin);
+void launch_pack_mfma_weights(Context &c, int cin, int cout, const void *w_bf16, short *pk);
+void launch_ptc_layer_mfma(Context &c, int cin, int cout, const float2 *in, float2 *out, const short *pk, int p);
 int launch_ptc_wgrad(Context &c, int cin, int cout, const float2 *in, const float2 *gout, int p, double *partial,
                      long partial_len);
 void launch_wgrad_finish(Context &c, const double *partial, int nblk, int nw, float *gw, bool accumulate);
@@ -46,6 +49,9 @@ struct dwf_net_s {
     double *wpart = nullptr;
     long wpart_len = 0;
     int cmax = 0;
+    short *wpk = nullptr;          // matrix-core operand order, per layer at pkoff[l]
+    std::vector<size_t> pkoff;
+    int fwd = DWF_NET_FWD_FP32;    // forward used by the preconditioner application
 };
 
 namespace dwf {
@@ -60,7 +66,7 @@ static size_t feat_elems(const Context &c, int C) { return (size_t)2 * C * 3 * c
 static void net_free(dwf_net_s *n)
 {
     for (void *p : {(void *)n->w32, (void *)n->gw, (void *)n->m, (void *)n->v, n->wbf, n->wadj, (void *)n->g0,
-                    (void *)n->g1, (void *)n->wpart})
+                    (void *)n->g1, (void *)n->wpart, (void *)n->wpk})
         if (p) (void)hipFree(p);
     for (auto *a : n->acts)
         if (a) (void)hipFree(a);
@@ -71,21 +77,30 @@ static void refresh_bf16(dwf_net_s *n)
 {
     Context &c = *n->c;
     launch_to_bf16(c, n->w32, n->wbf, n->nw);
-    for (int l = 0; l < n->nlayer; l++)
+    for (int l = 0; l < n->nlayer; l++) {
         launch_adjoint_weights(c, (const __hip_bfloat162 *)n->wbf + n->woff[l], (__hip_bfloat162 *)n->wadj + n->woff[l],
                                n->chans[l], n->chans[l + 1]);
+        launch_pack_mfma_weights(c, n->chans[l], n->chans[l + 1], (const __hip_bfloat162 *)n->wbf + n->woff[l],
+                                 n->wpk + n->pkoff[l]);
+    }
 }
 
 // forward of one sample whose input is acts[0] (4 channels); the last layer
 // is evaluated on odd sites only (the preconditioner's range)
-static void net_forward(dwf_net_s *n, bool all_parities)
+// (mfma: the matrix-core forward, BF16 operands with FP32 accumulation)
+static void net_forward(dwf_net_s *n, bool all_parities, bool mfma = false)
 {
     Context &c = *n->c;
     for (int l = 0; l < n->nlayer; l++) {
         const bool last = l == n->nlayer - 1;
-        for (int p = (last && !all_parities) ? 1 : 0; p < 2; p++)
-            launch_ptc_layer(c, n->chans[l], n->chans[l + 1], n->acts[l], n->acts[l + 1],
-                             (const __hip_bfloat162 *)n->wbf + n->woff[l], p);
+        for (int p = (last && !all_parities) ? 1 : 0; p < 2; p++) {
+            if (mfma)
+                launch_ptc_layer_mfma(c, n->chans[l], n->chans[l + 1], n->acts[l], n->acts[l + 1],
+                                      n->wpk + n->pkoff[l], p);
+            else
+                launch_ptc_layer(c, n->chans[l], n->chans[l + 1], n->acts[l], n->acts[l + 1],
+                                 (const __hip_bfloat162 *)n->wbf + n->woff[l], p);
+        }
     }
 }
 
@@ -179,6 +194,12 @@ dwf_status dwf_net_create(dwf_ctx ctx, int nlayer, const int *chans, dwf_net *ou
         HIPCHECK(hipMalloc(&n->m, 2 * sizeof(float) * n->nw));
         HIPCHECK(hipMalloc(&n->v, 2 * sizeof(float) * n->nw));
         HIPCHECK(hipMalloc(&n->wbf, 4 * (size_t)n->nw));
+        size_t pk = 0;
+        for (int l = 0; l < nlayer; l++) {
+            n->pkoff.push_back(pk);
+            pk += mfma_weight_elems(chans[l]);
+        }
+        HIPCHECK(hipMalloc(&n->wpk, pk * sizeof(short)));
         HIPCHECK(hipMalloc(&n->wadj, 4 * (size_t)n->nw));
         for (void *p : {(void *)n->w32, (void *)n->gw, (void *)n->m, (void *)n->v})
             HIPCHECK(hipMemset(p, 0, 2 * sizeof(float) * n->nw));
@@ -237,6 +258,15 @@ dwf_status dwf_net_get_weights(dwf_net net, float *w)
     DWF_API_END
 }
 
+dwf_status dwf_net_set_forward(dwf_net net, int mode)
+{
+    DWF_API_BEGIN
+    dwf_net_s &n = N_(net);
+    if (mode != DWF_NET_FWD_FP32 && mode != DWF_NET_FWD_MFMA_BF16) fail(DWF_EINVAL, "unknown forward mode");
+    n.fwd = mode;
+    DWF_API_END
+}
+
 dwf_status dwf_precond_apply(dwf_ctx ctx, dwf_net net, const double *in_odd, double *out_odd)
 {
     DWF_API_BEGIN
@@ -248,7 +278,7 @@ dwf_status dwf_precond_apply(dwf_ctx ctx, dwf_net net, const double *in_odd, dou
     Field a = ws_field(c, "net_io", P_F64);
     launch_import(c, P_F64, in_odd, a, 0, 0);
     launch_spinor_to_feat(c, P_F64, a, n.acts[0], 1, true);
-    net_forward(&n, false);
+    net_forward(&n, false, n.fwd == DWF_NET_FWD_MFMA_BF16);
     launch_feat_to_spinor(c, P_F64, n.acts[n.nlayer], a, 1);
     launch_export(c, P_F64, a, out_odd, 0, 0);
     DWF_API_END
@@ -333,7 +363,7 @@ static void precondition(dwf_net_s *n, Field r, Field z, bool normal)
         launch_feat_to_spinor(c, P_F64, adj, z, 1);  // keep odd part only
         launch_spinor_to_feat(c, P_F64, z, n->acts[0], 1, true);
     }
-    net_forward(n, false);
+    net_forward(n, false, n->fwd == DWF_NET_FWD_MFMA_BF16);
     launch_feat_to_spinor(c, P_F64, n->acts[n->nlayer], z, 1);
 }
 

@@ -20,6 +20,7 @@ DWF_OK, DWF_EINVAL, DWF_ENOMEM, DWF_EDEVICE, DWF_ENOCONV, DWF_ENOTSUP = 0, -1, -
 DWF_F64, DWF_F32, DWF_F16, DWF_BF16 = 0, 1, 2, 3
 DWF_SOLVE_F64, DWF_SOLVE_MIXED_F32, DWF_SOLVE_MIXED_F16, DWF_SOLVE_MIXED_BF16 = 0, 1, 2, 3
 DWF_K_DHOP, DWF_K_STENCIL, DWF_K_SLOCAL, DWF_K_BLAS, DWF_K_NET = 0, 1, 2, 3, 4
+DWF_NET_FWD_FP32, DWF_NET_FWD_MFMA_BF16 = 0, 1
 KCLASS_NAMES = {DWF_K_DHOP: "dhop", DWF_K_STENCIL: "stencil", DWF_K_SLOCAL: "slocal",
                 DWF_K_BLAS: "blas", DWF_K_NET: "net"}
 
@@ -86,6 +87,7 @@ SIGNATURES = {
     "dwf_net_set_weights": ([_NET, _P], C.c_int32),
     "dwf_net_get_weights": ([_NET, _P], C.c_int32),
     "dwf_precond_apply": ([_CTX, _NET, _P, _P], C.c_int32),
+    "dwf_net_set_forward": ([_NET, _I], C.c_int32),
     "dwf_net_backward": ([_NET, _P, _P, _P, _P], C.c_int32),
     "dwf_net_train_step": ([_NET, _I, C.POINTER(_P), C.POINTER(_P), C.POINTER(dwf_adam), C.POINTER(_D)], C.c_int32),
     "dwf_fgcr": ([_CTX, _NET, _P, _P, C.POINTER(dwf_solver_opts), C.POINTER(dwf_solver_stats)], C.c_int32),
@@ -279,6 +281,10 @@ def dwf_net_get_weights(net):
     a = np.empty(dwf_net_num_weights(net), dtype=np.complex64)
     _check(load().dwf_net_get_weights(net, a.ctypes.data))
     return a
+
+
+def dwf_net_set_forward(net, mode):
+    _check(load().dwf_net_set_forward(net, int(mode)))
 
 
 def dwf_precond_apply(ctx, net, in_odd, out_odd):

@@ -139,7 +139,8 @@ def train(lat, net, gauges, train_pairs, val_pairs, epochs: int, batch: int = 8,
     return hist
 
 
-def solve_table(lat, torch, nets: dict, b_full, tol: float, restart: int, maxit: int, normal_too: bool = False):
+def solve_table(lat, torch, nets: dict, b_full, tol: float, restart: int, maxit: int, normal_too: bool = False,
+                gcr: bool = True):
     """Time-to-tol of plain CG, plain GCR and FGCR with each network on one source
     (Schur system; with normal_too also the normal equations)."""
     rows = {}
@@ -149,7 +150,7 @@ def solve_table(lat, torch, nets: dict, b_full, tol: float, restart: int, maxit:
     rows["cg_f64"] = {"status": s, "iters": st["iters"], "seconds": st["seconds"], "res_full": st["res_full"]}
     for normal in ((False, True) if normal_too else (False,)):
         tag = "normal" if normal else "schur"
-        for name, net in [("gcr", None)] + list(nets.items()):
+        for name, net in ([("gcr", None)] if gcr else []) + list(nets.items()):
             x.zero_()
             dwf.dwf_kernel_timing_reset(lat.ctx)
             dwf.dwf_kernel_timing(lat.ctx, 1)
@@ -179,6 +180,8 @@ def main():
     ap.add_argument("--restart", type=int, default=32)
     ap.add_argument("--maxit", type=int, default=3000)
     ap.add_argument("--normal-too", action="store_true", help="also evaluate FGCR on the normal equations")
+    ap.add_argument("--skip-init", action="store_true", help="do not evaluate the untrained network")
+    ap.add_argument("--skip-gcr", action="store_true", help="do not evaluate plain GCR")
     args = ap.parse_args()
 
     import torch
@@ -221,12 +224,16 @@ def evaluate(args, torch, w0, wt):
     lat = dwf.Lattice(ev.dims, ev.Ls, ev.b, ev.c, ev.M5, ev.mf, ev.dirichlet, gauge=U)
     del U
     nets = {}
-    for name, wts in (("net_init", w0), ("net_trained", wt)):
+    for name, wts in (("net_init", w0), ("net_trained", wt), ("net_trained_mfma", wt)):
+        if name == "net_init" and args.skip_init:
+            continue
         nets[name] = dwf.dwf_net_create(lat.ctx, CHANS)
         dwf.dwf_net_set_weights(nets[name], wts)
+        if name.endswith("_mfma"):
+            dwf.dwf_net_set_forward(nets[name], dwf.DWF_NET_FWD_MFMA_BF16)
     for k in range(args.eval_sources):
         b = torch.from_numpy(synth.gaussian_fermion(ev.dims, ev.Ls, ev.source_seeds[k])).cuda()
-        rows = solve_table(lat, torch, nets, b, ev.tol, args.restart, args.maxit, args.normal_too)
+        rows = solve_table(lat, torch, nets, b, ev.tol, args.restart, args.maxit, args.normal_too, not args.skip_gcr)
         print(json.dumps({"phase": "eval", "workload": args.eval_workload, "source": ev.source_seeds[k],
                           "restart": args.restart, "rows": rows}), flush=True)
     for n in nets.values():

@@ -82,6 +82,50 @@ def test_precond_apply_matches_oracle(case):
         dwf.dwf_net_destroy(net)
 
 
+@pytest.mark.parametrize("chans", [CHANS, [4, 8, 12, 8, 4], [4, 4]])
+def test_precond_apply_mfma_matches_oracle(case, chans):
+    """Matrix-core forward: every transported input is rounded to BF16 (unit
+    roundoff 2^-9) before the FP32-accumulated channel mixing, with the same
+    BF16 weights as the oracle.  Without cancellation a layer's relative error
+    is at most 2^-9, four layers compound to (1 + 2^-9)^4 - 1 = 7.8e-3."""
+    Ws = random_weights(chans, 3)
+    net = dwf.dwf_net_create(case.ctx, chans)
+    try:
+        dwf.dwf_net_set_weights(net, flat(Ws))
+        dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_MFMA_BF16)
+        x = case.half(64)
+        out = torch().empty_like(to_gpu(x))
+        dwf.dwf_precond_apply(case.ctx, net, to_gpu(x), out)
+        expect = oracle.pick(case.P, oracle_forward(case, Ws, x)[-1], 1)
+        err = relerr(to_host(out), expect)
+        print(f"mfma forward {chans}: relative error {err:.2e}", flush=True)
+        assert err < 1e-2
+        # the FP32 forward is unchanged by the mode switch back
+        dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_FP32)
+        dwf.dwf_precond_apply(case.ctx, net, to_gpu(x), out)
+        assert relerr(to_host(out), expect) < 1e-5
+    finally:
+        dwf.dwf_net_destroy(net)
+
+
+def test_precond_apply_mfma_ragged_tile():
+    """A lattice whose 3 x (5D sites) columns do not fill the last 128-column tile."""
+    c = Case((4, 2, 2, 2), 3, mf=0.1, dirichlet=(0, 1, 0, 0), eps=0.5, seed=52)
+    Ws = random_weights(CHANS, 4)
+    net = dwf.dwf_net_create(c.ctx, CHANS)
+    try:
+        dwf.dwf_net_set_weights(net, flat(Ws))
+        dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_MFMA_BF16)
+        x = c.half(65)
+        out = torch().empty_like(to_gpu(x))
+        dwf.dwf_precond_apply(c.ctx, net, to_gpu(x), out)
+        expect = oracle.pick(c.P, oracle_forward(c, Ws, x)[-1], 1)
+        assert relerr(to_host(out), expect) < 1e-2
+    finally:
+        dwf.dwf_net_destroy(net)
+        c.close()
+
+
 def test_backward_matches_oracle(case):
     Ws = random_weights(CHANS, 2)
     net = dwf.dwf_net_create(case.ctx, CHANS)
