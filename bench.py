@@ -170,7 +170,7 @@ def measured_traffic():
 WEIGHTS = os.path.join(ROOT, "paper_2203_17119_amd", "weights", "ptc_4-12-12-12-4_8x8x8x8_ls8.npz")
 
 
-def learned_precond(lat, dwf, torch, b, tol, restart=32, maxit=2000, mfma=True):
+def learned_precond(lat, dwf, torch, b, tol, restart=32, maxit=2000, mfma=True, mode=None):
     """FGCR(restart) on the Schur system, right-preconditioned by the trained
     network (matrix-core or FP32 forward), to tol in the FP64 full residual
     (CG fallback on stagnation)."""
@@ -182,13 +182,16 @@ def learned_precond(lat, dwf, torch, b, tol, restart=32, maxit=2000, mfma=True):
         x = torch.zeros_like(b)
         dwf.dwf_kernel_timing_reset(lat.ctx)
         dwf.dwf_kernel_timing(lat.ctx, 1)
-        s, st = dwf.dwf_fgcr(lat.ctx, net, b, x, tol=tol, restart=restart, maxit=maxit, fallback=True)
+        mode = dwf.DWF_SOLVE_MIXED_F32 if mode is None else mode
+        s, st = dwf.dwf_fgcr(lat.ctx, net, b, x, tol=tol, restart=restart, maxit=maxit, fallback=True, mode=mode)
         kn = dwf.dwf_kernel_stats(lat.ctx, dwf.DWF_K_NET)
         dwf.dwf_kernel_timing(lat.ctx, 0)
     finally:
         dwf.dwf_net_destroy(net)
     return {"solver": f"FGCR({restart}) + PTC network 4-12-12-12-4 (trained on 8^4x8), "
-                      f"{'matrix-core BF16' if mfma else 'FP32'} forward", "status": s,
+                      f"{'matrix-core BF16' if mfma else 'FP32'} forward, "
+                      f"{'FP32 cycles + FP64 restarts' if mode == dwf.DWF_SOLVE_MIXED_F32 else 'FP64'}",
+            "status": s,
             "iters": st["iters"], "seconds": round(st["seconds"], 3), "res_full": st["res_full"],
             "converged": st["converged"], "fell_back": st["fell_back"],
             "network_ms": round(kn["ms"], 1), "network_launches": kn["launches"]}
@@ -311,8 +314,9 @@ def main():
     if not args.no_precond:
         lp = learned_precond(lat, dwf, torch, srcs[0], w.tol, mfma=True)
         log(f"learned preconditioner: {lp}")
-        lp["fp32_forward"] = learned_precond(lat, dwf, torch, srcs[0], w.tol, mfma=False)
-        log(f"learned preconditioner, FP32 forward: {lp['fp32_forward']}")
+        lp["fp64_fgcr_fp32_forward"] = learned_precond(lat, dwf, torch, srcs[0], w.tol, mfma=False,
+                                                       mode=dwf.DWF_SOLVE_F64)
+        log(f"learned preconditioner, FP64 FGCR, FP32 forward: {lp['fp64_fgcr_fp32_forward']}")
     table = None if args.no_table else dhop_table(lat, dwf, torch)
     cpu = None if args.no_cpu else cpu_baseline(w, U, b0_host)
 

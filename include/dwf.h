@@ -225,7 +225,11 @@ dwf_status dwf_net_train_step(dwf_net net, int nbatch, const double *const *b_od
 
 /* Flexible GCR(m) on the odd Schur system Mpc x_o = b~_o (o->normal = 0) or on
  * Mpc^+ Mpc x_o = Mpc^+ b~_o (o->normal = 1), right-preconditioned by net
- * (NULL: plain GCR; normal equations use N N^+), FP64 vectors, restart every
+ * (NULL: plain GCR; normal equations use N N^+).  o->mode DWF_SOLVE_F64 keeps
+ * every vector in FP64; DWF_SOLVE_MIXED_F32 runs the cycle (operator, network
+ * input and output, Krylov vectors) in FP32 storage with FP64 sums and folds
+ * each cycle's solution into the FP64 solution, whose residual is recomputed
+ * in FP64 at every restart (other modes: DWF_ENOTSUP).  Restart every
  * o->restart steps (default 16, at most 64) with the residual recomputed.
  * Stagnation means no 10% reduction of the residual norm over max(8 m, 256)
  * steps.  On stagnation or a non-finite residual it falls back to dwf_cg in

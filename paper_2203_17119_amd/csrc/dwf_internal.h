@@ -233,17 +233,18 @@ int launch_cg_update_xr(Context &c, int prec, Field x, Field r, Field p, Field a
 // p = r + beta p, pa = A p (beta = dscal[ib]); with ia >= 0 first x += alpha p
 // (alpha = dscal[ia], x in the accumulator precision of prec)
 void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pa, int ib, Field x = Field{}, int ia = -1);
-// Block Gram-Schmidt of flexible GCR (FP64 fields as flat complex arrays).
-// gs_dots: out[2j], out[2j+1] = Re, Im <X_j, y>, j < nv (X_dev: device array of
-// nv pointers; partial: gs_partials_needed doubles).  gs_project: y -= sum b_j X_j,
-// w -= sum b_j W_j, b_j = <X_j, y> / nq[3 j]; out = {|y|^2, Re <y, r>, Im <y, r>}.
-// gs_update: x += a z, r -= a q with a = (coef[1] + i coef[2]) / coef[0];
-// returns the number of |r|^2 partials written to c.partials.
+// Block Gram-Schmidt of flexible GCR (FP64 or FP32 fields as flat complex
+// arrays, FP64 sums).  gs_dots: out[2j], out[2j+1] = Re, Im <X_j, y>, j < nv
+// (X_dev: device array of nv field pointers; partial: gs_partials_needed
+// doubles).  gs_project: y -= sum b_j X_j, w -= sum b_j W_j, b_j = <X_j, y> /
+// nq[3 j]; out = {|y|^2, Re <y, r>, Im <y, r>}.  gs_update: x += a z, r -= a q
+// with a = (coef[1] + i coef[2]) / coef[0]; returns the number of |r|^2
+// partials written to c.partials.
 long gs_partials_needed(const Context &c, int nv);
-void launch_gs_dots(Context &c, const double2 *const *X_dev, int nv, Field y, double *partial, double *out);
-void launch_gs_project(Context &c, const double2 *const *X_dev, const double2 *const *W_dev, int nv,
+void launch_gs_dots(Context &c, int prec, const void *const *X_dev, int nv, Field y, double *partial, double *out);
+void launch_gs_project(Context &c, int prec, const void *const *X_dev, const void *const *W_dev, int nv,
                        const double *dots, const double *nq, Field y, Field w, Field r, double *partial, double *out);
-int launch_gs_update(Context &c, Field x, Field z, Field r, Field q, const double *coef);
+int launch_gs_update(Context &c, int prec, Field x, Field z, Field r, Field q, const double *coef);
 // x += dscal[ia] p, x in the accumulator precision of prec
 void launch_axpy_dev(Context &c, int prec, Field x, Field p, int ia);
 // device scalar arithmetic: dscal[out] = dscal[num] / dscal[den]

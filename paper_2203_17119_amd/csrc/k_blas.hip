@@ -343,18 +343,33 @@ __global__ void __launch_bounds__(BS) k_finish_b(const double *partial, int npar
 }
 
 // ---------------------------------------------------------------------------
-// Block Gram-Schmidt for flexible GCR.  FP64 fields are viewed as flat complex
-// arrays of m elements (the inner product does not depend on the layout).
-// Each thread owns GS_EPT elements of one chunk; partial sums are written per
-// workgroup, member-major ([member][block]), and summed in a fixed order.
+// Block Gram-Schmidt for flexible GCR.  FP64 or FP32 fields are viewed as flat
+// complex arrays of m elements (the inner product does not depend on the
+// layout); sums are accumulated in FP64.  Each thread owns GS_EPT elements of
+// one chunk; partial sums are written per workgroup, member-major
+// ([member][block]), and summed in a fixed order.
 
 static constexpr int GS_EPT = 8;
 
 static long gs_blocks(long m) { return (m + (long)BS * GS_EPT - 1) / ((long)BS * GS_EPT); }
 
+template <typename T2>
+__device__ __forceinline__ double2 ld2(const T2 *p, long k)
+{
+    const T2 v = p[k];
+    return make_double2(double(v.x), double(v.y));
+}
+
+template <typename T2>
+__device__ __forceinline__ void st2(T2 *p, long k, double2 v)
+{
+    using R = decltype(T2{}.x);
+    p[k] = T2{R(v.x), R(v.y)};
+}
+
 // partial[(2j + {0,1}) nblk + blk] = Re, Im of sum conj(X_j) y over the chunk, j < nv
-__global__ void __launch_bounds__(BS) k_gs_dots(const double2 *const *X, int nv, const double2 *y, long m,
-                                                double *partial)
+template <typename T2>
+__global__ void __launch_bounds__(BS) k_gs_dots(const T2 *const *X, int nv, const T2 *y, long m, double *partial)
 {
     const long nblk = gridDim.x;
     const long base = (long)blockIdx.x * BS * GS_EPT + threadIdx.x;
@@ -362,16 +377,16 @@ __global__ void __launch_bounds__(BS) k_gs_dots(const double2 *const *X, int nv,
 #pragma unroll
     for (int e = 0; e < GS_EPT; e++) {
         const long k = base + (long)e * BS;
-        yv[e] = k < m ? y[k] : make_double2(0.0, 0.0);
+        yv[e] = k < m ? ld2(y, k) : make_double2(0.0, 0.0);
     }
     for (int j = 0; j < nv; j++) {
-        const double2 *x = X[j];
+        const T2 *x = X[j];
         double re = 0, im = 0;
 #pragma unroll
         for (int e = 0; e < GS_EPT; e++) {
             const long k = base + (long)e * BS;
             if (k < m) {
-                const double2 xv = x[k];
+                const double2 xv = ld2(x, k);
                 re += xv.x * yv[e].x + xv.y * yv[e].y;
                 im += xv.x * yv[e].y - xv.y * yv[e].x;
             }
@@ -387,9 +402,10 @@ __global__ void __launch_bounds__(BS) k_gs_dots(const double2 *const *X, int nv,
 
 // y -= sum_j b_j X_j, w -= sum_j b_j W_j with b_j = dots_j / nq[3 j] (dots_j =
 // <X_j, y> as Re, Im pairs); partials of |y|^2 and <y, r> (new y) as members 0..2
-__global__ void __launch_bounds__(BS) k_gs_project(const double2 *const *X, const double2 *const *W, int nv,
-                                                   const double *dots, const double *nq, double2 *y, double2 *w,
-                                                   const double2 *r, long m, double *partial)
+template <typename T2>
+__global__ void __launch_bounds__(BS) k_gs_project(const T2 *const *X, const T2 *const *W, int nv, const double *dots,
+                                                   const double *nq, T2 *y, T2 *w, const T2 *r, long m,
+                                                   double *partial)
 {
     const long nblk = gridDim.x;
     const long base = (long)blockIdx.x * BS * GS_EPT + threadIdx.x;
@@ -398,19 +414,20 @@ __global__ void __launch_bounds__(BS) k_gs_project(const double2 *const *X, cons
     for (int e = 0; e < GS_EPT; e++) {
         const long k = base + (long)e * BS;
         if (k >= m) continue;
-        double2 yv = y[k], wv = w[k];
+        double2 yv = ld2(y, k), wv = ld2(w, k);
         for (int j = 0; j < nv; j++) {
             const double inv = 1.0 / nq[3 * j];
             const double bre = dots[2 * j] * inv, bim = dots[2 * j + 1] * inv;
-            const double2 xv = X[j][k], vv = W[j][k];
+            const double2 xv = ld2(X[j], k), vv = ld2(W[j], k);
             yv.x -= bre * xv.x - bim * xv.y;
             yv.y -= bre * xv.y + bim * xv.x;
             wv.x -= bre * vv.x - bim * vv.y;
             wv.y -= bre * vv.y + bim * vv.x;
         }
-        y[k] = yv;
-        w[k] = wv;
-        const double2 rv = r[k];
+        st2(y, k, yv);
+        st2(w, k, wv);
+        yv = ld2(y, k);  // as stored
+        const double2 rv = ld2(r, k);
         n2 += yv.x * yv.x + yv.y * yv.y;
         dre += yv.x * rv.x + yv.y * rv.y;
         dim_ += yv.x * rv.y - yv.y * rv.x;
@@ -426,8 +443,9 @@ __global__ void __launch_bounds__(BS) k_gs_project(const double2 *const *X, cons
 }
 
 // a = <q, r> / |q|^2 (coef = {|q|^2, Re, Im}); x += a z, r -= a q; partials |r|^2
-__global__ void __launch_bounds__(BS) k_gs_update(double2 *x, const double2 *z, double2 *r, const double2 *q,
-                                                  const double *coef, long m, double *partial)
+template <typename T2>
+__global__ void __launch_bounds__(BS) k_gs_update(T2 *x, const T2 *z, T2 *r, const T2 *q, const double *coef, long m,
+                                                  double *partial)
 {
     const long base = (long)blockIdx.x * BS * GS_EPT + threadIdx.x;
     const double inv = 1.0 / coef[0];
@@ -437,14 +455,14 @@ __global__ void __launch_bounds__(BS) k_gs_update(double2 *x, const double2 *z, 
     for (int e = 0; e < GS_EPT; e++) {
         const long k = base + (long)e * BS;
         if (k >= m) continue;
-        const double2 zv = z[k], qv = q[k];
-        double2 xv = x[k], rv = r[k];
+        const double2 zv = ld2(z, k), qv = ld2(q, k);
+        double2 xv = ld2(x, k), rv = ld2(r, k);
         xv.x += are * zv.x - aim * zv.y;
         xv.y += are * zv.y + aim * zv.x;
         rv.x -= are * qv.x - aim * qv.y;
         rv.y -= are * qv.y + aim * qv.x;
-        x[k] = xv;
-        r[k] = rv;
+        st2(x, k, xv);
+        st2(r, k, rv);
         n2 += rv.x * rv.x + rv.y * rv.y;
     }
     n2 = block_sum(n2);
@@ -765,36 +783,61 @@ void launch_accumulate_low(Context &c, int prec, Field xh, Field xl)
 
 long gs_partials_needed(const Context &c, int nv) { return gs_blocks(12 * c.n5h) * std::max(3, 2 * nv); }
 
-void launch_gs_dots(Context &c, const double2 *const *X_dev, int nv, Field y, double *partial, double *out)
+static void gs_prec_check(int prec)
 {
+    if (prec != P_F64 && prec != P_F32) fail(DWF_ENOTSUP, "Gram-Schmidt vectors must be FP64 or FP32");
+}
+
+void launch_gs_dots(Context &c, int prec, const void *const *X_dev, int nv, Field y, double *partial, double *out)
+{
+    gs_prec_check(prec);
     const long m = 12 * y.n, nblk = gs_blocks(m);
-    Timer tm(c, DWF_K_BLAS, (nv + 1.0) * 16.0 * m, 8.0 * nv * m);
-    hipLaunchKernelGGL(k_gs_dots, dim3((unsigned)nblk), dim3(BS), 0, c.stream, X_dev, nv, (const double2 *)y.data, m,
-                       partial);
+    const double eb = prec == P_F64 ? 16.0 : 8.0;
+    Timer tm(c, DWF_K_BLAS, (nv + 1.0) * eb * m, 8.0 * nv * m, prec);
+    if (prec == P_F64)
+        hipLaunchKernelGGL(k_gs_dots<double2>, dim3((unsigned)nblk), dim3(BS), 0, c.stream,
+                           (const double2 *const *)X_dev, nv, (const double2 *)y.data, m, partial);
+    else
+        hipLaunchKernelGGL(k_gs_dots<float2>, dim3((unsigned)nblk), dim3(BS), 0, c.stream,
+                           (const float2 *const *)X_dev, nv, (const float2 *)y.data, m, partial);
     HIPCHECK(hipGetLastError());
     hipLaunchKernelGGL(k_finish_b, dim3(2 * nv), dim3(BS), 0, c.stream, partial, (int)nblk, out);
     HIPCHECK(hipGetLastError());
 }
 
-void launch_gs_project(Context &c, const double2 *const *X_dev, const double2 *const *W_dev, int nv,
+void launch_gs_project(Context &c, int prec, const void *const *X_dev, const void *const *W_dev, int nv,
                        const double *dots, const double *nq, Field y, Field w, Field r, double *partial, double *out)
 {
+    gs_prec_check(prec);
     const long m = 12 * y.n, nblk = gs_blocks(m);
-    Timer tm(c, DWF_K_BLAS, (2.0 * nv + 5.0) * 16.0 * m, (16.0 * nv + 12.0) * m);
-    hipLaunchKernelGGL(k_gs_project, dim3((unsigned)nblk), dim3(BS), 0, c.stream, X_dev, W_dev, nv, dots, nq,
-                       (double2 *)y.data, (double2 *)w.data, (const double2 *)r.data, m, partial);
+    const double eb = prec == P_F64 ? 16.0 : 8.0;
+    Timer tm(c, DWF_K_BLAS, (2.0 * nv + 5.0) * eb * m, (16.0 * nv + 12.0) * m, prec);
+    if (prec == P_F64)
+        hipLaunchKernelGGL(k_gs_project<double2>, dim3((unsigned)nblk), dim3(BS), 0, c.stream,
+                           (const double2 *const *)X_dev, (const double2 *const *)W_dev, nv, dots, nq,
+                           (double2 *)y.data, (double2 *)w.data, (const double2 *)r.data, m, partial);
+    else
+        hipLaunchKernelGGL(k_gs_project<float2>, dim3((unsigned)nblk), dim3(BS), 0, c.stream,
+                           (const float2 *const *)X_dev, (const float2 *const *)W_dev, nv, dots, nq,
+                           (float2 *)y.data, (float2 *)w.data, (const float2 *)r.data, m, partial);
     HIPCHECK(hipGetLastError());
     hipLaunchKernelGGL(k_finish_b, dim3(3), dim3(BS), 0, c.stream, partial, (int)nblk, out);
     HIPCHECK(hipGetLastError());
 }
 
-int launch_gs_update(Context &c, Field x, Field z, Field r, Field q, const double *coef)
+int launch_gs_update(Context &c, int prec, Field x, Field z, Field r, Field q, const double *coef)
 {
+    gs_prec_check(prec);
     const long m = 12 * x.n, nblk = gs_blocks(m);
     need_partials(c, nblk, 1);
-    Timer tm(c, DWF_K_BLAS, 6.0 * 16.0 * m, 18.0 * m);
-    hipLaunchKernelGGL(k_gs_update, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (double2 *)x.data,
-                       (const double2 *)z.data, (double2 *)r.data, (const double2 *)q.data, coef, m, c.partials);
+    const double eb = prec == P_F64 ? 16.0 : 8.0;
+    Timer tm(c, DWF_K_BLAS, 6.0 * eb * m, 18.0 * m, prec);
+    if (prec == P_F64)
+        hipLaunchKernelGGL(k_gs_update<double2>, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (double2 *)x.data,
+                           (const double2 *)z.data, (double2 *)r.data, (const double2 *)q.data, coef, m, c.partials);
+    else
+        hipLaunchKernelGGL(k_gs_update<float2>, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (float2 *)x.data,
+                           (const float2 *)z.data, (float2 *)r.data, (const float2 *)q.data, coef, m, c.partials);
     HIPCHECK(hipGetLastError());
     return (int)nblk;
 }

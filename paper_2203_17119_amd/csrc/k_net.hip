@@ -133,11 +133,10 @@ __global__ void __launch_bounds__(256) k_ptc_fwd(NetGeo g, const float2 *in, flo
 // of M = COUT, K = 11 CIN over all columns.  It runs in real form,
 //   [Re out; Im out] = [[Wr, -Wi], [Wi, Wr]] [Re T; Im T],
 // as 32 x 32 x 8 BF16 MFMA tiles with FP32 accumulation (rows m' = 2a + re/im,
-// K index k' = 2q + re/im).  A wavefront owns 32 columns; each lane builds the
-// transported values of its own column in FP32 on the vector units (one link
-// row per path) and rounds them to BF16 for the B operand.  The weights are
-// BF16 already, so the A operand is exact; it is packed once per weight update
-// in operand order [step][lane][4].
+// K index k' = 2q + re/im).  The transported inputs are built in FP32 on the
+// vector units and rounded to BF16 for the B operand.  The weights are BF16
+// already, so the A operand is exact; it is packed once per weight update in
+// operand order [step][lane][4].
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -168,73 +167,113 @@ __global__ void k_pack_mfma_weights(const __hip_bfloat162 *w, short *pk)
     pk[t] = bf16_bits(v);
 }
 
+// One workgroup takes MF_S consecutive 5D sites (3 MF_S columns, column =
+// colour * MF_S + site).  Per path, every thread transports the input channels
+// of one site (two threads per site, half the channels each): one link load,
+// 3 x 3 complex products per channel on the vector units, BF16 rounding, into
+// LDS as B operand rows [channel pair][column].  The four wavefronts then run
+// the path's MFMA steps, three column tiles each.
+static constexpr int MF_S = 128;
+
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) k_ptc_fwd_mfma(NetGeo g, const float2 *in, float2 *out, const short *wpk, int p,
                                                       long n)
 {
     static_assert(CIN % 4 == 0 && 2 * COUT <= 32, "channel counts");
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int h = lane >> 5;
-    const long col = ((long)blockIdx.x * 4 + wave) * 32 + (lane & 31);  // (5D site, colour)
-    const bool ok = col < 3 * n;
-    const long i = ok ? col / 3 : 0;
-    const int cc = ok ? (int)(col - 3 * i) : 0;
-    const long j = i / g.Ls;
-    const int s = (int)(i - j * g.Ls);
+    constexpr int NCOL = 3 * MF_S, NP = CIN / 2, HP = NP / 2;
+    __shared__ bf16x4 Tb[NP * NCOL];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, jc = lane & 31;
+    const long i0 = (long)blockIdx.x * MF_S;
+    // transport role: site ts, channel pairs [th HP, th HP + HP)
+    const int ts = tid % MF_S, th = tid / MF_S;
+    const long it = i0 + ts;
+    const bool ok = it < n;
+    const long j = ok ? it / g.Ls : 0;
+    const int s = ok ? (int)(it - j * g.Ls) : 0;
     const bf16x4 *A = (const bf16x4 *)wpk + lane;
-    f32x16 acc;
+    f32x16 acc[3];
 #pragma unroll
-    for (int r = 0; r < 16; r++) acc[r] = 0.f;
+    for (int t = 0; t < 3; t++)
+#pragma unroll
+        for (int r = 0; r < 16; r++) acc[t][r] = 0.f;
     for (int pi = 0; pi < 11; pi++) {
         long src = 0;
         int sp = p;
         const bool have = ok && path_source(g, p, pi, j, s, src, sp);
         const bool hop = pi >= 1 && pi <= 8;
-        cx<float> u0 = mk(0.f, 0.f), u1 = u0, u2 = u0;
+        cx<float> u[9];
         if (have && hop) {
-            const float2 *L = (p ? g.links1 : g.links0) + ((long)(pi - 1) * 9 + 3 * cc) * g.vh + j;
-            u0 = c2(L[0]);
-            u1 = c2(L[g.vh]);
-            u2 = c2(L[2 * g.vh]);
+            const float2 *L = (p ? g.links1 : g.links0) + (long)(pi - 1) * 9 * g.vh + j;
+#pragma unroll
+            for (int k = 0; k < 9; k++) u[k] = c2(L[(long)k * g.vh]);
         }
         const float2 *base = in + (long)sp * CIN * 3 * n + src;
 #pragma unroll
-        for (int u = 0; u < CIN / 4; u++) {
-            const int b0 = 4 * u + 2 * h;
-            cx<float> t0 = mk(0.f, 0.f), t1 = t0;
-            if (have) {
-                if (hop) {
-                    const float2 *f0 = base + (long)(b0 * 3) * n, *f1 = base + (long)((b0 + 1) * 3) * n;
-                    t0 = cmul(u0, c2(f0[0]));
-                    cmac(t0, u1, c2(f0[n]));
-                    cmac(t0, u2, c2(f0[2 * n]));
-                    t1 = cmul(u0, c2(f1[0]));
-                    cmac(t1, u1, c2(f1[n]));
-                    cmac(t1, u2, c2(f1[2 * n]));
+        for (int q = 0; q < HP; q++) {
+            const int pp = th * HP + q;
+            cx<float> t[2][3];
+#pragma unroll
+            for (int e = 0; e < 2; e++) {
+                const float2 *f = base + (long)((2 * pp + e) * 3) * n;
+                if (have) {
+                    const cx<float> v0 = c2(f[0]), v1 = c2(f[n]), v2 = c2(f[2 * n]);
+                    if (hop) {
+#pragma unroll
+                        for (int r = 0; r < 3; r++) {
+                            t[e][r] = cmul(u[3 * r], v0);
+                            cmac(t[e][r], u[3 * r + 1], v1);
+                            cmac(t[e][r], u[3 * r + 2], v2);
+                        }
+                    } else {
+                        t[e][0] = v0;
+                        t[e][1] = v1;
+                        t[e][2] = v2;
+                    }
                 } else {
-                    t0 = c2(base[(long)(b0 * 3 + cc) * n]);
-                    t1 = c2(base[(long)((b0 + 1) * 3 + cc) * n]);
+#pragma unroll
+                    for (int r = 0; r < 3; r++) t[e][r] = mk(0.f, 0.f);
                 }
             }
-            bf16x4 bf;
-            bf[0] = bf16_bits(t0.re);
-            bf[1] = bf16_bits(t0.im);
-            bf[2] = bf16_bits(t1.re);
-            bf[3] = bf16_bits(t1.im);
-            const int step = pi * (CIN / 4) + u;
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A[step * 64], bf, acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                bf16x4 v;
+                v[0] = bf16_bits(t[0][r].re);
+                v[1] = bf16_bits(t[0][r].im);
+                v[2] = bf16_bits(t[1][r].re);
+                v[3] = bf16_bits(t[1][r].im);
+                Tb[pp * NCOL + r * MF_S + ts] = v;
+            }
         }
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < CIN / 4; st++) {
+            const bf16x4 a = A[(pi * (CIN / 4) + st) * 64];
+#pragma unroll
+            for (int tt = 0; tt < 3; tt++) {
+                const bf16x4 b = Tb[(2 * st + h) * NCOL + (wave * 3 + tt) * 32 + jc];
+                acc[tt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[tt], 0, 0, 0);
+            }
+        }
+        __syncthreads();
     }
-    if (!ok) return;
-    // accumulator register r holds row m' = 8 (r / 4) + 4 h + r % 4 of this column
+    // accumulator register r of tile tt holds row m' = 8 (r / 4) + 4 h + r % 4 of column
+    // (tile * 32 + jc): colour col / MF_S, site col % MF_S
     float2 *o = out + (long)p * COUT * 3 * n;
 #pragma unroll
-    for (int q = 0; q < 4; q++)
+    for (int tt = 0; tt < 3; tt++) {
+        const int col = (wave * 3 + tt) * 32 + jc;
+        const int cc = col / MF_S;
+        const long i = i0 + (col - cc * MF_S);
+        if (i >= n) continue;
 #pragma unroll
-        for (int hh = 0; hh < 2; hh++) {
-            const int a = 4 * q + 2 * h + hh;
-            if (a < COUT) o[(long)(a * 3 + cc) * n + i] = make_float2(acc[4 * q + 2 * hh], acc[4 * q + 2 * hh + 1]);
-        }
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int hh = 0; hh < 2; hh++) {
+                const int a = 4 * q + 2 * h + hh;
+                if (a < COUT)
+                    o[(long)(a * 3 + cc) * n + i] = make_float2(acc[tt][4 * q + 2 * hh], acc[tt][4 * q + 2 * hh + 1]);
+            }
+    }
 }
 
 // Weight gradient of one layer over the output sites of parity p:
@@ -459,8 +498,7 @@ void launch_pack_mfma_weights(Context &c, int cin, int cout, const void *w_bf16,
 void launch_ptc_layer_mfma(Context &c, int cin, int cout, const float2 *in, float2 *out, const short *pk, int p)
 {
     const NetGeo g = net_geo(c);
-    const long ncol = 3 * c.n5h;
-    const dim3 grid((unsigned)((ncol + 127) / 128)), blk(256);
+    const dim3 grid((unsigned)((c.n5h + MF_S - 1) / MF_S)), blk(256);
     const double flops = (double)c.n5h * (11.0 * cout * cin * 3 * 8 + 8.0 * cin * 66);
     Timer tm(c, DWF_K_NET, (double)c.n5h * 8.0 * 3 * (11 * cin + cout), flops);
 #define NETL(CI, CO) hipLaunchKernelGGL((k_ptc_fwd_mfma<CI, CO>), grid, blk, 0, c.stream, g, in, out, pk, p, c.n5h)

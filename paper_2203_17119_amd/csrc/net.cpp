@@ -352,19 +352,19 @@ dwf_status dwf_net_train_step(dwf_net net, int nbatch, const double *const *b_od
 
 namespace dwf {
 
-// z = N(r) (normal = false) or N N^+ r (normal = true), FP64 odd fields
-static void precondition(dwf_net_s *n, Field r, Field z, bool normal)
+// z = N(r) (normal = false) or N N^+ r (normal = true), odd fields of precision prec
+static void precondition(dwf_net_s *n, int prec, Field r, Field z, bool normal)
 {
     Context &c = *n->c;
-    launch_spinor_to_feat(c, P_F64, r, n->acts[0], 1, true);
+    launch_spinor_to_feat(c, prec, r, n->acts[0], 1, true);
     if (normal) {
         // N^+ r: adjoint network on the embedded residual, then N on its result
         const float2 *adj = net_adjoint(n, n->acts[0]);
-        launch_feat_to_spinor(c, P_F64, adj, z, 1);  // keep odd part only
-        launch_spinor_to_feat(c, P_F64, z, n->acts[0], 1, true);
+        launch_feat_to_spinor(c, prec, adj, z, 1);  // keep odd part only
+        launch_spinor_to_feat(c, prec, z, n->acts[0], 1, true);
     }
     net_forward(n, false, n->fwd == DWF_NET_FWD_MFMA_BF16);
-    launch_feat_to_spinor(c, P_F64, n->acts[n->nlayer], z, 1);
+    launch_feat_to_spinor(c, prec, n->acts[n->nlayer], z, 1);
 }
 
 static double dnorm2(Context &c, Field a)
@@ -384,14 +384,14 @@ static void ddot(Context &c, Field a, Field b, double &re, double &im)
     im = c.hscal[15];
 }
 
-static void fgcr_op(Context &c, Field in, Field out, bool normal)
+static void fgcr_op(Context &c, int prec, Field in, Field out, bool normal)
 {
     if (normal) {
-        Field t = ws_field(c, "fg_t", P_F64);
-        apply_mpc(c, P_F64, false, in, t, false);
-        apply_mpc(c, P_F64, true, t, out, false);
+        Field t = ws_field(c, "fg_t", prec);
+        apply_mpc(c, prec, false, in, t, false);
+        apply_mpc(c, prec, true, t, out, false);
     } else {
-        apply_mpc(c, P_F64, false, in, out, false);
+        apply_mpc(c, prec, false, in, out, false);
     }
 }
 
@@ -409,6 +409,12 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
     const int m = (o && o->restart > 0) ? std::min(o->restart, 64) : 16;
     const bool normal = o && o->normal;
     const bool fallback = !o || o->fallback;
+    // inner precision: FP64, or FP32 vectors and operator with the solution and
+    // the residual of every restart kept in FP64 (reliable restarts)
+    const int mode = o ? o->mode : DWF_SOLVE_F64;
+    if (mode != DWF_SOLVE_F64 && mode != DWF_SOLVE_MIXED_F32) fail(DWF_ENOTSUP, "FGCR mode must be F64 or MIXED_F32");
+    const int lp = mode == DWF_SOLVE_MIXED_F32 ? P_F32 : P_F64;
+    const bool mixed = lp != P_F64;
     HIPCHECK(hipStreamSynchronize(c.stream));
     const double t0 = wall();
     Field be = ws_field(c, "sv_be", P_F64), bo = ws_field(c, "sv_bo", P_F64), bt = ws_field(c, "sv_bt", P_F64);
@@ -427,9 +433,10 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
     else launch_copy(c, P_F64, bt, rhs);
     std::vector<Field> Z, Q;
     for (int k = 0; k < m; k++) {
-        Z.push_back(ws_field(c, "fg_z" + std::to_string(k), P_F64));
-        Q.push_back(ws_field(c, "fg_q" + std::to_string(k), P_F64));
+        Z.push_back(ws_field(c, "fg_z" + std::to_string(k), lp));
+        Q.push_back(ws_field(c, "fg_q" + std::to_string(k), lp));
     }
+    Field rl = mixed ? ws_field(c, "fg_rl", lp) : r, xl = mixed ? ws_field(c, "fg_xl", lp) : x;
     // device pointer tables of the Krylov vectors, Gram-Schmidt coefficients
     // (dots[2m]; info[3k] = {|q_k|^2, <q_k, r>} per step) and partial sums
     struct Dev {
@@ -450,8 +457,8 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
         }
         HIPCHECK(hipMemcpy(tab.p, h.data(), h.size() * sizeof(void *), hipMemcpyHostToDevice));
     }
-    const double2 *const *qtab = (const double2 *const *)tab.p;
-    const double2 *const *ztab = qtab + m;
+    void *const *qtab = (void *const *)tab.p;
+    void *const *ztab = qtab + m;
     double *dots = (double *)coef.p, *info = dots + 2 * m;
     double *partial = (double *)part.p;
     HIPCHECK(hipStreamSynchronize(c.stream));
@@ -459,21 +466,24 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
     const double bn = std::sqrt(dnorm2(c, rhs));
     launch_zero(c, P_F64, x);
     launch_copy(c, P_F64, rhs, r);
+    if (mixed) launch_zero(c, lp, xl);
     int it = 0;
     bool conv = bn == 0.0, stalled = false;
     double best = bn;
     int since_best = 0;
     while (!conv && !stalled && it < maxit) {
         int k = 0;
+        if (mixed) launch_convert(c, P_F64, r, lp, rl);
         for (; k < m && it < maxit; k++) {
-            if (net) precondition(net, r, Z[k], normal);
-            else launch_copy(c, P_F64, r, Z[k]);
-            fgcr_op(c, Z[k], Q[k], normal);
+            if (net) precondition(net, lp, rl, Z[k], normal);
+            else launch_copy(c, lp, rl, Z[k]);
+            fgcr_op(c, lp, Z[k], Q[k], normal);
             // classical Gram-Schmidt against the cycle's earlier directions in
             // one pass over the vectors; the residual stays orthogonal to them
-            if (k > 0) launch_gs_dots(c, qtab, k, Q[k], partial, dots);
-            launch_gs_project(c, qtab, ztab, k, dots, info, Q[k], Z[k], r, partial, info + 3 * k);
-            const int np = launch_gs_update(c, x, Z[k], r, Q[k], info + 3 * k);
+            if (k > 0) launch_gs_dots(c, lp, (const void *const *)qtab, k, Q[k], partial, dots);
+            launch_gs_project(c, lp, (const void *const *)qtab, (const void *const *)ztab, k, dots, info, Q[k], Z[k],
+                              rl, partial, info + 3 * k);
+            const int np = launch_gs_update(c, lp, xl, Z[k], rl, Q[k], info + 3 * k);
             launch_finish(c, np, 1, 12);
             read_scalars(c, 12, 1);
             it++;
@@ -491,8 +501,9 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
             }
             if (rn <= tol * bn) break;
         }
-        // restart: true residual
-        fgcr_op(c, x, t1, normal);
+        // restart: fold the low-precision solution in, true residual in FP64
+        if (mixed) launch_accumulate_low(c, lp, x, xl);
+        fgcr_op(c, P_F64, x, t1, normal);
         launch_axpby(c, P_F64, 1.0, rhs, -1.0, t1, r);
         const double rn = std::sqrt(dnorm2(c, r));
         if (!std::isfinite(rn)) stalled = true;

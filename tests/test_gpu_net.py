@@ -233,6 +233,16 @@ def test_trained_network_gain_over_plain_gcr():
         r = b - oracle.d5(c.P, c.Ud, to_host(x))
         assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-7
         assert s0 != dwf.DWF_OK or st1["iters"] < 0.7 * st0["iters"]
+        # FP32 cycles with FP64 restarts and the matrix-core forward reach the same FP64 residual
+        dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_MFMA_BF16)
+        x.zero_()
+        s2, st2 = dwf.dwf_fgcr(c.ctx, net, to_gpu(b), x, tol=1e-8, restart=32, maxit=1500, fallback=False,
+                               mode=dwf.DWF_SOLVE_MIXED_F32)
+        print(f"mixed FP32 FGCR, matrix-core network: status {s2} {st2['iters']} steps res {st2['res_full']:.2e}",
+              flush=True)
+        assert s2 == dwf.DWF_OK and st2["fell_back"] == 0
+        r = b - oracle.d5(c.P, c.Ud, to_host(x))
+        assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-7
     finally:
         dwf.dwf_net_destroy(net)
         c.close()
