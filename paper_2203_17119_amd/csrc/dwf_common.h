@@ -216,6 +216,42 @@ __device__ __forceinline__ void load_spinor_unscaled(const Field &f, long i, cx<
     }
 }
 
+// a spinor as stored (planes and scale), to be unpacked later; lets a kernel
+// issue the load early without holding the unpacked components
+template <typename S>
+struct RawSpinor {
+    uint4 q[Planes<S>::n];
+    float norm;
+};
+
+template <typename S>
+__device__ __forceinline__ void load_raw(const Field &f, long i, RawSpinor<S> &r)
+{
+    using P = Planes<S>;
+    const uint4 *d = (const uint4 *)f.data;
+#pragma unroll
+    for (int q = 0; q < P::n; q++) r.q[q] = d[q * f.n + i];
+    r.norm = S::has_norm ? f.norm[i] : 1.f;
+}
+
+template <typename S, typename C>
+__device__ __forceinline__ void unpack_raw(const RawSpinor<S> &r, cx<C> v[12])
+{
+    using P = Planes<S>;
+    const C scale = C(r.norm);
+#pragma unroll
+    for (int q = 0; q < P::n; q++) {
+        Vec16 w;
+        w.u = r.q[q];
+#pragma unroll
+        for (int k = 0; k < P::cpp; k++) {
+            cx<C> t = unpack<C>(vec_get<S>(w, k));
+            if constexpr (S::has_norm) t = scale * t;
+            v[q * P::cpp + k] = t;
+        }
+    }
+}
+
 template <typename S, typename C>
 __device__ __forceinline__ void store_spinor(const Field &f, long i, const cx<C> v[12])
 {
@@ -274,6 +310,24 @@ __device__ __forceinline__ cx<C> shift5(const cx<C> *blk, int c, int s, int Ls, 
         f = -mf;
     }
     return f * blk[src * 12 + c];
+}
+
+// the same, with the block laid out component-major: rows[c * Ls + s]
+// (consecutive lanes s touch consecutive words: no LDS bank conflicts)
+template <typename C>
+__device__ __forceinline__ cx<C> shift5t(const cx<C> *rows, int c, int s, int Ls, bool dag, C mf)
+{
+    const bool up = c < 6;
+    int src = (up != dag) ? s - 1 : s + 1;
+    C f = C(1);
+    if (src < 0) {
+        src = Ls - 1;
+        f = -mf;
+    } else if (src >= Ls) {
+        src = 0;
+        f = -mf;
+    }
+    return f * rows[c * Ls + src];
 }
 
 // Sum of v over the workgroup (fixed order: wavefront tree, then waves in

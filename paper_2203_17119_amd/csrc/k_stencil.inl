@@ -244,6 +244,19 @@ __device__ __forceinline__ Field batch_member(Field f, long stride)
     return f;
 }
 
+// byte offset of the self-input region in LDS: behind the staged links and
+// behind the epilogue's hop results (and dense matrix), which alias the links
+template <typename C>
+__host__ __device__ inline size_t stencil_self_offset(int epi, int sb, int Ls, int lsc)
+{
+    const size_t links = (size_t)sb * (72 * sizeof(cx<C>) + 8 * sizeof(int));
+    size_t epil = 0;
+    if (epi == EPI_TOEP) epil = (size_t)sb * 12 * (lsc * sizeof(cx<C>) + 16);
+    else if (epi != EPI_NONE) epil = (size_t)sb * Ls * 12 * sizeof(cx<C>);
+    if (epi == EPI_DENSE) epil += 2 * (size_t)Ls * Ls * sizeof(C);
+    return ((links > epil ? links : epil) + 15) & ~(size_t)15;
+}
+
 // o = T a for the twisted-circulant T of first column f (g = -mf f)
 template <typename C, int LSC>
 __device__ __forceinline__ void toeplitz_apply(const cx<C> av[LSC], cx<C> o[LSC], const C f[LSC], const C g[LSC])
@@ -277,15 +290,37 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
     const bool valid = cb < a.vh;
     const long i = cb * Ls + s;
 
-    // LDS: staged links + neighbour indices during the hop, then reused for the
-    // fifth-dimension epilogue (hop results, self input, dense matrix)
+    // LDS: staged links + neighbour indices during the hop, reused afterwards
+    // by the epilogue (hop results, dense matrix); the self input has its own
+    // region behind both, filled before the hop (stencil_lds_bytes)
     extern __shared__ unsigned char smem[];
     cx<C> *lk = (cx<C> *)smem;
     int *nbs = (int *)(lk + 72 * sb);
     cx<C> *lds_h = (cx<C> *)smem;
-    cx<C> *lds_s = lds_h + ((EPI != EPI_NONE) ? sb * Ls * 12 : 0);
-    C *lds_e = (C *)(lds_s + (SELF ? sb * Ls * 12 : 0));
+    C *lds_e = (C *)(lds_h + sb * Ls * 12);
+    cx<C> *lds_s = (cx<C> *)(smem + stencil_self_offset<C>(EPI, sb, Ls, LSC));
 
+    if constexpr (SELF) {
+        // the self input goes to LDS before the hop: its load overlaps the link
+        // staging and the hop, and it holds no registers during the hop
+        cx<C> own[12];
+        if (valid) {
+            load_spinor<S, C>(a.self, i, own);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; c++) own[c] = mk(C(0), C(0));
+        }
+        cx<C> *bs = lds_s + j * 12 * Ls + s;  // component-major rows [c][s]
+#pragma unroll
+        for (int c = 0; c < 12; c++) bs[c * Ls] = own[c];
+    }
+    // residual of the fused CG update: issued now, used after the hop
+    // (16-bit storage only; wider formats would hold too many registers)
+    constexpr bool PRE_R = RED == 2 && sizeof(typename S::elem) == 4;
+    RawSpinor<S> r_raw;
+    if constexpr (PRE_R) {
+        if (valid) load_raw<S>(a.out, i, r_raw);
+    }
     stage_links<S, C>(a, (long)tile * sb, sb, lk, nbs);
     __syncthreads();
     cx<C> acc[12];
@@ -301,17 +336,8 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
         hop_step<S, C, 6, DAG>(acc, a, lk, nbs, j, sb, s);
         hop_step<S, C, 7, DAG>(acc, a, lk, nbs, j, sb, s);
     }
-    if constexpr (EPI != EPI_NONE || SELF) __syncthreads();  // the staged links are dead from here
+    if constexpr (EPI != EPI_NONE) __syncthreads();  // the staged links are dead from here
     const C mf = C(a.mf);
-    cx<C> own[12];
-    if constexpr (SELF) {
-        if (valid) {
-            load_spinor<S, C>(a.self, i, own);
-        } else {
-#pragma unroll
-            for (int c = 0; c < 12; c++) own[c] = mk(C(0), C(0));
-        }
-    }
     cx<C> res[12];
     const C tau = C(a.tau);
     if constexpr (EPI == EPI_TOEP) {
@@ -347,14 +373,10 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
             res[c] = tau * rows[c * RS + (rev ? LSC - 1 - s : s)];
         }
     } else {
-        if constexpr (EPI != EPI_NONE || SELF) {
-            cx<C> *bh = lds_h + (j * Ls + s) * 12;
-            cx<C> *bs = lds_s + (j * Ls + s) * 12;
+        if constexpr (EPI != EPI_NONE) {
+            cx<C> *bh = lds_h + j * 12 * Ls + s;  // component-major rows [c][s]
 #pragma unroll
-            for (int c = 0; c < 12; c++) {
-                if constexpr (EPI != EPI_NONE) bh[c] = acc[c];
-                if constexpr (SELF) bs[c] = own[c];
-            }
+            for (int c = 0; c < 12; c++) bh[c * Ls] = acc[c];
             if constexpr (EPI == EPI_DENSE) {
                 const C *em = (const C *)a.emat;
                 const int tid = threadIdx.x + blockDim.x * threadIdx.y;
@@ -366,7 +388,7 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
 #pragma unroll
             for (int c = 0; c < 12; c++) res[c] = tau * acc[c];
         } else if constexpr (EPI == EPI_DENSE) {
-            const cx<C> *blk = lds_h + j * Ls * 12;
+            const cx<C> *blk = lds_h + j * 12 * Ls;
             const C *Mu = lds_e + s * Ls;            // P+ block row s
             const C *Ml = lds_e + Ls * Ls + s * Ls;  // P- block row s
 #pragma unroll
@@ -376,7 +398,7 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
 #pragma unroll
                 for (int c = 0; c < 12; c++) {
                     const C m = (c < 6) ? mu : ml;
-                    const cx<C> v = blk[t * 12 + c];
+                    const cx<C> v = blk[c * Ls + t];
                     res[c].re = fma(m, v.re, res[c].re);
                     res[c].im = fma(m, v.im, res[c].im);
                 }
@@ -384,17 +406,17 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
 #pragma unroll
             for (int c = 0; c < 12; c++) res[c] = tau * res[c];
         } else {
-            const cx<C> *blk = lds_h + j * Ls * 12;
+            const cx<C> *blk = lds_h + j * 12 * Ls;
             const C e0 = C(a.e0), e1 = C(a.e1);
 #pragma unroll
-            for (int c = 0; c < 12; c++) res[c] = tau * (e0 * acc[c] + e1 * shift5<C>(blk, c, s, Ls, a.edag, mf));
+            for (int c = 0; c < 12; c++) res[c] = tau * (e0 * acc[c] + e1 * shift5t<C>(blk, c, s, Ls, a.edag, mf));
         }
         if constexpr (SELF) {
-            const cx<C> *blk = lds_s + j * Ls * 12;
+            const cx<C> *blk = lds_s + j * 12 * Ls;
             const C s0 = C(a.s0), s1 = C(a.s1), sg = C(a.sigma);
 #pragma unroll
             for (int c = 0; c < 12; c++)
-                res[c] = res[c] + sg * (s0 * own[c] + s1 * shift5<C>(blk, c, s, Ls, a.sdag, mf));
+                res[c] = res[c] + sg * (s0 * blk[c * Ls + s] + s1 * shift5t<C>(blk, c, s, Ls, a.sdag, mf));
         }
     }
     if constexpr (RED == 2) {
@@ -402,7 +424,8 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
         const C al = C(*a.alpha);
         if (valid) {
             cx<C> rv[12];
-            load_spinor<S, C>(a.out, i, rv);
+            if constexpr (PRE_R) unpack_raw<S, C>(r_raw, rv);
+            else load_spinor<S, C>(a.out, i, rv);
 #pragma unroll
             for (int c = 0; c < 12; c++) res[c] = rv[c] - al * res[c];
         }
@@ -513,12 +536,8 @@ static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field s
     a.edag = sp.edag;
     a.sdag = sp.sdag;
     a.partial = c.partials;
-    size_t lds = 0;
-    if (epi == EPI_TOEP) lds += (size_t)sb * 12 * (Ls * sizeof(cx<C>) + 16);
-    else if (epi != EPI_NONE) lds += (size_t)sb * Ls * 12 * sizeof(cx<C>);
-    if (sp.self) lds += (size_t)sb * Ls * 12 * sizeof(cx<C>);
-    if (epi == EPI_DENSE) lds += 2 * (size_t)Ls * Ls * sizeof(C);
-    lds = std::max(lds, (size_t)sb * (72 * sizeof(cx<C>) + 8 * sizeof(int)));
+    const size_t lds = stencil_self_offset<C>(epi, sb, Ls, epi == EPI_TOEP ? Ls : 0) +
+                       (sp.self ? (size_t)sb * Ls * 12 * sizeof(cx<C>) : 0);
     dim3 blk(Ls, sb), grid((unsigned)nblk, (unsigned)nb);
     // algorithmic traffic: neighbour spinor, 8 links shared by the Ls slices,
     // output, self input, residual input of the fused update
