@@ -170,6 +170,31 @@ def measured_traffic():
 WEIGHTS = os.path.join(ROOT, "paper_2203_17119_amd", "weights", "ptc_4-12-12-12-4_8x8x8x8_ls8.npz")
 
 
+def multishift(dwf, synth, torch, mode):
+    """Batched multi-shift CG on the 16^4 x 12 Dirichlet block: 8 right-hand sides
+    x 12 rational shifts (96 systems) in one solve, each to 1e-8 in FP64."""
+    w = synth.WORKLOADS["16^4x12_multishift"]
+    U = synth.gauge_field(w.dims, w.eps, w.gauge_seed)
+    lat = dwf.Lattice(w.dims, w.Ls, w.b, w.c, w.M5, w.mf, w.dirichlet, gauge=U)
+    try:
+        shifts = synth.rational_shifts()
+        V = int(np.prod(w.dims))
+        bs = [torch.from_numpy(synth.gaussian_fermion(w.dims, w.Ls, s, nsites=V // 2)).cuda() for s in w.source_seeds]
+        xs = [torch.empty_like(bs[0]) for _ in range(len(bs) * len(shifts))]
+        dwf.dwf_tune(lat.ctx, dwf.DWF_F32 if mode == dwf.DWF_SOLVE_MIXED_F32 else dwf.DWF_F64, None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, st = dwf.dwf_multishift_cg(lat.ctx, bs, shifts, xs, tol=w.tol, mode=mode)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        lat.close()
+    return {"workload": "16^4x12_multishift: 8 rhs x 12 shifts in [1e-4, 10]", "status": s,
+            "mode": {0: "f64", 1: "mixed_f32"}[mode], "seconds": round(dt, 3),
+            "systems": len(st), "iters_max": max(x["iters"] for x in st),
+            "converged": sum(x["converged"] for x in st), "res_normal_max": max(x["res_normal"] for x in st)}
+
+
 def learned_precond(lat, dwf, torch, b, tol, restart=32, maxit=2000, mfma=True, mode=None):
     """FGCR(restart) on the Schur system, right-preconditioned by the trained
     network (matrix-core or FP32 forward), to tol in the FP64 full residual
@@ -235,6 +260,7 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="with --kernels-only: Dhop time over tile schedules")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the FGCR solve with the trained network preconditioner")
+    ap.add_argument("--no-multishift", action="store_true", help="skip the batched multi-shift solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the hot path is one GPU's Dirichlet block and needs no "
@@ -288,8 +314,9 @@ def main():
         x.zero_()
         dwf.dwf_cg(lat.ctx, srcs[i % len(srcs)], x, tol=w.tol, mode=args.mode)
 
+    # HIP events around the launches of the dominant (stencil) class only
     dwf.dwf_kernel_timing_reset(lat.ctx)
-    dwf.dwf_kernel_timing(lat.ctx, 1)
+    dwf.dwf_kernel_timing_mask(lat.ctx, 1 << dwf.DWF_K_STENCIL)
     stats = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -318,6 +345,14 @@ def main():
                                                        mode=dwf.DWF_SOLVE_F64)
         log(f"learned preconditioner, FP64 FGCR, FP32 forward: {lp['fp64_fgcr_fp32_forward']}")
     table = None if args.no_table else dhop_table(lat, dwf, torch)
+    ms = None
+    if not args.no_multishift:
+        lat.close()
+        del srcs, x
+        torch.cuda.empty_cache()
+        ms = {"mixed_f32": multishift(dwf, synth, torch, dwf.DWF_SOLVE_MIXED_F32),
+              "f64": multishift(dwf, synth, torch, dwf.DWF_SOLVE_F64)}
+        log(f"multishift: {ms}")
     cpu = None if args.no_cpu else cpu_baseline(w, U, b0_host)
 
     ms_step = t_total / args.steps * 1e3
@@ -358,6 +393,7 @@ def main():
                      "gflops": round(dom["flops"] / dom["ms"] / 1e6, 1),
                      "frac_of_copy": round(kern_gbs / copy["GB/s"], 4)},
         "learned_precond": lp,
+        "multishift": ms,
         "tile_schedule": sched,
         "copy": copy,
         "dhop": table,

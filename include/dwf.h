@@ -294,8 +294,11 @@ enum {
 };
 
 /* Enable (1) or disable (0) HIP-event timing of every launch on the context's
- * stream; statistics accumulate until reset. */
+ * stream; statistics accumulate until reset.  Each timed launch is bracketed
+ * by two events, which costs a few microseconds of idle time; the mask form
+ * times only the classes whose bit (1 << class) is set. */
 dwf_status dwf_kernel_timing(dwf_ctx ctx, int enable);
+dwf_status dwf_kernel_timing_mask(dwf_ctx ctx, int mask);
 dwf_status dwf_kernel_timing_reset(dwf_ctx ctx);
 /* Per kernel class: launches, summed device time (ms), summed algorithmic
  * bytes and flops, over launches whose fields have storage precision prec

@@ -76,7 +76,7 @@ const void *slmat(const Context &c, int op, bool f64)
 
 Timer::Timer(Context &c_, int k, double by, double fl, int pr) : c(c_), kclass(k), prec(pr), bytes(by), flops(fl)
 {
-    if (!c.timing) return;
+    if (!(c.timing >> k & 1)) return;
     if (c.event_pool.empty()) {
         hipEvent_t e;
         HIPCHECK(hipEventCreate(&e));
@@ -703,7 +703,17 @@ dwf_status dwf_kernel_timing(dwf_ctx ctx, int enable)
     DWF_API_BEGIN
     dwf::Context &c = C_(ctx);
     drain_timing(c);
-    c.timing = enable != 0;
+    c.timing = enable ? (1 << DWF_K_NCLASS) - 1 : 0;
+    DWF_API_END
+}
+
+dwf_status dwf_kernel_timing_mask(dwf_ctx ctx, int mask)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    if (mask < 0 || mask >= (1 << DWF_K_NCLASS)) fail(DWF_EINVAL, "unknown kernel class in mask");
+    drain_timing(c);
+    c.timing = mask;
     DWF_API_END
 }
 

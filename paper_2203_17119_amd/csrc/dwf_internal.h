@@ -108,7 +108,7 @@ struct Context {
 
     LaunchCfg cfg_stencil, cfg_slocal, cfg_blas;
 
-    bool timing = false;
+    int timing = 0;  // bit k: time launches of kernel class k
     std::vector<TimedLaunch> pending;
     std::vector<hipEvent_t> event_pool;
     KStats stats[DWF_K_NCLASS];

@@ -53,6 +53,11 @@ struct StencilKArgs {
     const double *alpha;   // RED = 2: device pointer to alpha
 };
 
+// LDS rows of staged links: 72 entries per site padded to 73, so that the
+// rows of the sites in a wavefront start in different banks; every entry of a
+// row is then at a compile-time offset from the row start
+constexpr int LK_STRIDE = 73;
+
 // half-spinor projection h = upper pair of (1 + P g_MU) v
 template <typename C, int MU, int P>
 __device__ __forceinline__ void project(const cx<C> v[12], cx<C> h[6])
@@ -182,38 +187,58 @@ __device__ __forceinline__ void link_accumulate(cx<C> acc[12], const cx<C> h[6],
 
 // one direction of the hop; the workgroup's links and neighbour indices are in
 // LDS: lk[(d*9 + k)*sb + j], nb[d*sb + j]
+// Buffer resources of an FP16 input field: the three 16-byte planes are read
+// with one 32-bit lane offset and a scalar plane offset, so a neighbour load
+// costs one integer multiply-add instead of 64-bit address arithmetic
+struct InRsrc {
+    __amdgpu_buffer_rsrc_t data, norm;
+    int plane;  // bytes between planes
+};
+
+__device__ __forceinline__ InRsrc in_rsrc(const Field &f)
+{
+    // word 3 of the descriptor: raw (untyped) access on gfx9-class devices
+    constexpr int kWord3 = 0x00020000;
+    InRsrc r;
+    r.plane = (int)(f.n * 16);
+    r.data = __builtin_amdgcn_make_buffer_rsrc(f.data, 0, 3 * r.plane, kWord3);
+    r.norm = __builtin_amdgcn_make_buffer_rsrc(f.norm, 0, (int)(f.n * 4), kWord3);
+    return r;
+}
+
 template <typename S, typename C, int D, bool DAG>
-__device__ __forceinline__ void hop_step(cx<C> acc[12], const StencilKArgs &a, const cx<C> *lk, const int *nbs, int j,
-                                         int sb, int s)
+__device__ __forceinline__ void hop_step(cx<C> acc[12], const StencilKArgs &a, const InRsrc &rs, const cx<C> *lk,
+                                         const int *nbs, int j, int sb, int s)
 {
     constexpr int MU = D & 3;
     constexpr int P0 = (D < 4) ? -1 : +1;
     constexpr int P = DAG ? -P0 : P0;
-    const long nb = nbs[D * sb + j];
-    const long i = nb * a.Ls + s;
+    const int nb = nbs[j * 8 + D];
     cx<C> h[6];
     C scale;
     if constexpr (S::prec == P_F16) {
-        const uint4 *d = (const uint4 *)a.in.data;
+        const int i = nb * a.Ls + s;  // < 2^27 for fields below 2 GB
         uint32_t r[12];
 #pragma unroll
         for (int q = 0; q < 3; q++) {
-            const uint4 w = d[q * a.in.n + i];
+            const uint4 w =
+                __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs.data, i * 16, q * rs.plane, 0));
             r[4 * q] = w.x;
             r[4 * q + 1] = w.y;
             r[4 * q + 2] = w.z;
             r[4 * q + 3] = w.w;
         }
-        scale = C(a.in.norm[i]);
+        scale = C(__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs.norm, i * 4, 0, 0)));
         project_f16<MU, P>(r, h);
     } else {
+        const long i = (long)nb * a.Ls + s;
         cx<C> v[12];
         load_spinor_unscaled<S, C>(a.in, i, v, scale);
         project<C, MU, P>(v, h);
     }
     cx<C> u[9];
 #pragma unroll
-    for (int k = 0; k < 9; k++) u[k] = lk[(D * 9 + k) * sb + j];
+    for (int k = 0; k < 9; k++) u[k] = lk[j * LK_STRIDE + D * 9 + k];
     link_accumulate<C, MU, P>(acc, h, u, D == 0, scale);
 }
 
@@ -229,8 +254,8 @@ __device__ __forceinline__ void stage_links(const StencilKArgs &a, long base, in
     const bool ok = site < a.vh;
     const typename S::elem *L = (const typename S::elem *)a.links;
     for (int dk = threadIdx.x; dk < 72; dk += blockDim.x)
-        lk[dk * sb + jj] = ok ? unpack<C>(L[(long)dk * a.vh + site]) : mk(C(0), C(0));
-    for (int d = threadIdx.x; d < 8; d += blockDim.x) nbs[d * sb + jj] = ok ? a.nbr[(long)d * a.vh + site] : 0;
+        lk[jj * LK_STRIDE + dk] = ok ? unpack<C>(L[(long)dk * a.vh + site]) : mk(C(0), C(0));
+    for (int d = threadIdx.x; d < 8; d += blockDim.x) nbs[jj * 8 + d] = ok ? a.nbr[(long)d * a.vh + site] : 0;
 }
 
 // batch member blockIdx.y of fields laid out `stride` bytes apart
@@ -249,7 +274,7 @@ __device__ __forceinline__ Field batch_member(Field f, long stride)
 template <typename C>
 __host__ __device__ inline size_t stencil_self_offset(int epi, int sb, int Ls, int lsc)
 {
-    const size_t links = (size_t)sb * (72 * sizeof(cx<C>) + 8 * sizeof(int));
+    const size_t links = (size_t)sb * (73 * sizeof(cx<C>) + 8 * sizeof(int));
     size_t epil = 0;
     if (epi == EPI_TOEP) epil = (size_t)sb * 12 * (lsc * sizeof(cx<C>) + 16);
     else if (epi != EPI_NONE) epil = (size_t)sb * Ls * 12 * sizeof(cx<C>);
@@ -295,7 +320,7 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
     // region behind both, filled before the hop (stencil_lds_bytes)
     extern __shared__ unsigned char smem[];
     cx<C> *lk = (cx<C> *)smem;
-    int *nbs = (int *)(lk + 72 * sb);
+    int *nbs = (int *)(lk + LK_STRIDE * sb);
     cx<C> *lds_h = (cx<C> *)smem;
     C *lds_e = (C *)(lds_h + sb * Ls * 12);
     cx<C> *lds_s = (cx<C> *)(smem + stencil_self_offset<C>(EPI, sb, Ls, LSC));
@@ -326,15 +351,17 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
     cx<C> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; c++) acc[c] = mk(C(0), C(0));
+    InRsrc rs{};
+    if constexpr (S::prec == P_F16) rs = in_rsrc(a.in);
     if (valid) {
-        hop_step<S, C, 0, DAG>(acc, a, lk, nbs, j, sb, s);
-        hop_step<S, C, 1, DAG>(acc, a, lk, nbs, j, sb, s);
-        hop_step<S, C, 2, DAG>(acc, a, lk, nbs, j, sb, s);
-        hop_step<S, C, 3, DAG>(acc, a, lk, nbs, j, sb, s);
-        hop_step<S, C, 4, DAG>(acc, a, lk, nbs, j, sb, s);
-        hop_step<S, C, 5, DAG>(acc, a, lk, nbs, j, sb, s);
-        hop_step<S, C, 6, DAG>(acc, a, lk, nbs, j, sb, s);
-        hop_step<S, C, 7, DAG>(acc, a, lk, nbs, j, sb, s);
+        hop_step<S, C, 0, DAG>(acc, a, rs, lk, nbs, j, sb, s);
+        hop_step<S, C, 1, DAG>(acc, a, rs, lk, nbs, j, sb, s);
+        hop_step<S, C, 2, DAG>(acc, a, rs, lk, nbs, j, sb, s);
+        hop_step<S, C, 3, DAG>(acc, a, rs, lk, nbs, j, sb, s);
+        hop_step<S, C, 4, DAG>(acc, a, rs, lk, nbs, j, sb, s);
+        hop_step<S, C, 5, DAG>(acc, a, rs, lk, nbs, j, sb, s);
+        hop_step<S, C, 6, DAG>(acc, a, rs, lk, nbs, j, sb, s);
+        hop_step<S, C, 7, DAG>(acc, a, rs, lk, nbs, j, sb, s);
     }
     if constexpr (EPI != EPI_NONE) __syncthreads();  // the staged links are dead from here
     const C mf = C(a.mf);

@@ -99,6 +99,7 @@ SIGNATURES = {
     "dwf_stream_copy": ([_CTX, _P, _P, C.c_size_t], C.c_int32),
     "dwf_kernel_timing": ([_CTX, _I], C.c_int32),
     "dwf_kernel_timing_reset": ([_CTX], C.c_int32),
+    "dwf_kernel_timing_mask": ([_CTX, _I], C.c_int32),
     "dwf_kernel_stats": ([_CTX, _I, _I, C.POINTER(C.c_long), C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)], C.c_int32),
 }
 
@@ -349,6 +350,10 @@ def dwf_stream_copy(ctx, src, dst, nbytes):
 
 def dwf_kernel_timing(ctx, enable):
     _check(load().dwf_kernel_timing(ctx, int(enable)))
+
+
+def dwf_kernel_timing_mask(ctx, mask):
+    _check(load().dwf_kernel_timing_mask(ctx, int(mask)))
 
 
 def dwf_kernel_timing_reset(ctx):
