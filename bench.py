@@ -195,7 +195,7 @@ def multishift(dwf, synth, torch, mode):
             "converged": sum(x["converged"] for x in st), "res_normal_max": max(x["res_normal"] for x in st)}
 
 
-def learned_precond(lat, dwf, torch, b, tol, restart=32, maxit=2000, mfma=True, mode=None):
+def learned_precond(lat, dwf, torch, b, tol, restart=16, maxit=2000, mfma=True, mode=None):
     """FGCR(restart) on the Schur system, right-preconditioned by the trained
     network (matrix-core or FP32 forward), to tol in the FP64 full residual
     (CG fallback on stagnation)."""

@@ -205,8 +205,10 @@ dwf_status dwf_net_get_weights(dwf_net net, float *w);
  *                          always uses it)
  *   DWF_NET_FWD_MFMA_BF16  channel mixing on the matrix cores, the transported
  *                          inputs rounded to BF16 (the weights are BF16 already),
- *                          FP32 accumulation; relative deviation from the FP32
- *                          forward of order 1e-2 over four layers */
+ *                          FP32 accumulation, activations between layers stored
+ *                          in BF16; relative deviation from the FP32 forward at
+ *                          most (1 + 2^-8)^L - 1 for L layers without
+ *                          cancellation (1.6e-2 for four) */
 enum { DWF_NET_FWD_FP32 = 0, DWF_NET_FWD_MFMA_BF16 = 1 };
 dwf_status dwf_net_set_forward(dwf_net net, int mode);
 /* out = restrict_odd(N(embed_odd(in))); canonical FP64 odd half fields */

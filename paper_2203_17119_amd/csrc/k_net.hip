@@ -175,8 +175,23 @@ __global__ void k_pack_mfma_weights(const __hip_bfloat162 *w, short *pk)
 // the path's MFMA steps, three column tiles each.
 static constexpr int MF_S = 128;
 
-template <int CIN, int COUT>
-__global__ void __launch_bounds__(256) k_ptc_fwd_mfma(NetGeo g, const float2 *in, float2 *out, const short *wpk, int p,
+// feature element k of a plane array in FP32 pairs or BF16 pairs
+template <bool BF>
+__device__ __forceinline__ cx<float> ld_feat(const void *base, long k)
+{
+    if constexpr (BF) {
+        const float2 f = __bfloat1622float2(((const __hip_bfloat162 *)base)[k]);
+        return mk(f.x, f.y);
+    } else {
+        return c2(((const float2 *)base)[k]);
+    }
+}
+
+// Activations between layers may be BF16 pairs (in_bf16 / out_bf16): the
+// matrix cores round their B operand to BF16 anyway, and BF16 storage halves
+// the bytes of the eleven path reads of every input channel.
+template <int CIN, int COUT, bool IBF, bool OBF>
+__global__ void __launch_bounds__(256) k_ptc_fwd_mfma(NetGeo g, const void *in, void *out, const short *wpk, int p,
                                                       long n)
 {
     static_assert(CIN % 4 == 0 && 2 * COUT <= 32, "channel counts");
@@ -207,16 +222,17 @@ __global__ void __launch_bounds__(256) k_ptc_fwd_mfma(NetGeo g, const float2 *in
 #pragma unroll
             for (int k = 0; k < 9; k++) u[k] = c2(L[(long)k * g.vh]);
         }
-        const float2 *base = in + (long)sp * CIN * 3 * n + src;
+        const long base = (long)sp * CIN * 3 * n + src;
 #pragma unroll
         for (int q = 0; q < HP; q++) {
             const int pp = th * HP + q;
             cx<float> t[2][3];
 #pragma unroll
             for (int e = 0; e < 2; e++) {
-                const float2 *f = base + (long)((2 * pp + e) * 3) * n;
+                const long f = base + (long)((2 * pp + e) * 3) * n;
                 if (have) {
-                    const cx<float> v0 = c2(f[0]), v1 = c2(f[n]), v2 = c2(f[2 * n]);
+                    const cx<float> v0 = ld_feat<IBF>(in, f), v1 = ld_feat<IBF>(in, f + n),
+                                    v2 = ld_feat<IBF>(in, f + 2 * n);
                     if (hop) {
 #pragma unroll
                         for (int r = 0; r < 3; r++) {
@@ -258,7 +274,7 @@ __global__ void __launch_bounds__(256) k_ptc_fwd_mfma(NetGeo g, const float2 *in
     }
     // accumulator register r of tile tt holds row m' = 8 (r / 4) + 4 h + r % 4 of column
     // (tile * 32 + jc): colour col / MF_S, site col % MF_S
-    float2 *o = out + (long)p * COUT * 3 * n;
+    const long obase = (long)p * COUT * 3 * n;
 #pragma unroll
     for (int tt = 0; tt < 3; tt++) {
         const int col = (wave * 3 + tt) * 32 + jc;
@@ -270,8 +286,13 @@ __global__ void __launch_bounds__(256) k_ptc_fwd_mfma(NetGeo g, const float2 *in
 #pragma unroll
             for (int hh = 0; hh < 2; hh++) {
                 const int a = 4 * q + 2 * h + hh;
-                if (a < COUT)
-                    o[(long)(a * 3 + cc) * n + i] = make_float2(acc[tt][4 * q + 2 * hh], acc[tt][4 * q + 2 * hh + 1]);
+                if (a >= COUT) continue;
+                const long k = obase + (long)(a * 3 + cc) * n + i;
+                const float2 v = make_float2(acc[tt][4 * q + 2 * hh], acc[tt][4 * q + 2 * hh + 1]);
+                if constexpr (OBF)
+                    ((__hip_bfloat162 *)out)[k] = __float22bfloat162_rn(v);
+                else
+                    ((float2 *)out)[k] = v;
             }
     }
 }
@@ -495,13 +516,26 @@ void launch_pack_mfma_weights(Context &c, int cin, int cout, const void *w_bf16,
     HIPCHECK(hipGetLastError());
 }
 
-void launch_ptc_layer_mfma(Context &c, int cin, int cout, const float2 *in, float2 *out, const short *pk, int p)
+void launch_ptc_layer_mfma(Context &c, int cin, int cout, const void *in, void *out, const short *pk, int p,
+                           bool in_bf16, bool out_bf16)
 {
     const NetGeo g = net_geo(c);
     const dim3 grid((unsigned)((c.n5h + MF_S - 1) / MF_S)), blk(256);
     const double flops = (double)c.n5h * (11.0 * cout * cin * 3 * 8 + 8.0 * cin * 66);
-    Timer tm(c, DWF_K_NET, (double)c.n5h * 8.0 * 3 * (11 * cin + cout), flops);
-#define NETL(CI, CO) hipLaunchKernelGGL((k_ptc_fwd_mfma<CI, CO>), grid, blk, 0, c.stream, g, in, out, pk, p, c.n5h)
+    Timer tm(c, DWF_K_NET, (double)c.n5h * 3 * (11.0 * cin * (in_bf16 ? 4 : 8) + cout * (out_bf16 ? 4 : 8)), flops);
+#define NETK(CI, CO, IB, OB) \
+    hipLaunchKernelGGL((k_ptc_fwd_mfma<CI, CO, IB, OB>), grid, blk, 0, c.stream, g, in, out, pk, p, c.n5h)
+#define NETL(CI, CO)                        \
+    do {                                    \
+        if (in_bf16 && out_bf16)            \
+            NETK(CI, CO, true, true);       \
+        else if (in_bf16)                   \
+            NETK(CI, CO, true, false);      \
+        else if (out_bf16)                  \
+            NETK(CI, CO, false, true);      \
+        else                                \
+            NETK(CI, CO, false, false);     \
+    } while (0)
     if (cin == 4 && cout == 12) NETL(4, 12);
     else if (cin == 12 && cout == 12) NETL(12, 12);
     else if (cin == 12 && cout == 4) NETL(12, 4);
@@ -513,6 +547,7 @@ void launch_ptc_layer_mfma(Context &c, int cin, int cout, const float2 *in, floa
     else if (cin == 8 && cout == 12) NETL(8, 12);
     else fail(DWF_ENOTSUP, "layer channel counts must be 4, 8 or 12");
 #undef NETL
+#undef NETK
     HIPCHECK(hipGetLastError());
 }
 

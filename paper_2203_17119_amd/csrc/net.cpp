@@ -20,7 +20,8 @@ namespace dwf {
 void launch_ptc_layer(Context &c, int cin, int cout, const float2 *in, float2 *out, const void *w_bf16, int p);
 size_t mfma_weight_elems(int cin);
 void launch_pack_mfma_weights(Context &c, int cin, int cout, const void *w_bf16, short *pk);
-void launch_ptc_layer_mfma(Context &c, int cin, int cout, const float2 *in, float2 *out, const short *pk, int p);
+void launch_ptc_layer_mfma(Context &c, int cin, int cout, const void *in, void *out, const short *pk, int p,
+                           bool in_bf16, bool out_bf16);
 int launch_ptc_wgrad(Context &c, int cin, int cout, const float2 *in, const float2 *gout, int p, double *partial,
                      long partial_len);
 void launch_wgrad_finish(Context &c, const double *partial, int nblk, int nw, float *gw, bool accumulate);
@@ -45,6 +46,7 @@ struct dwf_net_s {
     void *wbf = nullptr, *wadj = nullptr;
     int step = 0;
     std::vector<float2 *> acts;  // layer inputs (both parities), acts[nlayer] = output
+    std::vector<void *> acts_bf;  // BF16 inputs of layers 1 .. nlayer-1 for the matrix-core forward
     float2 *g0 = nullptr, *g1 = nullptr;  // gradient ping-pong (max channels)
     double *wpart = nullptr;
     long wpart_len = 0;
@@ -70,6 +72,8 @@ static void net_free(dwf_net_s *n)
         if (p) (void)hipFree(p);
     for (auto *a : n->acts)
         if (a) (void)hipFree(a);
+    for (auto *a : n->acts_bf)
+        if (a) (void)hipFree(a);
     delete n;
 }
 
@@ -94,12 +98,16 @@ static void net_forward(dwf_net_s *n, bool all_parities, bool mfma = false)
     for (int l = 0; l < n->nlayer; l++) {
         const bool last = l == n->nlayer - 1;
         for (int p = (last && !all_parities) ? 1 : 0; p < 2; p++) {
-            if (mfma)
-                launch_ptc_layer_mfma(c, n->chans[l], n->chans[l + 1], n->acts[l], n->acts[l + 1],
-                                      n->wpk + n->pkoff[l], p);
-            else
+            if (mfma) {
+                // FP32 network input and output, BF16 activations in between
+                const bool ibf = l > 0, obf = !last;
+                launch_ptc_layer_mfma(c, n->chans[l], n->chans[l + 1], ibf ? n->acts_bf[l] : (const void *)n->acts[l],
+                                      obf ? n->acts_bf[l + 1] : (void *)n->acts[l + 1], n->wpk + n->pkoff[l], p, ibf,
+                                      obf);
+            } else {
                 launch_ptc_layer(c, n->chans[l], n->chans[l + 1], n->acts[l], n->acts[l + 1],
                                  (const __hip_bfloat162 *)n->wbf + n->woff[l], p);
+            }
         }
     }
 }
@@ -207,6 +215,9 @@ dwf_status dwf_net_create(dwf_ctx ctx, int nlayer, const int *chans, dwf_net *ou
             float2 *a = nullptr;
             HIPCHECK(hipMalloc(&a, feat_elems(c, chans[l]) * sizeof(float2)));
             n->acts.push_back(a);
+            void *b = nullptr;
+            if (l > 0 && l < nlayer) HIPCHECK(hipMalloc(&b, feat_elems(c, chans[l]) * sizeof(__hip_bfloat162)));
+            n->acts_bf.push_back(b);
         }
         HIPCHECK(hipMalloc(&n->g0, feat_elems(c, n->cmax) * sizeof(float2)));
         HIPCHECK(hipMalloc(&n->g1, feat_elems(c, n->cmax) * sizeof(float2)));

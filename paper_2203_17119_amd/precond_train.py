@@ -140,7 +140,7 @@ def train(lat, net, gauges, train_pairs, val_pairs, epochs: int, batch: int = 8,
 
 
 def solve_table(lat, torch, nets: dict, b_full, tol: float, restart: int, maxit: int, normal_too: bool = False,
-                gcr: bool = True):
+                gcr: bool = True, mode: int = dwf.DWF_SOLVE_F64):
     """Time-to-tol of plain CG, plain GCR and FGCR with each network on one source
     (Schur system; with normal_too also the normal equations)."""
     rows = {}
@@ -155,7 +155,7 @@ def solve_table(lat, torch, nets: dict, b_full, tol: float, restart: int, maxit:
             dwf.dwf_kernel_timing_reset(lat.ctx)
             dwf.dwf_kernel_timing(lat.ctx, 1)
             s, st = dwf.dwf_fgcr(lat.ctx, net, b_full, x, tol=tol, restart=restart, normal=normal, maxit=maxit,
-                                 fallback=False)
+                                 fallback=False, mode=mode)
             kn = dwf.dwf_kernel_stats(lat.ctx, dwf.DWF_K_NET)
             dwf.dwf_kernel_timing(lat.ctx, 0)
             rows[f"{name}_{tag}"] = {"status": s, "iters": st["iters"], "seconds": st["seconds"],
@@ -182,6 +182,7 @@ def main():
     ap.add_argument("--normal-too", action="store_true", help="also evaluate FGCR on the normal equations")
     ap.add_argument("--skip-init", action="store_true", help="do not evaluate the untrained network")
     ap.add_argument("--skip-gcr", action="store_true", help="do not evaluate plain GCR")
+    ap.add_argument("--mixed", action="store_true", help="FGCR with FP32 cycles and FP64 restarts")
     args = ap.parse_args()
 
     import torch
@@ -233,7 +234,8 @@ def evaluate(args, torch, w0, wt):
             dwf.dwf_net_set_forward(nets[name], dwf.DWF_NET_FWD_MFMA_BF16)
     for k in range(args.eval_sources):
         b = torch.from_numpy(synth.gaussian_fermion(ev.dims, ev.Ls, ev.source_seeds[k])).cuda()
-        rows = solve_table(lat, torch, nets, b, ev.tol, args.restart, args.maxit, args.normal_too, not args.skip_gcr)
+        rows = solve_table(lat, torch, nets, b, ev.tol, args.restart, args.maxit, args.normal_too, not args.skip_gcr,
+                           dwf.DWF_SOLVE_MIXED_F32 if args.mixed else dwf.DWF_SOLVE_F64)
         print(json.dumps({"phase": "eval", "workload": args.eval_workload, "source": ev.source_seeds[k],
                           "restart": args.restart, "rows": rows}), flush=True)
     for n in nets.values():

@@ -86,8 +86,9 @@ def test_precond_apply_matches_oracle(case):
 def test_precond_apply_mfma_matches_oracle(case, chans):
     """Matrix-core forward: every transported input is rounded to BF16 (unit
     roundoff 2^-9) before the FP32-accumulated channel mixing, with the same
-    BF16 weights as the oracle.  Without cancellation a layer's relative error
-    is at most 2^-9, four layers compound to (1 + 2^-9)^4 - 1 = 7.8e-3."""
+    BF16 weights as the oracle, and the activations between layers are stored
+    in BF16 (another 2^-9).  Without cancellation a layer's relative error is
+    at most 2^-8; four layers compound to (1 + 2^-8)^4 - 1 = 1.57e-2."""
     Ws = random_weights(chans, 3)
     net = dwf.dwf_net_create(case.ctx, chans)
     try:
@@ -99,7 +100,7 @@ def test_precond_apply_mfma_matches_oracle(case, chans):
         expect = oracle.pick(case.P, oracle_forward(case, Ws, x)[-1], 1)
         err = relerr(to_host(out), expect)
         print(f"mfma forward {chans}: relative error {err:.2e}", flush=True)
-        assert err < 1e-2
+        assert err < 2e-2
         # the FP32 forward is unchanged by the mode switch back
         dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_FP32)
         dwf.dwf_precond_apply(case.ctx, net, to_gpu(x), out)
@@ -120,7 +121,7 @@ def test_precond_apply_mfma_ragged_tile():
         out = torch().empty_like(to_gpu(x))
         dwf.dwf_precond_apply(c.ctx, net, to_gpu(x), out)
         expect = oracle.pick(c.P, oracle_forward(c, Ws, x)[-1], 1)
-        assert relerr(to_host(out), expect) < 1e-2
+        assert relerr(to_host(out), expect) < 2e-2
     finally:
         dwf.dwf_net_destroy(net)
         c.close()
