@@ -430,6 +430,11 @@ dwf_status dwf_create(const dwf_params *p, const double *gauge, int gauge_on_dev
         c->e = p->c * (4.0 - p->M5) - 1.0;
         c->stream = (hipStream_t)stream;
         HIPCHECK(hipGetDevice(&c->device));
+        {
+            int lds = 0;
+            HIPCHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+            c->lds_max = std::min<size_t>(65536, (size_t)lds);
+        }
         HIPCHECK(hipMalloc(&c->nbr, (size_t)2 * 8 * c->vh * sizeof(int)));
         build_order(*c, 0, 0, 0);
         build_neighbours(*c);

@@ -3,6 +3,8 @@
 // .hip translation units.
 #pragma once
 
+#include <algorithm>
+
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -72,6 +74,7 @@ struct Context {
     double d, e;       // Mooee = d + e P5
     hipStream_t stream = nullptr;
     int device = 0;
+    size_t lds_max = 65536;  // dynamic LDS one workgroup may use
 
     int *nbr = nullptr;          // [2][8][vh]
     // Internal 4D site order, the same for both parities: internal index j of
@@ -116,7 +119,8 @@ struct Context {
 };
 
 // default 4D sites per workgroup: about 192 lanes
-inline int default_sb(const Context &c) { return c.Ls >= 192 ? 1 : 192 / c.Ls; }
+// 4D sites per workgroup by default: about 192 lanes, at most 64 sites
+inline int default_sb(const Context &c) { return c.Ls >= 192 ? 1 : std::min(64, 192 / c.Ls); }
 inline int cfg_sb(const Context &c, const LaunchCfg &g) { return g.sb > 0 ? g.sb : default_sb(c); }
 
 // sizes

@@ -521,7 +521,20 @@ template <typename S, typename C>
 static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field self, Field out)
 {
     const int Ls = c.Ls;
-    const int sb = cfg_sb(c, c.cfg_stencil);
+    // a dense epilogue whose operator is twisted-circulant runs as the Toeplitz epilogue
+    int epi = sp.epi;
+    const bool toep = epi == EPI_DENSE && sp.epi_op >= 0 && sp.epi_op < SL_NOP && c.toep_ok[sp.epi_op] &&
+                      (Ls == 8 || Ls == 12 || Ls == 16) && !sp.self && !sp.reduce && !sp.cg_update;
+    if (toep) epi = EPI_TOEP;
+    auto lds_of = [&](int sb_) {
+        return stencil_self_offset<C>(epi, sb_, Ls, epi == EPI_TOEP ? Ls : 0) +
+               (sp.self ? (size_t)sb_ * Ls * 12 * sizeof(cx<C>) : 0);
+    };
+    // the schedule's sites per workgroup, halved while the LDS would not fit
+    int sb = cfg_sb(c, c.cfg_stencil);
+    while (sb > 1 && lds_of(sb) > c.lds_max) sb = (sb + 1) / 2;
+    const size_t lds = lds_of(sb);
+    if (lds > c.lds_max) fail(DWF_ENOTSUP, "fifth dimension too long for the fused stencil's LDS");
     const long nblk = (c.vh + sb - 1) / sb;
     const int nb = std::max(1, sp.nbatch);
     if (sp.reduce && nblk * nb > c.partials_len) fail(DWF_EINVAL, "reduction buffer too small");
@@ -535,11 +548,6 @@ static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field s
     a.vh = c.vh;
     a.Ls = Ls;
     a.run = c.cfg_stencil.run;
-    // a dense epilogue whose operator is twisted-circulant runs as the Toeplitz epilogue
-    int epi = sp.epi;
-    const bool toep = epi == EPI_DENSE && sp.epi_op >= 0 && sp.epi_op < SL_NOP && c.toep_ok[sp.epi_op] &&
-                      (Ls == 8 || Ls == 12 || Ls == 16) && !sp.self && !sp.reduce && !sp.cg_update;
-    if (toep) epi = EPI_TOEP;
     a.emat = (epi == EPI_DENSE) ? slmat(c, sp.epi_op, sizeof(C) == 8) : nullptr;
     if (toep) {
         for (int k = 0; k < 16; k++) {
@@ -563,8 +571,6 @@ static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field s
     a.edag = sp.edag;
     a.sdag = sp.sdag;
     a.partial = c.partials;
-    const size_t lds = stencil_self_offset<C>(epi, sb, Ls, epi == EPI_TOEP ? Ls : 0) +
-                       (sp.self ? (size_t)sb * Ls * 12 * sizeof(cx<C>) : 0);
     dim3 blk(Ls, sb), grid((unsigned)nblk, (unsigned)nb);
     // algorithmic traffic: neighbour spinor, 8 links shared by the Ls slices,
     // output, self input, residual input of the fused update
