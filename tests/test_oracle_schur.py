@@ -2,7 +2,7 @@
 
 * Mooee^-1 against the closed form of the inverse of d + e S (S^Ls = -mf);
 * det D5 = det Mee * det Mpc (Schur complement on odd sites);
-* the Schur solve plus reconstruction solves D5 x = b (dense solve as judge);
+* the Schur solve plus reconstruction solves D5 x = b (checked against a dense solve);
 * the Dirichlet operator (face links zeroed, Sec. 2.4) is the diagonal block
   D_Omega of the operator on a lattice twice as long, and the determinant
   identity det D / (det D_Omega det D_Omegabar) = det chi of eq. (schur) and
