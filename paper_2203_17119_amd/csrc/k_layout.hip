@@ -102,6 +102,9 @@ void build_order(Context &c, int cxh, int cy, int cz)
 // sites in one column (one parity)
 long column_sites(const Context &c) { return (long)c.order[0] * c.order[1] * c.order[2] * c.L[3]; }
 
+// nbr[p][d][j]: internal index of the neighbour of site j (output parity p) in
+// direction d, or -1 where the link crosses a Dirichlet face (it is zero, so
+// the kernels skip the neighbour instead of reading across the block)
 void build_neighbours(Context &c)
 {
     std::vector<int> h((size_t)2 * 8 * c.vh);
@@ -111,9 +114,10 @@ void build_neighbours(Context &c)
             site_of_cb(c.L, c.perm_inv_h[j], p, x);
             for (int d = 0; d < 8; d++) {
                 const int mu = d & 3, step = d < 4 ? 1 : -1;
+                const bool cut = c.p.dirichlet[mu] && (d < 4 ? x[mu] == c.L[mu] - 1 : x[mu] == 0);
                 int y[4] = {x[0], x[1], x[2], x[3]};
                 y[mu] = (y[mu] + step + c.L[mu]) % c.L[mu];
-                h[((size_t)p * 8 + d) * c.vh + j] = c.perm_h[lex(c.L, y) >> 1];
+                h[((size_t)p * 8 + d) * c.vh + j] = cut ? -1 : c.perm_h[lex(c.L, y) >> 1];
             }
         }
     HIPCHECK(hipMemcpy(c.nbr, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice));

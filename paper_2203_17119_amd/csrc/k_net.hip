@@ -36,9 +36,10 @@ __device__ __forceinline__ bool path_source(const NetGeo &g, int p, int pi, long
     }
     if (pi <= 8) {
         const int d = (pi <= 4) ? pi - 1 : pi - 1;  // 1..4 -> 0..3 (+mu), 5..8 -> 4..7 (-mu)
-        src = (long)g.nbr[((long)p * 8 + d) * g.vh + j] * g.Ls + s;
+        const int nb = g.nbr[((long)p * 8 + d) * g.vh + j];
+        src = (long)(nb < 0 ? 0 : nb) * g.Ls + s;
         sp = 1 - p;
-        return true;
+        return nb >= 0;  // -1: link across a Dirichlet face (zero)
     }
     const int s2 = (pi == 9) ? s + 1 : s - 1;
     src = j * g.Ls + s2;

@@ -214,6 +214,7 @@ __device__ __forceinline__ void hop_step(cx<C> acc[12], const StencilKArgs &a, c
     constexpr int P0 = (D < 4) ? -1 : +1;
     constexpr int P = DAG ? -P0 : P0;
     const int nb = nbs[j * 8 + D];
+    if (nb < 0) return;  // link across a Dirichlet face: zero contribution, no load
     cx<C> h[6];
     C scale;
     if constexpr (S::prec == P_F16) {
