@@ -222,8 +222,11 @@ def learned_precond(lat, dwf, torch, b, tol, restart=16, maxit=2000, mfma=True, 
             "network_ms": round(kn["ms"], 1), "network_launches": kn["launches"]}
 
 
-def cpu_baseline(w, U, b_full):
-    """FP64 oracle Wilson hop (both parities, all s) on the same lattice and field."""
+def cpu_baseline(w, U, b_full, cg_iters):
+    """FP64 oracle on the host cores, same lattice and field: one Wilson hop
+    (both parities, all s) for the bandwidth figure, and one application of
+    the normal operator Mpc^+ Mpc, which times the oracle's CG iteration; its
+    time to 1e-8 is extrapolated with the GPU FP64 iteration count."""
     import oracle
 
     P = oracle.Params(w.dims, w.Ls, w.b, w.c, w.M5, w.mf)
@@ -233,7 +236,11 @@ def cpu_baseline(w, U, b_full):
     dt = time.perf_counter() - t0
     n5 = P.V * P.Ls  # a full-lattice hop = two half-lattice Dhop calls
     bytes_alg = n5 * 480.0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = oracle.num_threads()
+    odd = oracle.pick(P, b_full, 1)
+    t1 = time.perf_counter()
+    oracle.mpc(P, Ud, oracle.mpc(P, Ud, odd), True)
+    dt_op = time.perf_counter() - t1
     return {
         "value": round(bytes_alg / dt / 1e9, 3),
         "unit": "GB/s",
@@ -243,6 +250,8 @@ def cpu_baseline(w, U, b_full):
                   f"(both parities, all s), {dt:.2f} s; algorithmic bytes 480 B per 5D site",
         "seconds": round(dt, 3),
         "gflops": round(n5 * 1320.0 / dt / 1e9, 3),
+        "normal_op_seconds": round(dt_op, 3),
+        "cg_f64_time_to_1e-8_extrapolated_s": round(dt_op * cg_iters, 1),
     }
 
 
@@ -353,7 +362,7 @@ def main():
         ms = {"mixed_f32": multishift(dwf, synth, torch, dwf.DWF_SOLVE_MIXED_F32),
               "f64": multishift(dwf, synth, torch, dwf.DWF_SOLVE_F64)}
         log(f"multishift: {ms}")
-    cpu = None if args.no_cpu else cpu_baseline(w, U, b0_host)
+    cpu = None if args.no_cpu else cpu_baseline(w, U, b0_host, st64["iters"])
 
     ms_step = t_total / args.steps * 1e3
     tmixed = float(np.mean([s["seconds"] for s in stats]))

@@ -33,6 +33,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -91,6 +92,9 @@ static void init_gamma(void)
 }
 
 /* exported so tests can check the Clifford algebra of the table itself */
+/* threads the parallel loops of this library run on */
+int or_num_threads(void) { return omp_get_max_threads(); }
+
 void or_gamma(int mu, double *out /* 4x4 complex */)
 {
     init_gamma();

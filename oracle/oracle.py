@@ -61,13 +61,19 @@ def lib():
             "or_fgcr": [_p, _i, _d, _d, _d, _d, _p, _i, _p, _p, _p, _p, _d, _i, _i, _i, _p],
             "or_hop_sites": [_p, _i, _p, _p, _p, _l, _p, _i],
             "or_d5_sites": [_p, _i, _d, _d, _d, _d, _p, _p, _p, _l, _p],
+            "or_num_threads": [],
         }
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
-            f.restype = _i if name in ("or_cgne", "or_multishift", "or_fgcr") else None
+            f.restype = _i if name in ("or_cgne", "or_multishift", "or_fgcr", "or_num_threads") else None
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    """Threads the oracle's parallel loops use (OpenMP)."""
+    return int(lib().or_num_threads())
 
 
 def _ptr(a):
