@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--maxit", type=int, default=3000)
     ap.add_argument("--normal-too", action="store_true", help="also evaluate FGCR on the normal equations")
     ap.add_argument("--skip-init", action="store_true", help="do not evaluate the untrained network")
+    ap.add_argument("--chans", default=",".join(map(str, CHANS)),
+                    help="channel counts, comma separated (4 at both ends; 4, 8 or 12 each)")
     ap.add_argument("--skip-gcr", action="store_true", help="do not evaluate plain GCR")
     ap.add_argument("--mixed", action="store_true", help="FGCR with FP32 cycles and FP64 restarts")
     args = ap.parse_args()
@@ -190,7 +192,7 @@ def main():
     torch.cuda.set_device(0)
     if args.weights:
         data = np.load(args.weights)
-        evaluate(args, torch, data["init"], data["weights"])
+        evaluate(args, torch, data["init"], data["weights"], tuple(int(v) for v in data["chans"]))
         return
     w = synth.WORKLOADS["8^4x8_train"]
     gauges = [torch.from_numpy(synth.gauge_field(w.dims, w.eps, w.gauge_seed + f)).cuda() for f in range(args.fields)]
@@ -203,23 +205,25 @@ def main():
     train_pairs = [p[:-nval] for p in pairs]
     val_pairs = [p[-nval:] for p in pairs]
     log(f"{sum(map(len, pairs))} pairs in {t_pairs:.1f}s")
-    net = dwf.dwf_net_create(lat.ctx, CHANS)
-    w0 = init_weights(CHANS, d, seed=5)
+    chans = tuple(int(v) for v in args.chans.split(","))
+    net = dwf.dwf_net_create(lat.ctx, chans)
+    w0 = init_weights(chans, d, seed=5)
     dwf.dwf_net_set_weights(net, w0)
     hist = train(lat, net, gauges, train_pairs, val_pairs, args.epochs, lr=args.lr)
     wt = dwf.dwf_net_get_weights(net)
     dwf.dwf_net_destroy(net)
     lat.close()
     print(json.dumps({"phase": "train", "lattice": "8^4x8", "fields": args.fields, "sources": args.sources,
+                      "chans": list(chans),
                       "pairs": sum(map(len, pairs)), "pair_seconds": round(t_pairs, 2),
                       "history": [[e, round(a, 5), round(b, 5), round(s, 2)] for e, a, b, s in hist]}), flush=True)
     if args.out:
-        np.savez(args.out, weights=wt, chans=np.array(CHANS), init=w0)
+        np.savez(args.out, weights=wt, chans=np.array(chans), init=w0)
 
-    evaluate(args, torch, w0, wt)
+    evaluate(args, torch, w0, wt, chans)
 
 
-def evaluate(args, torch, w0, wt):
+def evaluate(args, torch, w0, wt, chans=CHANS):
     ev = synth.WORKLOADS[args.eval_workload]
     U = synth.gauge_field(ev.dims, ev.eps, ev.gauge_seed)
     lat = dwf.Lattice(ev.dims, ev.Ls, ev.b, ev.c, ev.M5, ev.mf, ev.dirichlet, gauge=U)
@@ -228,7 +232,7 @@ def evaluate(args, torch, w0, wt):
     for name, wts in (("net_init", w0), ("net_trained", wt), ("net_trained_mfma", wt)):
         if name == "net_init" and args.skip_init:
             continue
-        nets[name] = dwf.dwf_net_create(lat.ctx, CHANS)
+        nets[name] = dwf.dwf_net_create(lat.ctx, chans)
         dwf.dwf_net_set_weights(nets[name], wts)
         if name.endswith("_mfma"):
             dwf.dwf_net_set_forward(nets[name], dwf.DWF_NET_FWD_MFMA_BF16)
