@@ -243,6 +243,86 @@ __device__ __forceinline__ void hop_step(cx<C> acc[12], const StencilKArgs &a, c
     link_accumulate<C, MU, P>(acc, h, u, D == 0, scale);
 }
 
+// FP16 neighbour spinor as loaded: three 16-byte planes and the site scale
+struct NbF16 {
+    uint32_t r[12];
+    float scale;
+};
+
+// Loads carry no branch, so the next direction's loads can be issued before
+// this direction's arithmetic.  nb < 0 marks a link across a Dirichlet face:
+// its offset is then placed beyond the buffer's range, where a buffer load
+// returns zeros without a memory access, and the contribution vanishes with
+// the zero scale.
+__device__ __forceinline__ NbF16 load_nb_f16(const InRsrc &rs, int nb, int Ls, int s)
+{
+    constexpr int kOutOfRange = (int)0x80000000u;
+    const int i = nb * Ls + s;  // < 2^27 for fields below 2 GB
+    const int o16 = nb < 0 ? kOutOfRange : i * 16;
+    const int o4 = nb < 0 ? kOutOfRange : i * 4;
+    NbF16 v;
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        const uint4 w = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs.data, o16, q * rs.plane, 0));
+        v.r[4 * q] = w.x;
+        v.r[4 * q + 1] = w.y;
+        v.r[4 * q + 2] = w.z;
+        v.r[4 * q + 3] = w.w;
+    }
+    v.scale = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs.norm, o4, 0, 0));
+    return v;
+}
+
+// the accumulator is materialised here: left free, the compiler may sink each
+// direction's accumulation to the end and keep every direction's products live
+template <typename C>
+__device__ __forceinline__ void pin_acc(cx<C> acc[12])
+{
+#pragma unroll
+    for (int c = 0; c < 12; c++) asm volatile("" : "+v"(acc[c].re), "+v"(acc[c].im));
+}
+
+template <typename C, int D, bool DAG>
+__device__ __forceinline__ void hop_f16(cx<C> acc[12], const NbF16 &v, const cx<C> *lk, int j)
+{
+    constexpr int MU = D & 3;
+    constexpr int P0 = (D < 4) ? -1 : +1;
+    constexpr int P = DAG ? -P0 : P0;
+    cx<C> h[6];
+    project_f16<MU, P>(v.r, h);
+    cx<C> u[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) u[k] = lk[j * LK_STRIDE + D * 9 + k];
+    link_accumulate<C, MU, P>(acc, h, u, D == 0, C(v.scale));
+    pin_acc<C>(acc);
+}
+
+// the eight directions of the FP16 hop, loads running one direction ahead;
+// the scheduling barriers keep that order (left free, the scheduler may hoist
+// all eight loads and trade most of the occupancy for them)
+template <typename C, bool DAG>
+__device__ __forceinline__ void hop_f16_all(cx<C> acc[12], const InRsrc &rs, const cx<C> *lk, const int *nbs, int j,
+                                            int Ls, int s)
+{
+    const int *nj = nbs + j * 8;
+    NbF16 v[2];
+    v[0] = load_nb_f16(rs, nj[0], Ls, s);
+#define DWF_HOP_STAGE(D)                                               \
+    if constexpr (D < 7) v[(D + 1) & 1] = load_nb_f16(rs, nj[D + 1], Ls, s); \
+    __builtin_amdgcn_sched_barrier(0);                                 \
+    hop_f16<C, D, DAG>(acc, v[D & 1], lk, j);                          \
+    __builtin_amdgcn_sched_barrier(0);
+    DWF_HOP_STAGE(0)
+    DWF_HOP_STAGE(1)
+    DWF_HOP_STAGE(2)
+    DWF_HOP_STAGE(3)
+    DWF_HOP_STAGE(4)
+    DWF_HOP_STAGE(5)
+    DWF_HOP_STAGE(6)
+    DWF_HOP_STAGE(7)
+#undef DWF_HOP_STAGE
+}
+
 // cooperative load of the links and neighbour indices of sb consecutive
 // internal sites starting at tile*sb into LDS (each link read once per
 // workgroup instead of once per lane)
@@ -354,7 +434,9 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
     for (int c = 0; c < 12; c++) acc[c] = mk(C(0), C(0));
     InRsrc rs{};
     if constexpr (S::prec == P_F16) rs = in_rsrc(a.in);
-    if (valid) {
+    if constexpr (S::prec == P_F16) {
+        if (valid) hop_f16_all<C, DAG>(acc, rs, lk, nbs, j, Ls, s);
+    } else if (valid) {
         hop_step<S, C, 0, DAG>(acc, a, rs, lk, nbs, j, sb, s);
         hop_step<S, C, 1, DAG>(acc, a, rs, lk, nbs, j, sb, s);
         hop_step<S, C, 2, DAG>(acc, a, rs, lk, nbs, j, sb, s);
