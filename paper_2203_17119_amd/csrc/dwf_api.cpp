@@ -436,6 +436,7 @@ dwf_status dwf_create(const dwf_params *p, const double *gauge, int gauge_on_dev
             c->lds_max = std::min<size_t>(65536, (size_t)lds);
         }
         HIPCHECK(hipMalloc(&c->nbr, (size_t)2 * 8 * c->vh * sizeof(int)));
+        HIPCHECK(hipMalloc(&c->nbr_sm, (size_t)2 * 8 * c->vh * sizeof(int)));
         build_order(*c, 0, 0, 0);
         build_neighbours(*c);
         default_schedule(*c);
@@ -468,7 +469,10 @@ dwf_status dwf_destroy(dwf_ctx ctx)
     for (int pr = 0; pr < 4; pr++)
         for (int p = 0; p < 2; p++)
             if (c.links[pr][p]) (void)hipFree(c.links[pr][p]);
+    for (int p = 0; p < 2; p++)
+        if (c.links_net[p]) (void)hipFree(c.links_net[p]);
     if (c.nbr) (void)hipFree(c.nbr);
+    if (c.nbr_sm) (void)hipFree(c.nbr_sm);
     if (c.perm_inv) (void)hipFree(c.perm_inv);
     if (c.slmat64) (void)hipFree(c.slmat64);
     if (c.slmat32) (void)hipFree(c.slmat32);

@@ -76,7 +76,8 @@ struct Context {
     int device = 0;
     size_t lds_max = 65536;  // dynamic LDS one workgroup may use
 
-    int *nbr = nullptr;          // [2][8][vh]
+    int *nbr = nullptr;          // [2][8][vh] (network kernels)
+    int *nbr_sm = nullptr;       // [2][vh][8], site-major (stencil)
     // Internal 4D site order, the same for both parities: internal index j of
     // the site with checkerboard index cb is perm[cb]; perm_inv[j] = cb.
     // Sites are grouped in columns of (order[0] x order[1] x order[2]) sites in
@@ -84,7 +85,8 @@ struct Context {
     int *perm_inv = nullptr;     // device [vh]
     std::vector<int> perm_h, perm_inv_h;
     int order[3] = {0, 0, 0};
-    void *links[4][2] = {};      // [prec][parity] -> [8][9][vh] elements
+    void *links[4][2] = {};      // [prec][parity] -> [vh][8][9] elements, site-major (stencil)
+    void *links_net[2] = {};     // [parity] -> FP32 [8][9][vh] (network kernels), with links[P_F32]
     double *slmat64 = nullptr;   // [SL_NOP][2][Ls][Ls]
     // operators that are twisted-circulant on one chirality block (first column
     // toep_f) and its transpose on the other; toep_rev: the P+ block is the transpose

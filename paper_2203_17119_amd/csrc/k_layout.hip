@@ -104,10 +104,12 @@ long column_sites(const Context &c) { return (long)c.order[0] * c.order[1] * c.o
 
 // nbr[p][d][j]: internal index of the neighbour of site j (output parity p) in
 // direction d, or -1 where the link crosses a Dirichlet face (it is zero, so
-// the kernels skip the neighbour instead of reading across the block)
+// the kernels skip the neighbour instead of reading across the block).  The
+// stencil reads the same table site-major, nbr_sm[p][j][d]: the eight indices
+// of the sites of one workgroup are then one contiguous block.
 void build_neighbours(Context &c)
 {
-    std::vector<int> h((size_t)2 * 8 * c.vh);
+    std::vector<int> h((size_t)2 * 8 * c.vh), hs((size_t)2 * 8 * c.vh);
     for (int p = 0; p < 2; p++)
         for (long j = 0; j < c.vh; j++) {
             int x[4];
@@ -117,16 +119,22 @@ void build_neighbours(Context &c)
                 const bool cut = c.p.dirichlet[mu] && (d < 4 ? x[mu] == c.L[mu] - 1 : x[mu] == 0);
                 int y[4] = {x[0], x[1], x[2], x[3]};
                 y[mu] = (y[mu] + step + c.L[mu]) % c.L[mu];
-                h[((size_t)p * 8 + d) * c.vh + j] = cut ? -1 : c.perm_h[lex(c.L, y) >> 1];
+                const int nb = cut ? -1 : c.perm_h[lex(c.L, y) >> 1];
+                h[((size_t)p * 8 + d) * c.vh + j] = nb;
+                hs[((size_t)p * c.vh + j) * 8 + d] = nb;
             }
         }
     HIPCHECK(hipMemcpy(c.nbr, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(c.nbr_sm, hs.data(), hs.size() * sizeof(int), hipMemcpyHostToDevice));
 }
 
-// link[d][k][cb] of output parity p: U_mu(x) (d < 4) or U_mu(x-mu)^+ (d >= 4),
-// zero when the link crosses a Dirichlet face (leaves through x_mu = L_mu - 1)
+// links of output parity p, entry k = 3 r + col of direction d at internal
+// site j: U_mu(x) (d < 4) or U_mu(x-mu)^+ (d >= 4), zero when the link crosses
+// a Dirichlet face (leaves through x_mu = L_mu - 1).  site_major: [j][d][k]
+// (the 72 entries of a site contiguous, read by the stencil one workgroup
+// block at a time); else [d][k][j] (read per lane by the network kernels).
 template <typename S>
-__global__ void k_prepare_links(Geo g, const double2 *gauge, int p, int4 dir, typename S::elem *out)
+__global__ void k_prepare_links(Geo g, const double2 *gauge, int p, int4 dir, typename S::elem *out, int site_major)
 {
     const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (j >= g.vh) return;
@@ -152,7 +160,8 @@ __global__ void k_prepare_links(Geo g, const double2 *gauge, int p, int4 dir, ty
                 if (d < 4) v = mk(U[r * 3 + col].x, U[r * 3 + col].y);
                 else v = mk(U[col * 3 + r].x, -U[col * 3 + r].y);
                 if (zero) v = mk(0.0, 0.0);
-                out[((long)d * 9 + r * 3 + col) * g.vh + j] = pack<S, double>(v);
+                const long k = (long)d * 9 + r * 3 + col;
+                out[site_major ? j * 72 + k : k * g.vh + j] = pack<S, double>(v);
             }
     }
 }
@@ -177,12 +186,17 @@ void prepare_links(Context &c, int prec)
         const dim3 grid((unsigned)((c.vh + 255) / 256)), blk(256);
         const double2 *U = (const double2 *)c.gauge_canon;
         switch (prec) {
-        case P_F64: hipLaunchKernelGGL(k_prepare_links<F64>, grid, blk, 0, c.stream, g, U, p, dir, (double2 *)c.links[prec][p]); break;
-        case P_F32: hipLaunchKernelGGL(k_prepare_links<F32>, grid, blk, 0, c.stream, g, U, p, dir, (float2 *)c.links[prec][p]); break;
-        case P_F16: hipLaunchKernelGGL(k_prepare_links<F16>, grid, blk, 0, c.stream, g, U, p, dir, (__half2 *)c.links[prec][p]); break;
-        default: hipLaunchKernelGGL(k_prepare_links<BF16>, grid, blk, 0, c.stream, g, U, p, dir, (__hip_bfloat162 *)c.links[prec][p]); break;
+        case P_F64: hipLaunchKernelGGL(k_prepare_links<F64>, grid, blk, 0, c.stream, g, U, p, dir, (double2 *)c.links[prec][p], 1); break;
+        case P_F32: hipLaunchKernelGGL(k_prepare_links<F32>, grid, blk, 0, c.stream, g, U, p, dir, (float2 *)c.links[prec][p], 1); break;
+        case P_F16: hipLaunchKernelGGL(k_prepare_links<F16>, grid, blk, 0, c.stream, g, U, p, dir, (__half2 *)c.links[prec][p], 1); break;
+        default: hipLaunchKernelGGL(k_prepare_links<BF16>, grid, blk, 0, c.stream, g, U, p, dir, (__hip_bfloat162 *)c.links[prec][p], 1); break;
         }
         HIPCHECK(hipGetLastError());
+        if (prec == P_F32) {
+            if (!c.links_net[p]) HIPCHECK(hipMalloc(&c.links_net[p], bytes));
+            hipLaunchKernelGGL(k_prepare_links<F32>, grid, blk, 0, c.stream, g, U, p, dir, (float2 *)c.links_net[p], 0);
+            HIPCHECK(hipGetLastError());
+        }
     }
 }
 

@@ -463,8 +463,8 @@ static NetGeo net_geo(Context &c)
 {
     NetGeo g;
     g.nbr = c.nbr;
-    g.links0 = (const float2 *)c.links[P_F32][0];
-    g.links1 = (const float2 *)c.links[P_F32][1];
+    g.links0 = (const float2 *)c.links_net[0];
+    g.links1 = (const float2 *)c.links_net[1];
     g.vh = c.vh;
     g.Ls = c.Ls;
     return g;

@@ -38,8 +38,8 @@ namespace dwf {
 
 struct StencilKArgs {
     Field in, self, out;
-    const void *links;  // output-parity links [8][9][vh]
-    const int *nbr;     // output-parity neighbours [8][vh]
+    const void *links;  // output-parity links [vh][8][9]
+    const int *nbr;     // output-parity neighbours [vh][8]
     long vh;
     int Ls;
     int run;
@@ -185,8 +185,6 @@ __device__ __forceinline__ void link_accumulate(cx<C> acc[12], const cx<C> h[6],
     }
 }
 
-// one direction of the hop; the workgroup's links and neighbour indices are in
-// LDS: lk[(d*9 + k)*sb + j], nb[d*sb + j]
 // Buffer resources of an FP16 input field: the three 16-byte planes are read
 // with one 32-bit lane offset and a scalar plane offset, so a neighbour load
 // costs one integer multiply-add instead of 64-bit address arithmetic
@@ -206,6 +204,8 @@ __device__ __forceinline__ InRsrc in_rsrc(const Field &f)
     return r;
 }
 
+// one direction of the hop; the workgroup's links and neighbour indices are in
+// LDS: lk[j * LK_STRIDE + d * 9 + k], nbs[j * 8 + d]
 template <typename S, typename C, int D, bool DAG>
 __device__ __forceinline__ void hop_step(cx<C> acc[12], const StencilKArgs &a, const InRsrc &rs, const cx<C> *lk,
                                          const int *nbs, int j, int sb, int s)
@@ -282,6 +282,56 @@ __device__ __forceinline__ void pin_acc(cx<C> acc[12])
     for (int c = 0; c < 12; c++) asm volatile("" : "+v"(acc[c].re), "+v"(acc[c].im));
 }
 
+// acc += scale * (1 + P g_MU) U h, one colour row of the link at a time: row
+// r gives the colour-r entries of both projected spin vectors, and those alone
+// feed the four accumulator entries of colour r (upper pair, and lower pair
+// rebuilt), so only three link entries and two products are live at once.
+// The arithmetic per output entry is that of link_accumulate.
+template <typename C, int MU, int P>
+__device__ __forceinline__ void link_accumulate_rows(cx<C> acc[12], const cx<C> h[6], const cx<C> *u, bool first,
+                                                     C scale)
+{
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        const cx<C> u0 = u[r * 3 + 0], u1 = u[r * 3 + 1], u2 = u[r * 3 + 2];
+        cx<C> g0 = cmul(u0, h[0]);
+        cmac(g0, u1, h[1]);
+        cmac(g0, u2, h[2]);
+        cx<C> g1 = cmul(u0, h[3]);
+        cmac(g1, u1, h[4]);
+        cmac(g1, u2, h[5]);
+        cx<C> lo0, lo1;
+        if constexpr (MU == 0) {
+            lo0 = (P > 0) ? timesI(g1) : timesMinusI(g1);
+            lo1 = (P > 0) ? timesI(g0) : timesMinusI(g0);
+        } else if constexpr (MU == 1) {
+            lo0 = (P > 0) ? g1 : -g1;
+            lo1 = (P > 0) ? -g0 : g0;
+        } else if constexpr (MU == 2) {
+            lo0 = (P > 0) ? timesI(g0) : timesMinusI(g0);
+            lo1 = (P > 0) ? timesMinusI(g1) : timesI(g1);
+        } else {
+            lo0 = (P > 0) ? g0 : -g0;
+            lo1 = (P > 0) ? g1 : -g1;
+        }
+        if (first) {
+            acc[r] = scale * g0;
+            acc[3 + r] = scale * g1;
+            acc[6 + r] = scale * lo0;
+            acc[9 + r] = scale * lo1;
+        } else {
+            acc[r].re = fma(scale, g0.re, acc[r].re);
+            acc[r].im = fma(scale, g0.im, acc[r].im);
+            acc[3 + r].re = fma(scale, g1.re, acc[3 + r].re);
+            acc[3 + r].im = fma(scale, g1.im, acc[3 + r].im);
+            acc[6 + r].re = fma(scale, lo0.re, acc[6 + r].re);
+            acc[6 + r].im = fma(scale, lo0.im, acc[6 + r].im);
+            acc[9 + r].re = fma(scale, lo1.re, acc[9 + r].re);
+            acc[9 + r].im = fma(scale, lo1.im, acc[9 + r].im);
+        }
+    }
+}
+
 template <typename C, int D, bool DAG>
 __device__ __forceinline__ void hop_f16(cx<C> acc[12], const NbF16 &v, const cx<C> *lk, int j)
 {
@@ -290,10 +340,7 @@ __device__ __forceinline__ void hop_f16(cx<C> acc[12], const NbF16 &v, const cx<
     constexpr int P = DAG ? -P0 : P0;
     cx<C> h[6];
     project_f16<MU, P>(v.r, h);
-    cx<C> u[9];
-#pragma unroll
-    for (int k = 0; k < 9; k++) u[k] = lk[j * LK_STRIDE + D * 9 + k];
-    link_accumulate<C, MU, P>(acc, h, u, D == 0, C(v.scale));
+    link_accumulate_rows<C, MU, P>(acc, h, lk + j * LK_STRIDE + D * 9, D == 0, C(v.scale));
     pin_acc<C>(acc);
 }
 
@@ -323,20 +370,51 @@ __device__ __forceinline__ void hop_f16_all(cx<C> acc[12], const InRsrc &rs, con
 #undef DWF_HOP_STAGE
 }
 
-// cooperative load of the links and neighbour indices of sb consecutive
-// internal sites starting at tile*sb into LDS (each link read once per
-// workgroup instead of once per lane)
+// cooperative load of the links and neighbour indices of the sb consecutive
+// internal sites from base into LDS (each link read once per workgroup
+// instead of once per lane).  Both tables are site-major, so the workgroup's
+// entries are one contiguous block: it is read in 16-byte pieces spread over
+// all lanes, and every piece of a round is requested before any is used.
 template <typename S, typename C>
 __device__ __forceinline__ void stage_links(const StencilKArgs &a, long base, int sb, cx<C> *lk, int *nbs)
 {
-    // the Ls lanes of site j = threadIdx.y share its 72 link entries and 8 indices
-    const int jj = threadIdx.y;
-    const long site = base + jj;
-    const bool ok = site < a.vh;
-    const typename S::elem *L = (const typename S::elem *)a.links;
-    for (int dk = threadIdx.x; dk < 72; dk += blockDim.x)
-        lk[jj * LK_STRIDE + dk] = ok ? unpack<C>(L[(long)dk * a.vh + site]) : mk(C(0), C(0));
-    for (int d = threadIdx.x; d < 8; d += blockDim.x) nbs[jj * 8 + d] = ok ? a.nbr[(long)d * a.vh + site] : 0;
+    using P = Planes<S>;              // complex entries per 16-byte piece
+    constexpr int CPS = 72 / P::cpp;  // pieces per site
+    constexpr int R = 4;              // pieces per lane and round
+    const int nt = blockDim.x * blockDim.y;
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const long left = a.vh - base;
+    const int ns = left < sb ? (int)left : sb;  // sites of the workgroup inside the field
+    const int npc = ns * CPS;
+    const uint4 *src = (const uint4 *)a.links + base * CPS;
+    for (int c0 = tid; c0 < npc; c0 += R * nt) {
+        uint4 w[R];
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            const int c = c0 + k * nt;
+            if (c < npc) w[k] = src[c];
+        }
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            const int c = c0 + k * nt;
+            if (c < npc) {
+                const int site = c / CPS, e0 = (c - site * CPS) * P::cpp;
+                Vec16 v;
+                v.u = w[k];
+#pragma unroll
+                for (int e = 0; e < P::cpp; e++) lk[site * LK_STRIDE + e0 + e] = unpack<C>(vec_get<S>(v, e));
+            }
+        }
+    }
+    // eight indices per site: two 16-byte pieces, landing at nbs[site * 8 + d]
+    const int4 *nsrc = (const int4 *)a.nbr + base * 2;
+    for (int c = tid; c < 2 * ns; c += nt) {
+        const int4 v = nsrc[c];
+        nbs[4 * c] = v.x;
+        nbs[4 * c + 1] = v.y;
+        nbs[4 * c + 2] = v.z;
+        nbs[4 * c + 3] = v.w;
+    }
 }
 
 // batch member blockIdx.y of fields laid out `stride` bytes apart
@@ -627,7 +705,7 @@ static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field s
     a.self = self;
     a.out = out;
     a.links = c.links[S::prec][sp.out_parity];
-    a.nbr = c.nbr + (long)sp.out_parity * 8 * c.vh;
+    a.nbr = c.nbr_sm + (long)sp.out_parity * 8 * c.vh;
     a.vh = c.vh;
     a.Ls = Ls;
     a.run = c.cfg_stencil.run;
