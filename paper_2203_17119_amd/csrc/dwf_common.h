@@ -252,9 +252,12 @@ __device__ __forceinline__ void unpack_raw(const RawSpinor<S> &r, cx<C> v[12])
     }
 }
 
-template <typename S, typename C>
+// NT: non-temporal stores, for outputs that the writing kernel does not read
+// again (they are not kept in the caches at the expense of its inputs)
+template <typename S, typename C, bool NT = false>
 __device__ __forceinline__ void store_spinor(const Field &f, long i, const cx<C> v[12])
 {
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
     using P = Planes<S>;
     uint4 *d = (uint4 *)f.data;
     C inv = C(1);
@@ -263,7 +266,8 @@ __device__ __forceinline__ void store_spinor(const Field &f, long i, const cx<C>
 #pragma unroll
         for (int c = 0; c < 12; c++) m = fmax(m, fmax(fabs(v[c].re), fabs(v[c].im)));
         inv = (m > C(0)) ? C(1) / m : C(0);
-        f.norm[i] = float(m);
+        if constexpr (NT) __builtin_nontemporal_store(float(m), f.norm + i);
+        else f.norm[i] = float(m);
     }
 #pragma unroll
     for (int q = 0; q < P::n; q++) {
@@ -273,22 +277,9 @@ __device__ __forceinline__ void store_spinor(const Field &f, long i, const cx<C>
             const cx<C> t = S::has_norm ? inv * v[q * P::cpp + k] : v[q * P::cpp + k];
             vec_set<S>(w, k, pack<S, C>(t));
         }
-        d[q * f.n + i] = w.u;
+        if constexpr (NT) __builtin_nontemporal_store(__builtin_bit_cast(v4u, w.u), (v4u *)(d + q * f.n + i));
+        else d[q * f.n + i] = w.u;
     }
-}
-
-// Links of one output parity: 8 directions x 9 complex entries x vh sites.
-struct Links {
-    const void *data;
-    long vh;
-};
-
-template <typename S, typename C>
-__device__ __forceinline__ void load_link(const Links &l, int d, long cb, cx<C> u[9])
-{
-    const typename S::elem *p = (const typename S::elem *)l.data + (long)d * 9 * l.vh + cb;
-#pragma unroll
-    for (int k = 0; k < 9; k++) u[k] = unpack<C>(p[k * l.vh]);
 }
 
 // Value of (P5 psi) (dag = false) or (P5^+ psi) (dag = true) at slice s for

@@ -386,13 +386,15 @@ __device__ __forceinline__ void stage_links(const StencilKArgs &a, long base, in
     const long left = a.vh - base;
     const int ns = left < sb ? (int)left : sb;  // sites of the workgroup inside the field
     const int npc = ns * CPS;
+    // the block is read by this workgroup alone: non-temporal loads
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
     const uint4 *src = (const uint4 *)a.links + base * CPS;
     for (int c0 = tid; c0 < npc; c0 += R * nt) {
         uint4 w[R];
 #pragma unroll
         for (int k = 0; k < R; k++) {
             const int c = c0 + k * nt;
-            if (c < npc) w[k] = src[c];
+            if (c < npc) w[k] = __builtin_bit_cast(uint4, __builtin_nontemporal_load((const v4u *)(src + c)));
         }
 #pragma unroll
         for (int k = 0; k < R; k++) {
@@ -618,7 +620,7 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
             for (int c = 0; c < 12; c++) res[c] = rv[c] - al * res[c];
         }
     }
-    if (valid) store_spinor<S, C>(a.out, i, res);
+    if (valid) store_spinor<S, C, true>(a.out, i, res);
     if constexpr (RED != 0) {
         double n2 = 0;
         if (valid) {
