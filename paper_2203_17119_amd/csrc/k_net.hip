@@ -19,6 +19,9 @@ struct NetGeo {
     const int *nbr;        // [2][8][vh]
     const float2 *links0;  // FP32 links, output parity 0: [8][9][vh]
     const float2 *links1;  // output parity 1
+    const int *nbr_sm;     // [2][vh][8], site-major
+    const float2 *lsm0;    // FP32 links, output parity 0, site-major: [vh][8][9]
+    const float2 *lsm1;    // output parity 1
     long vh;
     int Ls;
 };
@@ -191,13 +194,20 @@ __device__ __forceinline__ cx<float> ld_feat(const void *base, long k)
 // Activations between layers may be BF16 pairs (in_bf16 / out_bf16): the
 // matrix cores round their B operand to BF16 anyway, and BF16 storage halves
 // the bytes of the eleven path reads of every input channel.
+// Held to four waves per SIMD: left free, the compiler puts the accumulators
+// in AGPRs on top of ~124 VGPRs and two waves per SIMD fit, too few to cover
+// the per-path load latency; in 128 registers the accumulators fit in VGPRs
+// without spills.
 template <int CIN, int COUT, bool IBF, bool OBF>
-__global__ void __launch_bounds__(256) k_ptc_fwd_mfma(NetGeo g, const void *in, void *out, const short *wpk, int p,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) k_ptc_fwd_mfma(NetGeo g, const void *in, void *out, const short *wpk, int p,
                                                       long n)
 {
     static_assert(CIN % 4 == 0 && 2 * COUT <= 32, "channel counts");
     constexpr int NCOL = 3 * MF_S, NP = CIN / 2, HP = NP / 2;
+    constexpr int JMAX = MF_S / 8 + 2;  // 4D sites a workgroup spans when Ls >= 8
     __shared__ bf16x4 Tb[NP * NCOL];
+    __shared__ cx<float> lks[JMAX * 72];
+    __shared__ int nbl[JMAX * 8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, jc = lane & 31;
     const long i0 = (long)blockIdx.x * MF_S;
     // transport role: site ts, channel pairs [th HP, th HP + HP)
@@ -207,6 +217,21 @@ __global__ void __launch_bounds__(256) k_ptc_fwd_mfma(NetGeo g, const void *in, 
     const long j = ok ? it / g.Ls : 0;
     const int s = ok ? (int)(it - j * g.Ls) : 0;
     const bf16x4 *A = (const bf16x4 *)wpk + lane;
+    // With Ls >= 8 the links and neighbour indices of the workgroup's 4D sites
+    // (one contiguous block of each site-major table) are staged in LDS once,
+    // instead of every lane loading them again for every path.
+    const bool staged = g.Ls >= 8;
+    const long j0 = i0 / g.Ls;
+    if (staged) {
+        const long ilast = (i0 + MF_S < n ? i0 + MF_S : n) - 1;
+        const int nj = (int)(ilast / g.Ls - j0) + 1;
+        const float2 *lsrc = (p ? g.lsm1 : g.lsm0) + j0 * 72;
+        for (int k = tid; k < nj * 72; k += 256) lks[k] = c2(lsrc[k]);
+        const int *nsrc = g.nbr_sm + ((long)p * g.vh + j0) * 8;
+        for (int k = tid; k < nj * 8; k += 256) nbl[k] = nsrc[k];
+        __syncthreads();
+    }
+    const int jl = ok ? (int)(j - j0) : 0;  // local 4D site of this lane's transport role
     f32x16 acc[3];
 #pragma unroll
     for (int t = 0; t < 3; t++)
@@ -215,13 +240,26 @@ __global__ void __launch_bounds__(256) k_ptc_fwd_mfma(NetGeo g, const void *in, 
     for (int pi = 0; pi < 11; pi++) {
         long src = 0;
         int sp = p;
-        const bool have = ok && path_source(g, p, pi, j, s, src, sp);
         const bool hop = pi >= 1 && pi <= 8;
+        bool have;
+        if (staged && hop) {
+            const int nb = nbl[jl * 8 + pi - 1];
+            src = (long)(nb < 0 ? 0 : nb) * g.Ls + s;
+            sp = 1 - p;
+            have = ok && nb >= 0;
+        } else {
+            have = ok && path_source(g, p, pi, j, s, src, sp);
+        }
         cx<float> u[9];
         if (have && hop) {
-            const float2 *L = (p ? g.links1 : g.links0) + (long)(pi - 1) * 9 * g.vh + j;
+            if (staged) {
 #pragma unroll
-            for (int k = 0; k < 9; k++) u[k] = c2(L[(long)k * g.vh]);
+                for (int k = 0; k < 9; k++) u[k] = lks[jl * 72 + (pi - 1) * 9 + k];
+            } else {
+                const float2 *L = (p ? g.links1 : g.links0) + (long)(pi - 1) * 9 * g.vh + j;
+#pragma unroll
+                for (int k = 0; k < 9; k++) u[k] = c2(L[(long)k * g.vh]);
+            }
         }
         const long base = (long)sp * CIN * 3 * n + src;
 #pragma unroll
@@ -465,6 +503,9 @@ static NetGeo net_geo(Context &c)
     g.nbr = c.nbr;
     g.links0 = (const float2 *)c.links_net[0];
     g.links1 = (const float2 *)c.links_net[1];
+    g.nbr_sm = c.nbr_sm;
+    g.lsm0 = (const float2 *)c.links[P_F32][0];
+    g.lsm1 = (const float2 *)c.links[P_F32][1];
     g.vh = c.vh;
     g.Ls = c.Ls;
     return g;

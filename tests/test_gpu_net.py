@@ -127,6 +127,30 @@ def test_precond_apply_mfma_ragged_tile():
         c.close()
 
 
+@pytest.mark.parametrize("Ls", [8, 9, 12, 16])
+def test_precond_apply_mfma_staged_links(Ls):
+    """Ls >= 8: the matrix-core forward stages the links and neighbour indices
+    of a workgroup's 4D sites in LDS.  A 128-site tile then starts inside a 4D
+    site (Ls = 9, 12) and the last tile is ragged; bound as in the matrix-core
+    test above."""
+    c = Case((4, 2, 2, 2), Ls, mf=0.1, dirichlet=(1, 0, 0, 1), eps=0.5, seed=53 + Ls)
+    Ws = random_weights(CHANS, 5)
+    net = dwf.dwf_net_create(c.ctx, CHANS)
+    try:
+        dwf.dwf_net_set_weights(net, flat(Ws))
+        dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_MFMA_BF16)
+        x = c.half(66)
+        out = torch().empty_like(to_gpu(x))
+        dwf.dwf_precond_apply(c.ctx, net, to_gpu(x), out)
+        expect = oracle.pick(c.P, oracle_forward(c, Ws, x)[-1], 1)
+        err = relerr(to_host(out), expect)
+        print(f"mfma forward Ls={Ls}: relative error {err:.2e}", flush=True)
+        assert err < 2e-2
+    finally:
+        dwf.dwf_net_destroy(net)
+        c.close()
+
+
 def test_backward_matches_oracle(case):
     Ws = random_weights(CHANS, 2)
     net = dwf.dwf_net_create(case.ctx, CHANS)
