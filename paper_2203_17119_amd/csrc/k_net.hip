@@ -11,6 +11,8 @@
 //   f[p][ch*3 + colour][i],  i = j*Ls + s (internal site order)
 // Weights are BF16 (re, im) pairs converted to FP32 in LDS; all arithmetic FP32,
 // weight-gradient partial sums FP64.
+#include <type_traits>
+
 #include "dwf_internal.h"
 
 namespace dwf {
@@ -191,15 +193,28 @@ __device__ __forceinline__ cx<float> ld_feat(const void *base, long k)
     }
 }
 
+// feature element from its raw load: a BF16 pair or an FP32 pair
+template <bool BF>
+__device__ __forceinline__ cx<float> raw_feat(typename std::conditional<BF, uint32_t, float2>::type r)
+{
+    if constexpr (BF) {
+        return mk(__uint_as_float(r << 16), __uint_as_float(r & 0xffff0000u));
+    } else {
+        return c2(r);
+    }
+}
+
 // Activations between layers may be BF16 pairs (in_bf16 / out_bf16): the
 // matrix cores round their B operand to BF16 anyway, and BF16 storage halves
 // the bytes of the eleven path reads of every input channel.
-// Held to four waves per SIMD: left free, the compiler puts the accumulators
-// in AGPRs on top of ~124 VGPRs and two waves per SIMD fit, too few to cover
-// the per-path load latency; in 128 registers the accumulators fit in VGPRs
-// without spills.
+// Occupancy target: left free, the compiler puts the accumulators in AGPRs on
+// top of the VGPRs and two waves per SIMD fit, too few to cover the per-path
+// load latency.  With the accumulators in VGPRs, four waves fit without spills
+// for CIN = 4 and three for wider inputs (whose prefetched features take more
+// registers).
 template <int CIN, int COUT, bool IBF, bool OBF>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) k_ptc_fwd_mfma(NetGeo g, const void *in, void *out, const short *wpk, int p,
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(CIN <= 4 ? 4 : 3, CIN <= 4 ? 4 : 3))) k_ptc_fwd_mfma(NetGeo g, const void *in, void *out, const short *wpk, int p,
                                                       long n)
 {
     static_assert(CIN % 4 == 0 && 2 * COUT <= 32, "channel counts");
@@ -237,19 +252,39 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
     for (int t = 0; t < 3; t++)
 #pragma unroll
         for (int r = 0; r < 16; r++) acc[t][r] = 0.f;
-    for (int pi = 0; pi < 11; pi++) {
+    // Feature loads of a path are issued at the start of the previous path's
+    // matrix-core phase, so they are in flight through it and its barrier;
+    // only the accumulators and operands are live there, so this costs no
+    // registers at the peak (the transport phase).
+    using RawT = typename std::conditional<IBF, uint32_t, float2>::type;
+    RawT raw[HP][2][3];
+    auto fetch = [&](int pi) -> bool {
         long src = 0;
         int sp = p;
-        const bool hop = pi >= 1 && pi <= 8;
-        bool have;
-        if (staged && hop) {
+        bool hv;
+        if (staged && pi >= 1 && pi <= 8) {
             const int nb = nbl[jl * 8 + pi - 1];
             src = (long)(nb < 0 ? 0 : nb) * g.Ls + s;
             sp = 1 - p;
-            have = ok && nb >= 0;
+            hv = ok && nb >= 0;
         } else {
-            have = ok && path_source(g, p, pi, j, s, src, sp);
+            hv = ok && path_source(g, p, pi, j, s, src, sp);
         }
+        const long base = (long)sp * CIN * 3 * n + src;
+#pragma unroll
+        for (int q = 0; q < HP; q++)
+#pragma unroll
+            for (int e = 0; e < 2; e++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const long f = base + (long)((2 * (th * HP + q) + e) * 3 + c) * n;
+                    if (hv) raw[q][e][c] = ((const RawT *)in)[f];
+                }
+        return hv;
+    };
+    bool have = fetch(0);
+    for (int pi = 0; pi < 11; pi++) {
+        const bool hop = pi >= 1 && pi <= 8;
         cx<float> u[9];
         if (have && hop) {
             if (staged) {
@@ -261,17 +296,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
                 for (int k = 0; k < 9; k++) u[k] = c2(L[(long)k * g.vh]);
             }
         }
-        const long base = (long)sp * CIN * 3 * n + src;
 #pragma unroll
         for (int q = 0; q < HP; q++) {
             const int pp = th * HP + q;
             cx<float> t[2][3];
 #pragma unroll
             for (int e = 0; e < 2; e++) {
-                const long f = base + (long)((2 * pp + e) * 3) * n;
                 if (have) {
-                    const cx<float> v0 = ld_feat<IBF>(in, f), v1 = ld_feat<IBF>(in, f + n),
-                                    v2 = ld_feat<IBF>(in, f + 2 * n);
+                    const cx<float> v0 = raw_feat<IBF>(raw[q][e][0]), v1 = raw_feat<IBF>(raw[q][e][1]),
+                                    v2 = raw_feat<IBF>(raw[q][e][2]);
                     if (hop) {
 #pragma unroll
                         for (int r = 0; r < 3; r++) {
@@ -300,6 +333,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
             }
         }
         __syncthreads();
+        const bool have_next = (pi + 1 < 11) ? fetch(pi + 1) : false;
 #pragma unroll
         for (int st = 0; st < CIN / 4; st++) {
             const bf16x4 a = A[(pi * (CIN / 4) + st) * 64];
@@ -310,6 +344,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
             }
         }
         __syncthreads();
+        have = have_next;
     }
     // accumulator register r of tile tt holds row m' = 8 (r / 4) + 4 h + r % 4 of column
     // (tile * 32 + jc): colour col / MF_S, site col % MF_S
