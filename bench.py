@@ -352,8 +352,7 @@ def main():
     if not args.no_precond:
         lp = learned_precond(lat, dwf, torch, srcs[0], w.tol, mfma=True)
         log(f"learned preconditioner: {lp}")
-        lp["compact_network"] = learned_precond(lat, dwf, torch, srcs[0], w.tol, mfma=False,
-                                                weights=WEIGHTS_COMPACT)
+        lp["compact_network"] = learned_precond(lat, dwf, torch, srcs[0], w.tol, weights=WEIGHTS_COMPACT)
         log(f"learned preconditioner, compact network: {lp['compact_network']}")
     table = None if args.no_table else dhop_table(lat, dwf, torch)
     ms = None
