@@ -201,15 +201,42 @@ static void build_slocal(Context &c)
             }
         return true;
     };
+    // first column of (beta + gamma S)(delta + eps S)^-1, S = S_up
+    auto rational_column = [&](double be, double ga, double de, double ep, double *f) {
+        const double r = -ep / de;
+        const double nrm = de * (1.0 + mf * std::pow(r, n));
+        for (int k = 0; k < n; k++) {
+            const double y = std::pow(r, k) / nrm;                         // (delta + eps S)^-1, column 0
+            const double y1 = k >= 1 ? std::pow(r, k - 1) / nrm : 0.0;     // shifted by one
+            f[k] = be * y + ga * y1;
+        }
+    };
+    const double cand[4][4] = {{b, cc, d, e}, {1.0, 0.0, d, e}, {b, cc, 1.0, 0.0}, {d, e, 1.0, 0.0}};
     for (int op = 0; op < SL_NOP; op++) {
         c.toep_ok[op] = false;
         c.toep_rev[op] = 0;
+        c.toep_rat[op] = false;
         if (n > 16) continue;
         if (twisted(blocks[2 * op], blocks[2 * op + 1], c.toep_f[op])) {
             c.toep_ok[op] = true;
         } else if (twisted(blocks[2 * op + 1], blocks[2 * op], c.toep_f[op])) {
             c.toep_ok[op] = true;
             c.toep_rev[op] = 1;
+        }
+        if (!c.toep_ok[op]) continue;
+        double fs = 0;
+        for (int k = 0; k < n; k++) fs = std::max(fs, std::fabs(c.toep_f[op][k]));
+        for (const auto &q : cand) {
+            if (q[2] == 0.0 || std::fabs(q[3] / q[2]) > 0.5) continue;
+            double fr[16];
+            rational_column(q[0], q[1], q[2], q[3], fr);
+            bool same = true;
+            for (int k = 0; k < n; k++) same = same && std::fabs(fr[k] - c.toep_f[op][k]) <= 1e-12 * fs;
+            if (same) {
+                c.toep_rat[op] = true;
+                for (int k = 0; k < 4; k++) c.toep_rc[op][k] = q[k];
+                break;
+            }
         }
     }
     std::vector<double> h64;

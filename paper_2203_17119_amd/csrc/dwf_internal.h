@@ -93,6 +93,11 @@ struct Context {
     bool toep_ok[SL_NOP] = {};
     int toep_rev[SL_NOP] = {};
     double toep_f[SL_NOP][16] = {};
+    // toep_rat: the same operator is (beta + gamma S)(delta + eps S)^-1 in the
+    // twisted shift S (checked against toep_f), with |eps/delta| small enough
+    // for the forward recurrence; toep_rc = {beta, gamma, delta, eps}
+    bool toep_rat[SL_NOP] = {};
+    double toep_rc[SL_NOP][4] = {};
     float *slmat32 = nullptr;
     double *gauge_canon = nullptr;  // canonical FP64 gauge, kept to rebuild low-precision links
 

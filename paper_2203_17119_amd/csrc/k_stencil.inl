@@ -50,6 +50,9 @@ struct StencilKArgs {
     long bstride;  // bytes between batch members (blockIdx.y), 0 for one field
     double tcoef[32];      // Toeplitz epilogue: f_k (k < Ls), then -mf f_k
     int trev;              // Toeplitz epilogue: P+ components use reversed s order
+    int trat;              // Toeplitz epilogue in rational form, coefficients rcoef:
+    double rcoef[24];      //   [0] y0 scale, [k] -mf r^k (1 <= k < Ls), [16] eps, [17] 1/delta,
+                           //   [18] beta, [19] gamma, [20] -mf gamma
     const double *alpha;   // RED = 2: device pointer to alpha
 };
 
@@ -461,6 +464,38 @@ __device__ __forceinline__ void toeplitz_apply(const cx<C> av[LSC], cx<C> o[LSC]
     }
 }
 
+// o = T a for T = (beta + gamma S)(delta + eps S)^-1 (the same twisted-circulant
+// operator in O(Ls)): y = (delta + eps S)^-1 a from its first entry
+//   y_0 = (a_0 - mf sum_{k>=1} r^k a_{Ls-k}) / (delta (1 + mf r^Ls)),  r = -eps/delta,
+// and the rows delta y_t + eps y_{t-1} = a_t; then o_t = beta y_t + gamma y_{t-1}
+// with the twisted wrap for t = 0
+template <typename C, int LSC>
+__device__ __forceinline__ void toeplitz_rational(const cx<C> av[LSC], cx<C> o[LSC], const double *rc)
+{
+    cx<C> y0 = av[0];
+#pragma unroll
+    for (int k = 1; k < LSC; k++) {
+        const C w = C(rc[k]);
+        y0.re = fma(w, av[LSC - k].re, y0.re);
+        y0.im = fma(w, av[LSC - k].im, y0.im);
+    }
+    const C ep = C(rc[16]), idl = C(rc[17]), be = C(rc[18]), ga = C(rc[19]), gw = C(rc[20]);
+    cx<C> y[LSC];
+    y[0] = C(rc[0]) * y0;
+#pragma unroll
+    for (int t = 1; t < LSC; t++) {
+        y[t].re = idl * fma(-ep, y[t - 1].re, av[t].re);
+        y[t].im = idl * fma(-ep, y[t - 1].im, av[t].im);
+    }
+    o[0].re = fma(be, y[0].re, gw * y[LSC - 1].re);
+    o[0].im = fma(be, y[0].im, gw * y[LSC - 1].im);
+#pragma unroll
+    for (int t = 1; t < LSC; t++) {
+        o[t].re = fma(be, y[t].re, ga * y[t - 1].re);
+        o[t].im = fma(be, y[t].im, ga * y[t - 1].im);
+    }
+}
+
 template <typename S, typename C, int EPI, bool SELF, bool DAG, int RED, int LSC>
 __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
 {
@@ -552,7 +587,10 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
             cx<C> av[LSC], o[LSC];
 #pragma unroll
             for (int t = 0; t < LSC; t++) av[t] = rows[c * RS + t];
-            toeplitz_apply<C, LSC>(av, o, f, g);
+            if (a.trat)
+                toeplitz_rational<C, LSC>(av, o, a.rcoef);
+            else
+                toeplitz_apply<C, LSC>(av, o, f, g);
 #pragma unroll
             for (int t = 0; t < LSC; t++) rows[c * RS + t] = o[t];
         }
@@ -676,6 +714,8 @@ __global__ void __launch_bounds__(256) k_slocal(Field in, Field out, const C *ma
 }  // namespace dwf
 
 // ------------------------------------------------------------ host launchers
+#include <cmath>
+
 #include "dwf_internal.h"
 
 namespace dwf {
@@ -718,9 +758,24 @@ static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field s
             a.tcoef[16 + k] = k < Ls ? -c.p.mf * c.toep_f[sp.epi_op][k] : 0.0;
         }
         a.trev = c.toep_rev[sp.epi_op];
+        a.trat = c.toep_rat[sp.epi_op] ? 1 : 0;
+        for (double &t : a.rcoef) t = 0.0;
+        if (a.trat) {
+            const double *q = c.toep_rc[sp.epi_op];
+            const double mf = c.p.mf, r = -q[3] / q[2];
+            a.rcoef[0] = 1.0 / (q[2] * (1.0 + mf * std::pow(r, Ls)));
+            for (int k = 1; k < Ls; k++) a.rcoef[k] = -mf * std::pow(r, k);
+            a.rcoef[16] = q[3];
+            a.rcoef[17] = 1.0 / q[2];
+            a.rcoef[18] = q[0];
+            a.rcoef[19] = q[1];
+            a.rcoef[20] = -mf * q[1];
+        }
     } else {
         for (double &t : a.tcoef) t = 0.0;
+        for (double &t : a.rcoef) t = 0.0;
         a.trev = 0;
+        a.trat = 0;
     }
     a.alpha = sp.cg_update ? c.dscal + sp.alpha_slot : nullptr;
     if (sp.cg_update && (sp.alpha_slot < 0 || !sp.reduce)) fail(DWF_EINVAL, "residual update needs alpha and reduce");

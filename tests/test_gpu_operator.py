@@ -16,8 +16,14 @@ from gpu_helpers import TOL, Case, relerr, to_gpu, to_host, torch
 pytestmark = pytest.mark.gpu
 
 # Ls = 8, 12 and 16 run the Toeplitz (twisted-circulant) form of the dense
-# fifth-dimension epilogue, the others the general dense form.
+# fifth-dimension epilogue, the others the general dense form.  The Toeplitz
+# form is applied as the recurrence of (b + c S)(d + e S)^-1 when |e/d| <= 1/2
+# (d = b (4 - M5) + 1, e = c (4 - M5) - 1): the default Moebius parameters
+# give |e/d| = 0.02, the r027 case 0.27; the Shamir case at M5 = 3.6 (0.71)
+# keeps the explicit Ls x Ls product.
 CASES = {
+    "2x2x4x2_ls8_r027": dict(dims=(2, 2, 4, 2), Ls=8, b=2.0, c=1.0, M5=1.2, mf=0.1, dirichlet=(0, 0, 1, 0), seed=35),
+    "2x2x2x4_ls12_shamir_dense": dict(dims=(2, 2, 2, 4), Ls=12, b=1.0, c=0.0, M5=3.6, mf=0.1, seed=36),
     "4^4x8_periodic": dict(dims=(4, 4, 4, 4), Ls=8, eps=0.4, seed=1001),
     "2x4x2x4_ls16_dirichlet": dict(dims=(2, 4, 2, 4), Ls=16, dirichlet=(0, 1, 0, 1), mf=0.03, seed=33),
     "4x2x2x2_ls12": dict(dims=(4, 2, 2, 2), Ls=12, mf=0.2, seed=34),
