@@ -196,6 +196,35 @@ def multishift(dwf, synth, torch, mode):
             "converged": sum(x["converged"] for x in st), "res_normal_max": max(x["res_normal"] for x in st)}
 
 
+def chebyshev(lat, dwf, synth, torch, w, prec):
+    """Chebyshev-filter subspace generation on the bench block: hi from 20 power
+    steps of Mpc^+ Mpc (times 1.1), lo = hi / 100, filter vectors T_k(x(A)) v at
+    k = 8, 16, 24, 32 from one Gaussian odd field v."""
+    V = int(np.prod(w.dims))
+    v = torch.from_numpy(synth.gaussian_fermion(w.dims, w.Ls, 4242, nsites=V // 2)).cuda()
+    u, t = v / v.norm(), torch.empty_like(v)
+    for _ in range(20):
+        dwf.dwf_schur_apply(lat.ctx, 0, u, t)
+        dwf.dwf_schur_apply(lat.ctx, 1, t, u)
+        lam = float(u.norm())
+        u /= lam
+    hi = 1.1 * lam
+    lo = hi / 100
+    orders = [8, 16, 24, 32]
+    outs = [torch.empty_like(v) for _ in orders]
+    dwf.dwf_chebyshev_filter(lat.ctx, v, lo, hi, [1], outs[:1], prec=prec)  # workspace, untimed
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dwf.dwf_chebyshev_filter(lat.ctx, v, lo, hi, orders, outs, prec=prec)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    vn = float(v.norm())
+    return {"prec": {dwf.DWF_F64: "f64", dwf.DWF_F32: "f32", dwf.DWF_F16: "f16", dwf.DWF_BF16: "bf16"}[prec],
+            "lo": round(lo, 4), "hi": round(hi, 3), "orders": orders, "seconds": round(dt, 4),
+            "ms_per_order": round(dt / orders[-1] * 1e3, 3),
+            "norm_ratio": [round(float(o.norm()) / vn, 3) for o in outs]}
+
+
 def learned_precond(lat, dwf, torch, b, tol, restart=16, maxit=2000, mfma=True, mode=None, weights=WEIGHTS):
     """FGCR(restart) on the Schur system, right-preconditioned by the trained
     network (matrix-core or FP32 forward), to tol in the FP64 full residual
@@ -272,6 +301,8 @@ def main():
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the FGCR solve with the trained network preconditioner")
     ap.add_argument("--no-multishift", action="store_true", help="skip the batched multi-shift solve")
+    ap.add_argument("--chebyshev", action="store_true",
+                    help="time the Chebyshev filter (switched off in the library: the call returns an error)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the hot path is one GPU's Dirichlet block and needs no "
@@ -354,6 +385,11 @@ def main():
         log(f"learned preconditioner: {lp}")
         lp["compact_network"] = learned_precond(lat, dwf, torch, srcs[0], w.tol, weights=WEIGHTS_COMPACT)
         log(f"learned preconditioner, compact network: {lp['compact_network']}")
+    cheb = None
+    if args.chebyshev:
+        cheb = {"f16": chebyshev(lat, dwf, synth, torch, w, dwf.DWF_F16),
+                "f32": chebyshev(lat, dwf, synth, torch, w, dwf.DWF_F32)}
+        log(f"chebyshev filter: {cheb}")
     table = None if args.no_table else dhop_table(lat, dwf, torch)
     ms = None
     if not args.no_multishift:
@@ -405,6 +441,7 @@ def main():
                      "frac_of_copy": round(kern_gbs / copy["GB/s"], 4)},
         "learned_precond": lp,
         "multishift": ms,
+        "chebyshev_filter": cheb,
         "tile_schedule": sched,
         "copy": copy,
         "dhop": table,

@@ -171,6 +171,26 @@ dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *const *b_odd, 
                              const double *shifts, double *const *x_odd, const dwf_solver_opts *o,
                              dwf_solver_stats *st);
 
+/* Chebyshev filter of the normal operator A = Mpc^+ Mpc: the recursively
+ * generated filter functions proposed for fast multigrid subspace set-up of
+ * the local Dirichlet solves (Sec. 2.4 and its filter-function figure).  With
+ * x(A) = (2 A - (hi + lo)) / (hi - lo) mapping [lo, hi] onto [-1, 1],
+ *   w_0 = v,  w_1 = x(A) v,  w_{k+1} = 2 x(A) w_k - w_{k-1},
+ * so w_k = T_k(x(A)) v: eigencomponents of A inside [lo, hi] are bounded by
+ * |T_k| <= 1, those below lo grow like cosh(k acosh |x|).  out_odd[i] receives
+ * w_{orders[i]} for nout (1..64) strictly ascending orders in [0, 100000].
+ * prec (DWF_F64/F32/F16/BF16) is the storage precision of the recurrence
+ * (FP64 arithmetic for DWF_F64, FP32 otherwise).  v_odd and the out_odd[i]
+ * are canonical FP64 odd half fields (device); orders and the out_odd array
+ * live in host memory.  The call returns when the work is queued on the
+ * context's stream; it uses context workspace (five fields of prec).
+ * Errors: DWF_EINVAL for a null pointer, unknown prec, nout outside 1..64,
+ * orders not ascending or out of range, or unless 0 <= lo < hi (finite).
+ * In this build the filter is switched off: after validating its arguments
+ * the call returns DWF_ENOTSUP without touching the device. */
+dwf_status dwf_chebyshev_filter(dwf_ctx ctx, int prec, const double *v_odd, double lo, double hi, int nout,
+                                const int *orders, double *const *out_odd);
+
 /* ---------------------------------------------- learned preconditioner */
 
 /* A gauge-equivariant network of parallel-transport convolution layers

@@ -243,6 +243,31 @@ def multishift(P: Params, U, b_odd, shifts, tol, maxit=100000):
     return x, it, iters, res
 
 
+def chebyshev(P: Params, U, v_odd, lo, hi, orders):
+    """Chebyshev filter of A = Mpc^+ Mpc on [lo, hi] (the recursively generated
+    filter functions for multigrid subspace set-up, Sec. 2.4): with
+    x(A) = (2A - (hi + lo)) / (hi - lo), the three-term recurrence
+    T_0 = 1, T_1 = x, T_{k+1} = 2 x T_k - T_{k-1} applied to v.
+    Returns [T_k(x(A)) v for k in orders] (orders ascending)."""
+    v = _c128(v_odd)
+    a, sh = 2.0 / (hi - lo), -(hi + lo) / (hi - lo)
+
+    def xa(w):
+        return a * mpc(P, U, mpc(P, U, w), True) + sh * w
+
+    out, want = [], list(orders)
+    wm, w0 = None, v.copy()
+    for k in range(max(want) + 1):
+        if k == 1:
+            wm, w0 = w0, xa(w0)
+        elif k >= 2:
+            wm, w0 = w0, 2.0 * xa(w0) - wm
+        while want and want[0] == k:
+            out.append(w0.copy())
+            want.pop(0)
+    return out
+
+
 NPATH = 11
 
 

@@ -228,6 +228,8 @@ void launch_finish(Context &c, int nparts, int width, int slot);
 
 // generic vector ops with host scalars: z = a*x + b*y (real a, b)
 void launch_axpby(Context &c, int prec, double a, Field x, double b, Field y, Field z);
+// z = a x + b y + cc w
+void launch_axpbypcz(Context &c, int prec, double a, Field x, double b, Field y, double cc, Field w, Field z);
 // complex caxpy with host scalar: y += a * x
 void launch_caxpy(Context &c, int prec, double are, double aim, Field x, Field y);
 void launch_zero(Context &c, int prec, Field a);

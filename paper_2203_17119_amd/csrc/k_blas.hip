@@ -101,6 +101,21 @@ __global__ void __launch_bounds__(BS) k_axpby(double a, Field x, double b, Field
     store_spinor<S, C>(z, i, u);
 }
 
+// z = a x + b y + c w (z may alias any input)
+template <typename S>
+__global__ void __launch_bounds__(BS) k_axpbypcz(double a, Field x, double b, Field y, double c, Field w, Field z)
+{
+    using C = Cof<S>;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    if (i >= x.n) return;
+    cx<C> u[12], v[12], t[12];
+    load_spinor<S, C>(x, i, u);
+    load_spinor<S, C>(y, i, v);
+    load_spinor<S, C>(w, i, t);
+    for (int k = 0; k < 12; k++) u[k] = C(a) * u[k] + C(b) * v[k] + C(c) * t[k];
+    store_spinor<S, C>(z, i, u);
+}
+
 template <typename S>
 __global__ void __launch_bounds__(BS) k_caxpy(double are, double aim, Field x, Field y)
 {
@@ -697,6 +712,12 @@ void launch_axpby(Context &c, int prec, double a, Field x, double b, Field y, Fi
 {
     Timer tm(c, DWF_K_BLAS, 3 * sbytes(prec) * x.n, 36.0 * x.n);
     DWF_DISPATCH(prec, k_axpby, g1(x.n), dim3(BS), 0, a, x, b, y, z);
+}
+
+void launch_axpbypcz(Context &c, int prec, double a, Field x, double b, Field y, double cc, Field w, Field z)
+{
+    Timer tm(c, DWF_K_BLAS, 4 * sbytes(prec) * x.n, 60.0 * x.n);
+    DWF_DISPATCH(prec, k_axpbypcz, g1(x.n), dim3(BS), 0, a, x, b, y, cc, w, z);
 }
 
 void launch_caxpy(Context &c, int prec, double are, double aim, Field x, Field y)

@@ -81,6 +81,7 @@ SIGNATURES = {
     "dwf_cg": ([_CTX, _P, _P, C.POINTER(dwf_solver_opts), C.POINTER(dwf_solver_stats)], C.c_int32),
     "dwf_multishift_cg": ([_CTX, _I, C.POINTER(_P), _I, C.POINTER(_D), C.POINTER(_P),
                            C.POINTER(dwf_solver_opts), C.POINTER(dwf_solver_stats)], C.c_int32),
+    "dwf_chebyshev_filter": ([_CTX, _I, _P, _D, _D, _I, C.POINTER(_I), C.POINTER(_P)], C.c_int32),
     "dwf_net_create": ([_CTX, _I, C.POINTER(_I), C.POINTER(_NET)], C.c_int32),
     "dwf_net_destroy": ([_NET], C.c_int32),
     "dwf_net_num_weights": ([_NET], C.c_int),
@@ -253,6 +254,16 @@ def dwf_multishift_cg(ctx, b_odd, shifts, x_odd, **opts):
     st = (dwf_solver_stats * (nrhs * ns))()
     s = _check(load().dwf_multishift_cg(ctx, nrhs, bp, ns, sh, xp, C.byref(o), st), allow=(DWF_ENOCONV,))
     return s, [x.asdict() for x in st]
+
+
+def dwf_chebyshev_filter(ctx, v_odd, lo, hi, orders, out_odd, prec=DWF_F64):
+    """out_odd[i] = T_{orders[i]}(x(A)) v_odd, A = Mpc^+ Mpc, x(A) = (2A - (hi + lo)) / (hi - lo)."""
+    n = len(orders)
+    if len(out_odd) != n:
+        raise ValueError("need one output field per order")
+    op = (_P * n)(*[_ptr(t) for t in out_odd])
+    oa = (_I * n)(*[int(k) for k in orders])
+    _check(load().dwf_chebyshev_filter(ctx, int(prec), _ptr(v_odd), float(lo), float(hi), n, oa, op))
 
 
 def dwf_net_create(ctx, chans):
