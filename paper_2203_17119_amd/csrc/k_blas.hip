@@ -382,12 +382,24 @@ __device__ __forceinline__ void st2(T2 *p, long k, double2 v)
     p[k] = T2{R(v.x), R(v.y)};
 }
 
-// partial[(2j + {0,1}) nblk + blk] = Re, Im of sum conj(X_j) y over the chunk, j < nv
+// wave-level sum (no barrier); lane 0 holds the result
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// partial[(2j + {0,1}) nblk + blk] = Re, Im of sum conj(X_j) y over the chunk, j < nv.
+// Each dot is reduced within the wavefront and the per-wave sums are kept in
+// LDS; one barrier at the end instead of two per dot.
+static constexpr int GS_MAXV = 64;
 template <typename T2>
 __global__ void __launch_bounds__(BS) k_gs_dots(const T2 *const *X, int nv, const T2 *y, long m, double *partial)
 {
+    __shared__ double red[2 * GS_MAXV][BS / 64];
     const long nblk = gridDim.x;
     const long base = (long)blockIdx.x * BS * GS_EPT + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double2 yv[GS_EPT];
 #pragma unroll
     for (int e = 0; e < GS_EPT; e++) {
@@ -396,27 +408,38 @@ __global__ void __launch_bounds__(BS) k_gs_dots(const T2 *const *X, int nv, cons
     }
     for (int j = 0; j < nv; j++) {
         const T2 *x = X[j];
-        double re = 0, im = 0;
+        double2 xv[GS_EPT];
 #pragma unroll
         for (int e = 0; e < GS_EPT; e++) {
             const long k = base + (long)e * BS;
-            if (k < m) {
-                const double2 xv = ld2(x, k);
-                re += xv.x * yv[e].x + xv.y * yv[e].y;
-                im += xv.x * yv[e].y - xv.y * yv[e].x;
-            }
+            xv[e] = k < m ? ld2(x, k) : make_double2(0.0, 0.0);
         }
-        re = block_sum(re);
-        im = block_sum(im);
-        if (threadIdx.x == 0) {
-            partial[(2 * j) * nblk + blockIdx.x] = re;
-            partial[(2 * j + 1) * nblk + blockIdx.x] = im;
+        double re = 0, im = 0;
+#pragma unroll
+        for (int e = 0; e < GS_EPT; e++) {
+            re += xv[e].x * yv[e].x + xv[e].y * yv[e].y;
+            im += xv[e].x * yv[e].y - xv[e].y * yv[e].x;
         }
+        re = wave_sum(re);
+        im = wave_sum(im);
+        if (lane == 0) {
+            red[2 * j][wave] = re;
+            red[2 * j + 1][wave] = im;
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 2 * nv; q += BS) {
+        double t = 0;
+#pragma unroll
+        for (int w = 0; w < BS / 64; w++) t += red[q][w];
+        partial[(long)q * nblk + blockIdx.x] = t;
     }
 }
 
 // y -= sum_j b_j X_j, w -= sum_j b_j W_j with b_j = dots_j / nq[3 j] (dots_j =
-// <X_j, y> as Re, Im pairs); partials of |y|^2 and <y, r> (new y) as members 0..2
+// <X_j, y> as Re, Im pairs); partials of |y|^2 and <y, r> (new y) as members 0..2.
+// The loop over j is outermost, so the loads of all elements of a thread for
+// one j are in flight together.
 template <typename T2>
 __global__ void __launch_bounds__(BS) k_gs_project(const T2 *const *X, const T2 *const *W, int nv, const double *dots,
                                                    const double *nq, T2 *y, T2 *w, const T2 *r, long m,
@@ -424,28 +447,50 @@ __global__ void __launch_bounds__(BS) k_gs_project(const T2 *const *X, const T2 
 {
     const long nblk = gridDim.x;
     const long base = (long)blockIdx.x * BS * GS_EPT + threadIdx.x;
+    double2 yv[GS_EPT], wv[GS_EPT];
+#pragma unroll
+    for (int e = 0; e < GS_EPT; e++) {
+        const long k = base + (long)e * BS;
+        yv[e] = k < m ? ld2(y, k) : make_double2(0.0, 0.0);
+        wv[e] = k < m ? ld2(w, k) : make_double2(0.0, 0.0);
+    }
+    for (int j = 0; j < nv; j++) {
+        const double inv = 1.0 / nq[3 * j];
+        const double bre = dots[2 * j] * inv, bim = dots[2 * j + 1] * inv;
+        const T2 *xj = X[j], *wj = W[j];
+        T2 xr[GS_EPT], vr[GS_EPT];
+#pragma unroll
+        for (int e = 0; e < GS_EPT; e++) {
+            const long k = base + (long)e * BS;
+            if (k < m) {
+                xr[e] = xj[k];
+                vr[e] = wj[k];
+            } else {
+                xr[e] = T2{};
+                vr[e] = T2{};
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < GS_EPT; e++) {
+            const double xx = double(xr[e].x), xy = double(xr[e].y), vx = double(vr[e].x), vy = double(vr[e].y);
+            yv[e].x -= bre * xx - bim * xy;
+            yv[e].y -= bre * xy + bim * xx;
+            wv[e].x -= bre * vx - bim * vy;
+            wv[e].y -= bre * vy + bim * vx;
+        }
+    }
     double n2 = 0, dre = 0, dim_ = 0;
 #pragma unroll
     for (int e = 0; e < GS_EPT; e++) {
         const long k = base + (long)e * BS;
         if (k >= m) continue;
-        double2 yv = ld2(y, k), wv = ld2(w, k);
-        for (int j = 0; j < nv; j++) {
-            const double inv = 1.0 / nq[3 * j];
-            const double bre = dots[2 * j] * inv, bim = dots[2 * j + 1] * inv;
-            const double2 xv = ld2(X[j], k), vv = ld2(W[j], k);
-            yv.x -= bre * xv.x - bim * xv.y;
-            yv.y -= bre * xv.y + bim * xv.x;
-            wv.x -= bre * vv.x - bim * vv.y;
-            wv.y -= bre * vv.y + bim * vv.x;
-        }
-        st2(y, k, yv);
-        st2(w, k, wv);
-        yv = ld2(y, k);  // as stored
+        st2(y, k, yv[e]);
+        st2(w, k, wv[e]);
+        const double2 ys = ld2(y, k);  // as stored
         const double2 rv = ld2(r, k);
-        n2 += yv.x * yv.x + yv.y * yv.y;
-        dre += yv.x * rv.x + yv.y * rv.y;
-        dim_ += yv.x * rv.y - yv.y * rv.x;
+        n2 += ys.x * ys.x + ys.y * ys.y;
+        dre += ys.x * rv.x + ys.y * rv.y;
+        dim_ += ys.x * rv.y - ys.y * rv.x;
     }
     n2 = block_sum(n2);
     dre = block_sum(dre);
@@ -812,6 +857,7 @@ static void gs_prec_check(int prec)
 void launch_gs_dots(Context &c, int prec, const void *const *X_dev, int nv, Field y, double *partial, double *out)
 {
     gs_prec_check(prec);
+    if (nv < 1 || nv > GS_MAXV) fail(DWF_EINVAL, "Gram-Schmidt block of 1..64 vectors");
     const long m = 12 * y.n, nblk = gs_blocks(m);
     const double eb = prec == P_F64 ? 16.0 : 8.0;
     Timer tm(c, DWF_K_BLAS, (nv + 1.0) * eb * m, 8.0 * nv * m, prec);
