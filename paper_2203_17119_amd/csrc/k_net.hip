@@ -91,10 +91,12 @@ __device__ __forceinline__ void transported(const NetGeo &g, const float2 *in, l
     }
 }
 
-// one layer, output parity p.  w: [11][COUT][CIN] BF16 pairs
+// one layer, output parity p.  w: [11][COUT][CIN] BF16 pairs.  Only the paths
+// in pmask (bit pi) are evaluated: the caller leaves out paths whose sources
+// are known to be zero.
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) k_ptc_fwd(NetGeo g, const float2 *in, float2 *out, const __hip_bfloat162 *w, int p,
-                                                 long n)
+                                                 long n, int pmask)
 {
     __shared__ cx<float> W[11 * COUT * CIN];
     const int tid = threadIdx.x + blockDim.x * threadIdx.y;
@@ -112,6 +114,7 @@ __global__ void __launch_bounds__(256) k_ptc_fwd(NetGeo g, const float2 *in, flo
 #pragma unroll
         for (int c = 0; c < 3; c++) acc[a][c] = mk(0.f, 0.f);
     for (int pi = 0; pi < 11; pi++) {
+        if (!(pmask >> pi & 1)) continue;
         cx<float> t[CIN][3];
         transported<CIN>(g, in, n, p, pi, j, s, t);
         const cx<float> *Wp = W + pi * COUT * CIN;
@@ -215,7 +218,7 @@ __device__ __forceinline__ cx<float> raw_feat(typename std::conditional<BF, uint
 template <int CIN, int COUT, bool IBF, bool OBF>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(CIN <= 4 ? 4 : 3, CIN <= 4 ? 4 : 3))) k_ptc_fwd_mfma(NetGeo g, const void *in, void *out, const short *wpk, int p,
-                                                      long n)
+                                                      long n, int pmask)
 {
     static_assert(CIN % 4 == 0 && 2 * COUT <= 32, "channel counts");
     constexpr int NCOL = 3 * MF_S, NP = CIN / 2, HP = NP / 2;
@@ -282,8 +285,14 @@ __global__ void __launch_bounds__(256)
                 }
         return hv;
     };
-    bool have = fetch(0);
-    for (int pi = 0; pi < 11; pi++) {
+    // the paths in pmask, in order (uniform over the workgroup)
+    int plist[11], npath = 0;
+#pragma unroll
+    for (int q = 0; q < 11; q++)
+        if (pmask >> q & 1) plist[npath++] = q;
+    bool have = npath > 0 ? fetch(plist[0]) : false;
+    for (int qi = 0; qi < npath; qi++) {
+        const int pi = plist[qi];
         const bool hop = pi >= 1 && pi <= 8;
         cx<float> u[9];
         if (have && hop) {
@@ -333,7 +342,7 @@ __global__ void __launch_bounds__(256)
             }
         }
         __syncthreads();
-        const bool have_next = (pi + 1 < 11) ? fetch(pi + 1) : false;
+        const bool have_next = (qi + 1 < npath) ? fetch(plist[qi + 1]) : false;
 #pragma unroll
         for (int st = 0; st < CIN / 4; st++) {
             const bf16x4 a = A[(pi * (CIN / 4) + st) * 64];
@@ -548,7 +557,7 @@ static NetGeo net_geo(Context &c)
 
 static int net_sb(const Context &c) { return std::max(1, std::min(64, 128 / c.Ls)); }
 
-void launch_ptc_layer(Context &c, int cin, int cout, const float2 *in, float2 *out, const void *w_bf16, int p)
+void launch_ptc_layer(Context &c, int cin, int cout, const float2 *in, float2 *out, const void *w_bf16, int p, int pmask)
 {
     const NetGeo g = net_geo(c);
     const int sb = net_sb(c);
@@ -556,7 +565,7 @@ void launch_ptc_layer(Context &c, int cin, int cout, const float2 *in, float2 *o
     const __hip_bfloat162 *w = (const __hip_bfloat162 *)w_bf16;
     const double flops = (double)c.n5h * (11.0 * cout * cin * 3 * 8 + 8.0 * cin * 66);
     Timer tm(c, DWF_K_NET, (double)c.n5h * 8.0 * 3 * (11 * cin + cout), flops);
-#define NETL(CI, CO) hipLaunchKernelGGL((k_ptc_fwd<CI, CO>), grid, blk, 0, c.stream, g, in, out, w, p, c.n5h)
+#define NETL(CI, CO) hipLaunchKernelGGL((k_ptc_fwd<CI, CO>), grid, blk, 0, c.stream, g, in, out, w, p, c.n5h, pmask)
     if (cin == 4 && cout == 12) NETL(4, 12);
     else if (cin == 12 && cout == 12) NETL(12, 12);
     else if (cin == 12 && cout == 4) NETL(12, 4);
@@ -594,14 +603,14 @@ void launch_pack_mfma_weights(Context &c, int cin, int cout, const void *w_bf16,
 }
 
 void launch_ptc_layer_mfma(Context &c, int cin, int cout, const void *in, void *out, const short *pk, int p,
-                           bool in_bf16, bool out_bf16)
+                           bool in_bf16, bool out_bf16, int pmask)
 {
     const NetGeo g = net_geo(c);
     const dim3 grid((unsigned)((c.n5h + MF_S - 1) / MF_S)), blk(256);
     const double flops = (double)c.n5h * (11.0 * cout * cin * 3 * 8 + 8.0 * cin * 66);
     Timer tm(c, DWF_K_NET, (double)c.n5h * 3 * (11.0 * cin * (in_bf16 ? 4 : 8) + cout * (out_bf16 ? 4 : 8)), flops);
 #define NETK(CI, CO, IB, OB) \
-    hipLaunchKernelGGL((k_ptc_fwd_mfma<CI, CO, IB, OB>), grid, blk, 0, c.stream, g, in, out, pk, p, c.n5h)
+    hipLaunchKernelGGL((k_ptc_fwd_mfma<CI, CO, IB, OB>), grid, blk, 0, c.stream, g, in, out, pk, p, c.n5h, pmask)
 #define NETL(CI, CO)                        \
     do {                                    \
         if (in_bf16 && out_bf16)            \

@@ -17,11 +17,14 @@
 using namespace dwf;
 
 namespace dwf {
-void launch_ptc_layer(Context &c, int cin, int cout, const float2 *in, float2 *out, const void *w_bf16, int p);
+// pmask: the paths (bit pi) to evaluate; the others must have zero sources
+constexpr int kAllPaths = 0x7ff;
+void launch_ptc_layer(Context &c, int cin, int cout, const float2 *in, float2 *out, const void *w_bf16, int p,
+                      int pmask = kAllPaths);
 size_t mfma_weight_elems(int cin);
 void launch_pack_mfma_weights(Context &c, int cin, int cout, const void *w_bf16, short *pk);
 void launch_ptc_layer_mfma(Context &c, int cin, int cout, const void *in, void *out, const short *pk, int p,
-                           bool in_bf16, bool out_bf16);
+                           bool in_bf16, bool out_bf16, int pmask = kAllPaths);
 int launch_ptc_wgrad(Context &c, int cin, int cout, const float2 *in, const float2 *gout, int p, double *partial,
                      long partial_len);
 void launch_wgrad_finish(Context &c, const double *partial, int nblk, int nw, float *gw, bool accumulate);
@@ -92,21 +95,28 @@ static void refresh_bf16(dwf_net_s *n)
 // forward of one sample whose input is acts[0] (4 channels); the last layer
 // is evaluated on odd sites only (the preconditioner's range)
 // (mfma: the matrix-core forward, BF16 operands with FP32 accumulation)
+// The network input is an odd-site field embedded with zeros on the even
+// sites (every caller fills acts[0] that way), so the first layer skips the
+// paths that only read even sites: for the odd output the eight hops (they
+// come from the other parity), for the even output the identity and s-paths.
+static constexpr int kHopPaths = 0x1fe, kLocalPaths = 0x601;
+
 static void net_forward(dwf_net_s *n, bool all_parities, bool mfma = false)
 {
     Context &c = *n->c;
     for (int l = 0; l < n->nlayer; l++) {
         const bool last = l == n->nlayer - 1;
         for (int p = (last && !all_parities) ? 1 : 0; p < 2; p++) {
+            const int pmask = l > 0 ? kAllPaths : (p == 1 ? kLocalPaths : kHopPaths);
             if (mfma) {
                 // FP32 network input and output, BF16 activations in between
                 const bool ibf = l > 0, obf = !last;
                 launch_ptc_layer_mfma(c, n->chans[l], n->chans[l + 1], ibf ? n->acts_bf[l] : (const void *)n->acts[l],
                                       obf ? n->acts_bf[l + 1] : (void *)n->acts[l + 1], n->wpk + n->pkoff[l], p, ibf,
-                                      obf);
+                                      obf, pmask);
             } else {
                 launch_ptc_layer(c, n->chans[l], n->chans[l + 1], n->acts[l], n->acts[l + 1],
-                                 (const __hip_bfloat162 *)n->wbf + n->woff[l], p);
+                                 (const __hip_bfloat162 *)n->wbf + n->woff[l], p, pmask);
             }
         }
     }
