@@ -470,9 +470,12 @@ dwf_status dwf_create(const dwf_params *p, const double *gauge, int gauge_on_dev
         build_slocal(*c);
         c->partials_len = 2 * (c->n5h / 64 + c->vh + 1024);
         HIPCHECK(hipMalloc(&c->partials, c->partials_len * sizeof(double)));
-        HIPCHECK(hipMalloc(&c->dscal, 256 * sizeof(double)));
-        HIPCHECK(hipMemset(c->dscal, 0, 256 * sizeof(double)));
-        HIPCHECK(hipHostMalloc(&c->hscal, 256 * sizeof(double), hipHostMallocDefault));
+        HIPCHECK(hipMalloc(&c->dscal, HS_MIRROR * sizeof(double)));
+        HIPCHECK(hipMemset(c->dscal, 0, HS_MIRROR * sizeof(double)));
+        HIPCHECK(hipHostMalloc(&c->hscal, HS_MIRROR * sizeof(double), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc(&c->hring, 2 * sizeof(double), hipHostMallocCoherent));
+        HIPCHECK(hipHostGetDevicePointer((void **)&c->dring, c->hring, 0));
+        for (auto &e : c->cg_ev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         upload_gauge(*c, gauge, gauge_on_device);
     } catch (...) {
         dwf_destroy(c);
@@ -492,6 +495,8 @@ dwf_status dwf_destroy(dwf_ctx ctx)
         (void)hipEventDestroy(t.b);
     }
     for (auto e : c.event_pool) (void)hipEventDestroy(e);
+    for (auto e : c.cg_ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto &kv : c.ws) (void)hipFree(kv.second.data);
     for (int pr = 0; pr < 4; pr++)
         for (int p = 0; p < 2; p++)
@@ -507,6 +512,7 @@ dwf_status dwf_destroy(dwf_ctx ctx)
     if (c.partials) (void)hipFree(c.partials);
     if (c.dscal) (void)hipFree(c.dscal);
     if (c.hscal) (void)hipHostFree(c.hscal);
+    if (c.hring) (void)hipHostFree(c.hring);
     delete ctx;
     return DWF_OK;
 }

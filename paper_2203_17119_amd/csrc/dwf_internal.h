@@ -106,6 +106,10 @@ struct Context {
     long partials_len = 0;
     double *dscal = nullptr;     // device scalars (see solvers)
     double *hscal = nullptr;     // pinned host mirror
+    // CG norm ring: coherent pinned host memory that the reduction kernel
+    // writes directly (host and device addresses), one event per slot
+    double *hring = nullptr, *dring = nullptr;
+    hipEvent_t cg_ev[2] = {nullptr, nullptr};
 
     // workspaces keyed by name
     struct Buf {
@@ -124,6 +128,9 @@ struct Context {
     KStats stats[DWF_K_NCLASS];
     KStats stats_prec[DWF_K_NCLASS][4];
 };
+
+// device scalar slots and their pinned host mirror
+constexpr int HS_MIRROR = 256;
 
 // default 4D sites per workgroup: about 192 lanes
 // 4D sites per workgroup by default: about 192 lanes, at most 64 sites
@@ -224,7 +231,9 @@ void ms_launch_step(Context &c, int prec, const MsState &s, Field r, Field ap, F
 // finish on the device that writes dscal[slot] (and dscal[slot+1] for dots)
 int launch_norm2(Context &c, int prec, Field a);
 int launch_dot(Context &c, int prec, Field a, Field b);
-void launch_finish(Context &c, int nparts, int width, int slot);
+// dscal[slot + w] = sum of the partials; mirror (device-visible host memory),
+// when given, receives the same values
+void launch_finish(Context &c, int nparts, int width, int slot, double *mirror = nullptr);
 
 // generic vector ops with host scalars: z = a*x + b*y (real a, b)
 void launch_axpby(Context &c, int prec, double a, Field x, double b, Field y, Field z);

@@ -66,7 +66,10 @@ __global__ void __launch_bounds__(BS) k_dot(Field a, Field b, double *partial)
 // One workgroup of FBS threads; thread t sums partials t, t + FBS, ... in four
 // interleaved running sums, so the order depends only on nparts.
 static constexpr int FBS = 1024;
-__global__ void __launch_bounds__(FBS) k_finish(const double *partial, int nparts, int width, double *dscal, int slot)
+// When mirror is set, the sums are also written there: host memory that the
+// host reads after an event behind this kernel.
+__global__ void __launch_bounds__(FBS) k_finish(const double *partial, int nparts, int width, double *dscal, int slot,
+                                                double *mirror)
 {
     for (int w = 0; w < width; w++) {
         double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
@@ -79,7 +82,10 @@ __global__ void __launch_bounds__(FBS) k_finish(const double *partial, int npart
         }
         for (; k < nparts; k += FBS) t0 += partial[(long)k * width + w];
         const double t = block_sum((t0 + t1) + (t2 + t3));
-        if (threadIdx.x == 0) dscal[slot + w] = t;
+        if (threadIdx.x == 0) {
+            dscal[slot + w] = t;
+            if (mirror) mirror[w] = t;
+        }
     }
 }
 
@@ -740,10 +746,10 @@ int launch_dot(Context &c, int prec, Field a, Field b)
     return (int)nb;
 }
 
-void launch_finish(Context &c, int nparts, int width, int slot)
+void launch_finish(Context &c, int nparts, int width, int slot, double *mirror)
 {
     Timer tm(c, DWF_K_BLAS, 8.0 * nparts * width, 0);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(FBS), 0, c.stream, c.partials, nparts, width, c.dscal, slot);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(FBS), 0, c.stream, c.partials, nparts, width, c.dscal, slot, mirror);
     HIPCHECK(hipGetLastError());
 }
 

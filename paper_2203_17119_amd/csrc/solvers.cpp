@@ -7,8 +7,9 @@
 //   dwf_multishift_cg   shifted systems from one Krylov space (Jegerlehner)
 //
 // Scalars that the loop needs are produced on the device (fixed-order FP64
-// reductions) and consumed there; the host reads back |r|^2 once per
-// iteration for the stopping and reliable-update decisions.
+// reductions) and consumed there; the host reads back |r|^2 of every
+// iteration, one iteration late, for the stopping and reliable-update
+// decisions.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -143,39 +144,58 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
     // solution update x += alpha p to the next p-update kernel, which reads p
     // anyway; before a reliable update or the exit it is applied on its own.
     const bool fused = sigma == 0.0;
-    while (st.iters < maxi) {
+    // The host learns each iteration's residual norm one iteration late. The
+    // reduction of iteration k writes the norm to a ring slot in host memory
+    // as well, and the host waits for it only after it has queued iteration
+    // k + 1, so the device never idles on the round trip. A reliable update or
+    // an exit that the norm of iteration k calls for follows iteration k + 1;
+    // it then reads that iteration's own norm.
+    int unread = -1;  // iteration whose norm the host has not read yet
+    auto norm_of = [&](int k) {
+        HIPCHECK(hipEventSynchronize(c.cg_ev[k & 1]));
+        const double v = *(volatile double *)(c.hring + (k & 1));
+        if (!std::isfinite(v)) fail(DWF_ENOCONV, "CG breakdown: non-finite residual");
+        return v;
+    };
+    while (true) {
         if (fused) {
             const int npm = apply_mpc(c, lp, false, p, m, true, true, pa);
             launch_finish(c, npm, 1, S_PAP);  // <p, Mpc^+ Mpc p> = |Mpc p|^2
             launch_scalar_div(c, S_ALPHA, S_RHO, S_PAP);
             const int np = apply_mpc(c, lp, true, m, r, false, false, Field{}, 1, 0, S_ALPHA);
-            launch_finish(c, np, 1, S_RHONEW);
+            launch_finish(c, np, 1, S_RHONEW, c.dring + (st.iters & 1));
         } else {
             normal_op(c, lp, sigma, p, ap, m, true, pa);
             launch_scalar_div(c, S_ALPHA, S_RHO, S_PAP);
             const int np = launch_cg_update_xr(c, lp, xl, r, p, ap, S_ALPHA);
-            launch_finish(c, np, 1, S_RHONEW);
+            launch_finish(c, np, 1, S_RHONEW, c.dring + (st.iters & 1));
         }
-        read_scalars(c, S_RHONEW, 1);
-        double rho1 = c.hscal[S_RHONEW];
-        st.iters++;
-        if (!std::isfinite(rho1)) fail(DWF_ENOCONV, "CG breakdown: non-finite residual");
-        const double rn = std::sqrt(rho1);
-        bool done = false;
+        const int k = st.iters++;
+        HIPCHECK(hipEventRecord(c.cg_ev[k & 1], c.stream));
+        // the check that the previous iteration's norm asks for
+        bool check = st.iters >= maxi;
+        if (unread >= 0) {
+            const double rn = std::sqrt(norm_of(unread));
+            check = check || rn <= target || (mixed && rn < delta * rmax);
+        }
+        unread = k;
         bool x_pending = fused;  // x += alpha p of this iteration not yet applied
-        if (mixed && (rn < delta * rmax || rn <= target)) {
-            // reliable update: fold the low-precision solution into x and
-            // recompute the residual exactly
-            if (x_pending) launch_axpy_dev(c, lp, xl, p, S_ALPHA);
-            x_pending = false;
-            launch_accumulate_low(c, xp, x, xl);
-            rho1 = true_residual();
-            launch_convert(c, P_F64, rh, lp, r);
-            rmax = std::sqrt(rho1);
-            st.reliable++;
-            if (std::sqrt(rho1) <= target) done = true;
-        } else if (!mixed && rn <= target) {
-            done = true;
+        bool done = false;
+        if (check) {
+            double rho1 = norm_of(k);
+            unread = -1;
+            if (mixed) {
+                // reliable update: fold the low-precision solution into x and
+                // recompute the residual exactly
+                if (x_pending) launch_axpy_dev(c, lp, xl, p, S_ALPHA);
+                x_pending = false;
+                launch_accumulate_low(c, xp, x, xl);
+                rho1 = true_residual();
+                launch_convert(c, P_F64, rh, lp, r);
+                rmax = std::sqrt(rho1);
+                st.reliable++;
+            }
+            done = std::sqrt(rho1) <= target;
         }
         if (done || st.iters >= maxi) {
             if (x_pending) launch_axpy_dev(c, lp, xl, p, S_ALPHA);
