@@ -43,6 +43,8 @@ HBM_PEAK_GBS = 8000.0
 # counter summary of the dominant kernel and the sources it was taken on
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "stencil_f16_32x32x32x32_ls12_mixed_cg.md")
 STENCIL_SOURCES = ("k_stencil.inl", "k_stencil_f16.hip", "dwf_common.h")
+# the autotuner's recorded choices; a workload missing from it is tuned and appended
+TUNE_CACHE = os.path.join(ROOT, "paper_2203_17119_amd", "tune_cache.jsonl")
 METRIC = "Dhop GB/s+GFLOP/s; CG time-to-1e-8 at 32^4×Ls12, plain FP64 vs chosen form"
 
 MODE_NAMES = {0: "f64", 1: "mixed_f32", 2: "mixed_f16", 3: "mixed_bf16"}
@@ -148,9 +150,10 @@ def stencil_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(schedule):
     """HBM bytes per launch of the FP16 stencil family from the committed counter
-    summary, or None when it is absent or was taken on other kernel sources."""
+    summary, or None when it is absent, was taken on other kernel sources or
+    under another tile schedule (sites per workgroup, XCD run)."""
     try:
         with open(TRAFFIC_SUMMARY) as fh:
             text = fh.read()
@@ -159,10 +162,12 @@ def measured_traffic():
     vals = {}
     for line in text.splitlines():
         line = line.strip().strip("`")
-        for key in ("source_sha256", "traffic_bytes_per_launch"):
+        for key in ("source_sha256", "traffic_bytes_per_launch", "tile_schedule"):
             if line.startswith(key + ":"):
                 vals[key] = line.split(":", 1)[1].strip()
     if vals.get("source_sha256") != stencil_source_hash() or "traffic_bytes_per_launch" not in vals:
+        return None
+    if vals.get("tile_schedule") != " ".join(str(v) for v in schedule):
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -171,7 +176,7 @@ WEIGHTS = os.path.join(ROOT, "paper_2203_17119_amd", "weights", "ptc_4-12-12-12-
 WEIGHTS_COMPACT = os.path.join(ROOT, "paper_2203_17119_amd", "weights", "ptc_4-4-4_8x8x8x8_ls8.npz")
 
 
-def multishift(dwf, synth, torch, mode):
+def multishift(dwf, synth, torch, mode, tune_cache):
     """Batched multi-shift CG on the 16^4 x 12 Dirichlet block: 8 right-hand sides
     x 12 rational shifts (96 systems) in one solve, each to 1e-8 in FP64."""
     w = synth.WORKLOADS["16^4x12_multishift"]
@@ -182,7 +187,7 @@ def multishift(dwf, synth, torch, mode):
         V = int(np.prod(w.dims))
         bs = [torch.from_numpy(synth.gaussian_fermion(w.dims, w.Ls, s, nsites=V // 2)).cuda() for s in w.source_seeds]
         xs = [torch.empty_like(bs[0]) for _ in range(len(bs) * len(shifts))]
-        dwf.dwf_tune(lat.ctx, dwf.DWF_F32 if mode == dwf.DWF_SOLVE_MIXED_F32 else dwf.DWF_F64, None)
+        dwf.dwf_tune(lat.ctx, dwf.DWF_F32 if mode == dwf.DWF_SOLVE_MIXED_F32 else dwf.DWF_F64, tune_cache)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s, st = dwf.dwf_multishift_cg(lat.ctx, bs, shifts, xs, tol=w.tol, mode=mode)
@@ -301,6 +306,8 @@ def main():
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the FGCR solve with the trained network preconditioner")
     ap.add_argument("--no-multishift", action="store_true", help="skip the batched multi-shift solve")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="autotuner record to read and append to; an empty string tunes afresh")
     ap.add_argument("--chebyshev", action="store_true",
                     help="time the Chebyshev filter (switched off in the library: the call returns an error)")
     args = ap.parse_args()
@@ -341,7 +348,8 @@ def main():
     copy = copy_bandwidth(lat, dwf, torch)
     log(f"stream copy {copy['GB/s']} GB/s")
     # tile schedule of the chosen storage precision, picked by the autotuner (untimed)
-    dwf.dwf_tune(lat.ctx, lowp, None)
+    tune_cache = args.tune_cache or None
+    dwf.dwf_tune(lat.ctx, lowp, tune_cache)
     sched = {"stencil": dwf.dwf_get_tile_schedule(lat.ctx, dwf.DWF_K_STENCIL),
              "slocal": dwf.dwf_get_tile_schedule(lat.ctx, dwf.DWF_K_SLOCAL)}
     log(f"tuned schedule {sched}")
@@ -377,7 +385,7 @@ def main():
     whole_gbs = sten["bytes"] / t_total / 1e9
     whole_gflops = sten["flops"] / t_total / 1e9
     kern_gbs = dom["bytes"] / dom["ms"] / 1e6
-    traffic = measured_traffic()
+    traffic = measured_traffic(sched["stencil"])
 
     lp = None
     if not args.no_precond:
@@ -396,8 +404,8 @@ def main():
         lat.close()
         del srcs, x
         torch.cuda.empty_cache()
-        ms = {"mixed_f32": multishift(dwf, synth, torch, dwf.DWF_SOLVE_MIXED_F32),
-              "f64": multishift(dwf, synth, torch, dwf.DWF_SOLVE_F64)}
+        ms = {"mixed_f32": multishift(dwf, synth, torch, dwf.DWF_SOLVE_MIXED_F32, tune_cache),
+              "f64": multishift(dwf, synth, torch, dwf.DWF_SOLVE_F64, tune_cache)}
         log(f"multishift: {ms}")
     cpu = None if args.no_cpu else cpu_baseline(w, U, b0_host, st64["iters"])
 
@@ -443,6 +451,7 @@ def main():
         "multishift": ms,
         "chebyshev_filter": cheb,
         "tile_schedule": sched,
+        "tune_cache": os.path.relpath(tune_cache, ROOT) if tune_cache else None,
         "copy": copy,
         "dhop": table,
         "cpu_baseline": cpu,

@@ -7,6 +7,8 @@
 * 16^4 x Ls=12, 8 right-hand sides x 12 shifts: batched multi-shift CG, every
   (rhs, shift) converged, sampled pairs re-checked with the oracle's Mpc.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -17,6 +19,12 @@ from gpu_helpers import Case, relerr, to_gpu, to_host, torch
 pytestmark = pytest.mark.gpu
 
 NSAMPLE = 64
+# the autotuner's recorded choices, which the benchmark applies
+TUNE_CACHE = os.path.join(os.path.dirname(dwf.__file__), "tune_cache.jsonl")
+
+
+def tuned_cache():
+    return TUNE_CACHE if os.path.exists(TUNE_CACHE) else None
 
 
 @pytest.fixture(scope="module")
@@ -50,7 +58,7 @@ def test_dhop_32x32x32x32_ls12_sampled(c3):
     got = out[torch().from_numpy(cbs).cuda()].cpu().numpy()
     assert relerr(got, expect) < 1e-12
     # FP16 storage, FP32 arithmetic, in the benchmark's tuned schedule
-    dwf.dwf_tune(c.ctx, dwf.DWF_F16, None)
+    dwf.dwf_tune(c.ctx, dwf.DWF_F16, tuned_cache())
     a, b = c.lat.internal(dwf.DWF_F16), c.lat.internal(dwf.DWF_F16)
     dwf.dwf_import(c.ctx, 0, dwf.DWF_F16, xg, a)
     dwf.dwf_dhop_internal(c.ctx, dwf.DWF_F16, 1, 0, a, b)
@@ -64,7 +72,7 @@ def test_mixed_cg_32x32x32x32_ls12_sampled_residual(c3):
     b = c.full(w.source_seeds[0])
     bg = to_gpu(b)
     x = torch().zeros_like(bg)
-    dwf.dwf_tune(c.ctx, dwf.DWF_F16, None)
+    dwf.dwf_tune(c.ctx, dwf.DWF_F16, tuned_cache())
     status, st = dwf.dwf_cg(c.ctx, bg, x, tol=w.tol, mode=dwf.DWF_SOLVE_MIXED_F16)
     print(st, flush=True)
     assert status == dwf.DWF_OK and st["res_normal"] <= w.tol * 1.0000001
