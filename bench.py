@@ -243,7 +243,7 @@ def learned_precond(lat, dwf, torch, b, tol, restart=16, maxit=2000, mfma=True, 
         x = torch.zeros_like(b)
         dwf.dwf_kernel_timing_reset(lat.ctx)
         dwf.dwf_kernel_timing(lat.ctx, 1)
-        mode = dwf.DWF_SOLVE_MIXED_F32 if mode is None else mode
+        mode = dwf.DWF_SOLVE_MIXED_BF16 if mode is None else mode
         s, st = dwf.dwf_fgcr(lat.ctx, net, b, x, tol=tol, restart=restart, maxit=maxit, fallback=True, mode=mode)
         kn = dwf.dwf_kernel_stats(lat.ctx, dwf.DWF_K_NET)
         dwf.dwf_kernel_timing(lat.ctx, 0)
@@ -251,7 +251,8 @@ def learned_precond(lat, dwf, torch, b, tol, restart=16, maxit=2000, mfma=True, 
         dwf.dwf_net_destroy(net)
     return {"solver": f"FGCR({restart}) + PTC network {chans} (trained on 8^4x8), "
                       f"{'matrix-core BF16' if mfma else 'FP32'} forward, "
-                      f"{'FP32 cycles + FP64 restarts' if mode == dwf.DWF_SOLVE_MIXED_F32 else 'FP64'}",
+                      + {dwf.DWF_SOLVE_MIXED_F32: "FP32 cycles + FP64 restarts",
+                         dwf.DWF_SOLVE_MIXED_BF16: "BF16 Krylov basis, FP32 cycles + FP64 restarts"}.get(mode, "FP64"),
             "status": s,
             "iters": st["iters"], "seconds": round(st["seconds"], 3), "res_full": st["res_full"],
             "converged": st["converged"], "fell_back": st["fell_back"],

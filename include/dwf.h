@@ -251,7 +251,10 @@ dwf_status dwf_net_train_step(dwf_net net, int nbatch, const double *const *b_od
  * every vector in FP64; DWF_SOLVE_MIXED_F32 runs the cycle (operator, network
  * input and output, Krylov vectors) in FP32 storage with FP64 sums and folds
  * each cycle's solution into the FP64 solution, whose residual is recomputed
- * in FP64 at every restart (other modes: DWF_ENOTSUP).  Restart every
+ * in FP64 at every restart; DWF_SOLVE_MIXED_BF16 does the same with the
+ * Krylov basis (network outputs and their operator images) stored in BF16
+ * and the operator applied in BF16 storage, the cycle's residual and solution
+ * staying FP32 (other modes: DWF_ENOTSUP).  Restart every
  * o->restart steps (default 16, at most 64) with the residual recomputed.
  * Stagnation means no 10% reduction of the residual norm over max(8 m, 256)
  * steps.  On stagnation or a non-finite residual it falls back to dwf_cg in

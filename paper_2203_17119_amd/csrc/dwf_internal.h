@@ -264,9 +264,11 @@ void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pa, int ib
 // partials written to c.partials.
 long gs_partials_needed(const Context &c, int nv);
 void launch_gs_dots(Context &c, int prec, const void *const *X_dev, int nv, Field y, double *partial, double *out);
-void launch_gs_project(Context &c, int prec, const void *const *X_dev, const void *const *W_dev, int nv,
+// prec is the precision of the basis vectors (X, W, y, w, z, q), rprec that of
+// the residual r and the solution x: FP64/FP64, FP32/FP32 or BF16/FP32.
+void launch_gs_project(Context &c, int prec, int rprec, const void *const *X_dev, const void *const *W_dev, int nv,
                        const double *dots, const double *nq, Field y, Field w, Field r, double *partial, double *out);
-int launch_gs_update(Context &c, int prec, Field x, Field z, Field r, Field q, const double *coef);
+int launch_gs_update(Context &c, int prec, int rprec, Field x, Field z, Field r, Field q, const double *coef);
 // x += dscal[ia] p, x in the accumulator precision of prec
 void launch_axpy_dev(Context &c, int prec, Field x, Field p, int ia);
 // device scalar arithmetic: dscal[out] = dscal[num] / dscal[den]

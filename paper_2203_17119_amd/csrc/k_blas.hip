@@ -366,7 +366,8 @@ __global__ void __launch_bounds__(BS) k_finish_b(const double *partial, int npar
 // ---------------------------------------------------------------------------
 // Block Gram-Schmidt for flexible GCR.  FP64 or FP32 fields are viewed as flat
 // complex arrays of m elements (the inner product does not depend on the
-// layout); sums are accumulated in FP64.  Each thread owns GS_EPT elements of
+// layout); sums are accumulated in FP64.  A BF16 basis has its own kernels
+// below.  Each thread owns GS_EPT elements of
 // one chunk; partial sums are written per workgroup, member-major
 // ([member][block]), and summed in a fixed order.
 
@@ -530,6 +531,182 @@ __global__ void __launch_bounds__(BS) k_gs_update(T2 *x, const T2 *z, T2 *r, con
         st2(x, k, xv);
         st2(r, k, rv);
         n2 += rv.x * rv.x + rv.y * rv.y;
+    }
+    n2 = block_sum(n2);
+    if (threadIdx.x == 0) partial[blockIdx.x] = n2;
+}
+
+// The same three steps with the basis vectors stored in BF16 and the residual
+// and solution in FP32.  A lane takes pairs of adjacent complex components:
+// 8 bytes of a basis vector and the matching 16 bytes of the residual, GS_PPT
+// pairs per lane, so that a lane keeps as many bytes in flight as the FP32
+// kernels.  The projection is accumulated in FP32 (its result is rounded to
+// BF16); sums are FP64.
+//
+// A field is stored as 16-byte planes, [plane][site][component in plane]:
+// BF16 holds four complex components per plane, FP32 two.  Pair p of a BF16
+// vector (components 4q + 2h and 4q + 2h + 1 of site i, p = 2 (q nsite + i) + h)
+// is the 16-byte piece (2q + h) nsite + i of the FP32 field.
+static constexpr int GS_PPT = 8;
+
+static long gs_blocks_bf(long m) { return (m / 2 + (long)BS * GS_PPT - 1) / ((long)BS * GS_PPT); }
+
+// a BF16 value is the upper half of the FP32 value; the lower 16 bits of a
+// 32-bit word hold the real part, the upper the imaginary part
+__device__ __forceinline__ float4 bf_pair(uint2 u)
+{
+    return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u), __uint_as_float(u.y << 16),
+                       __uint_as_float(u.y & 0xffff0000u));
+}
+
+__device__ __forceinline__ unsigned bf_word(float re, float im)
+{
+    const __hip_bfloat162 t = __float22bfloat162_rn(make_float2(re, im));  // round to nearest even
+    unsigned u;
+    __builtin_memcpy(&u, &t, sizeof(u));
+    return u;
+}
+
+__device__ __forceinline__ uint2 bf_pack(float4 v) { return make_uint2(bf_word(v.x, v.y), bf_word(v.z, v.w)); }
+
+// the launchers check 12 nsite < 2^32, so the site arithmetic fits 32 bits
+__device__ __forceinline__ long res_piece(long p, long nsite)
+{
+    const unsigned nu = (unsigned)nsite, quad = (unsigned)(p >> 1), h = (unsigned)(p & 1);
+    const unsigned q = quad / nu, i = quad - q * nu;
+    return (long)(2u * q + h) * nsite + i;
+}
+
+__global__ void __launch_bounds__(BS) k_gs_dots_bf(const uint2 *const *X, int nv, const uint2 *y, long m2,
+                                                   double *partial)
+{
+    __shared__ double red[2 * GS_MAXV][BS / 64];
+    const long nblk = gridDim.x;
+    const long base = (long)blockIdx.x * BS * GS_PPT + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float4 yv[GS_PPT];
+#pragma unroll
+    for (int e = 0; e < GS_PPT; e++) {
+        const long k = base + (long)e * BS;
+        yv[e] = k < m2 ? bf_pair(y[k]) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    for (int j = 0; j < nv; j++) {
+        const uint2 *x = X[j];
+        uint2 xr[GS_PPT];
+#pragma unroll
+        for (int e = 0; e < GS_PPT; e++) {
+            const long k = base + (long)e * BS;
+            xr[e] = k < m2 ? x[k] : make_uint2(0u, 0u);
+        }
+        double re = 0, im = 0;
+#pragma unroll
+        for (int e = 0; e < GS_PPT; e++) {
+            const float4 xv = bf_pair(xr[e]);
+            re += double(xv.x) * yv[e].x + double(xv.y) * yv[e].y + double(xv.z) * yv[e].z + double(xv.w) * yv[e].w;
+            im += double(xv.x) * yv[e].y - double(xv.y) * yv[e].x + double(xv.z) * yv[e].w - double(xv.w) * yv[e].z;
+        }
+        re = wave_sum(re);
+        im = wave_sum(im);
+        if (lane == 0) {
+            red[2 * j][wave] = re;
+            red[2 * j + 1][wave] = im;
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 2 * nv; q += BS) {
+        double t = 0;
+#pragma unroll
+        for (int w = 0; w < BS / 64; w++) t += red[q][w];
+        partial[(long)q * nblk + blockIdx.x] = t;
+    }
+}
+
+__global__ void __launch_bounds__(BS) k_gs_project_bf(const uint2 *const *X, const uint2 *const *W, int nv,
+                                                      const double *dots, const double *nq, uint2 *y, uint2 *w,
+                                                      const float4 *r, long m2, long nsite, double *partial)
+{
+    const long nblk = gridDim.x;
+    const long base = (long)blockIdx.x * BS * GS_PPT + threadIdx.x;
+    float4 yv[GS_PPT], wv[GS_PPT];
+#pragma unroll
+    for (int e = 0; e < GS_PPT; e++) {
+        const long k = base + (long)e * BS;
+        yv[e] = k < m2 ? bf_pair(y[k]) : make_float4(0.f, 0.f, 0.f, 0.f);
+        wv[e] = k < m2 ? bf_pair(w[k]) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    for (int j = 0; j < nv; j++) {
+        const double inv = 1.0 / nq[3 * j];
+        const float bre = float(dots[2 * j] * inv), bim = float(dots[2 * j + 1] * inv);
+        const uint2 *xj = X[j], *wj = W[j];
+        uint2 xr[GS_PPT], vr[GS_PPT];
+#pragma unroll
+        for (int e = 0; e < GS_PPT; e++) {
+            const long k = base + (long)e * BS;
+            xr[e] = k < m2 ? xj[k] : make_uint2(0u, 0u);
+            vr[e] = k < m2 ? wj[k] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int e = 0; e < GS_PPT; e++) {
+            const float4 xd = bf_pair(xr[e]), vd = bf_pair(vr[e]);
+            yv[e].x -= bre * xd.x - bim * xd.y;
+            yv[e].y -= bre * xd.y + bim * xd.x;
+            yv[e].z -= bre * xd.z - bim * xd.w;
+            yv[e].w -= bre * xd.w + bim * xd.z;
+            wv[e].x -= bre * vd.x - bim * vd.y;
+            wv[e].y -= bre * vd.y + bim * vd.x;
+            wv[e].z -= bre * vd.z - bim * vd.w;
+            wv[e].w -= bre * vd.w + bim * vd.z;
+        }
+    }
+    double n2 = 0, dre = 0, dim_ = 0;
+#pragma unroll
+    for (int e = 0; e < GS_PPT; e++) {
+        const long k = base + (long)e * BS;
+        if (k >= m2) continue;
+        const uint2 yb = bf_pack(yv[e]);
+        y[k] = yb;
+        w[k] = bf_pack(wv[e]);
+        const float4 ys = bf_pair(yb);  // as stored
+        const float4 rv = r[res_piece(k, nsite)];
+        n2 += double(ys.x) * ys.x + double(ys.y) * ys.y + double(ys.z) * ys.z + double(ys.w) * ys.w;
+        dre += double(ys.x) * rv.x + double(ys.y) * rv.y + double(ys.z) * rv.z + double(ys.w) * rv.w;
+        dim_ += double(ys.x) * rv.y - double(ys.y) * rv.x + double(ys.z) * rv.w - double(ys.w) * rv.z;
+    }
+    n2 = block_sum(n2);
+    dre = block_sum(dre);
+    dim_ = block_sum(dim_);
+    if (threadIdx.x == 0) {
+        partial[0 * nblk + blockIdx.x] = n2;
+        partial[1 * nblk + blockIdx.x] = dre;
+        partial[2 * nblk + blockIdx.x] = dim_;
+    }
+}
+
+__global__ void __launch_bounds__(BS) k_gs_update_bf(float4 *x, const uint2 *z, float4 *r, const uint2 *q,
+                                                     const double *coef, long m2, long nsite, double *partial)
+{
+    const long base = (long)blockIdx.x * BS * GS_PPT + threadIdx.x;
+    const double inv = 1.0 / coef[0];
+    const double are = coef[1] * inv, aim = coef[2] * inv;
+    double n2 = 0;
+#pragma unroll
+    for (int e = 0; e < GS_PPT; e++) {
+        const long k = base + (long)e * BS;
+        if (k >= m2) continue;
+        const float4 zv = bf_pair(z[k]), qv = bf_pair(q[k]);
+        const long kr = res_piece(k, nsite);
+        float4 xv = x[kr], rv = r[kr];
+        xv.x = float(xv.x + (are * zv.x - aim * zv.y));
+        xv.y = float(xv.y + (are * zv.y + aim * zv.x));
+        xv.z = float(xv.z + (are * zv.z - aim * zv.w));
+        xv.w = float(xv.w + (are * zv.w + aim * zv.z));
+        rv.x = float(rv.x - (are * qv.x - aim * qv.y));
+        rv.y = float(rv.y - (are * qv.y + aim * qv.x));
+        rv.z = float(rv.z - (are * qv.z - aim * qv.w));
+        rv.w = float(rv.w - (are * qv.w + aim * qv.z));
+        x[kr] = xv;
+        r[kr] = rv;
+        n2 += double(rv.x) * rv.x + double(rv.y) * rv.y + double(rv.z) * rv.z + double(rv.w) * rv.w;
     }
     n2 = block_sum(n2);
     if (threadIdx.x == 0) partial[blockIdx.x] = n2;
@@ -855,19 +1032,28 @@ void launch_accumulate_low(Context &c, int prec, Field xh, Field xl)
 
 long gs_partials_needed(const Context &c, int nv) { return gs_blocks(12 * c.n5h) * std::max(3, 2 * nv); }
 
-static void gs_prec_check(int prec)
+// basis precision prec, residual and solution precision rprec: FP64/FP64,
+// FP32/FP32 or BF16/FP32
+static void gs_prec_check(int prec, int rprec, long m)
 {
-    if (prec != P_F64 && prec != P_F32) fail(DWF_ENOTSUP, "Gram-Schmidt vectors must be FP64 or FP32");
+    const bool ok = (prec == P_F64 && rprec == P_F64) || (prec == P_F32 && rprec == P_F32) ||
+                    (prec == P_BF16 && rprec == P_F32);
+    if (!ok) fail(DWF_ENOTSUP, "Gram-Schmidt vectors must be FP64, FP32, or BF16 with an FP32 residual");
+    if (m >= (1L << 32)) fail(DWF_ENOTSUP, "Gram-Schmidt vectors of 2^32 or more components");
 }
+
+static double gs_elem_bytes(int prec) { return prec == P_F64 ? 16.0 : prec == P_F32 ? 8.0 : 4.0; }
 
 void launch_gs_dots(Context &c, int prec, const void *const *X_dev, int nv, Field y, double *partial, double *out)
 {
-    gs_prec_check(prec);
+    const long m = 12 * y.n, nblk = prec == P_BF16 ? gs_blocks_bf(m) : gs_blocks(m);
+    gs_prec_check(prec, prec == P_BF16 ? P_F32 : prec, m);
     if (nv < 1 || nv > GS_MAXV) fail(DWF_EINVAL, "Gram-Schmidt block of 1..64 vectors");
-    const long m = 12 * y.n, nblk = gs_blocks(m);
-    const double eb = prec == P_F64 ? 16.0 : 8.0;
-    Timer tm(c, DWF_K_BLAS, (nv + 1.0) * eb * m, 8.0 * nv * m, prec);
-    if (prec == P_F64)
+    Timer tm(c, DWF_K_BLAS, (nv + 1.0) * gs_elem_bytes(prec) * m, 8.0 * nv * m, prec);
+    if (prec == P_BF16)
+        hipLaunchKernelGGL(k_gs_dots_bf, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (const uint2 *const *)X_dev, nv,
+                           (const uint2 *)y.data, m / 2, partial);
+    else if (prec == P_F64)
         hipLaunchKernelGGL(k_gs_dots<double2>, dim3((unsigned)nblk), dim3(BS), 0, c.stream,
                            (const double2 *const *)X_dev, nv, (const double2 *)y.data, m, partial);
     else
@@ -878,14 +1064,18 @@ void launch_gs_dots(Context &c, int prec, const void *const *X_dev, int nv, Fiel
     HIPCHECK(hipGetLastError());
 }
 
-void launch_gs_project(Context &c, int prec, const void *const *X_dev, const void *const *W_dev, int nv,
+void launch_gs_project(Context &c, int prec, int rprec, const void *const *X_dev, const void *const *W_dev, int nv,
                        const double *dots, const double *nq, Field y, Field w, Field r, double *partial, double *out)
 {
-    gs_prec_check(prec);
-    const long m = 12 * y.n, nblk = gs_blocks(m);
-    const double eb = prec == P_F64 ? 16.0 : 8.0;
-    Timer tm(c, DWF_K_BLAS, (2.0 * nv + 5.0) * eb * m, (16.0 * nv + 12.0) * m, prec);
-    if (prec == P_F64)
+    const long m = 12 * y.n, nblk = prec == P_BF16 ? gs_blocks_bf(m) : gs_blocks(m);
+    gs_prec_check(prec, rprec, m);
+    Timer tm(c, DWF_K_BLAS, ((2.0 * nv + 4.0) * gs_elem_bytes(prec) + gs_elem_bytes(rprec)) * m,
+             (16.0 * nv + 12.0) * m, prec);
+    if (prec == P_BF16)
+        hipLaunchKernelGGL(k_gs_project_bf, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (const uint2 *const *)X_dev,
+                           (const uint2 *const *)W_dev, nv, dots, nq, (uint2 *)y.data, (uint2 *)w.data,
+                           (const float4 *)r.data, m / 2, y.n, partial);
+    else if (prec == P_F64)
         hipLaunchKernelGGL(k_gs_project<double2>, dim3((unsigned)nblk), dim3(BS), 0, c.stream,
                            (const double2 *const *)X_dev, (const double2 *const *)W_dev, nv, dots, nq,
                            (double2 *)y.data, (double2 *)w.data, (const double2 *)r.data, m, partial);
@@ -898,14 +1088,17 @@ void launch_gs_project(Context &c, int prec, const void *const *X_dev, const voi
     HIPCHECK(hipGetLastError());
 }
 
-int launch_gs_update(Context &c, int prec, Field x, Field z, Field r, Field q, const double *coef)
+int launch_gs_update(Context &c, int prec, int rprec, Field x, Field z, Field r, Field q, const double *coef)
 {
-    gs_prec_check(prec);
-    const long m = 12 * x.n, nblk = gs_blocks(m);
+    const long m = 12 * x.n, nblk = prec == P_BF16 ? gs_blocks_bf(m) : gs_blocks(m);
+    gs_prec_check(prec, rprec, m);
     need_partials(c, nblk, 1);
-    const double eb = prec == P_F64 ? 16.0 : 8.0;
-    Timer tm(c, DWF_K_BLAS, 6.0 * eb * m, 18.0 * m, prec);
-    if (prec == P_F64)
+    Timer tm(c, DWF_K_BLAS, (2.0 * gs_elem_bytes(prec) + 4.0 * gs_elem_bytes(rprec)) * m, 18.0 * m, prec);
+    if (prec == P_BF16)
+        hipLaunchKernelGGL(k_gs_update_bf, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (float4 *)x.data,
+                           (const uint2 *)z.data, (float4 *)r.data, (const uint2 *)q.data, coef, m / 2, x.n,
+                           c.partials);
+    else if (prec == P_F64)
         hipLaunchKernelGGL(k_gs_update<double2>, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (double2 *)x.data,
                            (const double2 *)z.data, (double2 *)r.data, (const double2 *)q.data, coef, m, c.partials);
     else

@@ -374,18 +374,20 @@ dwf_status dwf_net_train_step(dwf_net net, int nbatch, const double *const *b_od
 namespace dwf {
 
 // z = N(r) (normal = false) or N N^+ r (normal = true), odd fields of precision prec
-static void precondition(dwf_net_s *n, int prec, Field r, Field z, bool normal)
+// z = N r (N N^+ r for the normal equations); r is read in precision rprec, z
+// is written in zprec
+static void precondition(dwf_net_s *n, int rprec, Field r, int zprec, Field z, bool normal)
 {
     Context &c = *n->c;
-    launch_spinor_to_feat(c, prec, r, n->acts[0], 1, true);
+    launch_spinor_to_feat(c, rprec, r, n->acts[0], 1, true);
     if (normal) {
         // N^+ r: adjoint network on the embedded residual, then N on its result
         const float2 *adj = net_adjoint(n, n->acts[0]);
-        launch_feat_to_spinor(c, prec, adj, z, 1);  // keep odd part only
-        launch_spinor_to_feat(c, prec, z, n->acts[0], 1, true);
+        launch_feat_to_spinor(c, zprec, adj, z, 1);  // keep odd part only
+        launch_spinor_to_feat(c, zprec, z, n->acts[0], 1, true);
     }
     net_forward(n, false, n->fwd == DWF_NET_FWD_MFMA_BF16);
-    launch_feat_to_spinor(c, prec, n->acts[n->nlayer], z, 1);
+    launch_feat_to_spinor(c, zprec, n->acts[n->nlayer], z, 1);
 }
 
 static double dnorm2(Context &c, Field a)
@@ -430,11 +432,16 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
     const int m = (o && o->restart > 0) ? std::min(o->restart, 64) : 16;
     const bool normal = o && o->normal;
     const bool fallback = !o || o->fallback;
-    // inner precision: FP64, or FP32 vectors and operator with the solution and
-    // the residual of every restart kept in FP64 (reliable restarts)
+    // inner precision: FP64; or FP32 vectors and operator with the solution and
+    // the residual of every restart kept in FP64 (reliable restarts); or, for
+    // MIXED_BF16, the same with the Krylov basis (the preconditioned directions
+    // and their images) stored in BF16 and the operator applied in BF16 storage,
+    // while the cycle's residual and solution stay FP32
     const int mode = o ? o->mode : DWF_SOLVE_F64;
-    if (mode != DWF_SOLVE_F64 && mode != DWF_SOLVE_MIXED_F32) fail(DWF_ENOTSUP, "FGCR mode must be F64 or MIXED_F32");
-    const int lp = mode == DWF_SOLVE_MIXED_F32 ? P_F32 : P_F64;
+    if (mode != DWF_SOLVE_F64 && mode != DWF_SOLVE_MIXED_F32 && mode != DWF_SOLVE_MIXED_BF16)
+        fail(DWF_ENOTSUP, "FGCR mode must be F64, MIXED_F32 or MIXED_BF16");
+    const int lp = mode == DWF_SOLVE_MIXED_F32 ? P_F32 : mode == DWF_SOLVE_MIXED_BF16 ? P_BF16 : P_F64;
+    const int rp = lp == P_BF16 ? P_F32 : lp;  // residual and solution of a cycle
     const bool mixed = lp != P_F64;
     HIPCHECK(hipStreamSynchronize(c.stream));
     const double t0 = wall();
@@ -457,7 +464,7 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
         Z.push_back(ws_field(c, "fg_z" + std::to_string(k), lp));
         Q.push_back(ws_field(c, "fg_q" + std::to_string(k), lp));
     }
-    Field rl = mixed ? ws_field(c, "fg_rl", lp) : r, xl = mixed ? ws_field(c, "fg_xl", lp) : x;
+    Field rl = mixed ? ws_field(c, "fg_rl", rp) : r, xl = mixed ? ws_field(c, "fg_xl", rp) : x;
     // device pointer tables of the Krylov vectors, Gram-Schmidt coefficients
     // (dots[2m]; info[3k] = {|q_k|^2, <q_k, r>} per step) and partial sums
     struct Dev {
@@ -487,24 +494,25 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
     const double bn = std::sqrt(dnorm2(c, rhs));
     launch_zero(c, P_F64, x);
     launch_copy(c, P_F64, rhs, r);
-    if (mixed) launch_zero(c, lp, xl);
+    if (mixed) launch_zero(c, rp, xl);
     int it = 0;
     bool conv = bn == 0.0, stalled = false;
     double best = bn;
     int since_best = 0;
     while (!conv && !stalled && it < maxit) {
         int k = 0;
-        if (mixed) launch_convert(c, P_F64, r, lp, rl);
+        if (mixed) launch_convert(c, P_F64, r, rp, rl);
         for (; k < m && it < maxit; k++) {
-            if (net) precondition(net, lp, rl, Z[k], normal);
-            else launch_copy(c, lp, rl, Z[k]);
+            if (net) precondition(net, rp, rl, lp, Z[k], normal);
+            else if (rp == lp) launch_copy(c, lp, rl, Z[k]);
+            else launch_convert(c, rp, rl, lp, Z[k]);
             fgcr_op(c, lp, Z[k], Q[k], normal);
             // classical Gram-Schmidt against the cycle's earlier directions in
             // one pass over the vectors; the residual stays orthogonal to them
             if (k > 0) launch_gs_dots(c, lp, (const void *const *)qtab, k, Q[k], partial, dots);
-            launch_gs_project(c, lp, (const void *const *)qtab, (const void *const *)ztab, k, dots, info, Q[k], Z[k],
-                              rl, partial, info + 3 * k);
-            const int np = launch_gs_update(c, lp, xl, Z[k], rl, Q[k], info + 3 * k);
+            launch_gs_project(c, lp, rp, (const void *const *)qtab, (const void *const *)ztab, k, dots, info, Q[k],
+                              Z[k], rl, partial, info + 3 * k);
+            const int np = launch_gs_update(c, lp, rp, xl, Z[k], rl, Q[k], info + 3 * k);
             launch_finish(c, np, 1, 12);
             read_scalars(c, 12, 1);
             it++;
@@ -523,7 +531,7 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
             if (rn <= tol * bn) break;
         }
         // restart: fold the low-precision solution in, true residual in FP64
-        if (mixed) launch_accumulate_low(c, lp, x, xl);
+        if (mixed) launch_accumulate_low(c, rp, x, xl);
         fgcr_op(c, P_F64, x, t1, normal);
         launch_axpby(c, P_F64, 1.0, rhs, -1.0, t1, r);
         const double rn = std::sqrt(dnorm2(c, r));

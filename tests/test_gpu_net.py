@@ -225,6 +225,38 @@ def test_fgcr_reaches_tolerance_or_falls_back(case, normal):
         dwf.dwf_net_destroy(net)
 
 
+@pytest.mark.parametrize("normal", [False, True])
+def test_fgcr_bf16_basis_reaches_tolerance(case, normal):
+    """FP32 cycles with the Krylov basis stored in BF16 (and the operator applied
+    in BF16 storage), FP64 restarts.  Plain GCR reaches the FP64 tolerance
+    without the CG fallback, checked by the oracle's D5.  With an untrained
+    network, whose directions gain less per step than the BF16 rounding of the
+    basis, the solve may stagnate; the result must then come from the fallback
+    and still meet the tolerance.  (The trained network converges without the
+    fallback: test_trained_network_gain_over_plain_gcr.)"""
+    b = case.full(83)
+    x = torch().zeros_like(to_gpu(b))
+    status, st = dwf.dwf_fgcr(case.ctx, None, to_gpu(b), x, tol=1e-9, restart=16, normal=normal, maxit=4000,
+                              fallback=False, mode=dwf.DWF_SOLVE_MIXED_BF16)
+    print(f"bf16 basis GCR normal={normal}: {st['iters']} steps res {st['res_full']:.2e}", flush=True)
+    assert status == dwf.DWF_OK and st["fell_back"] == 0
+    r = b - oracle.d5(case.P, case.Ud, to_host(x))
+    assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-7
+    net = dwf.dwf_net_create(case.ctx, CHANS)
+    try:
+        dwf.dwf_net_set_weights(net, flat(random_weights(CHANS, 4, scale=0.02)))
+        x.zero_()
+        status, st2 = dwf.dwf_fgcr(case.ctx, net, to_gpu(b), x, tol=1e-9, restart=16, normal=normal, maxit=4000,
+                                   fallback=True, mode=dwf.DWF_SOLVE_MIXED_BF16)
+        print(f"bf16 basis FGCR normal={normal}: {st2['iters']} steps res {st2['res_full']:.2e} "
+              f"fell back {st2['fell_back']}", flush=True)
+        assert status == dwf.DWF_OK
+        r = b - oracle.d5(case.P, case.Ud, to_host(x))
+        assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-7
+    finally:
+        dwf.dwf_net_destroy(net)
+
+
 def test_fgcr_without_fallback_reports_noconv(case):
     b = case.full(82)
     x = torch().zeros_like(to_gpu(b))
@@ -266,6 +298,15 @@ def test_trained_network_gain_over_plain_gcr():
         print(f"mixed FP32 FGCR, matrix-core network: status {s2} {st2['iters']} steps res {st2['res_full']:.2e}",
               flush=True)
         assert s2 == dwf.DWF_OK and st2["fell_back"] == 0
+        r = b - oracle.d5(c.P, c.Ud, to_host(x))
+        assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-7
+        # the same with the Krylov basis in BF16
+        x.zero_()
+        s3, st3 = dwf.dwf_fgcr(c.ctx, net, to_gpu(b), x, tol=1e-8, restart=32, maxit=1500, fallback=False,
+                               mode=dwf.DWF_SOLVE_MIXED_BF16)
+        print(f"BF16-basis FGCR, matrix-core network: status {s3} {st3['iters']} steps res {st3['res_full']:.2e}",
+              flush=True)
+        assert s3 == dwf.DWF_OK and st3["fell_back"] == 0
         r = b - oracle.d5(c.P, c.Ud, to_host(x))
         assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-7
     finally:
