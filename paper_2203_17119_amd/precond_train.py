@@ -21,7 +21,7 @@ Recipe:
      ``include/dwf.h``), initialised to N = 1/d (the inverse of Mooee's diagonal)
      plus small noise.
 3. Evaluation on ``24^4x12_fgcr``. Each solve is judged by its FP64 full residual:
-   - plain FP64 CG;
+   - plain FP64 CG, and the mixed FP16 CG;
    - plain GCR (no network);
    - FGCR with the initial network;
    - FGCR with the trained network.
@@ -148,6 +148,9 @@ def solve_table(lat, torch, nets: dict, b_full, tol: float, restart: int, maxit:
     torch.cuda.synchronize()
     s, st = dwf.dwf_cg(lat.ctx, b_full, x, tol=tol, mode=dwf.DWF_SOLVE_F64)
     rows["cg_f64"] = {"status": s, "iters": st["iters"], "seconds": st["seconds"], "res_full": st["res_full"]}
+    x.zero_()
+    s, st = dwf.dwf_cg(lat.ctx, b_full, x, tol=tol, mode=dwf.DWF_SOLVE_MIXED_F16)
+    rows["cg_mixed_f16"] = {"status": s, "iters": st["iters"], "seconds": st["seconds"], "res_full": st["res_full"]}
     for normal in ((False, True) if normal_too else (False,)):
         tag = "normal" if normal else "schur"
         for name, net in ([("gcr", None)] if gcr else []) + list(nets.items()):
@@ -185,6 +188,10 @@ def main():
                     help="channel counts, comma separated (4 at both ends; 4, 8 or 12 each)")
     ap.add_argument("--skip-gcr", action="store_true", help="do not evaluate plain GCR")
     ap.add_argument("--mixed", action="store_true", help="FGCR with FP32 cycles and FP64 restarts")
+    ap.add_argument("--bf16-basis", action="store_true",
+                    help="FGCR with FP32 cycles, the Krylov basis in BF16 and FP64 restarts")
+    ap.add_argument("--forward", default="both", choices=("both", "fp32", "mfma"),
+                    help="network forward(s) to evaluate")
     args = ap.parse_args()
 
     import torch
@@ -232,6 +239,8 @@ def evaluate(args, torch, w0, wt, chans=CHANS):
     for name, wts in (("net_init", w0), ("net_trained", wt), ("net_trained_mfma", wt)):
         if name == "net_init" and args.skip_init:
             continue
+        if (name.endswith("_mfma") and args.forward == "fp32") or (name == "net_trained" and args.forward == "mfma"):
+            continue
         nets[name] = dwf.dwf_net_create(lat.ctx, chans)
         dwf.dwf_net_set_weights(nets[name], wts)
         if name.endswith("_mfma"):
@@ -239,7 +248,8 @@ def evaluate(args, torch, w0, wt, chans=CHANS):
     for k in range(args.eval_sources):
         b = torch.from_numpy(synth.gaussian_fermion(ev.dims, ev.Ls, ev.source_seeds[k])).cuda()
         rows = solve_table(lat, torch, nets, b, ev.tol, args.restart, args.maxit, args.normal_too, not args.skip_gcr,
-                           dwf.DWF_SOLVE_MIXED_F32 if args.mixed else dwf.DWF_SOLVE_F64)
+                           dwf.DWF_SOLVE_MIXED_BF16 if args.bf16_basis
+                           else dwf.DWF_SOLVE_MIXED_F32 if args.mixed else dwf.DWF_SOLVE_F64)
         print(json.dumps({"phase": "eval", "workload": args.eval_workload, "source": ev.source_seeds[k],
                           "restart": args.restart, "rows": rows}), flush=True)
     for n in nets.values():
