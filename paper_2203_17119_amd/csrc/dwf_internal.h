@@ -251,10 +251,12 @@ inline int accum_prec(int prec) { return (prec == P_F16 || prec == P_BF16) ? P_F
 // x += alpha p ; r -= alpha ap ; partials of |r|^2        (alpha = dscal[ia];
 // x in accum_prec(prec), the others in prec)
 int launch_cg_update_xr(Context &c, int prec, Field x, Field r, Field p, Field ap, int ia);
-// p = r + beta p ; pa = A p (A = b + c P5)                 (beta = dscal[ib])
-// p = r + beta p, pa = A p (beta = dscal[ib]); with ia >= 0 first x += alpha p
-// (alpha = dscal[ia], x in the accumulator precision of prec)
-void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pa, int ib, Field x = Field{}, int ia = -1);
+// pout = r + beta p, pa = A pout (A = b + c P5, beta = dscal[ib]).  With ia >= 0
+// the pending solution updates come first: x += alpha2 pprev when ia2 >= 0, then
+// x += alpha p (alpha = dscal[ia], alpha2 = dscal[ia2]; x in the accumulator
+// precision of prec).  pout may alias p or pprev.
+void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pout, Field pa, int ib, Field x = Field{},
+                        int ia = -1, Field pprev = Field{}, int ia2 = -1);
 // Block Gram-Schmidt of flexible GCR (FP64 or FP32 fields as flat complex
 // arrays, FP64 sums).  gs_dots: out[2j], out[2j+1] = Re, Im <X_j, y>, j < nv
 // (X_dev: device array of nv field pointers; partial: gs_partials_needed

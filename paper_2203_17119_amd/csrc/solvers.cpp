@@ -24,7 +24,7 @@ using namespace dwf;
 namespace dwf {
 
 // device scalar slots
-enum { S_RHO = 0, S_RHONEW = 1, S_PAP = 2, S_ALPHA = 3, S_BETA = 4, S_ONE = 5, S_TMP = 6, S_DOT = 8 };
+enum { S_RHO = 0, S_RHONEW = 1, S_PAP = 2, S_ALPHA = 3, S_BETA = 4, S_ONE = 5, S_TMP = 6, S_ALPHA1 = 7, S_DOT = 8 };
 
 static double now()
 {
@@ -119,7 +119,11 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
     const int xp = accum_prec(lp);
     Field r = mixed ? ws_field(c, "cg_rl", lp) : rh;
     Field xl = mixed ? ws_field(c, "cg_xl", xp) : x;
-    Field p = ws_field(c, "cg_p", lp), pa = ws_field(c, "cg_pa", lp);
+    // two direction buffers: the current p, and the previous one while its
+    // solution update is still pending
+    Field pbuf[2] = {ws_field(c, "cg_p", lp), ws_field(c, "cg_p2", lp)};
+    Field pa = ws_field(c, "cg_pa", lp);
+    int cur = 0;
     Field m = mixed ? ws_field(c, "cg_m", lp) : m64, ap = mixed ? ws_field(c, "cg_ap", lp) : ap64;
 
     double rho = true_residual();
@@ -129,8 +133,8 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
     }
     // p = r, pa = A p  (via p = r + 0 p)
     set_scalar(c, S_BETA, 0.0);
-    launch_zero(c, lp, p);
-    launch_cg_update_p(c, lp, r, p, pa, S_BETA);
+    launch_zero(c, lp, pbuf[0]);
+    launch_cg_update_p(c, lp, r, pbuf[0], pbuf[0], pa, S_BETA);
     set_scalar(c, S_RHO, rho);
     double rmax = std::sqrt(rho);
     if (std::sqrt(rho) <= target) {
@@ -141,9 +145,13 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
     const int maxi = maxit > 0 ? maxit : 100000;
     // Unshifted systems fuse the residual update into the last stencil stage
     // (r -= alpha Mpc^+ Mpc p without storing the product) and defer the
-    // solution update x += alpha p to the next p-update kernel, which reads p
-    // anyway; before a reliable update or the exit it is applied on its own.
+    // solution update x += alpha p to a p-update kernel, which reads p anyway.
+    // Every second p-update folds two iterations' updates into one pass over x:
+    // the older direction stays in the other buffer until then, and alpha
+    // alternates between two slots.  Before a reliable update or the exit the
+    // pending updates are applied on their own.
     const bool fused = sigma == 0.0;
+    int pend_slot = -1;  // alpha slot of the previous iteration's pending update
     // The host learns each iteration's residual norm one iteration late. The
     // reduction of iteration k writes the norm to a ring slot in host memory
     // as well, and the host waits for it only after it has queued iteration
@@ -158,16 +166,18 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
         return v;
     };
     while (true) {
+        const Field p = pbuf[cur];
+        const int aslot = (st.iters & 1) ? S_ALPHA1 : S_ALPHA;
         if (fused) {
             const int npm = apply_mpc(c, lp, false, p, m, true, true, pa);
             launch_finish(c, npm, 1, S_PAP);  // <p, Mpc^+ Mpc p> = |Mpc p|^2
-            launch_scalar_div(c, S_ALPHA, S_RHO, S_PAP);
-            const int np = apply_mpc(c, lp, true, m, r, false, false, Field{}, 1, 0, S_ALPHA);
+            launch_scalar_div(c, aslot, S_RHO, S_PAP);
+            const int np = apply_mpc(c, lp, true, m, r, false, false, Field{}, 1, 0, aslot);
             launch_finish(c, np, 1, S_RHONEW, c.dring + (st.iters & 1));
         } else {
             normal_op(c, lp, sigma, p, ap, m, true, pa);
-            launch_scalar_div(c, S_ALPHA, S_RHO, S_PAP);
-            const int np = launch_cg_update_xr(c, lp, xl, r, p, ap, S_ALPHA);
+            launch_scalar_div(c, aslot, S_RHO, S_PAP);
+            const int np = launch_cg_update_xr(c, lp, xl, r, p, ap, aslot);
             launch_finish(c, np, 1, S_RHONEW, c.dring + (st.iters & 1));
         }
         const int k = st.iters++;
@@ -180,6 +190,12 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
         }
         unread = k;
         bool x_pending = fused;  // x += alpha p of this iteration not yet applied
+        auto flush = [&]() {
+            if (pend_slot >= 0) launch_axpy_dev(c, lp, xl, pbuf[1 - cur], pend_slot);
+            if (x_pending) launch_axpy_dev(c, lp, xl, p, aslot);
+            pend_slot = -1;
+            x_pending = false;
+        };
         bool done = false;
         if (check) {
             double rho1 = norm_of(k);
@@ -187,8 +203,7 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
             if (mixed) {
                 // reliable update: fold the low-precision solution into x and
                 // recompute the residual exactly
-                if (x_pending) launch_axpy_dev(c, lp, xl, p, S_ALPHA);
-                x_pending = false;
+                flush();
                 launch_accumulate_low(c, xp, x, xl);
                 rho1 = true_residual();
                 launch_convert(c, P_F64, rh, lp, r);
@@ -198,13 +213,23 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
             done = std::sqrt(rho1) <= target;
         }
         if (done || st.iters >= maxi) {
-            if (x_pending) launch_axpy_dev(c, lp, xl, p, S_ALPHA);
+            flush();
             if (done) st.converged = 1;
             break;
         }
         launch_scalar_div(c, S_BETA, S_RHONEW, S_RHO);
         launch_scalar_div(c, S_RHO, S_RHONEW, S_ONE);
-        launch_cg_update_p(c, lp, r, p, pa, S_BETA, xl, x_pending ? S_ALPHA : -1);
+        // the new direction goes to the other buffer, whose direction has no
+        // pending update left once this kernel has run
+        const Field pnew = pbuf[1 - cur];
+        if (x_pending && pend_slot >= 0) {
+            launch_cg_update_p(c, lp, r, p, pnew, pa, S_BETA, xl, aslot, pnew, pend_slot);
+            pend_slot = -1;
+        } else {
+            launch_cg_update_p(c, lp, r, p, pnew, pa, S_BETA);
+            pend_slot = x_pending ? aslot : -1;
+        }
+        cur = 1 - cur;
     }
     if (mixed && !st.converged) launch_accumulate_low(c, xp, x, xl);
     // final FP64 check
