@@ -232,8 +232,12 @@ void ms_launch_step(Context &c, int prec, const MsState &s, Field r, Field ap, F
 int launch_norm2(Context &c, int prec, Field a);
 int launch_dot(Context &c, int prec, Field a, Field b);
 // dscal[slot + w] = sum of the partials; mirror (device-visible host memory),
-// when given, receives the same values
-void launch_finish(Context &c, int nparts, int width, int slot, double *mirror = nullptr);
+// when given, receives the same values; with qslot >= 0 (width 1) also
+// dscal[qslot] = dscal[nslot] / sum
+void launch_finish(Context &c, int nparts, int width, int slot, double *mirror = nullptr, int qslot = -1,
+                   int nslot = -1);
+// dscal[beta] = dscal[rho_new] / dscal[rho], then dscal[rho] = dscal[rho_new]
+void launch_cg_beta(Context &c, int beta, int rho, int rho_new);
 
 // generic vector ops with host scalars: z = a*x + b*y (real a, b)
 void launch_axpby(Context &c, int prec, double a, Field x, double b, Field y, Field z);

@@ -67,9 +67,10 @@ __global__ void __launch_bounds__(BS) k_dot(Field a, Field b, double *partial)
 // interleaved running sums, so the order depends only on nparts.
 static constexpr int FBS = 1024;
 // When mirror is set, the sums are also written there: host memory that the
-// host reads after an event behind this kernel.
+// host reads after an event behind this kernel.  With qslot >= 0 (width 1) the
+// quotient dscal[qslot] = dscal[nslot] / sum follows.
 __global__ void __launch_bounds__(FBS) k_finish(const double *partial, int nparts, int width, double *dscal, int slot,
-                                                double *mirror)
+                                                double *mirror, int qslot, int nslot)
 {
     for (int w = 0; w < width; w++) {
         double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
@@ -85,6 +86,7 @@ __global__ void __launch_bounds__(FBS) k_finish(const double *partial, int npart
         if (threadIdx.x == 0) {
             dscal[slot + w] = t;
             if (mirror) mirror[w] = t;
+            if (qslot >= 0 && w == 0) dscal[qslot] = dscal[nslot] / t;
         }
     }
 }
@@ -92,6 +94,16 @@ __global__ void __launch_bounds__(FBS) k_finish(const double *partial, int npart
 __global__ void k_scalar_div(double *dscal, int out, int num, int den)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) dscal[out] = dscal[num] / dscal[den];
+}
+
+// CG step scalars: beta = rho_new / rho, then rho = rho_new
+__global__ void k_cg_beta(double *dscal, int beta, int rho, int rho_new)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double rn = dscal[rho_new];
+        dscal[beta] = rn / dscal[rho];
+        dscal[rho] = rn;
+    }
 }
 
 template <typename S>
@@ -932,16 +944,24 @@ int launch_dot(Context &c, int prec, Field a, Field b)
     return (int)nb;
 }
 
-void launch_finish(Context &c, int nparts, int width, int slot, double *mirror)
+void launch_finish(Context &c, int nparts, int width, int slot, double *mirror, int qslot, int nslot)
 {
+    if (qslot >= 0 && (width != 1 || nslot < 0)) fail(DWF_EINVAL, "quotient needs one sum and a numerator slot");
     Timer tm(c, DWF_K_BLAS, 8.0 * nparts * width, 0);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(FBS), 0, c.stream, c.partials, nparts, width, c.dscal, slot, mirror);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(FBS), 0, c.stream, c.partials, nparts, width, c.dscal, slot, mirror,
+                       qslot, nslot);
     HIPCHECK(hipGetLastError());
 }
 
 void launch_scalar_div(Context &c, int out, int num, int den)
 {
     hipLaunchKernelGGL(k_scalar_div, dim3(1), dim3(64), 0, c.stream, c.dscal, out, num, den);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_cg_beta(Context &c, int beta, int rho, int rho_new)
+{
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, c.stream, c.dscal, beta, rho, rho_new);
     HIPCHECK(hipGetLastError());
 }
 

@@ -170,8 +170,8 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
         const int aslot = (st.iters & 1) ? S_ALPHA1 : S_ALPHA;
         if (fused) {
             const int npm = apply_mpc(c, lp, false, p, m, true, true, pa);
-            launch_finish(c, npm, 1, S_PAP);  // <p, Mpc^+ Mpc p> = |Mpc p|^2
-            launch_scalar_div(c, aslot, S_RHO, S_PAP);
+            // <p, Mpc^+ Mpc p> = |Mpc p|^2, and alpha = rho / <p, Mpc^+ Mpc p>
+            launch_finish(c, npm, 1, S_PAP, nullptr, aslot, S_RHO);
             const int np = apply_mpc(c, lp, true, m, r, false, false, Field{}, 1, 0, aslot);
             launch_finish(c, np, 1, S_RHONEW, c.dring + (st.iters & 1));
         } else {
@@ -217,8 +217,7 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
             if (done) st.converged = 1;
             break;
         }
-        launch_scalar_div(c, S_BETA, S_RHONEW, S_RHO);
-        launch_scalar_div(c, S_RHO, S_RHONEW, S_ONE);
+        launch_cg_beta(c, S_BETA, S_RHO, S_RHONEW);
         // the new direction goes to the other buffer, whose direction has no
         // pending update left once this kernel has run
         const Field pnew = pbuf[1 - cur];
