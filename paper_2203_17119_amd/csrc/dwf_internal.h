@@ -255,12 +255,20 @@ inline int accum_prec(int prec) { return (prec == P_F16 || prec == P_BF16) ? P_F
 // x += alpha p ; r -= alpha ap ; partials of |r|^2        (alpha = dscal[ia];
 // x in accum_prec(prec), the others in prec)
 int launch_cg_update_xr(Context &c, int prec, Field x, Field r, Field p, Field ap, int ia);
+// Older CG directions whose solution updates are still pending, oldest first,
+// with the device slots of their alphas.
+struct CgOlder {
+    static constexpr int MAX = 3;
+    Field dir[MAX];
+    int slot[MAX] = {-1, -1, -1};
+    int n = 0;
+};
 // pout = r + beta p, pa = A pout (A = b + c P5, beta = dscal[ib]).  With ia >= 0
-// the pending solution updates come first: x += alpha2 pprev when ia2 >= 0, then
-// x += alpha p (alpha = dscal[ia], alpha2 = dscal[ia2]; x in the accumulator
-// precision of prec).  pout may alias p or pprev.
+// the pending solution updates come first: x += alpha_j q_j over `older`, then
+// x += alpha p (alpha = dscal[ia]; x in the accumulator precision of prec).
+// pout may alias p or one of the older directions.
 void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pout, Field pa, int ib, Field x = Field{},
-                        int ia = -1, Field pprev = Field{}, int ia2 = -1);
+                        int ia = -1, const CgOlder &older = CgOlder{});
 // Block Gram-Schmidt of flexible GCR (FP64 or FP32 fields as flat complex
 // arrays, FP64 sums).  gs_dots: out[2j], out[2j+1] = Re, Im <X_j, y>, j < nv
 // (X_dev: device array of nv field pointers; partial: gs_partials_needed

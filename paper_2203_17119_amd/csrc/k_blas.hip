@@ -202,13 +202,14 @@ __global__ void __launch_bounds__(BS) k_cg_update_xr(Field x, Field r, Field p, 
 
 // pout = r + beta p ; pa = (b + c P5) pout   (workgroup = Ls x sb lanes, one 4D
 // site per row).  With ia >= 0 the pending solution updates are folded in
-// first, x in storage precision SX: x += alpha2 q (alpha2 = dscal[ia2], q = pprev,
-// when ia2 >= 0), then x += alpha p (alpha = dscal[ia], the old p).  pout may be
-// p or pprev: every lane reads its elements before it writes them.
+// first, x in storage precision SX: x += alpha_j q_j over the older directions
+// of `older` (oldest first, alpha_j = dscal[slot_j]), then x += alpha p (alpha =
+// dscal[ia], the old p).  pout may be p or an older direction: every lane reads
+// its elements before it writes them.
 template <typename S, typename SX>
-__global__ void __launch_bounds__(256) k_cg_update_p(Field r, Field p, Field pout, Field pa, Field x, Field pprev,
-                                                     const double *dscal, int ib, int ia, int ia2, long vh, int Ls,
-                                                     double bb, double cc, double mf)
+__global__ void __launch_bounds__(256) k_cg_update_p(Field r, Field p, Field pout, Field pa, Field x, CgOlder older,
+                                                     const double *dscal, int ib, int ia, long vh, int Ls, double bb,
+                                                     double cc, double mf)
 {
     using C = Cof<S>;
     const int s = threadIdx.x, j = threadIdx.y, sb = blockDim.y;
@@ -226,10 +227,10 @@ __global__ void __launch_bounds__(256) k_cg_update_p(Field r, Field p, Field pou
             const C alpha = C(dscal[ia]);
             cx<C> xv[12];
             load_spinor<SX, C>(x, i, xv);
-            if (ia2 >= 0) {
-                const C alpha2 = C(dscal[ia2]);
+            for (int q = 0; q < older.n; q++) {
+                const C alpha2 = C(dscal[older.slot[q]]);
                 cx<C> qv[12];
-                load_spinor<S, C>(pprev, i, qv);
+                load_spinor<S, C>(older.dir[q], i, qv);
                 for (int c = 0; c < 12; c++) xv[c] = xv[c] + alpha2 * qv[c];
             }
             for (int c = 0; c < 12; c++) xv[c] = xv[c] + alpha * pv[c];
@@ -1024,7 +1025,7 @@ int launch_cg_update_xr(Context &c, int prec, Field x, Field r, Field p, Field a
     HIPCHECK(hipGetLastError())
 
 void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pout, Field pa, int ib, Field x, int ia,
-                        Field pprev, int ia2)
+                        const CgOlder &older)
 {
     const int Ls = c.Ls;
     const int sb = default_sb(c);
@@ -1032,11 +1033,14 @@ void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pout, Fiel
     const size_t csz = (prec == P_F64) ? 16 : 8;
     const size_t lds = (size_t)sb * Ls * 12 * csz;
     if (ia >= 0 && !x.data) fail(DWF_EINVAL, "solution update needs x");
-    if (ia2 >= 0 && (ia < 0 || !pprev.data)) fail(DWF_EINVAL, "second solution update needs x and its direction");
-    const double xb = ia >= 0 ? 2 * sbytes(accum_prec(prec)) + (ia2 >= 0 ? sbytes(prec) : 0.0) : 0.0;
+    if (older.n < 0 || older.n > CgOlder::MAX || (older.n > 0 && ia < 0))
+        fail(DWF_EINVAL, "older solution updates need x and at most three directions");
+    for (int q = 0; q < older.n; q++)
+        if (!older.dir[q].data || older.slot[q] < 0) fail(DWF_EINVAL, "older solution update without a direction");
+    const double xb = ia >= 0 ? 2 * sbytes(accum_prec(prec)) + older.n * sbytes(prec) : 0.0;
     Timer tm(c, DWF_K_BLAS, (4 * sbytes(prec) + xb) * c.n5h, 96.0 * c.n5h, prec);
-    DWF_DISPATCH_X(prec, k_cg_update_p, dim3((unsigned)nblk), dim3(Ls, sb), lds, r, p, pout, pa, x, pprev, c.dscal, ib,
-                   ia, ia2, c.vh, Ls, c.p.b, c.p.c, c.p.mf);
+    DWF_DISPATCH_X(prec, k_cg_update_p, dim3((unsigned)nblk), dim3(Ls, sb), lds, r, p, pout, pa, x, older, c.dscal, ib,
+                   ia, c.vh, Ls, c.p.b, c.p.c, c.p.mf);
 }
 
 void launch_axpy_dev(Context &c, int prec, Field x, Field p, int ia)

@@ -25,6 +25,10 @@ namespace dwf {
 
 // device scalar slots
 enum { S_RHO = 0, S_RHONEW = 1, S_PAP = 2, S_ALPHA = 3, S_BETA = 4, S_ONE = 5, S_TMP = 6, S_ALPHA1 = 7, S_DOT = 8 };
+// two more alpha slots of the CG direction ring, clear of the other solvers' slots
+enum { S_ALPHA2 = 250, S_ALPHA3 = 251 };
+static constexpr int CG_RING = 4;  // directions per pass of the solution update
+static constexpr int kAlphaSlot[CG_RING] = {S_ALPHA, S_ALPHA1, S_ALPHA2, S_ALPHA3};
 
 static double now()
 {
@@ -119,9 +123,10 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
     const int xp = accum_prec(lp);
     Field r = mixed ? ws_field(c, "cg_rl", lp) : rh;
     Field xl = mixed ? ws_field(c, "cg_xl", xp) : x;
-    // two direction buffers: the current p, and the previous one while its
-    // solution update is still pending
-    Field pbuf[2] = {ws_field(c, "cg_p", lp), ws_field(c, "cg_p2", lp)};
+    // a ring of direction buffers: the current p, and up to three older ones
+    // whose solution updates are still pending
+    Field pbuf[CG_RING];
+    for (int q = 0; q < CG_RING; q++) pbuf[q] = ws_field(c, "cg_p" + std::to_string(q), lp);
     Field pa = ws_field(c, "cg_pa", lp);
     int cur = 0;
     Field m = mixed ? ws_field(c, "cg_m", lp) : m64, ap = mixed ? ws_field(c, "cg_ap", lp) : ap64;
@@ -146,12 +151,13 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
     // Unshifted systems fuse the residual update into the last stencil stage
     // (r -= alpha Mpc^+ Mpc p without storing the product) and defer the
     // solution update x += alpha p to a p-update kernel, which reads p anyway.
-    // Every second p-update folds two iterations' updates into one pass over x:
-    // the older direction stays in the other buffer until then, and alpha
-    // alternates between two slots.  Before a reliable update or the exit the
-    // pending updates are applied on their own.
+    // Every fourth p-update folds four iterations' updates into one pass over
+    // x: the older directions stay in the ring until then, each with its alpha
+    // in the slot of its ring position.  Before a reliable update or the exit
+    // the pending updates are applied on their own.
     const bool fused = sigma == 0.0;
-    int pend_slot = -1;  // alpha slot of the previous iteration's pending update
+    int npend = 0;  // older iterations whose solution updates are pending
+    auto ring = [&](int back) { return (cur - back + CG_RING) % CG_RING; };
     // The host learns each iteration's residual norm one iteration late. The
     // reduction of iteration k writes the norm to a ring slot in host memory
     // as well, and the host waits for it only after it has queued iteration
@@ -167,7 +173,7 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
     };
     while (true) {
         const Field p = pbuf[cur];
-        const int aslot = (st.iters & 1) ? S_ALPHA1 : S_ALPHA;
+        const int aslot = kAlphaSlot[cur];
         if (fused) {
             const int npm = apply_mpc(c, lp, false, p, m, true, true, pa);
             // <p, Mpc^+ Mpc p> = |Mpc p|^2, and alpha = rho / <p, Mpc^+ Mpc p>
@@ -191,9 +197,9 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
         unread = k;
         bool x_pending = fused;  // x += alpha p of this iteration not yet applied
         auto flush = [&]() {
-            if (pend_slot >= 0) launch_axpy_dev(c, lp, xl, pbuf[1 - cur], pend_slot);
+            for (int back = npend; back >= 1; back--) launch_axpy_dev(c, lp, xl, pbuf[ring(back)], kAlphaSlot[ring(back)]);
             if (x_pending) launch_axpy_dev(c, lp, xl, p, aslot);
-            pend_slot = -1;
+            npend = 0;
             x_pending = false;
         };
         bool done = false;
@@ -218,17 +224,22 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
             break;
         }
         launch_cg_beta(c, S_BETA, S_RHO, S_RHONEW);
-        // the new direction goes to the other buffer, whose direction has no
-        // pending update left once this kernel has run
-        const Field pnew = pbuf[1 - cur];
-        if (x_pending && pend_slot >= 0) {
-            launch_cg_update_p(c, lp, r, p, pnew, pa, S_BETA, xl, aslot, pnew, pend_slot);
-            pend_slot = -1;
+        // The new direction goes to the next ring position. It holds no pending
+        // direction, or the oldest one, whose update this kernel applies first.
+        const int nxt = (cur + 1) % CG_RING;
+        if (x_pending && npend == CG_RING - 1) {
+            CgOlder older;
+            for (int back = npend; back >= 1; back--) {
+                older.dir[older.n] = pbuf[ring(back)];
+                older.slot[older.n++] = kAlphaSlot[ring(back)];
+            }
+            launch_cg_update_p(c, lp, r, p, pbuf[nxt], pa, S_BETA, xl, aslot, older);
+            npend = 0;
         } else {
-            launch_cg_update_p(c, lp, r, p, pnew, pa, S_BETA);
-            pend_slot = x_pending ? aslot : -1;
+            launch_cg_update_p(c, lp, r, p, pbuf[nxt], pa, S_BETA);
+            npend = x_pending ? npend + 1 : 0;
         }
-        cur = 1 - cur;
+        cur = nxt;
     }
     if (mixed && !st.converged) launch_accumulate_low(c, xp, x, xl);
     // final FP64 check
