@@ -236,6 +236,8 @@ int launch_dot(Context &c, int prec, Field a, Field b);
 // dscal[qslot] = dscal[nslot] / sum
 void launch_finish(Context &c, int nparts, int width, int slot, double *mirror = nullptr, int qslot = -1,
                    int nslot = -1);
+// dscal[slot] = v, queued on the stream (the host does not wait)
+void launch_set_scalar(Context &c, int slot, double v);
 // dscal[beta] = dscal[rho_new] / dscal[rho], then dscal[rho] = dscal[rho_new]
 void launch_cg_beta(Context &c, int beta, int rho, int rho_new);
 

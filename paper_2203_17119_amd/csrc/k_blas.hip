@@ -96,6 +96,12 @@ __global__ void k_scalar_div(double *dscal, int out, int num, int den)
     if (threadIdx.x == 0 && blockIdx.x == 0) dscal[out] = dscal[num] / dscal[den];
 }
 
+// dscal[slot] = v, the value passed by argument: stream-ordered, no host wait
+__global__ void k_set_scalar(double *dscal, int slot, double v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) dscal[slot] = v;
+}
+
 // CG step scalars: beta = rho_new / rho, then rho = rho_new
 __global__ void k_cg_beta(double *dscal, int beta, int rho, int rho_new)
 {
@@ -957,6 +963,12 @@ void launch_finish(Context &c, int nparts, int width, int slot, double *mirror, 
 void launch_scalar_div(Context &c, int out, int num, int den)
 {
     hipLaunchKernelGGL(k_scalar_div, dim3(1), dim3(64), 0, c.stream, c.dscal, out, num, den);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_set_scalar(Context &c, int slot, double v)
+{
+    hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, c.stream, c.dscal, slot, v);
     HIPCHECK(hipGetLastError());
 }
 

@@ -49,8 +49,7 @@ static int prec_of_mode(int mode)
 static void set_scalar(Context &c, int slot, double v)
 {
     c.hscal[slot] = v;
-    HIPCHECK(hipMemcpyAsync(c.dscal + slot, c.hscal + slot, sizeof(double), hipMemcpyHostToDevice, c.stream));
-    HIPCHECK(hipStreamSynchronize(c.stream));
+    launch_set_scalar(c, slot, v);
 }
 
 static double norm2(Context &c, int prec, Field a, int slot = S_TMP)
