@@ -224,8 +224,15 @@ struct MsState {
 void ms_launch_norm2(Context &c, int prec, Field a, int nb, long stride, double *out);
 void ms_launch_redot(Context &c, int prec, Field a, Field b, int nb, long stride, double *out);
 void ms_launch_axpy(Context &c, int prec, double a, Field x, Field y, int nb, long stride);
-void ms_launch_step(Context &c, int prec, const MsState &s, Field r, Field ap, Field X, Field P, int nrhs, int nshift,
-                    int kmin, long stride, double *rho_new, int it);
+// One multi-shift step: alpha, r -= alpha A p, |r|^2, the shift recurrences
+// (coefficients into s.coef), then the shifted directions into Pn.  Solution
+// updates go in pairs (see k_ms_update_b): an odd it leaves its update pending
+// (direction in P, coefficients in s.coef), the next applies it from Pn with
+// the coefficients cprev, and its own.
+void ms_launch_step(Context &c, int prec, const MsState &s, Field r, Field ap, Field X, Field P, Field Pn,
+                    const double *cprev, int nrhs, int nshift, int kmin, long stride, double *rho_new, int it);
+// x += a p for every member whose coefficients in coef are on
+void ms_launch_flush(Context &c, int prec, Field X, Field P, const double *coef, int nrhs, int nshift, long stride);
 
 // reductions: partial sums (2 doubles per workgroup for dots) then a fixed-order
 // finish on the device that writes dscal[slot] (and dscal[slot+1] for dots)

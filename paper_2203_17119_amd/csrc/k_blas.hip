@@ -836,10 +836,16 @@ __global__ void k_ms_recur(MsState s, const double *rho_new, int nrhs, int nshif
     }
 }
 
-// x_kj += a p_kj ; p_kj = z r_j + b p_kj for the active shifts (member k*nrhs + j)
+// Shifted directions and solutions of every active (shift, rhs) member:
+// pnew = z r + b p, written to the other direction set Pn.  The solution
+// updates go in pairs: with flush = 0 the update x += a p of this iteration
+// is left pending (p stays in P); with flush = 1 x += a' p' of the previous
+// iteration (coefficients cprev, direction in Pn, read before pnew overwrites
+// it) and then x += a p are applied in one pass over x.  A member frozen in
+// this iteration still receives its pending update.
 template <typename S>
-__global__ void __launch_bounds__(BS) k_ms_update_b(int nrhs, int nshift, Field X, Field P, Field r, long stride,
-                                                     const double *coef)
+__global__ void __launch_bounds__(BS) k_ms_update_b(int nrhs, int nshift, Field X, Field P, Field Pn, Field r,
+                                                     long stride, const double *coef, const double *cprev, int flush)
 {
     using C = Cof<S>;
     const int j = blockIdx.y;
@@ -849,19 +855,56 @@ __global__ void __launch_bounds__(BS) k_ms_update_b(int nrhs, int nshift, Field 
     cx<C> rv[12];
     load_spinor<S, C>(r, i, rv);
     for (int k = 0; k < nshift; k++) {
-        const double *cf = coef + 4 * (long)(k * nrhs + j);
-        if (cf[3] == 0.0) continue;
-        const C a = C(cf[0]), z = C(cf[1]), b = C(cf[2]);
-        const Field x = member(X, k * nrhs + j, stride), p = member(P, k * nrhs + j, stride);
+        const long q = k * nrhs + j;
+        const double *cf = coef + 4 * q;
+        const bool on = cf[3] != 0.0, pend = flush && cprev[4 * q + 3] != 0.0;
+        if (!on && !pend) continue;
+        const Field p = member(P, q, stride), pn = member(Pn, q, stride);
+        cx<C> pv[12];
+        if (on) load_spinor<S, C>(p, i, pv);
+        if (flush) {
+            const Field x = member(X, q, stride);
+            cx<C> xv[12];
+            load_spinor<S, C>(x, i, xv);
+            if (pend) {
+                const C ap = C(cprev[4 * q]);
+                cx<C> qv[12];
+                load_spinor<S, C>(pn, i, qv);
+                for (int c = 0; c < 12; c++) xv[c] = xv[c] + ap * qv[c];
+            }
+            if (on) {
+                const C a = C(cf[0]);
+                for (int c = 0; c < 12; c++) xv[c] = xv[c] + a * pv[c];
+            }
+            store_spinor<S, C>(x, i, xv);
+        }
+        if (on) {
+            const C z = C(cf[1]), b = C(cf[2]);
+            for (int c = 0; c < 12; c++) pv[c] = z * rv[c] + b * pv[c];
+            store_spinor<S, C>(pn, i, pv);
+        }
+    }
+}
+
+// x += a p for the members whose update of the last iteration is still pending
+template <typename S>
+__global__ void __launch_bounds__(BS) k_ms_flush_b(int nrhs, int nshift, Field X, Field P, long stride,
+                                                    const double *coef)
+{
+    using C = Cof<S>;
+    const int j = blockIdx.y;
+    const long i = blockIdx.x * (long)BS + threadIdx.x;
+    if (i >= X.n) return;
+    for (int k = 0; k < nshift; k++) {
+        const long q = k * nrhs + j;
+        if (coef[4 * q + 3] == 0.0) continue;
+        const C a = C(coef[4 * q]);
+        const Field x = member(X, q, stride), p = member(P, q, stride);
         cx<C> xv[12], pv[12];
         load_spinor<S, C>(x, i, xv);
         load_spinor<S, C>(p, i, pv);
-        for (int c = 0; c < 12; c++) {
-            xv[c] = xv[c] + a * pv[c];
-            pv[c] = z * rv[c] + b * pv[c];
-        }
+        for (int c = 0; c < 12; c++) xv[c] = xv[c] + a * pv[c];
         store_spinor<S, C>(x, i, xv);
-        store_spinor<S, C>(p, i, pv);
     }
 }
 
@@ -891,8 +934,8 @@ void ms_launch_axpy(Context &c, int prec, double a, Field x, Field y, int nb, lo
     DWF_DISPATCH(prec, k_axpy_b, dim3((unsigned)((x.n + BS - 1) / BS), nb), dim3(BS), 0, a, x, y, stride);
 }
 
-void ms_launch_step(Context &c, int prec, const MsState &s, Field r, Field ap, Field X, Field P, int nrhs, int nshift,
-                    int kmin, long stride, double *rho_new, int it)
+void ms_launch_step(Context &c, int prec, const MsState &s, Field r, Field ap, Field X, Field P, Field Pn,
+                    const double *cprev, int nrhs, int nshift, int kmin, long stride, double *rho_new, int it)
 {
     const long np = (r.n + BS - 1) / BS;
     if (np * nrhs > c.partials_len) fail(DWF_EINVAL, "reduction buffer too small");
@@ -904,8 +947,18 @@ void ms_launch_step(Context &c, int prec, const MsState &s, Field r, Field ap, F
     hipLaunchKernelGGL(k_finish_b, dim3(nrhs), dim3(BS), 0, c.stream, c.partials, (int)np, rho_new);
     hipLaunchKernelGGL(k_ms_recur, dim3(nrhs), dim3(64), 0, c.stream, s, rho_new, nrhs, nshift, kmin, it);
     HIPCHECK(hipGetLastError());
-    Timer tm(c, DWF_K_BLAS, nrhs * (1 + 4.0 * nshift) * (12.0 * elem_bytes(prec)) * r.n, 0);
-    DWF_DISPATCH(prec, k_ms_update_b, dim3((unsigned)np, nrhs), dim3(BS), 0, nrhs, nshift, X, P, r, stride, s.coef);
+    // pairs of iterations: the first (odd it) leaves its solution update pending
+    const int flush = (it % 2 == 0) ? 1 : 0;
+    Timer tm(c, DWF_K_BLAS, nrhs * (1 + (flush ? 5.0 : 2.0) * nshift) * (12.0 * elem_bytes(prec)) * r.n, 0);
+    DWF_DISPATCH(prec, k_ms_update_b, dim3((unsigned)np, nrhs), dim3(BS), 0, nrhs, nshift, X, P, Pn, r, stride, s.coef,
+                 cprev, flush);
+}
+
+void ms_launch_flush(Context &c, int prec, Field X, Field P, const double *coef, int nrhs, int nshift, long stride)
+{
+    const long np = (X.n + BS - 1) / BS;
+    Timer tm(c, DWF_K_BLAS, nrhs * 3.0 * nshift * (12.0 * elem_bytes(prec)) * X.n, 0);
+    DWF_DISPATCH(prec, k_ms_flush_b, dim3((unsigned)np, nrhs), dim3(BS), 0, nrhs, nshift, X, P, stride, coef);
 }
 
 // plain 16-byte streaming copy, grid-stride

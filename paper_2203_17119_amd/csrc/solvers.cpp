@@ -420,17 +420,20 @@ extern "C" dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *con
         if (shifts[k] < shifts[kmin]) kmin = k;
     const long stride = batch_stride(c, lp);
     const int nq = nrhs * nshift;
-    // batches: B, R, AP, M over rhs; X, P over (shift, rhs), member k*nrhs + j
+    // batches: B, R, AP, M over rhs; X and the direction sets over (shift, rhs), member k*nrhs + j
     Field B = ws_batch(c, "ms_B", lp, nrhs), R = ws_batch(c, "ms_R", lp, nrhs);
     Field AP = ws_batch(c, "ms_AP", lp, nrhs), M = ws_batch(c, "ms_M", lp, nrhs);
-    Field X = ws_batch(c, "ms_X", lp, nq), P = ws_batch(c, "ms_P", lp, nq);
+    // two direction sets: the current directions, and the new ones (which hold
+    // the previous directions while their solution updates are pending)
+    Field X = ws_batch(c, "ms_X", lp, nq);
+    Field Pset[2] = {ws_batch(c, "ms_P", lp, nq), ws_batch(c, "ms_P2", lp, nq)};
     Field b64 = ws_field(c, "ms_b64", P_F64), x64 = ws_field(c, "ms_x64", P_F64);
     for (int j = 0; j < nrhs; j++) {
         launch_import(c, P_F64, b_odd[j], b64, 0, 0);
         launch_convert(c, P_F64, b64, lp, member(B, j, stride));
     }
     // device state
-    DevBuf dstate(sizeof(double) * (7 * nrhs + 2 * nq + 4 * nq + nshift) + sizeof(int) * 2 * nq);
+    DevBuf dstate(sizeof(double) * (7 * nrhs + 2 * nq + 4 * nq + nshift + 4 * nq) + sizeof(int) * 2 * nq);
     double *db = dstate.as<double>();
     MsState s;
     s.rho = db;
@@ -444,10 +447,11 @@ extern "C" dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *con
     s.zeta_old = s.zeta + nq;
     s.coef = s.zeta_old + nq;
     s.shifts = s.coef + 4 * nq;
-    s.active = (int *)(s.shifts + nshift);
+    double *coefs[2] = {s.coef, s.shifts + nshift};  // this and the previous iteration's coefficients
+    s.active = (int *)(coefs[1] + 4 * nq);
     s.iters = s.active + nq;
     {
-        std::vector<double> h(7 * nrhs + 6 * nq + nshift, 0.0);
+        std::vector<double> h(7 * nrhs + 6 * nq + nshift + 4 * nq, 0.0);
         std::vector<int> hi(2 * nq, 0);
         ms_launch_norm2(c, lp, B, nrhs, stride, c.dscal + 16);
         read_scalars(c, 16, nrhs);
@@ -465,19 +469,23 @@ extern "C" dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *con
     for (int j = 0; j < nrhs; j++) launch_copy(c, lp, member(B, j, stride), member(R, j, stride));
     for (int q = 0; q < nq; q++) {
         launch_zero(c, lp, member(X, q, stride));
-        launch_copy(c, lp, member(B, q % nrhs, stride), member(P, q, stride));
+        launch_copy(c, lp, member(B, q % nrhs, stride), member(Pset[0], q, stride));
     }
-    const Field Pbase = member(P, kmin * nrhs, stride);
     const int maxi = maxit > 0 ? maxit : 100000;
     std::vector<int> act(nq);
-    int it = 0;
+    int it = 0, cur = 0;  // Pset[cur] holds the current directions
     while (it < maxi) {
+        const Field Pbase = member(Pset[cur], kmin * nrhs, stride);
         apply_mpc(c, lp, false, Pbase, M, false, false, Field{}, nrhs, stride);
         apply_mpc(c, lp, true, M, AP, false, false, Field{}, nrhs, stride);
         if (shifts[kmin] != 0.0) ms_launch_axpy(c, lp, shifts[kmin], Pbase, AP, nrhs, stride);
         ms_launch_redot(c, lp, Pbase, AP, nrhs, stride, s.pap);
         it++;
-        ms_launch_step(c, lp, s, R, AP, X, P, nrhs, nshift, kmin, stride, rho_new, it);
+        MsState si = s;
+        si.coef = coefs[cur];
+        ms_launch_step(c, lp, si, R, AP, X, Pset[cur], Pset[1 - cur], coefs[1 - cur], nrhs, nshift, kmin, stride,
+                       rho_new, it);
+        cur = 1 - cur;
         if (it % 8 == 0 || it == maxi) {
             HIPCHECK(hipMemcpyAsync(act.data(), s.active, nq * sizeof(int), hipMemcpyDeviceToHost, c.stream));
             HIPCHECK(hipStreamSynchronize(c.stream));
@@ -486,6 +494,8 @@ extern "C" dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *con
             if (n == 0) break;
         }
     }
+    // an odd last iteration left its solution updates pending
+    if (it % 2 == 1) ms_launch_flush(c, lp, X, Pset[1 - cur], coefs[1 - cur], nrhs, nshift, stride);
     std::vector<int> its(nq);
     HIPCHECK(hipMemcpy(its.data(), s.iters, nq * sizeof(int), hipMemcpyDeviceToHost));
     HIPCHECK(hipMemcpy(act.data(), s.active, nq * sizeof(int), hipMemcpyDeviceToHost));
