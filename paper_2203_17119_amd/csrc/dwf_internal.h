@@ -292,6 +292,10 @@ void launch_gs_dots(Context &c, int prec, const void *const *X_dev, int nv, Fiel
 void launch_gs_project(Context &c, int prec, int rprec, const void *const *X_dev, const void *const *W_dev, int nv,
                        const double *dots, const double *nq, Field y, Field w, Field r, double *partial, double *out);
 int launch_gs_update(Context &c, int prec, int rprec, Field x, Field z, Field r, Field q, const double *coef);
+// BF16 basis: x += sum_j a_j Z_j over nz directions (Z_dev: device array of
+// their pointers), a_j from coef[3j..3j+2] as in gs_update; x FP32.  With it
+// the per-step update may pass an empty x.
+void launch_gs_combine(Context &c, int prec, Field x, const void *const *Z_dev, int nz, const double *coef);
 // x += dscal[ia] p, x in the accumulator precision of prec
 void launch_axpy_dev(Context &c, int prec, Field x, Field p, int ia);
 // device scalar arithmetic: dscal[out] = dscal[num] / dscal[den]

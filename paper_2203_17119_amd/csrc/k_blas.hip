@@ -710,6 +710,8 @@ __global__ void __launch_bounds__(BS) k_gs_project_bf(const uint2 *const *X, con
     }
 }
 
+// x += a z (skipped when x is null: the caller combines the cycle's directions
+// into x at the restart, k_gs_combine_bf), r -= a q, partials of |r|^2
 __global__ void __launch_bounds__(BS) k_gs_update_bf(float4 *x, const uint2 *z, float4 *r, const uint2 *q,
                                                      const double *coef, long m2, long nsite, double *partial)
 {
@@ -721,23 +723,69 @@ __global__ void __launch_bounds__(BS) k_gs_update_bf(float4 *x, const uint2 *z, 
     for (int e = 0; e < GS_PPT; e++) {
         const long k = base + (long)e * BS;
         if (k >= m2) continue;
-        const float4 zv = bf_pair(z[k]), qv = bf_pair(q[k]);
+        const float4 qv = bf_pair(q[k]);
         const long kr = res_piece(k, nsite);
-        float4 xv = x[kr], rv = r[kr];
-        xv.x = float(xv.x + (are * zv.x - aim * zv.y));
-        xv.y = float(xv.y + (are * zv.y + aim * zv.x));
-        xv.z = float(xv.z + (are * zv.z - aim * zv.w));
-        xv.w = float(xv.w + (are * zv.w + aim * zv.z));
+        if (x) {
+            const float4 zv = bf_pair(z[k]);
+            float4 xv = x[kr];
+            xv.x = float(xv.x + (are * zv.x - aim * zv.y));
+            xv.y = float(xv.y + (are * zv.y + aim * zv.x));
+            xv.z = float(xv.z + (are * zv.z - aim * zv.w));
+            xv.w = float(xv.w + (are * zv.w + aim * zv.z));
+            x[kr] = xv;
+        }
+        float4 rv = r[kr];
         rv.x = float(rv.x - (are * qv.x - aim * qv.y));
         rv.y = float(rv.y - (are * qv.y + aim * qv.x));
         rv.z = float(rv.z - (are * qv.z - aim * qv.w));
         rv.w = float(rv.w - (are * qv.w + aim * qv.z));
-        x[kr] = xv;
         r[kr] = rv;
         n2 += double(rv.x) * rv.x + double(rv.y) * rv.y + double(rv.z) * rv.z + double(rv.w) * rv.w;
     }
     n2 = block_sum(n2);
     if (threadIdx.x == 0) partial[blockIdx.x] = n2;
+}
+
+// x += sum_j a_j Z_j over nz BF16 directions, oldest first, with a_j =
+// (coef[3j+1] + i coef[3j+2]) / coef[3j]; x FP32
+__global__ void __launch_bounds__(BS) k_gs_combine_bf(float4 *x, const uint2 *const *Z, int nz, const double *coef,
+                                                      long m2, long nsite)
+{
+    const long base = (long)blockIdx.x * BS * GS_PPT + threadIdx.x;
+    double4 acc[GS_PPT];
+#pragma unroll
+    for (int e = 0; e < GS_PPT; e++) acc[e] = make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int j = 0; j < nz; j++) {
+        const double inv = 1.0 / coef[3 * j];
+        const double are = coef[3 * j + 1] * inv, aim = coef[3 * j + 2] * inv;
+        const uint2 *zj = Z[j];
+        uint2 zr[GS_PPT];
+#pragma unroll
+        for (int e = 0; e < GS_PPT; e++) {
+            const long k = base + (long)e * BS;
+            zr[e] = k < m2 ? zj[k] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int e = 0; e < GS_PPT; e++) {
+            const float4 zv = bf_pair(zr[e]);
+            acc[e].x += are * zv.x - aim * zv.y;
+            acc[e].y += are * zv.y + aim * zv.x;
+            acc[e].z += are * zv.z - aim * zv.w;
+            acc[e].w += are * zv.w + aim * zv.z;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < GS_PPT; e++) {
+        const long k = base + (long)e * BS;
+        if (k >= m2) continue;
+        const long kr = res_piece(k, nsite);
+        float4 xv = x[kr];
+        xv.x = float(xv.x + acc[e].x);
+        xv.y = float(xv.y + acc[e].y);
+        xv.z = float(xv.z + acc[e].z);
+        xv.w = float(xv.w + acc[e].w);
+        x[kr] = xv;
+    }
 }
 
 // y_j += a x_j (host scalar), batched
@@ -1190,13 +1238,15 @@ void launch_gs_project(Context &c, int prec, int rprec, const void *const *X_dev
 
 int launch_gs_update(Context &c, int prec, int rprec, Field x, Field z, Field r, Field q, const double *coef)
 {
-    const long m = 12 * x.n, nblk = prec == P_BF16 ? gs_blocks_bf(m) : gs_blocks(m);
+    const long m = 12 * r.n, nblk = prec == P_BF16 ? gs_blocks_bf(m) : gs_blocks(m);
     gs_prec_check(prec, rprec, m);
+    if (!x.data && prec != P_BF16) fail(DWF_EINVAL, "Gram-Schmidt update needs x");
     need_partials(c, nblk, 1);
-    Timer tm(c, DWF_K_BLAS, (2.0 * gs_elem_bytes(prec) + 4.0 * gs_elem_bytes(rprec)) * m, 18.0 * m, prec);
+    const double xb = x.data ? gs_elem_bytes(prec) + 2.0 * gs_elem_bytes(rprec) : 0.0;
+    Timer tm(c, DWF_K_BLAS, (gs_elem_bytes(prec) + 2.0 * gs_elem_bytes(rprec) + xb) * m, 18.0 * m, prec);
     if (prec == P_BF16)
         hipLaunchKernelGGL(k_gs_update_bf, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (float4 *)x.data,
-                           (const uint2 *)z.data, (float4 *)r.data, (const uint2 *)q.data, coef, m / 2, x.n,
+                           (const uint2 *)z.data, (float4 *)r.data, (const uint2 *)q.data, coef, m / 2, r.n,
                            c.partials);
     else if (prec == P_F64)
         hipLaunchKernelGGL(k_gs_update<double2>, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (double2 *)x.data,
@@ -1206,6 +1256,18 @@ int launch_gs_update(Context &c, int prec, int rprec, Field x, Field z, Field r,
                            (const float2 *)z.data, (float2 *)r.data, (const float2 *)q.data, coef, m, c.partials);
     HIPCHECK(hipGetLastError());
     return (int)nblk;
+}
+
+void launch_gs_combine(Context &c, int prec, Field x, const void *const *Z_dev, int nz, const double *coef)
+{
+    const long m = 12 * x.n, nblk = gs_blocks_bf(m);
+    gs_prec_check(prec, P_F32, m);
+    if (prec != P_BF16) fail(DWF_ENOTSUP, "deferred solution combination needs a BF16 basis");
+    if (nz < 1 || nz > GS_MAXV) fail(DWF_EINVAL, "combination of 1..64 directions");
+    Timer tm(c, DWF_K_BLAS, (nz * 4.0 + 16.0) * m, 8.0 * nz * m, prec);
+    hipLaunchKernelGGL(k_gs_combine_bf, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (float4 *)x.data,
+                       (const uint2 *const *)Z_dev, nz, coef, m / 2, x.n);
+    HIPCHECK(hipGetLastError());
 }
 
 void launch_ms_update(Context &c, int prec, int nshift, Field *x, Field *p, Field r, const double *coef_dev,

@@ -500,7 +500,9 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
     double best = bn;
     int since_best = 0;
     while (!conv && !stalled && it < maxit) {
-        int k = 0;
+        int k = 0, ndir = 0;  // ndir: directions of this cycle applied to the residual
+        // with a BF16 basis the cycle's solution update is combined at the restart
+        const bool defer_x = lp == P_BF16;
         if (mixed) launch_convert(c, P_F64, r, rp, rl);
         for (; k < m && it < maxit; k++) {
             if (net) precondition(net, rp, rl, lp, Z[k], normal);
@@ -512,7 +514,8 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
             if (k > 0) launch_gs_dots(c, lp, (const void *const *)qtab, k, Q[k], partial, dots);
             launch_gs_project(c, lp, rp, (const void *const *)qtab, (const void *const *)ztab, k, dots, info, Q[k],
                               Z[k], rl, partial, info + 3 * k);
-            const int np = launch_gs_update(c, lp, rp, xl, Z[k], rl, Q[k], info + 3 * k);
+            const int np = launch_gs_update(c, lp, rp, defer_x ? Field{} : xl, Z[k], rl, Q[k], info + 3 * k);
+            ndir = k + 1;
             launch_finish(c, np, 1, 12);
             read_scalars(c, 12, 1);
             it++;
@@ -531,6 +534,7 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
             if (rn <= tol * bn) break;
         }
         // restart: fold the low-precision solution in, true residual in FP64
+        if (defer_x && ndir > 0) launch_gs_combine(c, lp, xl, (const void *const *)ztab, ndir, info);
         if (mixed) launch_accumulate_low(c, rp, x, xl);
         fgcr_op(c, P_F64, x, t1, normal);
         launch_axpby(c, P_F64, 1.0, rhs, -1.0, t1, r);
