@@ -164,6 +164,12 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
     // an exit that the norm of iteration k calls for follows iteration k + 1;
     // it then reads that iteration's own norm.
     int unread = -1;  // iteration whose norm the host has not read yet
+    // A low-precision recurrence drifts from the true residual with every
+    // iteration; on an ill-conditioned operator the residual may fall by the
+    // factor delta only after hundreds of them.  A reliable update is also due
+    // after kMaxSinceUpdate iterations without one.
+    static constexpr int kMaxSinceUpdate = 150;
+    int since_update = 0;
     auto norm_of = [&](int k) {
         HIPCHECK(hipEventSynchronize(c.cg_ev[k & 1]));
         const double v = *(volatile double *)(c.hring + (k & 1));
@@ -188,7 +194,8 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
         const int k = st.iters++;
         HIPCHECK(hipEventRecord(c.cg_ev[k & 1], c.stream));
         // the check that the previous iteration's norm asks for
-        bool check = st.iters >= maxi;
+        since_update++;
+        bool check = st.iters >= maxi || (mixed && since_update >= kMaxSinceUpdate);
         if (unread >= 0) {
             const double rn = std::sqrt(norm_of(unread));
             check = check || rn <= target || (mixed && rn < delta * rmax);
@@ -214,6 +221,7 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
                 launch_convert(c, P_F64, rh, lp, r);
                 rmax = std::sqrt(rho1);
                 st.reliable++;
+                since_update = 0;
             }
             done = std::sqrt(rho1) <= target;
         }
