@@ -136,9 +136,10 @@ typedef struct {
     int mode;          /* DWF_SOLVE_*                                             */
     double delta;      /* reliable-update threshold (<= 0: 0.1): the FP64 residual
                           is recomputed once the iterated one has fallen by this
-                          factor.  Larger values recompute more often; with FP16
-                          storage on an ill-conditioned operator that saves
-                          iterations (see the design notes on 24^4 x 12)        */
+                          factor, and after 150 iterations without an update.
+                          Larger values recompute more often; with FP16 storage
+                          on an ill-conditioned operator that saves iterations
+                          (see the design notes on 24^4 x 12)                   */
     int x0_is_guess;   /* 1: x holds an initial guess on entry                    */
     int restart;       /* FGCR restart length m (<= 0: 16)                         */
     int normal;        /* FGCR: 1 solves the normal equations Mpc^+ Mpc, 0 Mpc    */
