@@ -203,7 +203,8 @@ static CoreStats cg_core(Context &c, int mode, double sigma, Field rhs, Field x,
         unread = k;
         bool x_pending = fused;  // x += alpha p of this iteration not yet applied
         auto flush = [&]() {
-            for (int back = npend; back >= 1; back--) launch_axpy_dev(c, lp, xl, pbuf[ring(back)], kAlphaSlot[ring(back)]);
+            for (int back = npend; back >= 1; back--)
+                launch_axpy_dev(c, lp, xl, pbuf[ring(back)], kAlphaSlot[ring(back)]);
             if (x_pending) launch_axpy_dev(c, lp, xl, p, aslot);
             npend = 0;
             x_pending = false;
