@@ -129,7 +129,8 @@ struct Context {
     KStats stats_prec[DWF_K_NCLASS][4];
 };
 
-// device scalar slots and their pinned host mirror
+// device scalar slots and their pinned host mirror.  Slots in use: CG 0-9 and
+// 250-251 (its alpha ring), FGCR 10-15, multi-shift 16 onwards (one per rhs).
 constexpr int HS_MIRROR = 256;
 
 // default 4D sites per workgroup: about 192 lanes
