@@ -23,6 +23,7 @@ FLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+    "-Werror=return-type",
     "-I" + os.path.join(ROOT, "include"),
 ]
 
@@ -31,13 +32,23 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str) -> str:
+# the host pass does not know the packed-FP32 target feature; that note is
+# expected and harmless, every other diagnostic is shown
+_KNOWN_NOTE = "packed-fp32-ops"
+
+
+def _diagnostics(text: str) -> str:
+    keep = [ln for ln in text.splitlines() if ln.strip() and _KNOWN_NOTE not in ln]
+    return "\n".join(keep)
+
+
+def _compile(src: str) -> tuple[str, str]:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
-    return obj
+    return obj, _diagnostics(r.stdout + r.stderr)
 
 
 def build(jobs: int | None = None, verbose: bool = False) -> str:
@@ -46,7 +57,11 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        done = list(ex.map(_compile, srcs))
+    objs = [o for o, _ in done]
+    for src, (_, diag) in zip(srcs, done):
+        if diag:
+            print(f"[hipcc] {os.path.basename(src)}:\n{diag}", file=sys.stderr, flush=True)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -391,21 +391,6 @@ void launch_slocal(Context &c, int prec, int op, Field in, Field out, int nbatch
 
 // ================================================================ C ABI
 
-#define DWF_API_BEGIN try {
-#define DWF_API_END                              \
-    return DWF_OK;                               \
-    }                                            \
-    catch (const dwf::Error &e)                  \
-    {                                            \
-        dwf::set_error(e.msg);                   \
-        return e.code;                           \
-    }                                            \
-    catch (const std::exception &e)              \
-    {                                            \
-        dwf::set_error(e.what());                \
-        return DWF_ENOMEM;                       \
-    }
-
 static void check_prec(int prec)
 {
     if (prec < 0 || prec > 3) fail(DWF_EINVAL, "unknown precision");

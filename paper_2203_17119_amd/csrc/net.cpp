@@ -163,21 +163,6 @@ static float2 *net_backward(dwf_net_s *n)
 
 // ================================================================ C ABI
 
-#define DWF_API_BEGIN try {
-#define DWF_API_END                              \
-    return DWF_OK;                               \
-    }                                            \
-    catch (const dwf::Error &e)                  \
-    {                                            \
-        dwf::set_error(e.msg);                   \
-        return e.code;                           \
-    }                                            \
-    catch (const std::exception &e)              \
-    {                                            \
-        dwf::set_error(e.what());                \
-        return DWF_ENOMEM;                       \
-    }
-
 static dwf_net_s &N_(dwf_net n)
 {
     if (!n) fail(DWF_EINVAL, "null network");

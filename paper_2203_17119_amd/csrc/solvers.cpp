@@ -270,20 +270,6 @@ static void fill_opts(const dwf_solver_opts *o, double &tol, int &maxit, int &mo
 
 }  // namespace dwf
 
-#define DWF_API_BEGIN try {
-#define DWF_API_END                              \
-    }                                            \
-    catch (const dwf::Error &e)                  \
-    {                                            \
-        dwf::set_error(e.msg);                   \
-        return e.code;                           \
-    }                                            \
-    catch (const std::exception &e)              \
-    {                                            \
-        dwf::set_error(e.what());                \
-        return DWF_ENOMEM;                       \
-    }
-
 extern "C" {
 
 dwf_status dwf_cg(dwf_ctx ctx, const double *b_full, double *x_full, const dwf_solver_opts *o, dwf_solver_stats *st)
@@ -566,7 +552,6 @@ extern "C" dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *con
 // w_0 = v, w_1 = x(A) v, w_{k+1} = 2 x(A) w_k - w_{k-1}.  Three fields rotate
 // through the recurrence; each step is one A application (four stencil
 // launches) and one three-term combination.
-static constexpr bool kChebyshevEnabled = false;
 
 extern "C" dwf_status dwf_chebyshev_filter(dwf_ctx ctx, int prec, const double *v_odd, double lo, double hi,
                                            int nout, const int *orders, double *const *out_odd)
@@ -583,9 +568,6 @@ extern "C" dwf_status dwf_chebyshev_filter(dwf_ctx ctx, int prec, const double *
         if (orders[i] < 0 || orders[i] > 100000) fail(DWF_EINVAL, "orders must be in [0, 100000]");
         if (i > 0 && orders[i] <= orders[i - 1]) fail(DWF_EINVAL, "orders must be strictly ascending");
     }
-    // Switched off: its first GPU run did not return (no fault reported) and no
-    // cause has been found; the arguments are still validated above.
-    if (!kChebyshevEnabled) fail(DWF_ENOTSUP, "Chebyshev filter is disabled in this build");
     dwf::Context &c = *ctx;
     const int lp = prec;
     const double a = 2.0 / (hi - lo), sh = -(hi + lo) / (hi - lo);  // x(A) = a A + sh

@@ -88,21 +88,6 @@ double time_normal_op(Context &c, int prec, Field a, Field b, Field m, int reps)
 
 }  // namespace dwf
 
-#define DWF_API_BEGIN try {
-#define DWF_API_END                              \
-    return DWF_OK;                               \
-    }                                            \
-    catch (const dwf::Error &e)                  \
-    {                                            \
-        dwf::set_error(e.msg);                   \
-        return e.code;                           \
-    }                                            \
-    catch (const std::exception &e)              \
-    {                                            \
-        dwf::set_error(e.what());                \
-        return DWF_ENOMEM;                       \
-    }
-
 extern "C" dwf_status dwf_tune(dwf_ctx ctx, int prec, const char *cache_path, double *best_ms)
 {
     DWF_API_BEGIN

@@ -16,11 +16,6 @@ from gpu_helpers import Case, relerr, to_gpu, to_host, torch
 
 pytestmark = pytest.mark.gpu
 
-# The first GPU run of the filter did not return (no fault reported) and no
-# cause has been found, so the library switches the filter off: after its
-# argument checks it returns DWF_ENOTSUP.  The parity tests stay, skipped.
-DISABLED = "dwf_chebyshev_filter is switched off: its first GPU run did not return and no cause was found"
-
 UNIT = {dwf.DWF_F64: 1e-13, dwf.DWF_F32: 6e-8, dwf.DWF_F16: 4.9e-4, dwf.DWF_BF16: 3.9e-3}
 ORDERS = [0, 1, 2, 5, 8]
 
@@ -50,7 +45,6 @@ def spectrum_top(c, v):
     return 1.1 * lam
 
 
-@pytest.mark.skip(reason=DISABLED)
 @pytest.mark.parametrize("prec", [dwf.DWF_F64, dwf.DWF_F32, dwf.DWF_F16, dwf.DWF_BF16])
 def test_chebyshev_matches_oracle(case, prec):
     v = case.half(83)
@@ -65,7 +59,6 @@ def test_chebyshev_matches_oracle(case, prec):
         assert err < bound(prec, k), (prec, k)
 
 
-@pytest.mark.skip(reason=DISABLED)
 def test_chebyshev_single_orders_and_repeat_calls(case):
     """Order 0 alone is the input; a call for a single high order equals the same
     order taken from a longer list; and a second call on the same context gives
@@ -87,7 +80,7 @@ def test_chebyshev_single_orders_and_repeat_calls(case):
 
 
 def test_chebyshev_argument_errors(case):
-    """argument checks run before any device work (and before the switch-off)"""
+    """argument checks run before any device work"""
     g = to_gpu(case.half(85))
     o = torch().empty_like(g)
     for lo, hi, orders in [(1.0, 1.0, [1]), (-0.1, 1.0, [1]), (0.0, float("inf"), [1]), (0.0, 1.0, [2, 2]),
@@ -98,13 +91,3 @@ def test_chebyshev_argument_errors(case):
     with pytest.raises(dwf.DWFError) as e:
         dwf.dwf_chebyshev_filter(case.ctx, g, 0.0, 1.0, list(range(65)), [o] * 65)
     assert e.value.status == dwf.DWF_EINVAL
-
-
-def test_chebyshev_switched_off(case):
-    """valid arguments: the switched-off filter reports DWF_ENOTSUP and writes nothing"""
-    g = to_gpu(case.half(86))
-    o = torch().zeros_like(g)
-    with pytest.raises(dwf.DWFError) as e:
-        dwf.dwf_chebyshev_filter(case.ctx, g, 0.0, 1.0, [0, 3], [o, o.clone()])
-    assert e.value.status == dwf.DWF_ENOTSUP
-    assert float(o.abs().max()) == 0.0
