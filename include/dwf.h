@@ -176,6 +176,50 @@ dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *const *b_odd, 
                              const double *shifts, double *const *x_odd, const dwf_solver_opts *o,
                              dwf_solver_stats *st);
 
+/* ------------------------------------------------------------- DD-RHMC */
+
+/* A rational function in partial fractions,
+ *   r(x) = a0 + sum_{k < n} alpha[k] / (x + beta[k]),   1 <= n <= 64, beta[k] >= 0,
+ * the form in which the one-flavour (RHMC) actions apply fractional powers of
+ * a normal operator.  alpha and beta are host arrays.  The library evaluates
+ * r; the coefficients (e.g. a best relative approximation of x^p on an interval
+ * covering the spectrum, computed by paper_2203_17119_amd/rational/remez.py)
+ * are the caller's. */
+typedef struct {
+    int n;
+    double a0;
+    const double *alpha;
+    const double *beta;
+} dwf_rational;
+
+/* out = r(A) in with A = Mpc^+ Mpc of the context: one multi-shift solve with
+ * the shifts beta[k] (modes and tolerance of dwf_multishift_cg: every shifted
+ * system meets o->tol in FP64), then out = a0 in + sum_k alpha[k] x_k on the
+ * device.  in_odd and out_odd are canonical FP64 odd half fields (device; they
+ * may be the same buffer).  st (may be NULL) receives the statistics of the
+ * worst shifted system (largest iteration count, converged only when all are).
+ * Errors: DWF_EINVAL for a null pointer, n outside 1..64, negative or
+ * non-finite beta, non-finite a0 or alpha; DWF_ENOCONV when a shift missed the
+ * tolerance (out then holds the combination of the last iterates). */
+dwf_status dwf_rational_apply(dwf_ctx ctx, const dwf_rational *r, const double *in_odd, double *out_odd,
+                              const dwf_solver_opts *o, dwf_solver_stats *st);
+
+/* The one-flavour boundary action of DD-RHMC (Sec. 2.3.1, following eq.
+ * (ddrhmc)): with A = Mpc^+ Mpc of ctx (the operator of the whole lattice) and
+ * A_d that of ctx_dirichlet (the same field with its Dirichlet faces cut),
+ *   S = phi^+ r_q(A_d) r_m(A) r_q(A_d) phi,   r_q ~ x^{1/4},  r_m ~ x^{-1/2},
+ * evaluated as psi = r_q(A_d) phi, chi = r_m(A) psi, S = Re <psi, chi> (FP64
+ * sum on the device).  Since det D5 = det Mee det Mpc with Mee field-independent,
+ * a Gaussian phi with this action samples det D / det D_dirichlet, the
+ * boundary determinant of eq. (ddrhmc).  The two contexts must have the same
+ * lattice, Ls and operator parameters.  phi_odd: canonical FP64 odd half field
+ * (device).  action: host.  st (may be NULL): two entries, the r_q and r_m
+ * solves as in dwf_rational_apply.  Errors as dwf_rational_apply, and
+ * DWF_EINVAL for contexts of different geometry or parameters. */
+dwf_status dwf_ddrhmc_action(dwf_ctx ctx, dwf_ctx ctx_dirichlet, const dwf_rational *r_quarter,
+                             const dwf_rational *r_minus_half, const double *phi_odd, const dwf_solver_opts *o,
+                             double *action, dwf_solver_stats *st);
+
 /* Chebyshev filter of the normal operator A = Mpc^+ Mpc: the recursively
  * generated filter functions proposed for fast multigrid subspace set-up of
  * the local Dirichlet solves (Sec. 2.4 and its filter-function figure).  With
@@ -190,9 +234,7 @@ dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *const *b_odd, 
  * live in host memory.  The call returns when the work is queued on the
  * context's stream; it uses context workspace (five fields of prec).
  * Errors: DWF_EINVAL for a null pointer, unknown prec, nout outside 1..64,
- * orders not ascending or out of range, or unless 0 <= lo < hi (finite).
- * In this build the filter is switched off: after validating its arguments
- * the call returns DWF_ENOTSUP without touching the device. */
+ * orders not ascending or out of range, or unless 0 <= lo < hi (finite). */
 dwf_status dwf_chebyshev_filter(dwf_ctx ctx, int prec, const double *v_odd, double lo, double hi, int nout,
                                 const int *orders, double *const *out_odd);
 

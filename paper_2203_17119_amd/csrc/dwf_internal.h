@@ -130,7 +130,8 @@ struct Context {
 };
 
 // device scalar slots and their pinned host mirror.  Slots in use: CG 0-9 and
-// 250-251 (its alpha ring), FGCR 10-15, multi-shift 16 onwards (one per rhs).
+// 250-251 (its alpha ring), FGCR 10-15, multi-shift 16 onwards (one per rhs,
+// at most 64), the DD-RHMC action 246-247.
 constexpr int HS_MIRROR = 256;
 
 // default 4D sites per workgroup: about 192 lanes
@@ -326,3 +327,20 @@ int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduc
 
 // the opaque handle of the C ABI
 struct dwf_context : public dwf::Context {};
+
+// Body of every C entry point: errors thrown inside become a status and the
+// thread-local message; falling through the body returns DWF_OK.
+#define DWF_API_BEGIN try {
+#define DWF_API_END                              \
+    return DWF_OK;                               \
+    }                                            \
+    catch (const dwf::Error &e)                  \
+    {                                            \
+        dwf::set_error(e.msg);                   \
+        return e.code;                           \
+    }                                            \
+    catch (const std::exception &e)              \
+    {                                            \
+        dwf::set_error(e.what());                \
+        return DWF_ENOMEM;                       \
+    }
