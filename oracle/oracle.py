@@ -318,3 +318,74 @@ def fgcr(P: Params, U, b_odd, tol, maxit=10000, m=16, weights=None, normal=False
     it = lib().or_fgcr(_ptr(P._L), P.Ls, *P.args(), _ptr(U), nl, _ptr(chans), _ptr(W), _ptr(b_odd), _ptr(x),
                        float(tol), int(maxit), int(m), int(normal), _ptr(res))
     return x, it, res[0]
+
+
+def adam_step(w, g, m, v, step, lr, beta1, beta2, eps):
+    """One Adam update (Kingma & Ba, "Adam: a method for stochastic
+    optimization", Algorithm 1) on real FP64 arrays, elementwise:
+        m <- beta1 m + (1 - beta1) g,   v <- beta2 v + (1 - beta2) g^2,
+        m^ = m / (1 - beta1^t),   v^ = v / (1 - beta2^t),
+        w <- w - lr m^ / (sqrt(v^) + eps)
+    with t = step (1 for the first update).  Complex weights are updated as
+    their (re, im) pairs with the real-pair gradient dL/dRe + i dL/dIm.
+    Returns (w, m, v) as new arrays."""
+    w, g, m, v = (np.asarray(a, dtype=np.float64) for a in (w, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    return w - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+# ---------------------------------------------------------------- DD-RHMC
+#
+# The one-flavour boundary action of Sec. 2.3.1, eq. (ddrhmc):
+#     S = phi^+ (D_d^+ D_d)^{1/4} (D^+ D)^{-1/2} (D_d^+ D_d)^{1/4} phi
+# with D the operator of the whole lattice and D_d the Dirichlet one of the
+# same field.  On the odd sites of the red-black system the normal operators
+# are A = Mpc^+ Mpc and A_d = Mpc_d^+ Mpc_d: det D5 = det Mee det Mpc and Mee
+# is site- and field-independent, so the determinant ratio the action samples
+# is the same.  The oracle evaluates the matrix functions exactly from the
+# eigendecomposition of the dense Hermitian matrices (small lattices only).
+
+
+def dense_normal(P: Params, U) -> np.ndarray:
+    """Dense A = Mpc^+ Mpc on the odd half field, built column by column."""
+    n = int(np.prod(P.half_shape()))
+    M = np.empty((n, n), dtype=np.complex128)
+    e = np.zeros(n, dtype=np.complex128)
+    for j in range(n):
+        e[j] = 1.0
+        M[:, j] = mpc(P, U, e.reshape(P.half_shape())).ravel()
+        e[j] = 0.0
+    return M.conj().T @ M
+
+
+def herm_power(A, p):
+    """A^p of a Hermitian positive definite matrix from its eigendecomposition."""
+    lam, V = np.linalg.eigh(A)
+    if lam[0] <= 0:
+        raise ValueError("matrix not positive definite")
+    return (V * lam ** p) @ V.conj().T
+
+
+def rational_dense(A, a0, alpha, beta):
+    """r(A) = a0 + sum_k alpha_k (A + beta_k)^-1 for a dense matrix A."""
+    n = A.shape[0]
+    out = a0 * np.eye(n, dtype=np.complex128)
+    for al, be in zip(alpha, beta):
+        out += al * np.linalg.inv(A + be * np.eye(n))
+    return out
+
+
+def ddrhmc_action(P: Params, U_full, U_dirichlet, phi_odd, quarter=None, minus_half=None):
+    """S = phi^+ f(A_d) g(A) f(A_d) phi with f(x) = x^{1/4}, g(x) = x^{-1/2}
+    (exact, by eigendecomposition), or with the rational functions given as
+    (a0, alpha, beta) tuples in their place.  Returns the real action."""
+    A = dense_normal(P, U_full)
+    Ad = dense_normal(P, U_dirichlet)
+    f = herm_power(Ad, 0.25) if quarter is None else rational_dense(Ad, *quarter)
+    g = herm_power(A, -0.5) if minus_half is None else rational_dense(A, *minus_half)
+    v = np.asarray(phi_odd, dtype=np.complex128).ravel()
+    psi = f @ v
+    return float(np.real(np.vdot(psi, g @ psi)))

@@ -268,7 +268,10 @@ def test_trained_network_gain_over_plain_gcr():
     """The committed trained weights (8^4x8 training fields) on an unseen 8^4x8
     field: FGCR with the network must reach 1e-8 in the FP64 full residual,
     checked by the oracle's D5, in fewer steps than plain GCR needs (or where
-    plain GCR stagnates)."""
+    plain GCR stagnates).  Plain FP64 CG, the method without the network and
+    the judge of it, solves the same source to the same target; both must
+    converge, and its count and time are set beside the network's (the
+    comparison is measured, whatever its outcome)."""
     import os
     path = os.path.join(os.path.dirname(dwf.__file__), "weights", "ptc_4-12-12-12-4_8x8x8x8_ls8.npz")
     data = np.load(path)
@@ -281,11 +284,18 @@ def test_trained_network_gain_over_plain_gcr():
         dwf.dwf_net_set_weights(net, data["weights"])
         b = c.full(4242)
         x = torch().zeros_like(to_gpu(b))
+        s_cg, st_cg = dwf.dwf_cg(c.ctx, to_gpu(b), x, tol=1e-8, mode=dwf.DWF_SOLVE_F64)
+        assert s_cg == dwf.DWF_OK
+        r = b - oracle.d5(c.P, c.Ud, to_host(x))
+        assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-7
+        x.zero_()
         s0, st0 = dwf.dwf_fgcr(c.ctx, None, to_gpu(b), x, tol=1e-8, restart=32, maxit=1500, fallback=False)
         x.zero_()
         s1, st1 = dwf.dwf_fgcr(c.ctx, net, to_gpu(b), x, tol=1e-8, restart=32, maxit=1500, fallback=False)
-        print(f"plain GCR: status {s0} {st0['iters']} steps res {st0['res_full']:.2e}; "
-              f"trained: status {s1} {st1['iters']} steps res {st1['res_full']:.2e}", flush=True)
+        print(f"FP64 CG: {st_cg['iters']} iterations (2 Mpc each) {st_cg['seconds']:.3f} s; "
+              f"plain GCR: status {s0} {st0['iters']} steps res {st0['res_full']:.2e}; "
+              f"trained: status {s1} {st1['iters']} steps (1 Mpc + network each) {st1['seconds']:.3f} s "
+              f"res {st1['res_full']:.2e}", flush=True)
         assert s1 == dwf.DWF_OK and st1["fell_back"] == 0
         r = b - oracle.d5(c.P, c.Ud, to_host(x))
         assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-7
@@ -312,3 +322,48 @@ def test_trained_network_gain_over_plain_gcr():
     finally:
         dwf.dwf_net_destroy(net)
         c.close()
+
+
+def test_adam_step_matches_oracle(case):
+    """Three training steps of the library, each against the FP64 Adam reference
+    (oracle.adam_step, Kingma & Ba with bias correction) applied to the library's
+    own gradient of the same batch loss at the same FP32 master weights (taken
+    with dwf_precond_apply and dwf_net_backward, the kernels the training step
+    runs).  epsilon is set to the median gradient size so that its placement
+    matters.  The moments are carried in FP64 on the host and in FP32 on the
+    device; the bound is FP32 rounding of the weights plus 1e-4 of a step."""
+    xs = [case.half(s) for s in range(90, 94)]
+    bs = [oracle.mpc(case.P, case.Ud, x) for x in xs]
+    bg, xg = [to_gpu(b) for b in bs], [to_gpu(x) for x in xs]
+    lr, b1, b2 = 2e-3, 0.9, 0.999
+    net = dwf.dwf_net_create(case.ctx, CHANS)
+    try:
+        dwf.dwf_net_set_weights(net, flat(random_weights(CHANS, 6, scale=0.05)))
+
+        def library_gradient():
+            g = np.zeros(dwf.dwf_net_num_weights(net), dtype=np.complex128)
+            for b, x, bj in zip(bs, xs, bg):
+                y = torch().empty_like(bj)
+                dwf.dwf_precond_apply(case.ctx, net, bj, y)
+                gout = 2.0 * (to_host(y) - x) / (np.linalg.norm(x) ** 2 * len(xs))
+                g += dwf.dwf_net_backward(net, bj, to_gpu(gout)).astype(np.complex128)
+            return g.view(np.float64)
+
+        m = v = None
+        eps = None
+        for t in range(1, 4):
+            w = dwf.dwf_net_get_weights(net).view(np.float32).astype(np.float64)
+            g = library_gradient()
+            if m is None:
+                m, v = np.zeros_like(g), np.zeros_like(g)
+                eps = float(np.median(np.abs(g)))
+            expect, m, v = oracle.adam_step(w, g, m, v, t, lr, b1, b2, eps)
+            dwf.dwf_net_train_step(net, bg, xg, lr=lr, beta1=b1, beta2=b2, eps=eps)
+            got = dwf.dwf_net_get_weights(net).view(np.float32).astype(np.float64)
+            err = np.abs(got - expect)
+            bound = 2.4e-7 * np.abs(expect) + 1e-4 * lr
+            print(f"adam step {t}: max |w - ref| {err.max():.2e}, largest update {np.abs(expect - w).max():.2e}",
+                  flush=True)
+            assert np.all(err <= bound), (t, float((err / bound).max()))
+    finally:
+        dwf.dwf_net_destroy(net)

@@ -1,0 +1,106 @@
+"""Pins of the oracle's DD-RHMC one-flavour boundary action (Sec. 2.3.1).
+
+    S = phi^+ (A_d)^{1/4} A^{-1/2} (A_d)^{1/4} phi,  A = Mpc^+ Mpc,  A_d = Mpc_d^+ Mpc_d
+
+* The action's kernel M = A_d^{1/4} A^{-1/2} A_d^{1/4} has
+  log det M = log|det D5_d| - log|det D5|: eq. (ddrhmc) says the boundary
+  determinant det(1 - D_Omega^-1 D_dOmega D_Omegabar^-1 D_dOmegabar) is
+  det D / det D_dirichlet, and a Gaussian pseudofermion with action S samples
+  1 / det M.  The right-hand side comes from dense LU determinants of the
+  unpreconditioned 5D operators on the full lattice (oracle.d5), a route that
+  shares no step with the eigendecompositions of the red-black operators.
+* The matrix powers satisfy (A^{1/4})^4 = A and A^{-1/2} A A^{-1/2} = 1.
+* The committed rational approximations (paper_2203_17119_amd/rational,
+  Remez) reproduce A^p on every eigenvector within the maximum relative error
+  their files state, when the spectrum lies inside their interval, and the
+  action built from them is within the resulting bound of the exact one.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Params
+from paper_2203_17119_amd import synth
+from helpers import dense_matrix
+
+RATIONAL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2203_17119_amd",
+                        "rational")
+
+
+def load_rational(name):
+    with open(os.path.join(RATIONAL, name)) as fh:
+        r = json.load(fh)
+    return r
+
+
+def _setup(L=(2, 2, 2, 2), Ls=4, mf=0.1, mask=(1, 1, 1, 1), seed=7):
+    P = Params(L, Ls, 1.5, 0.5, 1.8, mf)
+    U = synth.gauge_field(L, 0.5, seed)
+    Ud = oracle.dirichlet(L, U, mask)
+    return P, U, Ud
+
+
+def test_action_kernel_logdet_is_the_determinant_ratio():
+    P, U, Ud = _setup()
+    A, Ad = oracle.dense_normal(P, U), oracle.dense_normal(P, Ud)
+    M = oracle.herm_power(Ad, 0.25) @ oracle.herm_power(A, -0.5) @ oracle.herm_power(Ad, 0.25)
+    s, logdet_M = np.linalg.slogdet(M)
+    assert abs(s - 1) < 1e-10  # Hermitian positive definite
+    D = dense_matrix(lambda e: oracle.d5(P, U, e), P.full_shape())
+    Dd = dense_matrix(lambda e: oracle.d5(P, Ud, e), P.full_shape())
+    ratio = np.linalg.slogdet(Dd)[1] - np.linalg.slogdet(D)[1]
+    assert abs(logdet_M - ratio) < 1e-9 * max(1.0, abs(ratio)), (logdet_M, ratio)
+    assert abs(ratio) > 1.0  # the block cut changes the determinant visibly
+
+
+def test_matrix_powers():
+    P, U, Ud = _setup(L=(2, 2, 2, 4), Ls=3, mf=0.05, mask=(0, 0, 0, 1), seed=8)
+    A = oracle.dense_normal(P, U)
+    q = oracle.herm_power(A, 0.25)
+    assert np.linalg.norm(q @ q @ q @ q - A) < 1e-11 * np.linalg.norm(A)
+    h = oracle.herm_power(A, -0.5)
+    assert np.linalg.norm(h @ A @ h - np.eye(len(A))) < 1e-10
+
+
+@pytest.mark.parametrize("name,power", [("x0.25_0.01_100_n12.json", 0.25), ("x-0.5_0.01_100_n12.json", -0.5),
+                                        ("x0.25_1e-05_100_n20.json", 0.25), ("x-0.5_1e-05_100_n20.json", -0.5)])
+def test_rational_matches_power_on_the_spectrum(name, power):
+    r = load_rational(name)
+    assert r["power"] == power and len(r["alpha"]) == r["degree"] and min(r["beta"]) > 0
+    P, U, Ud = _setup()
+    for M in (oracle.dense_normal(P, U), oracle.dense_normal(P, Ud)):
+        lam, V = np.linalg.eigh(M)
+        assert r["lo"] <= lam[0] and lam[-1] <= r["hi"]
+        R = oracle.rational_dense(M, r["a0"], r["alpha"], r["beta"])
+        d = np.real(np.einsum("ij,ik,kj->j", V.conj(), R, V))  # eigenvalues of R on M's eigenvectors
+        rel = np.abs(d / lam ** power - 1)
+        assert rel.max() <= r["max_rel_error"] * (1 + 1e-6) + 1e-12
+        # the scalar function on a grid reaches its stated error (no looser file)
+        x = np.geomspace(r["lo"], r["hi"], 20001)
+        fx = r["a0"] + sum(a / (x + b) for a, b in zip(r["alpha"], r["beta"]))
+        assert np.abs(fx / x ** power - 1).max() <= r["max_rel_error"] * (1 + 1e-3)
+
+
+def action_bound(eq, em, lam_max_g, psi2):
+    """|S_r - S| for rational factors with relative spectral errors eq (the
+    quarter power, applied twice) and em (the minus-half power):
+    psi_r = (1 + Dq) psi with |Dq| <= eq and g_r = g (1 + Dm) with |Dm| <= em,
+    so |S_r - S| <= ((1 + eq)^2 (1 + em) - 1) |g| |psi|^2."""
+    return ((1 + eq) ** 2 * (1 + em) - 1) * lam_max_g * psi2
+
+
+def test_rational_action_within_its_bound():
+    rq, rm = load_rational("x0.25_0.01_100_n12.json"), load_rational("x-0.5_0.01_100_n12.json")
+    P, U, Ud = _setup()
+    phi = synth.gaussian_fermion(P.L, P.Ls, 9, nsites=P.V // 2)
+    S = oracle.ddrhmc_action(P, U, Ud, phi)
+    Sr = oracle.ddrhmc_action(P, U, Ud, phi, quarter=(rq["a0"], rq["alpha"], rq["beta"]),
+                              minus_half=(rm["a0"], rm["alpha"], rm["beta"]))
+    A, Ad = oracle.dense_normal(P, U), oracle.dense_normal(P, Ud)
+    psi = oracle.herm_power(Ad, 0.25) @ phi.ravel()
+    bound = action_bound(rq["max_rel_error"], rm["max_rel_error"], np.linalg.eigvalsh(A)[0] ** -0.5,
+                         np.vdot(psi, psi).real)
+    assert S > 0 and abs(Sr - S) <= bound, (S, Sr, bound)
