@@ -14,6 +14,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -27,6 +28,8 @@ namespace dwf {
 enum { S_RHO = 0, S_RHONEW = 1, S_PAP = 2, S_ALPHA = 3, S_BETA = 4, S_ONE = 5, S_TMP = 6, S_ALPHA1 = 7, S_DOT = 8 };
 // two more alpha slots of the CG direction ring, clear of the other solvers' slots
 enum { S_ALPHA2 = 250, S_ALPHA3 = 251 };
+// Re and Im of the DD-RHMC action's inner product
+enum { S_DD_DOT = 246 };
 static constexpr int CG_RING = 4;  // directions per pass of the solution update
 static constexpr int kAlphaSlot[CG_RING] = {S_ALPHA, S_ALPHA1, S_ALPHA2, S_ALPHA3};
 
@@ -384,22 +387,19 @@ struct DevBuf {
 
 }  // namespace dwf
 
-extern "C" dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *const *b_odd, int nshift,
-                                        const double *shifts, double *const *x_odd, const dwf_solver_opts *o,
-                                        dwf_solver_stats *st)
+namespace dwf {
+
+// Receives the FP64 solution of system (rhs j, shift k) in the internal layout
+// once it has met its tolerance (or the iteration limit); the field is reused
+// for the next system, so the sink consumes it on the stream before returning.
+using MsSink = std::function<void(int j, int k, Field x64)>;
+
+// Multi-shift CG on (Mpc^+ Mpc + shifts[k]) x_{j,k} = b_j for canonical FP64
+// odd fields b_odd[j] (device).  Arguments are validated by the caller.
+// Returns true when every system met the tolerance in FP64.
+static bool ms_solve(Context &c, int nrhs, const double *const *b_odd, int nshift, const double *shifts,
+                     const MsSink &sink, const dwf_solver_opts *o, dwf_solver_stats *st)
 {
-    DWF_API_BEGIN
-    if (!ctx) fail(DWF_EINVAL, "null context");
-    if (nrhs < 1 || nrhs > 64 || nshift < 1 || nshift > 64) fail(DWF_EINVAL, "need 1 <= nrhs, nshift <= 64");
-    if (!b_odd || !x_odd || !shifts) fail(DWF_EINVAL, "null pointer");
-    for (int k = 0; k < nshift; k++)
-        if (!(shifts[k] >= 0.0) || !std::isfinite(shifts[k])) fail(DWF_EINVAL, "shifts must be finite and >= 0");
-    for (int j = 0; j < nrhs; j++) {
-        if (!b_odd[j]) fail(DWF_EINVAL, "null right-hand side");
-        for (int k = 0; k < nshift; k++)
-            if (!x_odd[j * nshift + k]) fail(DWF_EINVAL, "null solution pointer");
-    }
-    dwf::Context &c = *ctx;
     double tol, delta;
     int maxit, mode;
     bool guess;
@@ -521,7 +521,7 @@ extern "C" dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *con
                     res = cs.rel_res;
                 }
             }
-            launch_export(c, P_F64, x64, x_odd[j * nshift + k], 0, 0);
+            sink(j, k, x64);
             const bool ok = res <= tol * 1.0000001;
             all_ok = all_ok && ok;
             if (st) {
@@ -542,7 +542,131 @@ extern "C" dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *con
             st[q].t_final = t2 - t1;
             st[q].seconds = t2 - t0;
         }
-    return all_ok ? DWF_OK : DWF_ENOCONV;
+    return all_ok;
+}
+
+static void check_shifts(int nshift, const double *shifts)
+{
+    for (int k = 0; k < nshift; k++)
+        if (!(shifts[k] >= 0.0) || !std::isfinite(shifts[k])) fail(DWF_EINVAL, "shifts must be finite and >= 0");
+}
+
+}  // namespace dwf
+
+extern "C" dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *const *b_odd, int nshift,
+                                        const double *shifts, double *const *x_odd, const dwf_solver_opts *o,
+                                        dwf_solver_stats *st)
+{
+    DWF_API_BEGIN
+    if (!ctx) fail(DWF_EINVAL, "null context");
+    if (nrhs < 1 || nrhs > 64 || nshift < 1 || nshift > 64) fail(DWF_EINVAL, "need 1 <= nrhs, nshift <= 64");
+    if (!b_odd || !x_odd || !shifts) fail(DWF_EINVAL, "null pointer");
+    check_shifts(nshift, shifts);
+    for (int j = 0; j < nrhs; j++) {
+        if (!b_odd[j]) fail(DWF_EINVAL, "null right-hand side");
+        for (int k = 0; k < nshift; k++)
+            if (!x_odd[j * nshift + k]) fail(DWF_EINVAL, "null solution pointer");
+    }
+    dwf::Context &c = *ctx;
+    auto sink = [&](int j, int k, Field x64) { launch_export(c, P_F64, x64, x_odd[j * nshift + k], 0, 0); };
+    if (!ms_solve(c, nrhs, b_odd, nshift, shifts, sink, o, st)) return DWF_ENOCONV;
+    DWF_API_END
+}
+
+// ------------------------------------------------------- rational functions
+//
+// r(A) v = a0 v + sum_k alpha_k (A + beta_k)^-1 v with A = Mpc^+ Mpc: one
+// multi-shift solve with the shifts beta_k, the solutions summed on the
+// device as they are produced.  The one-flavour actions of DD-RHMC apply the
+// fractional powers x^{1/4} and x^{-1/2} of the normal operators this way
+// (Sec. 2.3.1).
+
+namespace dwf {
+
+static void check_rational(const dwf_rational *r)
+{
+    if (!r || !r->alpha || !r->beta) fail(DWF_EINVAL, "null rational function");
+    if (r->n < 1 || r->n > 64) fail(DWF_EINVAL, "rational function needs 1 <= n <= 64 poles");
+    if (!std::isfinite(r->a0)) fail(DWF_EINVAL, "non-finite a0");
+    for (int k = 0; k < r->n; k++)
+        if (!std::isfinite(r->alpha[k])) fail(DWF_EINVAL, "non-finite alpha");
+    check_shifts(r->n, r->beta);
+}
+
+// acc = r(A) in, with in a canonical FP64 odd field and acc an internal FP64
+// field; st (may be NULL) gets the worst system's statistics.
+static bool rational_core(Context &c, const dwf_rational *r, const double *in_odd, Field acc,
+                          const dwf_solver_opts *o, dwf_solver_stats *st)
+{
+    launch_import(c, P_F64, in_odd, acc, 0, 0);
+    launch_axpby(c, P_F64, r->a0, acc, 0.0, acc, acc);
+    auto sink = [&](int, int k, Field x64) { launch_axpby(c, P_F64, 1.0, acc, r->alpha[k], x64, acc); };
+    std::vector<dwf_solver_stats> per(r->n);
+    const bool ok = ms_solve(c, 1, &in_odd, r->n, r->beta, sink, o, per.data());
+    if (st) {
+        dwf_solver_stats w = per[0];
+        int conv = 1;
+        for (const auto &s : per) {
+            if (s.iters > w.iters) w = s;
+            conv = conv && s.converged;
+        }
+        w.converged = conv;
+        *st = w;
+    }
+    return ok;
+}
+
+}  // namespace dwf
+
+extern "C" dwf_status dwf_rational_apply(dwf_ctx ctx, const dwf_rational *r, const double *in_odd, double *out_odd,
+                                         const dwf_solver_opts *o, dwf_solver_stats *st)
+{
+    DWF_API_BEGIN
+    if (!ctx) fail(DWF_EINVAL, "null context");
+    if (!in_odd || !out_odd) fail(DWF_EINVAL, "null field pointer");
+    check_rational(r);
+    dwf::Context &c = *ctx;
+    Field acc = ws_field(c, "ra_acc", P_F64);
+    const bool ok = rational_core(c, r, in_odd, acc, o, st);
+    launch_export(c, P_F64, acc, out_odd, 0, 0);
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    if (!ok) return DWF_ENOCONV;
+    DWF_API_END
+}
+
+// S = phi^+ r_q(A_d) r_m(A) r_q(A_d) phi = <psi, r_m(A) psi>, psi = r_q(A_d) phi
+// (r_q(A_d) is Hermitian).  psi passes from the Dirichlet context to the other
+// in the canonical layout, in a workspace field of the Dirichlet context.
+extern "C" dwf_status dwf_ddrhmc_action(dwf_ctx ctx, dwf_ctx ctx_dirichlet, const dwf_rational *r_quarter,
+                                        const dwf_rational *r_minus_half, const double *phi_odd,
+                                        const dwf_solver_opts *o, double *action, dwf_solver_stats *st)
+{
+    DWF_API_BEGIN
+    if (!ctx || !ctx_dirichlet) fail(DWF_EINVAL, "null context");
+    if (!phi_odd || !action) fail(DWF_EINVAL, "null pointer");
+    check_rational(r_quarter);
+    check_rational(r_minus_half);
+    dwf::Context &c = *ctx, &cd = *ctx_dirichlet;
+    for (int mu = 0; mu < 4; mu++)
+        if (c.L[mu] != cd.L[mu]) fail(DWF_EINVAL, "contexts of different lattices");
+    if (c.Ls != cd.Ls || c.p.b != cd.p.b || c.p.c != cd.p.c || c.p.M5 != cd.p.M5 || c.p.mf != cd.p.mf)
+        fail(DWF_EINVAL, "contexts of different operator parameters");
+    if (c.device != cd.device) fail(DWF_EINVAL, "contexts on different devices");
+    // psi = r_q(A_d) phi, exported to a canonical buffer that the other context reads
+    Field accd = ws_field(cd, "ra_acc", P_F64);
+    Field canon = ws_field(cd, "dd_psi", P_F64);
+    const bool ok1 = rational_core(cd, r_quarter, phi_odd, accd, o, st);
+    launch_export(cd, P_F64, accd, (double *)canon.data, 0, 0);
+    HIPCHECK(hipStreamSynchronize(cd.stream));
+    // chi = r_m(A) psi ; S = Re <psi, chi>
+    Field acc = ws_field(c, "ra_acc", P_F64), psi = ws_field(c, "dd_psi_in", P_F64);
+    const bool ok2 = rational_core(c, r_minus_half, (const double *)canon.data, acc, o, st ? st + 1 : nullptr);
+    launch_import(c, P_F64, (const double *)canon.data, psi, 0, 0);
+    const int np = launch_dot(c, P_F64, psi, acc);
+    launch_finish(c, np, 2, S_DD_DOT);
+    read_scalars(c, S_DD_DOT, 2);
+    *action = c.hscal[S_DD_DOT];
+    if (!(ok1 && ok2)) return DWF_ENOCONV;
     DWF_API_END
 }
 

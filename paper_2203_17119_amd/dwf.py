@@ -51,6 +51,24 @@ class DWFError(RuntimeError):
         self.status = status
 
 
+class dwf_rational(C.Structure):
+    _fields_ = [("n", C.c_int), ("a0", C.c_double), ("alpha", C.POINTER(C.c_double)),
+                ("beta", C.POINTER(C.c_double))]
+
+
+def make_rational(a0, alpha, beta):
+    """A dwf_rational r(x) = a0 + sum_k alpha[k] / (x + beta[k]); the returned
+    object keeps its coefficient arrays alive."""
+    n = len(alpha)
+    if len(beta) != n:
+        raise ValueError("alpha and beta differ in length")
+    al = (C.c_double * n)(*[float(a) for a in alpha])
+    be = (C.c_double * n)(*[float(b) for b in beta])
+    r = dwf_rational(n, float(a0), al, be)
+    r._keep = (al, be)
+    return r
+
+
 class dwf_adam(C.Structure):
     _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
 
@@ -81,6 +99,10 @@ SIGNATURES = {
     "dwf_cg": ([_CTX, _P, _P, C.POINTER(dwf_solver_opts), C.POINTER(dwf_solver_stats)], C.c_int32),
     "dwf_multishift_cg": ([_CTX, _I, C.POINTER(_P), _I, C.POINTER(_D), C.POINTER(_P),
                            C.POINTER(dwf_solver_opts), C.POINTER(dwf_solver_stats)], C.c_int32),
+    "dwf_rational_apply": ([_CTX, C.POINTER(dwf_rational), _P, _P, C.POINTER(dwf_solver_opts),
+                            C.POINTER(dwf_solver_stats)], C.c_int32),
+    "dwf_ddrhmc_action": ([_CTX, _CTX, C.POINTER(dwf_rational), C.POINTER(dwf_rational), _P,
+                           C.POINTER(dwf_solver_opts), C.POINTER(_D), C.POINTER(dwf_solver_stats)], C.c_int32),
     "dwf_chebyshev_filter": ([_CTX, _I, _P, _D, _D, _I, C.POINTER(_I), C.POINTER(_P)], C.c_int32),
     "dwf_net_create": ([_CTX, _I, C.POINTER(_I), C.POINTER(_NET)], C.c_int32),
     "dwf_net_destroy": ([_NET], C.c_int32),
@@ -254,6 +276,25 @@ def dwf_multishift_cg(ctx, b_odd, shifts, x_odd, **opts):
     st = (dwf_solver_stats * (nrhs * ns))()
     s = _check(load().dwf_multishift_cg(ctx, nrhs, bp, ns, sh, xp, C.byref(o), st), allow=(DWF_ENOCONV,))
     return s, [x.asdict() for x in st]
+
+
+def dwf_rational_apply(ctx, r, in_odd, out_odd, **opts):
+    """out = r(A) in, A = Mpc^+ Mpc; r from make_rational.  Returns (status, stats of the worst shift)."""
+    o = _opts(**opts)
+    st = dwf_solver_stats()
+    s = _check(load().dwf_rational_apply(ctx, C.byref(r), _ptr(in_odd), _ptr(out_odd), C.byref(o), C.byref(st)),
+               allow=(DWF_ENOCONV,))
+    return s, st.asdict()
+
+
+def dwf_ddrhmc_action(ctx, ctx_dirichlet, r_quarter, r_minus_half, phi_odd, **opts):
+    """S = phi^+ r_q(A_d) r_m(A) r_q(A_d) phi.  Returns (status, S, [stats of r_q, stats of r_m])."""
+    o = _opts(**opts)
+    st = (dwf_solver_stats * 2)()
+    S = C.c_double()
+    s = _check(load().dwf_ddrhmc_action(ctx, ctx_dirichlet, C.byref(r_quarter), C.byref(r_minus_half),
+                                        _ptr(phi_odd), C.byref(o), C.byref(S), st), allow=(DWF_ENOCONV,))
+    return s, S.value, [x.asdict() for x in st]
 
 
 def dwf_chebyshev_filter(ctx, v_odd, lo, hi, orders, out_odd, prec=DWF_F64):
