@@ -153,12 +153,13 @@ def test_action_argument_errors(pair):
 def test_inverse_square_root_squared_at_8x8x8x8_ls8():
     """At a size the dense oracle cannot reach: A r_m(A)^2 v = v.  With
     r_m(l) = l^{-1/2} (1 + d), |d| <= eps on the spectrum (the n = 20
-    approximation on [1e-5, 100]), y = r_m(A) v + d1 and z = r_m(A) y + d2,
+    approximation on [1e-5, 1000]), y = r_m(A) v + d1 and z = r_m(A) y + d2,
         A z - v = (A r_m(A)^2 - 1) v + A r_m(A) d1 + A d2,
     so |A z - v| <= (2 eps + eps^2) |v| + tol S0 (sqrt(top) (1 + eps) |v| + top |y|)
     with S0 = sum_k |alpha_k| / beta_k and top the spectrum's upper end
-    (bounded by oracle power steps)."""
-    r = load_rational("x-0.5_1e-05_100_n20.json")
+    (estimated by oracle power steps, with a margin of 1.5; the
+    approximation's interval reaches ten times further)."""
+    r = load_rational("x-0.5_1e-05_1000_n20.json")
     c = Case((8, 8, 8, 8), 8, mf=0.02, dirichlet=(1, 1, 1, 1), eps=0.7, seed=41)
     print("\n[ddrhmc 8x8x8x8_ls8 dirichlet]", flush=True)
     try:
@@ -168,7 +169,7 @@ def test_inverse_square_root_squared_at_8x8x8x8_ls8():
             w = oracle.mpc(c.P, c.Ud, oracle.mpc(c.P, c.Ud, w), True)
             top = np.linalg.norm(w)
             w = w / top
-        top *= 1.2
+        top *= 1.5
         assert top < r["hi"]
         tol = 1e-11
         rm = dwf.make_rational(*coeffs(r))
