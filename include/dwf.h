@@ -120,6 +120,20 @@ dwf_status dwf_mooeeinv(dwf_ctx ctx, int dagger, const double *in_half, double *
 dwf_status dwf_schur_apply(dwf_ctx ctx, int dagger, const double *in_odd, double *out_odd);
 /* Same on internal odd fields of precision prec; in and out must differ. */
 dwf_status dwf_schur_apply_internal(dwf_ctx ctx, int prec, int dagger, const void *in, void *out);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same operator
+ * and the same kernels as dwf_schur_apply_internal, with the intermediate
+ * fields in a fixed device array of 128 MiB per device instead of context
+ * workspaces, and no allocation of any kind (kernel timing is off for the
+ * call).  The array holds two intermediate fields of precision prec (one for
+ * dagger = 1): DWF_EINVAL when batch-aligned field bytes exceed that (e.g.
+ * FP64 beyond about 350k odd 5D sites).  The links of prec must already be
+ * prepared (FP64 always is; other precisions after any earlier operator or
+ * solver call in that precision), else DWF_EINVAL.  Every call on one device
+ * shares the array: calls that overlap on one device (different streams or
+ * host threads) race and must be serialised by the caller; nothing in the
+ * array needs to start at zero. */
+dwf_status dwf_schur_apply_internal_noalloc(dwf_ctx ctx, int prec, int dagger, const void *in, void *out);
 
 /* --------------------------------------------------------------- solvers */
 

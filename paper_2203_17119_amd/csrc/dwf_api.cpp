@@ -298,12 +298,13 @@ Field ws_batch(Context &c, const std::string &name, int prec, int nbatch)
 }
 
 int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduce, bool in_is_A_applied, Field pa,
-              int nbatch, long bstride, int alpha_slot)
+              int nbatch, long bstride, int alpha_slot, Field ws_ta, Field ws_y)
 {
     if (alpha_slot >= 0 && (!dagger || nbatch > 1)) fail(DWF_EINVAL, "fused residual update needs Mpc^+, one field");
     ensure_links(c, prec);
     const int nb = std::max(1, nbatch);
-    Field y = ws_batch(c, "mpc_y", prec, nb);
+    if ((ws_y.data || ws_ta.data) && nb > 1) fail(DWF_EINVAL, "caller workspaces hold one field");
+    Field y = ws_y.data ? ws_y : ws_batch(c, "mpc_y", prec, nb);
     if (nb > 1 && bstride != batch_stride(c, prec)) fail(DWF_EINVAL, "batched fields must use the batch stride");
     auto batched = [&](StencilSpec &s) {
         s.nbatch = nb;
@@ -312,7 +313,7 @@ int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduc
     if (!dagger) {
         Field ta = pa;
         if (!in_is_A_applied) {
-            ta = ws_batch(c, "mpc_ta", prec, nb);
+            ta = ws_ta.data ? ws_ta : ws_batch(c, "mpc_ta", prec, nb);
             launch_slocal(c, prec, SL_A, in, ta, nb, bstride);
         }
         StencilSpec s1;
@@ -442,6 +443,7 @@ dwf_status dwf_create(const dwf_params *p, const double *gauge, int gauge_on_dev
         c->e = p->c * (4.0 - p->M5) - 1.0;
         c->stream = (hipStream_t)stream;
         HIPCHECK(hipGetDevice(&c->device));
+        scratch_init(c->device);
         {
             int lds = 0;
             HIPCHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));

@@ -310,6 +310,10 @@ void launch_accumulate_low(Context &c, int prec, Field xh, Field xl);
 void launch_ms_update(Context &c, int prec, int nshift, Field *x, Field *p, Field r, const double *coef_dev,
                       const int *active_host);
 
+// resolve the device address of the fixed scratch array on `device` (the
+// current device); called once per context creation
+void scratch_init(int device);
+
 void read_scalars(Context &c, int first, int count);  // dscal -> hscal, synchronising
 void launch_stream_copy(Context &c, const void *src, void *dst, size_t bytes);
 
@@ -319,9 +323,12 @@ void launch_stream_copy(Context &c, const void *src, void *dst, size_t bytes);
 // precision; if reduce, partials of |out|^2 are written and their count returned.
 // With dagger and alpha_slot >= 0 the result is not stored: out holds a
 // residual r on entry and becomes r - dscal[alpha_slot] Mpc^+ in, with the
-// partials of its |r|^2 (reduce implied).
+// partials of its |r|^2 (reduce implied).  The intermediate fields are
+// context workspaces unless ws_ta and ws_y (one field each) are given; ws_ta
+// is needed only when in_is_A_applied is false and dagger is not set.
 int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduce, bool in_is_A_applied = false,
-              Field pa = Field{}, int nbatch = 1, long bstride = 0, int alpha_slot = -1);
+              Field pa = Field{}, int nbatch = 1, long bstride = 0, int alpha_slot = -1, Field ws_ta = Field{},
+              Field ws_y = Field{});
 
 }  // namespace dwf
 

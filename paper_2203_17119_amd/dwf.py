@@ -96,6 +96,7 @@ SIGNATURES = {
     "dwf_mooeeinv": ([_CTX, _I, _P, _P], C.c_int32),
     "dwf_schur_apply": ([_CTX, _I, _P, _P], C.c_int32),
     "dwf_schur_apply_internal": ([_CTX, _I, _I, _P, _P], C.c_int32),
+    "dwf_schur_apply_internal_noalloc": ([_CTX, _I, _I, _P, _P], C.c_int32),
     "dwf_cg": ([_CTX, _P, _P, C.POINTER(dwf_solver_opts), C.POINTER(dwf_solver_stats)], C.c_int32),
     "dwf_multishift_cg": ([_CTX, _I, C.POINTER(_P), _I, C.POINTER(_D), C.POINTER(_P),
                            C.POINTER(dwf_solver_opts), C.POINTER(dwf_solver_stats)], C.c_int32),
@@ -249,6 +250,10 @@ def dwf_schur_apply(ctx, dagger, in_odd, out_odd):
 
 def dwf_schur_apply_internal(ctx, prec, dagger, inp, out):
     _check(load().dwf_schur_apply_internal(ctx, int(prec), int(dagger), _ptr(inp), _ptr(out)))
+
+
+def dwf_schur_apply_internal_noalloc(ctx, prec, dagger, inp, out):
+    _check(load().dwf_schur_apply_internal_noalloc(ctx, int(prec), int(dagger), _ptr(inp), _ptr(out)))
 
 
 def _opts(tol=1e-8, maxit=0, mode=DWF_SOLVE_F64, delta=0.0, x0_is_guess=False, restart=0, normal=False,
