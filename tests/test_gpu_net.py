@@ -269,9 +269,10 @@ def test_trained_network_gain_over_plain_gcr():
     field: FGCR with the network must reach 1e-8 in the FP64 full residual,
     checked by the oracle's D5, in fewer steps than plain GCR needs (or where
     plain GCR stagnates).  Plain FP64 CG, the method without the network and
-    the judge of it, solves the same source to the same target; both must
-    converge, and its count and time are set beside the network's (the
-    comparison is measured, whatever its outcome)."""
+    the judge of it, solves the same source to the same target.  The network
+    must save operator applications against CG (one Mpc per FGCR step, two
+    per CG iteration); wall time is set beside it and not asserted: each
+    network application costs several Mpc."""
     import os
     path = os.path.join(os.path.dirname(dwf.__file__), "weights", "ptc_4-12-12-12-4_8x8x8x8_ls8.npz")
     data = np.load(path)
@@ -300,6 +301,9 @@ def test_trained_network_gain_over_plain_gcr():
         r = b - oracle.d5(c.P, c.Ud, to_host(x))
         assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-7
         assert s0 != dwf.DWF_OK or st1["iters"] < 0.7 * st0["iters"]
+        print(f"against FP64 CG: Mpc applications {st1['iters']} vs {2 * st_cg['iters']}, "
+              f"time {st1['seconds']:.3f} s vs {st_cg['seconds']:.3f} s", flush=True)
+        assert st1["iters"] < 2 * st_cg["iters"]
         # FP32 cycles with FP64 restarts and the matrix-core forward reach the same FP64 residual
         dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_MFMA_BF16)
         x.zero_()

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_2203_17119_amd import dwf
-from gpu_helpers import TOL, Case, relerr, to_gpu, to_host, torch
+from gpu_helpers import SITE_TOL, TOL, Case, relerr, site_relerr, to_gpu, to_host, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -84,11 +84,21 @@ def test_internal_precisions(case, prec):
     for out_parity, dagger in [(0, 0), (1, 1)]:
         dwf.dwf_dhop_internal(case.ctx, prec, out_parity, dagger, xin, xout)
         dwf.dwf_export(case.ctx, 0, prec, xout, back)
-        assert relerr(to_host(back), case.oracle_dhop(x, out_parity, bool(dagger))) < TOL[prec]
+        expect = case.oracle_dhop(x, out_parity, bool(dagger))
+        got = to_host(back)
+        print(f"prec {prec} dhop: global {relerr(got, expect):.2e}, worst site {site_relerr(got, expect):.2e}",
+              flush=True)
+        assert relerr(got, expect) < TOL[prec]
+        assert site_relerr(got, expect) < SITE_TOL[prec]
     for dagger in (0, 1):
         dwf.dwf_schur_apply_internal(case.ctx, prec, dagger, xin, xout)
         dwf.dwf_export(case.ctx, 0, prec, xout, back)
-        assert relerr(to_host(back), oracle.mpc(case.P, case.Ud, x, bool(dagger))) < TOL[prec]
+        expect = oracle.mpc(case.P, case.Ud, x, bool(dagger))
+        got = to_host(back)
+        print(f"prec {prec} Mpc dagger {dagger}: global {relerr(got, expect):.2e}, "
+              f"worst site {site_relerr(got, expect):.2e}", flush=True)
+        assert relerr(got, expect) < TOL[prec]
+        assert site_relerr(got, expect) < SITE_TOL[prec]
 
 
 def test_dhop_16x16x16x16_ls12_dirichlet():
