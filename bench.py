@@ -22,7 +22,11 @@ Printed JSON line:
   time_to_1e-8   FP64 CG vs the chosen mixed form and vs FGCR with the trained
                  network preconditioner, on the same source
   dhop           standalone Dhop GB/s and GFLOP/s per storage precision
-  copy           stream-copy bandwidth, the achievable-HBM reference
+  copy           stream-copy bandwidth; bandwidth_probes: copy, read-only and
+                 2-read/1-write streams, the best of several loads in flight
+                 and non-temporal variants (the last is the roofline's ceiling)
+  c5_...         the learned preconditioner's 24^4 x 12 periodic lattice:
+                 FP64 CG, mixed CG and FGCR + network, median of 3 each
   cpu_baseline   the FP64 oracle's Wilson hop on this lattice, host cores
 """
 from __future__ import annotations
@@ -142,6 +146,60 @@ def copy_bandwidth(lat, dwf, torch, nbytes=1 << 31, reps=5):
             "GB/s": round(st["bytes"] / st["ms"] / 1e6, 1)}
 
 
+PROBE_KINDS = {0: "copy", 1: "read", 2: "read2_write1"}
+
+
+def bandwidth_ceiling(lat, dwf, torch, nbytes=1 << 31, reps=5):
+    """Achievable HBM bandwidth: the library's streaming probes (copy, read-only,
+    and two streams read per stream written, the hop's mix) over 1, 2, 4 and 8
+    16-byte loads in flight per lane, plain and non-temporal, 2 GiB per stream;
+    the best of each kind, and torch's own copy on the same buffers for
+    comparison.  Bytes counted = read + written."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    d = torch.empty_like(a)
+    a.fill_(1)
+    b.fill_(2)
+    out = {}
+    for kind, name in PROBE_KINDS.items():
+        rows = []
+        for unroll in (1, 2, 4, 8):
+            for nt in (0, 1):
+                dwf.dwf_stream_probe(lat.ctx, kind, unroll, nt, a, b, d, nbytes)
+                dwf.dwf_kernel_timing_reset(lat.ctx)
+                dwf.dwf_kernel_timing(lat.ctx, 1)
+                for _ in range(reps):
+                    dwf.dwf_stream_probe(lat.ctx, kind, unroll, nt, a, b, d, nbytes)
+                st = dwf.dwf_kernel_stats(lat.ctx, dwf.DWF_K_BLAS)
+                dwf.dwf_kernel_timing(lat.ctx, 0)
+                rows.append({"unroll": unroll, "nontemporal": nt, "ms": round(st["ms"] / st["launches"], 4),
+                             "GB/s": round(st["bytes"] / st["ms"] / 1e6, 1)})
+        best = max(rows, key=lambda r: r["GB/s"])
+        out[name] = {"GB/s": best["GB/s"], "unroll": best["unroll"], "nontemporal": best["nontemporal"],
+                     "configs": rows}
+    # torch's copy on the same buffers, timed with events on torch's stream
+    d.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        d.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out["torch_copy"] = {"GB/s": round(2 * nbytes / ms / 1e6, 1), "ms": round(ms, 4)}
+    del a, b, d
+    torch.cuda.empty_cache()
+    return out
+
+
+def timed_solves(fn, reps=3):
+    """Median over reps of fn() -> (status, stats), after fn's own warm-up."""
+    runs = [fn() for _ in range(reps)]
+    secs = sorted(r[1]["seconds"] for r in runs)
+    med = secs[len(secs) // 2]
+    return med, runs
+
+
 def stencil_source_hash():
     h = hashlib.sha256()
     for f in STENCIL_SOURCES:
@@ -230,7 +288,8 @@ def chebyshev(lat, dwf, synth, torch, w, prec):
             "norm_ratio": [round(float(o.norm()) / vn, 3) for o in outs]}
 
 
-def learned_precond(lat, dwf, torch, b, tol, restart=16, maxit=2000, mfma=True, mode=None, weights=WEIGHTS):
+def learned_precond(lat, dwf, torch, b, tol, restart=16, maxit=2000, mfma=True, mode=None, weights=WEIGHTS,
+                    fallback=True):
     """FGCR(restart) on the Schur system, right-preconditioned by the trained
     network (matrix-core or FP32 forward), to tol in the FP64 full residual
     (CG fallback on stagnation)."""
@@ -244,7 +303,8 @@ def learned_precond(lat, dwf, torch, b, tol, restart=16, maxit=2000, mfma=True, 
         dwf.dwf_kernel_timing_reset(lat.ctx)
         dwf.dwf_kernel_timing(lat.ctx, 1)
         mode = dwf.DWF_SOLVE_MIXED_BF16 if mode is None else mode
-        s, st = dwf.dwf_fgcr(lat.ctx, net, b, x, tol=tol, restart=restart, maxit=maxit, fallback=True, mode=mode)
+        s, st = dwf.dwf_fgcr(lat.ctx, net, b, x, tol=tol, restart=restart, maxit=maxit, fallback=fallback,
+                             mode=mode)
         kn = dwf.dwf_kernel_stats(lat.ctx, dwf.DWF_K_NET)
         dwf.dwf_kernel_timing(lat.ctx, 0)
     finally:
@@ -261,19 +321,30 @@ def learned_precond(lat, dwf, torch, b, tol, restart=16, maxit=2000, mfma=True, 
 
 def cpu_baseline(w, U, b_full, cg_iters):
     """FP64 oracle on the host cores, same lattice and field: one Wilson hop
-    (both parities, all s) for the bandwidth figure, and one application of
-    the normal operator Mpc^+ Mpc, which times the oracle's CG iteration; its
-    time to 1e-8 is extrapolated with the GPU FP64 iteration count."""
+    (both parities, all s), median of 3 on every core and once on one core,
+    for the bandwidth figure, and one application of the normal operator
+    Mpc^+ Mpc, which times the oracle's CG iteration; its time to 1e-8 is
+    extrapolated with the GPU FP64 iteration count."""
     import oracle
 
     P = oracle.Params(w.dims, w.Ls, w.b, w.c, w.M5, w.mf)
     Ud = oracle.dirichlet(w.dims, U, w.dirichlet)
-    t0 = time.perf_counter()
-    oracle.hop(P, Ud, b_full)
-    dt = time.perf_counter() - t0
+    cores = oracle.num_threads()
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.hop(P, Ud, b_full)
+        times.append(time.perf_counter() - t0)
+    dt = sorted(times)[1]
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.hop(P, Ud, b_full)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(cores)
     n5 = P.V * P.Ls  # a full-lattice hop = two half-lattice Dhop calls
     bytes_alg = n5 * 480.0
-    cores = oracle.num_threads()
     odd = oracle.pick(P, b_full, 1)
     t1 = time.perf_counter()
     oracle.mpc(P, Ud, oracle.mpc(P, Ud, odd), True)
@@ -284,12 +355,61 @@ def cpu_baseline(w, U, b_full, cg_iters):
         "cores": cores,
         "kind": "oracle",
         "sample": f"one FP64 Wilson hop over the full {'x'.join(map(str, w.dims))}x{w.Ls} lattice "
-                  f"(both parities, all s), {dt:.2f} s; algorithmic bytes 480 B per 5D site",
+                  f"(both parities, all s), median of 3, {dt:.2f} s; algorithmic bytes 480 B per 5D site",
         "seconds": round(dt, 3),
         "gflops": round(n5 * 1320.0 / dt / 1e9, 3),
+        "one_thread": {"seconds": round(dt1, 3), "GB/s": round(bytes_alg / dt1 / 1e9, 3),
+                       "gflops": round(n5 * 1320.0 / dt1 / 1e9, 3)},
         "normal_op_seconds": round(dt_op, 3),
         "cg_f64_time_to_1e-8_extrapolated_s": round(dt_op * cg_iters, 1),
     }
+
+
+def c5_comparison(dwf, synth, torch, tune_cache, reps=3):
+    """The learned preconditioner's deployment lattice, 24^4 x 12 periodic
+    (mf 0.01, eps 0.7), source 2020: FP64 CG, mixed CG in FP32 and FP16
+    storage, and FGCR(32) with the trained 4-12-12-12-4 network (matrix-core
+    forward, BF16 Krylov basis), each to 1e-8; median of reps solves after a
+    short warm-up solve that allocates the workspaces; the FP64 full residual
+    each reached is reported beside its time."""
+    w = synth.WORKLOADS["24^4x12_fgcr"]
+    U = synth.gauge_field(w.dims, w.eps, w.gauge_seed)
+    lat = dwf.Lattice(w.dims, w.Ls, w.b, w.c, w.M5, w.mf, w.dirichlet, gauge=U)
+    del U
+    data = np.load(WEIGHTS)
+    net = dwf.dwf_net_create(lat.ctx, [int(v) for v in data["chans"]])
+    out = {"workload": "24^4x12_fgcr: 24^4 x Ls=12 Moebius mf=0.01, periodic, SU(3) eps=0.7, source 2020"}
+    try:
+        dwf.dwf_net_set_weights(net, data["weights"])
+        dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_MFMA_BF16)
+        b = torch.from_numpy(synth.gaussian_fermion(w.dims, w.Ls, w.source_seeds[0])).cuda()
+        x = torch.zeros_like(b)
+        dwf.dwf_tune(lat.ctx, dwf.DWF_F16, tune_cache)
+
+        def cg(mode, maxit=0):
+            x.zero_()
+            return dwf.dwf_cg(lat.ctx, b, x, tol=w.tol, mode=mode, maxit=maxit)
+
+        def fgcr(maxit=3000):
+            x.zero_()
+            return dwf.dwf_fgcr(lat.ctx, net, b, x, tol=w.tol, restart=32, maxit=maxit, fallback=False,
+                                mode=dwf.DWF_SOLVE_MIXED_BF16)
+
+        legs = {"f64_cg": lambda: cg(dwf.DWF_SOLVE_F64), "mixed_f32_cg": lambda: cg(dwf.DWF_SOLVE_MIXED_F32),
+                "mixed_f16_cg": lambda: cg(dwf.DWF_SOLVE_MIXED_F16), "fgcr32_learned": fgcr}
+        warm = {"f64_cg": lambda: cg(dwf.DWF_SOLVE_F64, 20), "mixed_f32_cg": lambda: cg(dwf.DWF_SOLVE_MIXED_F32, 20),
+                "mixed_f16_cg": lambda: cg(dwf.DWF_SOLVE_MIXED_F16, 20), "fgcr32_learned": lambda: fgcr(40)}
+        for name, fn in legs.items():
+            warm[name]()
+            med, runs = timed_solves(fn, reps)
+            out[name] = {"seconds_median": round(med, 4), "seconds": [round(r[1]["seconds"], 4) for r in runs],
+                         "status": [r[0] for r in runs], "iters": runs[0][1]["iters"],
+                         "res_full": max(r[1]["res_full"] for r in runs)}
+            log(f"24^4x12 {name}: {out[name]}")
+    finally:
+        dwf.dwf_net_destroy(net)
+        lat.close()
+    return out
 
 
 def main():
@@ -307,6 +427,8 @@ def main():
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the FGCR solve with the trained network preconditioner")
     ap.add_argument("--no-multishift", action="store_true", help="skip the batched multi-shift solve")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the 24^4 x 12 periodic comparison (FP64 CG, mixed CG, FGCR + network)")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
                     help="autotuner record to read and append to; an empty string tunes afresh")
     ap.add_argument("--chebyshev", action="store_true",
@@ -329,7 +451,8 @@ def main():
     lat = dwf.Lattice(w.dims, w.Ls, w.b, w.c, w.M5, w.mf, w.dirichlet, gauge=U)
     lowp = {1: dwf.DWF_F32, 2: dwf.DWF_F16, 3: dwf.DWF_BF16}.get(args.mode, dwf.DWF_F64)
     if args.kernels_only:
-        out = {"copy": copy_bandwidth(lat, dwf, torch), "dhop": dhop_table(lat, dwf, torch, reps=5)}
+        out = {"copy": copy_bandwidth(lat, dwf, torch), "ceiling": bandwidth_ceiling(lat, dwf, torch),
+               "dhop": dhop_table(lat, dwf, torch, reps=5)}
         if args.sweep:
             out["sweep"] = schedule_sweep(lat, dwf, torch)
         print(json.dumps(out), flush=True)
@@ -346,8 +469,10 @@ def main():
             del b
     log(f"{len(srcs)} sources resident, setup {time.time() - t0:.1f}s")
     x = torch.zeros_like(srcs[0])
-    copy = copy_bandwidth(lat, dwf, torch)
-    log(f"stream copy {copy['GB/s']} GB/s")
+    ceiling = bandwidth_ceiling(lat, dwf, torch)
+    copy = {k: ceiling["copy"][k] for k in ("GB/s", "unroll", "nontemporal")}
+    log(f"bandwidth probes: copy {ceiling['copy']['GB/s']}, read {ceiling['read']['GB/s']}, "
+        f"2 reads : 1 write {ceiling['read2_write1']['GB/s']}, torch copy {ceiling['torch_copy']['GB/s']} GB/s")
     # tile schedule of the chosen storage precision, picked by the autotuner (untimed)
     tune_cache = args.tune_cache or None
     dwf.dwf_tune(lat.ctx, lowp, tune_cache)
@@ -355,10 +480,17 @@ def main():
              "slocal": dwf.dwf_get_tile_schedule(lat.ctx, dwf.DWF_K_SLOCAL)}
     log(f"tuned schedule {sched}")
 
-    # plain FP64 CG (reference leg of the metric)
-    torch.cuda.synchronize()
-    s64, st64 = dwf.dwf_cg(lat.ctx, srcs[0], x, tol=w.tol, mode=dwf.DWF_SOLVE_F64)
-    log(f"fp64 cg: {st64['iters']} iters, {st64['seconds']:.3f}s, res_full {st64['res_full']:.2e}")
+    # plain FP64 CG (reference leg of the metric): a short solve allocates its
+    # workspaces, then the median of three full solves
+    def cg64(maxit=0):
+        x.zero_()
+        return dwf.dwf_cg(lat.ctx, srcs[0], x, tol=w.tol, mode=dwf.DWF_SOLVE_F64, maxit=maxit)
+
+    cg64(20)
+    t64, runs64 = timed_solves(cg64)
+    st64 = runs64[0][1]
+    log(f"fp64 cg: {st64['iters']} iters, median {t64:.3f}s of {[round(r[1]['seconds'], 3) for r in runs64]}, "
+        f"res_full {st64['res_full']:.2e}")
 
     # warmup of the chosen form
     for i in range(args.warmup):
@@ -390,9 +522,19 @@ def main():
 
     lp = None
     if not args.no_precond:
-        lp = learned_precond(lat, dwf, torch, srcs[0], w.tol, mfma=True)
+        def fgcr_leg(weights):
+            learned_precond(lat, dwf, torch, srcs[0], w.tol, weights=weights, maxit=20, fallback=False)
+            runs = [learned_precond(lat, dwf, torch, srcs[0], w.tol, weights=weights) for _ in range(3)]
+            med = sorted(r["seconds"] for r in runs)[1]
+            out = dict(runs[0])
+            out["seconds"] = med
+            out["seconds_runs"] = [r["seconds"] for r in runs]
+            out["res_full"] = max(r["res_full"] for r in runs)
+            return out
+
+        lp = fgcr_leg(WEIGHTS)
         log(f"learned preconditioner: {lp}")
-        lp["compact_network"] = learned_precond(lat, dwf, torch, srcs[0], w.tol, weights=WEIGHTS_COMPACT)
+        lp["compact_network"] = fgcr_leg(WEIGHTS_COMPACT)
         log(f"learned preconditioner, compact network: {lp['compact_network']}")
     cheb = None
     if args.chebyshev:
@@ -408,10 +550,18 @@ def main():
         ms = {"mixed_f32": multishift(dwf, synth, torch, dwf.DWF_SOLVE_MIXED_F32, tune_cache),
               "f64": multishift(dwf, synth, torch, dwf.DWF_SOLVE_F64, tune_cache)}
         log(f"multishift: {ms}")
+    c5 = None
+    if not args.no_c5:
+        if args.no_multishift:
+            lat.close()
+            del srcs, x
+            torch.cuda.empty_cache()
+        c5 = c5_comparison(dwf, synth, torch, tune_cache)
     cpu = None if args.no_cpu else cpu_baseline(w, U, b0_host, st64["iters"])
 
     ms_step = t_total / args.steps * 1e3
-    tmixed = float(np.mean([s["seconds"] for s in stats]))
+    tmixed = float(np.median([s["seconds"] for s in stats]))
+    ceil_gbs = ceiling["read2_write1"]["GB/s"]
     result = {
         "metric": METRIC,
         "value": round(whole_gbs, 1),
@@ -430,12 +580,18 @@ def main():
                    "solver": f"red-black CGNE, {MODE_NAMES[args.mode]} + FP64 reliable updates, tol 1e-8"},
         "gflops": round(whole_gflops, 1),
         "value_definition": "algorithmic bytes of all hop stencils of the timed solves / their wall time",
-        "time_to_1e-8_s": {"f64": round(st64["seconds"], 4), MODE_NAMES[args.mode]: round(tmixed, 4),
+        "time_to_1e-8_s": {"f64": round(t64, 4), MODE_NAMES[args.mode]: round(tmixed, 4),
                            "fgcr_learned": lp["seconds"] if lp else None,
                            "fgcr_learned_compact": lp["compact_network"]["seconds"] if lp else None},
         "iters": {"f64": st64["iters"], MODE_NAMES[args.mode]: [s["iters"] for s in stats]},
-        "res_full": {"f64": st64["res_full"], MODE_NAMES[args.mode]: max(s["res_full"] for s in stats)},
-        "speedup_vs_f64": round(st64["seconds"] / tmixed, 3),
+        "time_definition": "median over solves (FP64 CG and each FGCR leg: 3 after a workspace warm-up; the "
+                           "mixed form: the timed steps); CG stops on the normal-equation residual, FGCR on the "
+                           "Schur residual, so res_full gives the FP64 full residual each leg reached",
+        "res_full": {"f64": max(r[1]["res_full"] for r in runs64),
+                     MODE_NAMES[args.mode]: max(s["res_full"] for s in stats),
+                     "fgcr_learned": lp["res_full"] if lp else None,
+                     "fgcr_learned_compact": lp["compact_network"]["res_full"] if lp else None},
+        "speedup_vs_f64": round(t64 / tmixed, 3),
         "kernel_classes": {k: {"launches": v["launches"], "ms": round(v["ms"], 2),
                                "GB/s": round(v["bytes"] / v["ms"] / 1e6, 1) if v["ms"] > 0 else None}
                            for k, v in ks.items()},
@@ -447,13 +603,18 @@ def main():
                      "avg_launch_ms": round(dom["ms"] / dom["launches"], 4),
                      "bytes_per_launch": dom["bytes"] / dom["launches"],
                      "gflops": round(dom["flops"] / dom["ms"] / 1e6, 1),
-                     "frac_of_copy": round(kern_gbs / copy["GB/s"], 4)},
+                     "frac_of_copy": round(kern_gbs / copy["GB/s"], 4),
+                     "ceiling": {"GB/s": ceil_gbs, "probe": "two streams read per stream written, best of the "
+                                                           "library's probes (the hop's read:write mix)"},
+                     "frac_of_ceiling": round(kern_gbs / ceil_gbs, 4)},
         "learned_precond": lp,
         "multishift": ms,
         "chebyshev_filter": cheb,
         "tile_schedule": sched,
         "tune_cache": os.path.relpath(tune_cache, ROOT) if tune_cache else None,
         "copy": copy,
+        "bandwidth_probes": {k: {kk: v[kk] for kk in v if kk != "configs"} for k, v in ceiling.items()},
+        "c5_24x24x24x24_ls12_periodic": c5,
         "dhop": table,
         "cpu_baseline": cpu,
     }

@@ -368,6 +368,18 @@ dwf_status dwf_tune(dwf_ctx ctx, int prec, const char *cache_path, double *best_
  * the roofline and as the calibration kernel for memory counters. */
 dwf_status dwf_stream_copy(dwf_ctx ctx, const void *src, void *dst, size_t bytes);
 
+/* Bandwidth probes, the achievable-bandwidth references of the rooflines (not
+ * part of the method).  kind 0: dst = a (bytes read, bytes written); 1: a is
+ * read (bytes) and each workgroup writes the XOR of its part to one 16-byte
+ * word of dst, which must hold 16 * min(65536, ceil(bytes / (4096 unroll)))
+ * bytes; 2: dst = a XOR b (2 bytes read per byte written, the read:write mix of
+ * the hop).  Each lane keeps `unroll` (1, 2, 4 or 8) independent 16-byte loads
+ * in flight; nontemporal != 0 uses non-temporal loads and stores.  Device
+ * pointers, 16-byte aligned; bytes a multiple of 16.  Timed as DWF_K_BLAS with
+ * the bytes moved (read + written). */
+dwf_status dwf_stream_probe(dwf_ctx ctx, int kind, int unroll, int nontemporal, const void *a, const void *b,
+                            void *dst, size_t bytes);
+
 /* ------------------------------------------------------ kernel statistics */
 
 enum {

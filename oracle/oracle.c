@@ -95,6 +95,9 @@ static void init_gamma(void)
 /* threads the parallel loops of this library run on */
 int or_num_threads(void) { return omp_get_max_threads(); }
 
+/* Threads of the following parallel loops (the CPU baseline times one and all). */
+void or_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
 void or_gamma(int mu, double *out /* 4x4 complex */)
 {
     init_gamma();

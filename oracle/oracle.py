@@ -62,6 +62,7 @@ def lib():
             "or_hop_sites": [_p, _i, _p, _p, _p, _l, _p, _i],
             "or_d5_sites": [_p, _i, _d, _d, _d, _d, _p, _p, _p, _l, _p],
             "or_num_threads": [],
+            "or_set_num_threads": [_i],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -74,6 +75,11 @@ def lib():
 def num_threads() -> int:
     """Threads the oracle's parallel loops use (OpenMP)."""
     return int(lib().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's following parallel loops."""
+    lib().or_set_num_threads(int(n))
 
 
 def _ptr(a):

@@ -727,6 +727,22 @@ dwf_status dwf_stream_copy(dwf_ctx ctx, const void *src, void *dst, size_t bytes
     DWF_API_END
 }
 
+dwf_status dwf_stream_probe(dwf_ctx ctx, int kind, int unroll, int nontemporal, const void *a, const void *b,
+                            void *dst, size_t bytes)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    if (kind < 0 || kind > 2) fail(DWF_EINVAL, "probe kind must be 0 (copy), 1 (read) or 2 (two reads, one write)");
+    if (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8) fail(DWF_EINVAL, "unroll must be 1, 2, 4 or 8");
+    require(a, "a");
+    require(dst, "dst");
+    if (kind == 2) require(b, "b");
+    if (bytes % 16 || ((uintptr_t)a % 16) || ((uintptr_t)dst % 16) || (b && (uintptr_t)b % 16))
+        fail(DWF_EINVAL, "probes need 16-byte aligned pointers and a multiple of 16 bytes");
+    if (bytes) launch_stream_probe(c, kind, unroll, nontemporal != 0, a, b, dst, bytes);
+    DWF_API_END
+}
+
 dwf_status dwf_kernel_timing(dwf_ctx ctx, int enable)
 {
     DWF_API_BEGIN

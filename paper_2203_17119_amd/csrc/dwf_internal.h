@@ -316,6 +316,11 @@ void scratch_init(int device);
 
 void read_scalars(Context &c, int first, int count);  // dscal -> hscal, synchronising
 void launch_stream_copy(Context &c, const void *src, void *dst, size_t bytes);
+// bandwidth probes (kind 0 copy, 1 read-only, 2 two reads per write), unroll
+// loads in flight per lane (1, 2, 4 or 8), non-temporal when nt
+long stream_probe_blocks(size_t bytes, int unroll);
+void launch_stream_probe(Context &c, int kind, int unroll, bool nt, const void *a, const void *b, void *dst,
+                         size_t bytes);
 
 // ---------------------------------------------------------------- Mpc helpers
 

@@ -1015,6 +1015,110 @@ __global__ void __launch_bounds__(BS) k_stream_copy(const uint4 *__restrict__ sr
     for (long i = blockIdx.x * (long)BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) dst[i] = src[i];
 }
 
+// Bandwidth probes, the achievable-HBM references for the stencil's rooflines.
+// Each lane keeps U independent 16-byte loads in flight per round (addresses
+// a grid apart, so a round of the grid reads U contiguous blocks), loads and
+// stores non-temporal when NT.  KIND 0: dst = a (copy); 1: read a only, each
+// workgroup writes the XOR of what it read to dst[blockIdx.x]; 2: dst = a ^ b
+// (two streams read per stream written, the hop's read:write mix).
+typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ v4u_t probe_load(const v4u_t *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <bool NT>
+__device__ __forceinline__ void probe_store(v4u_t *p, v4u_t v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <int KIND, int U, bool NT>
+__global__ void __launch_bounds__(BS) k_stream_probe(const v4u_t *__restrict__ a, const v4u_t *__restrict__ b,
+                                                     v4u_t *__restrict__ dst, long n)
+{
+    const long G = (long)gridDim.x * BS;
+    const long t = blockIdx.x * (long)BS + threadIdx.x;
+    v4u_t acc = {0u, 0u, 0u, 0u};
+    for (long i0 = t; i0 < n; i0 += U * G) {
+        v4u_t va[U], vb[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const long i = i0 + u * G;
+            if (i < n) {
+                va[u] = probe_load<NT>(a + i);
+                if constexpr (KIND == 2) vb[u] = probe_load<NT>(b + i);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const long i = i0 + u * G;
+            if (i < n) {
+                if constexpr (KIND == 0) probe_store<NT>(dst + i, va[u]);
+                else if constexpr (KIND == 2) probe_store<NT>(dst + i, va[u] ^ vb[u]);
+                else acc ^= va[u];
+            }
+        }
+    }
+    if constexpr (KIND == 1) {
+        __shared__ v4u_t red[BS];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = BS / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] ^= red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) dst[blockIdx.x] = red[0];
+    }
+}
+
+long stream_probe_blocks(size_t bytes, int unroll)
+{
+    const long n = (long)(bytes / 16);
+    return std::max<long>(1, std::min<long>((n + (long)BS * unroll - 1) / ((long)BS * unroll), 65536L));
+}
+
+void launch_stream_probe(Context &c, int kind, int unroll, bool nt, const void *a, const void *b, void *dst,
+                         size_t bytes)
+{
+    const long n = (long)(bytes / 16);
+    const long nblk = stream_probe_blocks(bytes, unroll);
+    const double moved = kind == 0 ? 2.0 * bytes : (kind == 1 ? (double)bytes : 3.0 * bytes);
+    Timer tm(c, DWF_K_BLAS, moved, 0);
+    const v4u_t *pa = (const v4u_t *)a, *pb = (const v4u_t *)b;
+    v4u_t *pd = (v4u_t *)dst;
+#define DWF_PROBE(K, U)                                                                                        \
+    do {                                                                                                       \
+        if (nt)                                                                                                \
+            hipLaunchKernelGGL((k_stream_probe<K, U, true>), dim3((unsigned)nblk), dim3(BS), 0, c.stream, pa, pb, \
+                               pd, n);                                                                         \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_stream_probe<K, U, false>), dim3((unsigned)nblk), dim3(BS), 0, c.stream, pa,   \
+                               pb, pd, n);                                                                     \
+    } while (0)
+#define DWF_PROBE_U(K)                        \
+    do {                                      \
+        switch (unroll) {                     \
+        case 1: DWF_PROBE(K, 1); break;       \
+        case 2: DWF_PROBE(K, 2); break;       \
+        case 4: DWF_PROBE(K, 4); break;       \
+        default: DWF_PROBE(K, 8); break;      \
+        }                                     \
+    } while (0)
+    switch (kind) {
+    case 0: DWF_PROBE_U(0); break;
+    case 1: DWF_PROBE_U(1); break;
+    default: DWF_PROBE_U(2); break;
+    }
+#undef DWF_PROBE_U
+#undef DWF_PROBE
+    HIPCHECK(hipGetLastError());
+}
+
 void launch_stream_copy(Context &c, const void *src, void *dst, size_t bytes)
 {
     const long n = (long)(bytes / 16);

@@ -121,6 +121,7 @@ SIGNATURES = {
     "dwf_get_tile_schedule": ([_CTX, _I, C.POINTER(_I), C.POINTER(_I)], C.c_int32),
     "dwf_tune": ([_CTX, _I, C.c_char_p, C.POINTER(_D)], C.c_int32),
     "dwf_stream_copy": ([_CTX, _P, _P, C.c_size_t], C.c_int32),
+    "dwf_stream_probe": ([_CTX, _I, _I, _I, _P, _P, _P, C.c_size_t], C.c_int32),
     "dwf_kernel_timing": ([_CTX, _I], C.c_int32),
     "dwf_kernel_timing_reset": ([_CTX], C.c_int32),
     "dwf_kernel_timing_mask": ([_CTX, _I], C.c_int32),
@@ -403,6 +404,11 @@ def dwf_tune(ctx, prec, cache_path=None):
 
 def dwf_stream_copy(ctx, src, dst, nbytes):
     _check(load().dwf_stream_copy(ctx, _ptr(src), _ptr(dst), int(nbytes)))
+
+
+def dwf_stream_probe(ctx, kind, unroll, nontemporal, a, b, dst, nbytes):
+    _check(load().dwf_stream_probe(ctx, int(kind), int(unroll), int(nontemporal), _ptr(a), _ptr(b), _ptr(dst),
+                                   int(nbytes)))
 
 
 def dwf_kernel_timing(ctx, enable):
