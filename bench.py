@@ -89,12 +89,14 @@ def dhop_table(lat, dwf, torch, reps=20):
     return out
 
 
-def schedule_sweep(lat, dwf, torch, precs=(1, 2), reps=5):
+def schedule_sweep(lat, dwf, torch, precs=(1, 2), reps=5, orders=None):
     """Standalone Dhop GB/s over site orders and (sites per workgroup, XCD run) schedules."""
     res = {}
     src = torch.view_as_complex(torch.randn(lat.half_shape() + (2,), dtype=torch.float64, device="cuda"))
     L = lat.dims
-    orders = [(0, 0, 0), (L[0], L[1], L[2]), (16, 8, 8), (8, 16, 8), (8, 8, 8), (16, 16, 8), (8, 8, 16), (4, 8, 8)]
+    if orders is None:
+        orders = [(0, 0, 0), (L[0], L[1], L[2]), (16, 8, 8), (8, 16, 8), (8, 8, 8), (16, 16, 8), (8, 8, 16),
+                  (4, 8, 8)]
     for order in orders:
         dwf.dwf_set_site_order(lat.ctx, *order)
         got = dwf.dwf_get_site_order(lat.ctx)
@@ -424,6 +426,9 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the stream copy and the standalone Dhop per precision (for counter runs)")
     ap.add_argument("--sweep", action="store_true", help="with --kernels-only: Dhop time over tile schedules")
+    ap.add_argument("--orders", default=None,
+                    help="with --sweep: site-order column extents to try, e.g. '4,2,2;8,8,8'")
+    ap.add_argument("--sweep-precs", default="1,2", help="with --sweep: storage precisions to time")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the FGCR solve with the trained network preconditioner")
     ap.add_argument("--no-multishift", action="store_true", help="skip the batched multi-shift solve")
@@ -454,7 +459,9 @@ def main():
         out = {"copy": copy_bandwidth(lat, dwf, torch), "ceiling": bandwidth_ceiling(lat, dwf, torch),
                "dhop": dhop_table(lat, dwf, torch, reps=5)}
         if args.sweep:
-            out["sweep"] = schedule_sweep(lat, dwf, torch)
+            orders = [tuple(int(v) for v in o.split(",")) for o in args.orders.split(";")] if args.orders else None
+            out["sweep"] = schedule_sweep(lat, dwf, torch, precs=tuple(int(v) for v in args.sweep_precs.split(",")),
+                                          orders=orders)
         print(json.dumps(out), flush=True)
         lat.close()
         return
