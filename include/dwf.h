@@ -95,6 +95,38 @@ dwf_status dwf_destroy(dwf_ctx ctx);
 dwf_status dwf_set_gauge(dwf_ctx ctx, const double *gauge, int on_device);
 dwf_status dwf_set_stream(dwf_ctx ctx, void *stream);
 
+/* ------------------------------------------------------------ workspaces
+ *
+ * The library's workspace fields (solver vectors, the operators'
+ * intermediates) are allocated on first use and kept by the context, unless
+ * the caller hands it a device buffer: while one is set, every workspace
+ * buffer is carved from it (256-byte aligned, in order of first use), so that
+ * the caller's allocator owns that memory.  The context's own state (the
+ * gauge copies per precision, neighbour tables, reduction scalars) stays
+ * library-owned: dwf_create allocates it, and the links of a storage precision
+ * other than FP64 on first use or by dwf_prepare_links. */
+enum {
+    DWF_OP_CG = 0,           /* dwf_cg in `mode`                                       */
+    DWF_OP_MULTISHIFT = 1,   /* dwf_multishift_cg in `mode` with nrhs x nshift systems */
+    DWF_OP_RATIONAL = 2,     /* dwf_rational_apply, `nshift` poles (nrhs ignored)      */
+    DWF_OP_SCHUR_APPLY = 3   /* dwf_schur_apply (mode, nrhs, nshift ignored)           */
+};
+/* Bytes of caller workspace the operation needs on a context that has none
+ * of its buffers yet (an upper bound otherwise).  DWF_EINVAL for an unknown
+ * op or sizes out of range, DWF_ENOTSUP for a mode the operation lacks. */
+dwf_status dwf_workspace_bytes(dwf_ctx ctx, int op, int mode, int nrhs, int nshift, size_t *bytes);
+/* Hand the context a device buffer (256-byte aligned; NULL returns to library
+ * allocation).  Buffers carved from an earlier caller workspace are forgotten
+ * (the caller may free it after this call); the library's own earlier
+ * allocations stay.  A later call that needs more than is left returns
+ * DWF_ENOMEM and names the size.  The buffer must stay valid while set. */
+dwf_status dwf_set_workspace(dwf_ctx ctx, void *ws, size_t bytes);
+/* Bytes of the caller workspace in use (0 when none is set). */
+dwf_status dwf_workspace_used(dwf_ctx ctx, size_t *bytes);
+/* Prepare the links in storage precision prec now (they are otherwise
+ * prepared by the first call in that precision). */
+dwf_status dwf_prepare_links(dwf_ctx ctx, int prec);
+
 /* Bytes of one internal field: full != 0 for both parities, else one parity. */
 dwf_status dwf_field_bytes(dwf_ctx ctx, int full, int prec, size_t *bytes);
 /* Convert a canonical FP64 half field (full == 0) to the internal layout in

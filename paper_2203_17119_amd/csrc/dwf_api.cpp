@@ -53,19 +53,68 @@ Field make_field(const Context &c, void *data, int prec)
     return f;
 }
 
-Field ws_field(Context &c, const std::string &name, int prec)
+// device memory for a workspace buffer: carved from the caller's workspace
+// when one is set, else allocated (and then owned) by the library
+static void *ws_alloc(Context &c, size_t bytes, bool &owned)
 {
-    const std::string key = name + "#" + std::to_string(prec);
+    if (c.uws) {
+        const size_t off = (c.uws_used + 255) & ~(size_t)255;
+        if (off + bytes > c.uws_bytes)
+            fail(DWF_ENOMEM, "caller workspace too small: " + std::to_string(off + bytes) + " bytes needed, " +
+                                 std::to_string(c.uws_bytes) + " given (dwf_workspace_bytes)");
+        c.uws_used = off + bytes;
+        owned = false;
+        return c.uws + off;
+    }
+    void *p = nullptr;
+    HIPCHECK(hipMalloc(&p, bytes));
+    owned = true;
+    return p;
+}
+
+static Context::Buf &ws_get(Context &c, const std::string &key, size_t bytes, int prec)
+{
     auto it = c.ws.find(key);
     if (it == c.ws.end()) {
         Context::Buf b;
-        b.bytes = field_bytes(c, c.n5h, prec);
-        HIPCHECK(hipMalloc(&b.data, b.bytes));
+        b.bytes = bytes;
+        b.data = ws_alloc(c, bytes, b.owned);
         HIPCHECK(hipMemsetAsync(b.data, 0, b.bytes, c.stream));
         b.prec = prec;
         it = c.ws.emplace(key, b).first;
     }
-    return make_field(c, it->second.data, prec);
+    return it->second;
+}
+
+Field ws_field(Context &c, const std::string &name, int prec)
+{
+    const std::string key = name + "#" + std::to_string(prec);
+    return make_field(c, ws_get(c, key, field_bytes(c, c.n5h, prec), prec).data, prec);
+}
+
+void *ws_raw(Context &c, const std::string &name, size_t bytes)
+{
+    Context::Buf &b = ws_get(c, name + "#raw", bytes, -1);
+    if (b.bytes < bytes) fail(DWF_EINVAL, "workspace buffer " + name + " reused with a larger size");
+    return b.data;
+}
+
+size_t ws_plan_bytes(const Context &c, const std::vector<WsKey> &plan)
+{
+    size_t total = 0;
+    std::vector<std::string> seen;
+    for (const WsKey &k : plan) {
+        const std::string key = k.prec < 0 ? k.name + "#raw"
+                                : k.nbatch <= 1 ? k.name + "#" + std::to_string(k.prec)
+                                                : k.name + "#" + std::to_string(k.prec) + "x" + std::to_string(k.nbatch);
+        if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+        seen.push_back(key);
+        size_t b = k.prec < 0 ? k.raw
+                   : k.nbatch <= 1 ? field_bytes(c, c.n5h, k.prec)
+                                   : (size_t)batch_stride(c, k.prec) * k.nbatch;
+        total += (b + 255) & ~(size_t)255;
+    }
+    return total;
 }
 
 const void *slmat(const Context &c, int op, bool f64)
@@ -285,16 +334,7 @@ Field ws_batch(Context &c, const std::string &name, int prec, int nbatch)
 {
     if (nbatch <= 1) return ws_field(c, name, prec);
     const std::string key = name + "#" + std::to_string(prec) + "x" + std::to_string(nbatch);
-    auto it = c.ws.find(key);
-    if (it == c.ws.end()) {
-        Context::Buf b;
-        b.bytes = (size_t)batch_stride(c, prec) * nbatch;
-        HIPCHECK(hipMalloc(&b.data, b.bytes));
-        HIPCHECK(hipMemsetAsync(b.data, 0, b.bytes, c.stream));
-        b.prec = prec;
-        it = c.ws.emplace(key, b).first;
-    }
-    return make_field(c, it->second.data, prec);
+    return make_field(c, ws_get(c, key, (size_t)batch_stride(c, prec) * nbatch, prec).data, prec);
 }
 
 int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduce, bool in_is_A_applied, Field pa,
@@ -484,7 +524,8 @@ dwf_status dwf_destroy(dwf_ctx ctx)
     for (auto e : c.event_pool) (void)hipEventDestroy(e);
     for (auto e : c.cg_ev)
         if (e) (void)hipEventDestroy(e);
-    for (auto &kv : c.ws) (void)hipFree(kv.second.data);
+    for (auto &kv : c.ws)
+        if (kv.second.owned) (void)hipFree(kv.second.data);
     for (int pr = 0; pr < 4; pr++)
         for (int p = 0; p < 2; p++)
             if (c.links[pr][p]) (void)hipFree(c.links[pr][p]);
@@ -502,6 +543,43 @@ dwf_status dwf_destroy(dwf_ctx ctx)
     if (c.hring) (void)hipHostFree(c.hring);
     delete ctx;
     return DWF_OK;
+}
+
+dwf_status dwf_set_workspace(dwf_ctx ctx, void *ws, size_t bytes)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    if (ws && ((uintptr_t)ws % 256)) fail(DWF_EINVAL, "workspace must be 256-byte aligned");
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    // buffers carved from the previous caller workspace are forgotten; the
+    // library's own allocations stay
+    for (auto it = c.ws.begin(); it != c.ws.end();) {
+        if (!it->second.owned) it = c.ws.erase(it);
+        else ++it;
+    }
+    c.uws = ws ? (char *)ws : nullptr;
+    c.uws_bytes = ws ? bytes : 0;
+    c.uws_used = 0;
+    DWF_API_END
+}
+
+dwf_status dwf_workspace_used(dwf_ctx ctx, size_t *bytes)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    require(bytes, "bytes");
+    *bytes = c.uws_used;
+    DWF_API_END
+}
+
+dwf_status dwf_prepare_links(dwf_ctx ctx, int prec)
+{
+    DWF_API_BEGIN
+    dwf::Context &c = C_(ctx);
+    check_prec(prec);
+    ensure_links(c, prec);
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    DWF_API_END
 }
 
 dwf_status dwf_set_gauge(dwf_ctx ctx, const double *gauge, int on_device)

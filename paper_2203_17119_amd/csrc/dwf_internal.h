@@ -117,8 +117,13 @@ struct Context {
         float *norm = nullptr;
         size_t bytes = 0;
         int prec = -1;
+        bool owned = true;  // allocated by the library (else carved from uws)
     };
     std::map<std::string, Buf> ws;
+    // caller-provided workspace (dwf_set_workspace): while set, workspace
+    // buffers are carved from it in order of first use, 256-byte aligned
+    char *uws = nullptr;
+    size_t uws_bytes = 0, uws_used = 0;
 
     LaunchCfg cfg_stencil, cfg_slocal, cfg_blas;
 
@@ -145,6 +150,19 @@ size_t field_bytes(const Context &c, long n5, int prec);
 
 // workspace field of one parity in precision prec (allocated on first use)
 Field ws_field(Context &c, const std::string &name, int prec);
+// untyped workspace buffer of at least `bytes` (allocated on first use)
+void *ws_raw(Context &c, const std::string &name, size_t bytes);
+
+// One workspace buffer an operation takes: a field (nbatch == 0: one field by
+// ws_field; nbatch >= 1: a batch by ws_batch) or raw bytes (prec < 0).
+struct WsKey {
+    std::string name;
+    int prec;
+    int nbatch;
+    size_t raw;
+};
+// bytes the buffers of a plan take in a caller workspace (each 256-aligned)
+size_t ws_plan_bytes(const Context &c, const std::vector<WsKey> &plan);
 Field make_field(const Context &c, void *data, int prec);  // caller memory (FP16: norm follows data)
 
 const void *slmat(const Context &c, int op, bool f64);

@@ -371,19 +371,60 @@ dwf_status dwf_cg(dwf_ctx ctx, const double *b_full, double *x_full, const dwf_s
 
 namespace dwf {
 
-struct DevBuf {
-    void *p = nullptr;
-    DevBuf(size_t bytes) { HIPCHECK(hipMalloc(&p, bytes)); }
-    ~DevBuf()
-    {
-        if (p) (void)hipFree(p);
+// device state of the batched multi-shift solver: per-rhs scalars, per
+// (shift, rhs) recurrences and two coefficient sets, the shifts, flags.  The
+// buffer is sized for the largest batch (64 x 64), so that one workspace
+// buffer serves every call.
+static size_t ms_state_bytes(int nrhs, int nshift)
+{
+    (void)nrhs;
+    (void)nshift;
+    const size_t nq = 64 * 64;
+    return sizeof(double) * (7 * 64 + 2 * nq + 4 * nq + 64 + 4 * nq) + sizeof(int) * 2 * nq;
+}
+
+// Workspace buffers of cg_core in a mode (keys as its ws_field calls)
+static void plan_cg_core(std::vector<WsKey> &k, int mode)
+{
+    const int lp = prec_of_mode(mode), xp = accum_prec(lp);
+    const bool mixed = lp != P_F64;
+    for (const char *n : {"cg_m64", "cg_ap64", "cg_rh", "mpc_y", "mpc_ta"}) k.push_back({n, P_F64, 0, 0});
+    for (int q = 0; q < CG_RING; q++) k.push_back({"cg_p" + std::to_string(q), lp, 0, 0});
+    k.push_back({"cg_pa", lp, 0, 0});
+    if (mixed) {
+        k.push_back({"cg_rl", lp, 0, 0});
+        k.push_back({"cg_xl", xp, 0, 0});
+        k.push_back({"cg_m", lp, 0, 0});
+        k.push_back({"cg_ap", lp, 0, 0});
+        k.push_back({"mpc_y", lp, 0, 0});
     }
-    template <typename T>
-    T *as() const
-    {
-        return (T *)p;
-    }
-};
+}
+
+std::vector<WsKey> plan_cg(int mode)
+{
+    std::vector<WsKey> k;
+    for (const char *n : {"sv_be", "sv_bo", "sv_bt", "sv_rhs", "sv_xo", "sv_xe", "sv_t1", "sv_t2", "sv_ax"})
+        k.push_back({n, P_F64, 0, 0});
+    plan_cg_core(k, mode);
+    return k;
+}
+
+std::vector<WsKey> plan_multishift(int mode, int nrhs, int nshift)
+{
+    const int lp = prec_of_mode(mode);
+    const int nq = nrhs * nshift;
+    std::vector<WsKey> k;
+    for (const char *n : {"ms_B", "ms_R", "ms_AP", "ms_M"}) k.push_back({n, lp, nrhs, 0});
+    for (const char *n : {"ms_X", "ms_P", "ms_P2"}) k.push_back({n, lp, nq, 0});
+    // the batched operator's intermediates (one field when nrhs == 1)
+    k.push_back({"mpc_y", lp, nrhs, 0});
+    k.push_back({"mpc_ta", lp, nrhs, 0});
+    for (const char *n : {"ms_b64", "ms_x64", "ms_t1", "ms_t2"}) k.push_back({n, P_F64, 0, 0});
+    k.push_back({"ms_state", -1, 0, ms_state_bytes(nrhs, nshift)});
+    // the FP64 residual check and the refinement of systems that missed the tolerance
+    plan_cg_core(k, mode);
+    return k;
+}
 
 }  // namespace dwf
 
@@ -428,8 +469,7 @@ static bool ms_solve(Context &c, int nrhs, const double *const *b_odd, int nshif
         launch_convert(c, P_F64, b64, lp, member(B, j, stride));
     }
     // device state
-    DevBuf dstate(sizeof(double) * (7 * nrhs + 2 * nq + 4 * nq + nshift + 4 * nq) + sizeof(int) * 2 * nq);
-    double *db = dstate.as<double>();
+    double *db = (double *)ws_raw(c, "ms_state", ms_state_bytes(nrhs, nshift));
     MsState s;
     s.rho = db;
     s.pap = db + nrhs;
@@ -570,6 +610,33 @@ extern "C" dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *con
     dwf::Context &c = *ctx;
     auto sink = [&](int j, int k, Field x64) { launch_export(c, P_F64, x64, x_odd[j * nshift + k], 0, 0); };
     if (!ms_solve(c, nrhs, b_odd, nshift, shifts, sink, o, st)) return DWF_ENOCONV;
+    DWF_API_END
+}
+
+extern "C" dwf_status dwf_workspace_bytes(dwf_ctx ctx, int op, int mode, int nrhs, int nshift, size_t *bytes)
+{
+    DWF_API_BEGIN
+    if (!ctx) fail(DWF_EINVAL, "null context");
+    if (!bytes) fail(DWF_EINVAL, "null bytes");
+    dwf::Context &c = *ctx;
+    std::vector<WsKey> plan;
+    switch (op) {
+    case DWF_OP_CG: plan = plan_cg(mode); break;
+    case DWF_OP_MULTISHIFT:
+    case DWF_OP_RATIONAL:
+        if (mode != DWF_SOLVE_F64 && mode != DWF_SOLVE_MIXED_F32)
+            fail(DWF_ENOTSUP, "multi-shift mode must be F64 or MIXED_F32");
+        if (op == DWF_OP_RATIONAL) nrhs = 1;
+        if (nrhs < 1 || nrhs > 64 || nshift < 1 || nshift > 64) fail(DWF_EINVAL, "need 1 <= nrhs, nshift <= 64");
+        plan = plan_multishift(mode, nrhs, nshift);
+        if (op == DWF_OP_RATIONAL) plan.push_back({"ra_acc", P_F64, 0, 0});
+        break;
+    case DWF_OP_SCHUR_APPLY:
+        for (const char *n : {"io_a", "io_b", "mpc_y", "mpc_ta"}) plan.push_back({n, P_F64, 0, 0});
+        break;
+    default: fail(DWF_EINVAL, "unknown operation");
+    }
+    *bytes = ws_plan_bytes(c, plan);
     DWF_API_END
 }
 

@@ -21,6 +21,7 @@ DWF_F64, DWF_F32, DWF_F16, DWF_BF16 = 0, 1, 2, 3
 DWF_SOLVE_F64, DWF_SOLVE_MIXED_F32, DWF_SOLVE_MIXED_F16, DWF_SOLVE_MIXED_BF16 = 0, 1, 2, 3
 DWF_K_DHOP, DWF_K_STENCIL, DWF_K_SLOCAL, DWF_K_BLAS, DWF_K_NET = 0, 1, 2, 3, 4
 DWF_NET_FWD_FP32, DWF_NET_FWD_MFMA_BF16 = 0, 1
+DWF_OP_CG, DWF_OP_MULTISHIFT, DWF_OP_RATIONAL, DWF_OP_SCHUR_APPLY = 0, 1, 2, 3
 KCLASS_NAMES = {DWF_K_DHOP: "dhop", DWF_K_STENCIL: "stencil", DWF_K_SLOCAL: "slocal",
                 DWF_K_BLAS: "blas", DWF_K_NET: "net"}
 
@@ -88,6 +89,10 @@ SIGNATURES = {
     "dwf_set_gauge": ([_CTX, _P, _I], C.c_int32),
     "dwf_set_stream": ([_CTX, _P], C.c_int32),
     "dwf_field_bytes": ([_CTX, _I, _I, C.POINTER(C.c_size_t)], C.c_int32),
+    "dwf_workspace_bytes": ([_CTX, _I, _I, _I, _I, C.POINTER(C.c_size_t)], C.c_int32),
+    "dwf_set_workspace": ([_CTX, _P, C.c_size_t], C.c_int32),
+    "dwf_workspace_used": ([_CTX, C.POINTER(C.c_size_t)], C.c_int32),
+    "dwf_prepare_links": ([_CTX, _I], C.c_int32),
     "dwf_import": ([_CTX, _I, _I, _P, _P], C.c_int32),
     "dwf_export": ([_CTX, _I, _I, _P, _P], C.c_int32),
     "dwf_dhop": ([_CTX, _I, _I, _P, _P], C.c_int32),
@@ -219,6 +224,31 @@ def dwf_field_bytes(ctx, full, prec) -> int:
     n = C.c_size_t()
     _check(load().dwf_field_bytes(ctx, int(full), int(prec), C.byref(n)))
     return n.value
+
+
+def dwf_workspace_bytes(ctx, op, mode=DWF_SOLVE_F64, nrhs=1, nshift=1) -> int:
+    n = C.c_size_t()
+    _check(load().dwf_workspace_bytes(ctx, int(op), int(mode), int(nrhs), int(nshift), C.byref(n)))
+    return n.value
+
+
+def dwf_set_workspace(ctx, ws, nbytes=None):
+    """ws: a device tensor (its storage is used; keep it alive while set) or None."""
+    if ws is None:
+        _check(load().dwf_set_workspace(ctx, None, 0))
+    else:
+        n = ws.numel() * ws.element_size() if nbytes is None else int(nbytes)
+        _check(load().dwf_set_workspace(ctx, _ptr(ws), n))
+
+
+def dwf_workspace_used(ctx) -> int:
+    n = C.c_size_t()
+    _check(load().dwf_workspace_used(ctx, C.byref(n)))
+    return n.value
+
+
+def dwf_prepare_links(ctx, prec):
+    _check(load().dwf_prepare_links(ctx, int(prec)))
 
 
 def dwf_import(ctx, full, prec, canon, internal):
