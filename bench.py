@@ -247,7 +247,11 @@ def multishift(dwf, synth, torch, mode, tune_cache):
         V = int(np.prod(w.dims))
         bs = [torch.from_numpy(synth.gaussian_fermion(w.dims, w.Ls, s, nsites=V // 2)).cuda() for s in w.source_seeds]
         xs = [torch.empty_like(bs[0]) for _ in range(len(bs) * len(shifts))]
-        dwf.dwf_tune(lat.ctx, dwf.DWF_F32 if mode == dwf.DWF_SOLVE_MIXED_F32 else dwf.DWF_F64, tune_cache)
+        prec = dwf.DWF_F32 if mode == dwf.DWF_SOLVE_MIXED_F32 else dwf.DWF_F64
+        dwf.dwf_tune(lat.ctx, prec, tune_cache)
+        dwf.dwf_tune_op(lat.ctx, dwf.DWF_TUNE_BATCHED, prec, len(bs), tune_cache)
+        sched = {"single": dwf.dwf_get_tile_schedule(lat.ctx, dwf.DWF_K_STENCIL),
+                 "batched": dwf.dwf_get_tile_schedule(lat.ctx, dwf.DWF_SCHED_STENCIL_BATCHED)}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s, st = dwf.dwf_multishift_cg(lat.ctx, bs, shifts, xs, tol=w.tol, mode=mode)
@@ -258,7 +262,8 @@ def multishift(dwf, synth, torch, mode, tune_cache):
     return {"workload": "16^4x12_multishift: 8 rhs x 12 shifts in [1e-4, 10]", "status": s,
             "mode": {0: "f64", 1: "mixed_f32"}[mode], "seconds": round(dt, 3),
             "systems": len(st), "iters_max": max(x["iters"] for x in st),
-            "converged": sum(x["converged"] for x in st), "res_normal_max": max(x["res_normal"] for x in st)}
+            "converged": sum(x["converged"] for x in st), "res_normal_max": max(x["res_normal"] for x in st),
+            "tile_schedule": sched}
 
 
 def chebyshev(lat, dwf, synth, torch, w, prec):

@@ -359,8 +359,13 @@ dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, double *x_fu
 
 /* ------------------------------------------------------ tile schedules */
 
+/* Schedule selector (not a timing class): the fused stencil stages launched
+ * over a batch of fields, as the multi-shift solver launches them. */
+enum { DWF_SCHED_STENCIL_BATCHED = 8 };
+
 /* Launch shape of a kernel family (DWF_K_STENCIL covers the hop and every
- * fused stencil stage, DWF_K_SLOCAL the fifth-dimension kernels):
+ * fused stencil stage on one field, DWF_SCHED_STENCIL_BATCHED the same stages
+ * over a batch of fields, DWF_K_SLOCAL the fifth-dimension kernels):
  * sites_per_group 4D sites per workgroup (workgroup = Ls x sites_per_group
  * lanes, at most 256; 0 = default) and xcd_run, the number of consecutive
  * tiles each of the 8 XCDs processes before the next XCD takes over (1 = the
@@ -391,6 +396,15 @@ dwf_status dwf_get_site_order(dwf_ctx ctx, int *cx, int *cy, int *cz);
  * with the same key reads the cache instead of timing.  Synchronises the
  * stream.  best_ms (may be NULL) returns the time of the chosen schedule. */
 dwf_status dwf_tune(dwf_ctx ctx, int prec, const char *cache_path, double *best_ms);
+
+/* The autotuner for one operation: op DWF_TUNE_NORMAL times the normal
+ * operator on one field (dwf_tune's search; nrhs must be 1) and sets the
+ * DWF_K_STENCIL schedule; DWF_TUNE_BATCHED times the normal operator over a
+ * batch of nrhs fields (1 <= nrhs <= 64), the multi-shift solver's launch, and
+ * sets the DWF_SCHED_STENCIL_BATCHED schedule.  Cache keys carry the op and
+ * nrhs (the single-field key is dwf_tune's).  Otherwise as dwf_tune. */
+enum { DWF_TUNE_NORMAL = 0, DWF_TUNE_BATCHED = 1 };
+dwf_status dwf_tune_op(dwf_ctx ctx, int op, int prec, int nrhs, const char *cache_path, double *best_ms);
 
 /* ------------------------------------------------------ measurement */
 

@@ -324,6 +324,7 @@ void default_schedule(Context &c)
     const long col = column_sites(c);
     c.cfg_stencil.sb = 0;
     c.cfg_stencil.run = (col < c.vh && col % sb == 0) ? (int)std::min<long>(col / sb, 1 << 20) : 1;
+    c.cfg_stencil_batch = c.cfg_stencil;
 }
 
 // ---------------------------------------------------------------- Mpc
@@ -736,8 +737,9 @@ static LaunchCfg &cfg_of(dwf::Context &c, int kclass)
     switch (kclass) {
     case DWF_K_DHOP:
     case DWF_K_STENCIL: return c.cfg_stencil;
+    case DWF_SCHED_STENCIL_BATCHED: return c.cfg_stencil_batch;
     case DWF_K_SLOCAL: return c.cfg_slocal;
-    default: fail(DWF_EINVAL, "tile schedules exist for DWF_K_STENCIL and DWF_K_SLOCAL");
+    default: fail(DWF_EINVAL, "tile schedules exist for DWF_K_STENCIL, DWF_SCHED_STENCIL_BATCHED and DWF_K_SLOCAL");
     }
 }
 

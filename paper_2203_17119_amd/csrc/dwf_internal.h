@@ -126,6 +126,9 @@ struct Context {
     size_t uws_bytes = 0, uws_used = 0;
 
     LaunchCfg cfg_stencil, cfg_slocal, cfg_blas;
+    // schedule of the batched stencil launches (several fields per launch,
+    // as the multi-shift solver's), tuned apart from the single-field one
+    LaunchCfg cfg_stencil_batch;
 
     int timing = 0;  // bit k: time launches of kernel class k
     std::vector<TimedLaunch> pending;

@@ -734,7 +734,8 @@ static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field s
                (sp.self ? (size_t)sb_ * Ls * 12 * sizeof(cx<C>) : 0);
     };
     // the schedule's sites per workgroup, halved while the LDS would not fit
-    int sb = cfg_sb(c, c.cfg_stencil);
+    const LaunchCfg &cfg = sp.nbatch > 1 ? c.cfg_stencil_batch : c.cfg_stencil;
+    int sb = cfg_sb(c, cfg);
     while (sb > 1 && lds_of(sb) > c.lds_max) sb = (sb + 1) / 2;
     const size_t lds = lds_of(sb);
     if (lds > c.lds_max) fail(DWF_ENOTSUP, "fifth dimension too long for the fused stencil's LDS");
@@ -750,7 +751,7 @@ static int launch_stencil_t(Context &c, const StencilSpec &sp, Field in, Field s
     a.nbr = c.nbr_sm + (long)sp.out_parity * 8 * c.vh;
     a.vh = c.vh;
     a.Ls = Ls;
-    a.run = c.cfg_stencil.run;
+    a.run = cfg.run;
     a.emat = (epi == EPI_DENSE) ? slmat(c, sp.epi_op, sizeof(C) == 8) : nullptr;
     if (toep) {
         for (int k = 0; k < 16; k++) {

@@ -1,12 +1,14 @@
-// Autotuner of the fused stencil's tile schedule.
+// Autotuner of the fused stencil's tile schedules.
 //
 // A candidate schedule is (4D sites per workgroup, XCD run length).  Each is
 // timed with HIP events on the context's stream over the normal operator
-// Mpc^+ Mpc in the requested storage precision; the fastest few are re-timed
+// Mpc^+ Mpc in the requested storage precision, on one field (the schedule of
+// single-field launches) or on a batch of fields at the batch stride (the
+// schedule of batched launches, as the multi-shift solver's); the fastest few are re-timed
 // best-of-three and the winner is applied if it beats the current schedule by
 // more than 2%.  The
 // choice is cached as one JSON object per line:
-//   {"key": "<arch>/<Lx>x<Ly>x<Lz>x<Lt>/Ls<n>/p<prec>/d<dirichlet>", "sb": s, "run": r, "ms": t}
+//   {"key": "<arch>/<Lx>x<Ly>x<Lz>x<Lt>/Ls<n>/p<prec>/d<dirichlet>[/batch<nrhs>]", "sb": s, "run": r, "ms": t}
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,13 +24,14 @@ using namespace dwf;
 
 namespace dwf {
 
-static std::string tune_key(const Context &c, int prec)
+static std::string tune_key(const Context &c, int prec, int op, int nrhs)
 {
     hipDeviceProp_t prop;
     HIPCHECK(hipGetDeviceProperties(&prop, c.device));
     std::ostringstream k;
     k << prop.gcnArchName << "/" << c.L[0] << "x" << c.L[1] << "x" << c.L[2] << "x" << c.L[3] << "/Ls" << c.Ls
       << "/p" << prec << "/d" << c.p.dirichlet[0] << c.p.dirichlet[1] << c.p.dirichlet[2] << c.p.dirichlet[3];
+    if (op == DWF_TUNE_BATCHED) k << "/batch" << nrhs;
     return k.str();
 }
 
@@ -63,19 +66,22 @@ static void cache_store(const char *path, const std::string &key, int sb, int ru
     f << "{\"key\": \"" << key << "\", \"sb\": " << sb << ", \"run\": " << run << ", \"ms\": " << ms << "}\n";
 }
 
-double time_normal_op(Context &c, int prec, Field a, Field b, Field m, int reps)
+// time of one normal-operator application Mpc^+ Mpc on nb fields (batches
+// of nb fields at the batch stride when nb > 1)
+double time_normal_op(Context &c, int prec, Field a, Field b, Field m, int reps, int nb = 1)
 {
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
+    const long stride = nb > 1 ? batch_stride(c, prec) : 0;
     for (int i = 0; i < 2; i++) {
-        apply_mpc(c, prec, false, a, m, false);
-        apply_mpc(c, prec, true, m, b, false);
+        apply_mpc(c, prec, false, a, m, false, false, Field{}, nb, stride);
+        apply_mpc(c, prec, true, m, b, false, false, Field{}, nb, stride);
     }
     HIPCHECK(hipEventRecord(e0, c.stream));
     for (int i = 0; i < reps; i++) {
-        apply_mpc(c, prec, false, a, m, false);
-        apply_mpc(c, prec, true, m, b, false);
+        apply_mpc(c, prec, false, a, m, false, false, Field{}, nb, stride);
+        apply_mpc(c, prec, true, m, b, false, false, Field{}, nb, stride);
     }
     HIPCHECK(hipEventRecord(e1, c.stream));
     HIPCHECK(hipEventSynchronize(e1));
@@ -88,24 +94,29 @@ double time_normal_op(Context &c, int prec, Field a, Field b, Field m, int reps)
 
 }  // namespace dwf
 
-extern "C" dwf_status dwf_tune(dwf_ctx ctx, int prec, const char *cache_path, double *best_ms)
+extern "C" dwf_status dwf_tune_op(dwf_ctx ctx, int op, int prec, int nrhs, const char *cache_path, double *best_ms)
 {
     DWF_API_BEGIN
     if (!ctx) fail(DWF_EINVAL, "null context");
     if (prec < 0 || prec > 3) fail(DWF_EINVAL, "unknown precision");
+    if (op != DWF_TUNE_NORMAL && op != DWF_TUNE_BATCHED) fail(DWF_EINVAL, "unknown tuning operation");
+    if (op == DWF_TUNE_NORMAL && nrhs != 1) fail(DWF_EINVAL, "the single-field operator has nrhs 1");
+    if (nrhs < 1 || nrhs > 64) fail(DWF_EINVAL, "need 1 <= nrhs <= 64");
     Context &c = *ctx;
-    const std::string key = tune_key(c, prec);
+    const int nb = op == DWF_TUNE_BATCHED ? nrhs : 1;
+    LaunchCfg &target = op == DWF_TUNE_BATCHED ? c.cfg_stencil_batch : c.cfg_stencil;
+    const std::string key = tune_key(c, prec, op, nrhs);
     int sb = 0, run = 1;
     double ms = 0;
     if (cache_path && cache_lookup(cache_path, key, sb, run, ms)) {
         if (sb < 0 || (long)sb * c.Ls > 256 || run < 1) fail(DWF_EINVAL, "corrupt tune cache entry for " + key);
-        c.cfg_stencil.sb = sb;
-        c.cfg_stencil.run = run;
+        target.sb = sb;
+        target.run = run;
         if (best_ms) *best_ms = ms;
         return DWF_OK;
     }
     // scratch fields, filled with a finite bit pattern
-    const size_t bytes = field_bytes(c, c.n5h, prec);
+    const size_t bytes = nb > 1 ? (size_t)batch_stride(c, prec) * nb : field_bytes(c, c.n5h, prec);
     std::vector<void *> bufs(3, nullptr);
     struct Free {
         std::vector<void *> &b;
@@ -126,8 +137,8 @@ extern "C" dwf_status dwf_tune(dwf_ctx ctx, int prec, const char *cache_path, do
         if ((long)s * c.Ls <= 256 && std::find(sbs.begin(), sbs.end(), s) == sbs.end()) sbs.push_back(s);
     }
     const long work = c.vh;
-    const LaunchCfg saved = c.cfg_stencil;
-    const int reps = work > 100000 ? 5 : 20;
+    const LaunchCfg saved = target;
+    const int reps = work * nb > 100000 ? 5 : 20;
     const long col = column_sites(c);
     // candidates: the context's current schedule first, then the grid of
     // (sites per workgroup, XCD run); whole columns per XCD where they tile
@@ -144,8 +155,8 @@ extern "C" dwf_status dwf_tune(dwf_ctx ctx, int prec, const char *cache_path, do
             if (!dup) cands.push_back(g);
         }
     auto timed = [&](const LaunchCfg &g, int n) {
-        c.cfg_stencil = g;
-        return time_normal_op(c, prec, a, b, m, n);
+        target = g;
+        return time_normal_op(c, prec, a, b, m, n, nb);
     };
     // first pass: every candidate once; second pass: the four fastest and the
     // current schedule, best of three longer runs each, interleaved
@@ -164,8 +175,13 @@ extern "C" dwf_status dwf_tune(dwf_ctx ctx, int prec, const char *cache_path, do
         if (tbest[k] < tbest[pick] && tbest[k] < 0.98 * tbest[0]) pick = k;
     double best = tbest[pick];
     LaunchCfg best_cfg = cands[finals[pick]];
-    c.cfg_stencil = best_cfg;
+    target = best_cfg;
     if (cache_path) cache_store(cache_path, key, best_cfg.sb, best_cfg.run, best);
     if (best_ms) *best_ms = best;
     DWF_API_END
+}
+
+extern "C" dwf_status dwf_tune(dwf_ctx ctx, int prec, const char *cache_path, double *best_ms)
+{
+    return dwf_tune_op(ctx, DWF_TUNE_NORMAL, prec, 1, cache_path, best_ms);
 }

@@ -22,6 +22,8 @@ DWF_SOLVE_F64, DWF_SOLVE_MIXED_F32, DWF_SOLVE_MIXED_F16, DWF_SOLVE_MIXED_BF16 = 
 DWF_K_DHOP, DWF_K_STENCIL, DWF_K_SLOCAL, DWF_K_BLAS, DWF_K_NET = 0, 1, 2, 3, 4
 DWF_NET_FWD_FP32, DWF_NET_FWD_MFMA_BF16 = 0, 1
 DWF_OP_CG, DWF_OP_MULTISHIFT, DWF_OP_RATIONAL, DWF_OP_SCHUR_APPLY = 0, 1, 2, 3
+DWF_SCHED_STENCIL_BATCHED = 8
+DWF_TUNE_NORMAL, DWF_TUNE_BATCHED = 0, 1
 KCLASS_NAMES = {DWF_K_DHOP: "dhop", DWF_K_STENCIL: "stencil", DWF_K_SLOCAL: "slocal",
                 DWF_K_BLAS: "blas", DWF_K_NET: "net"}
 
@@ -125,6 +127,7 @@ SIGNATURES = {
     "dwf_set_tile_schedule": ([_CTX, _I, _I, _I], C.c_int32),
     "dwf_get_tile_schedule": ([_CTX, _I, C.POINTER(_I), C.POINTER(_I)], C.c_int32),
     "dwf_tune": ([_CTX, _I, C.c_char_p, C.POINTER(_D)], C.c_int32),
+    "dwf_tune_op": ([_CTX, _I, _I, _I, C.c_char_p, C.POINTER(_D)], C.c_int32),
     "dwf_stream_copy": ([_CTX, _P, _P, C.c_size_t], C.c_int32),
     "dwf_stream_probe": ([_CTX, _I, _I, _I, _P, _P, _P, C.c_size_t], C.c_int32),
     "dwf_kernel_timing": ([_CTX, _I], C.c_int32),
@@ -429,6 +432,15 @@ def dwf_tune(ctx, prec, cache_path=None):
     """Autotune the stencil schedule for prec; returns the chosen schedule's time (ms)."""
     ms = C.c_double()
     _check(load().dwf_tune(ctx, int(prec), cache_path.encode() if cache_path else None, C.byref(ms)))
+    return ms.value
+
+
+def dwf_tune_op(ctx, op, prec, nrhs=1, cache_path=None):
+    """Autotune the single-field (DWF_TUNE_NORMAL) or batched (DWF_TUNE_BATCHED,
+    nrhs fields) stencil schedule; returns the chosen schedule's time (ms)."""
+    ms = C.c_double()
+    _check(load().dwf_tune_op(ctx, int(op), int(prec), int(nrhs), cache_path.encode() if cache_path else None,
+                              C.byref(ms)))
     return ms.value
 
 
