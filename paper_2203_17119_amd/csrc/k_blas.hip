@@ -245,6 +245,10 @@ __global__ void __launch_bounds__(256) k_cg_update_p(Field r, Field p, Field pou
         load_spinor<S, C>(r, i, rv);
         for (int c = 0; c < 12; c++) pv[c] = rv[c] + beta * pv[c];
         store_spinor<S, C>(pout, i, pv);
+        // A is applied to the direction as stored: the operator then sees the
+        // same vector in its hop terms (through pa) as in its diagonal terms
+        // (through pout), and the solution update uses that vector too
+        storage_round<S, C>(pv);
     } else {
         for (int c = 0; c < 12; c++) pv[c] = mk(C(0), C(0));
     }

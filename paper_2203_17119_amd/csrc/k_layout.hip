@@ -161,7 +161,9 @@ __global__ void k_prepare_links(Geo g, const double2 *gauge, int p, int4 dir, ty
                 else v = mk(U[col * 3 + r].x, -U[col * 3 + r].y);
                 if (zero) v = mk(0.0, 0.0);
                 const long k = (long)d * 9 + r * 3 + col;
-                out[site_major ? j * 72 + k : k * g.vh + j] = pack<S, double>(v);
+                const long idx = site_major ? j * 72 + k : k * g.vh + j;
+                if constexpr (LinkQ15<S>::value) ((uint32_t *)out)[idx] = pack_q15(v.re, v.im);
+                else out[idx] = pack<S, double>(v);
             }
     }
 }

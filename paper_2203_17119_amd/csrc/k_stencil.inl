@@ -407,7 +407,12 @@ __device__ __forceinline__ void stage_links(const StencilKArgs &a, long base, in
                 Vec16 v;
                 v.u = w[k];
 #pragma unroll
-                for (int e = 0; e < P::cpp; e++) lk[site * LK_STRIDE + e0 + e] = unpack<C>(vec_get<S>(v, e));
+                for (int e = 0; e < P::cpp; e++) {
+                    if constexpr (LinkQ15<S>::value)
+                        lk[site * LK_STRIDE + e0 + e] = unpack_q15<C>(((const uint32_t *)&v.u)[e]);
+                    else
+                        lk[site * LK_STRIDE + e0 + e] = unpack<C>(vec_get<S>(v, e));
+                }
             }
         }
     }
@@ -659,6 +664,8 @@ __global__ void __launch_bounds__(256) k_stencil(StencilKArgs a)
         }
     }
     if (valid) store_spinor<S, C, true>(a.out, i, res);
+    // the reduction sees the field as stored (storage rounding applied)
+    if constexpr (RED != 0) storage_round<S, C>(res);
     if constexpr (RED != 0) {
         double n2 = 0;
         if (valid) {
