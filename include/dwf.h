@@ -190,6 +190,12 @@ typedef struct {
     int restart;       /* FGCR restart length m (<= 0: 16)                         */
     int normal;        /* FGCR: 1 solves the normal equations Mpc^+ Mpc, 0 Mpc    */
     int fallback;      /* FGCR: 1 falls back to CG on stagnation / NaN            */
+    int tile_sb;       /* multi-shift: schedule of its batched stencil launches:
+                          0 keeps the context's DWF_SCHED_STENCIL_BATCHED schedule,
+                          > 0 sets it to 4D sites per workgroup (with tile_run),
+                          -1 autotunes it (dwf_tune_op, no cache); a schedule set
+                          or tuned here stays set on the context */
+    int tile_run;      /* multi-shift with tile_sb > 0: XCD run length (>= 1)     */
 } dwf_solver_opts;
 
 typedef struct {

@@ -608,6 +608,19 @@ extern "C" dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *con
             if (!x_odd[j * nshift + k]) fail(DWF_EINVAL, "null solution pointer");
     }
     dwf::Context &c = *ctx;
+    if (o && o->tile_sb != 0) {
+        const int lp = prec_of_mode(o->mode);
+        if (o->tile_sb == -1) {
+            HIPCHECK(hipStreamSynchronize(c.stream));
+            const dwf_status ts = dwf_tune_op(ctx, DWF_TUNE_BATCHED, lp, nrhs, nullptr, nullptr);
+            if (ts != DWF_OK) return ts;
+        } else {
+            if (o->tile_sb < 0 || (long)o->tile_sb * c.Ls > 256 || o->tile_run < 1 || o->tile_run > (1 << 20))
+                fail(DWF_EINVAL, "tile_sb * Ls must be <= 256 and tile_run in [1, 2^20]");
+            c.cfg_stencil_batch.sb = o->tile_sb;
+            c.cfg_stencil_batch.run = o->tile_run;
+        }
+    }
     auto sink = [&](int j, int k, Field x64) { launch_export(c, P_F64, x64, x_odd[j * nshift + k], 0, 0); };
     if (!ms_solve(c, nrhs, b_odd, nshift, shifts, sink, o, st)) return DWF_ENOCONV;
     DWF_API_END

@@ -35,7 +35,8 @@ class dwf_params(C.Structure):
 
 class dwf_solver_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("mode", C.c_int), ("delta", C.c_double),
-                ("x0_is_guess", C.c_int), ("restart", C.c_int), ("normal", C.c_int), ("fallback", C.c_int)]
+                ("x0_is_guess", C.c_int), ("restart", C.c_int), ("normal", C.c_int), ("fallback", C.c_int),
+                ("tile_sb", C.c_int), ("tile_run", C.c_int)]
 
 
 class dwf_solver_stats(C.Structure):
@@ -291,8 +292,9 @@ def dwf_schur_apply_internal_noalloc(ctx, prec, dagger, inp, out):
 
 
 def _opts(tol=1e-8, maxit=0, mode=DWF_SOLVE_F64, delta=0.0, x0_is_guess=False, restart=0, normal=False,
-          fallback=True):
-    return dwf_solver_opts(tol, maxit, mode, delta, int(x0_is_guess), restart, int(normal), int(fallback))
+          fallback=True, tile_sb=0, tile_run=1):
+    return dwf_solver_opts(tol, maxit, mode, delta, int(x0_is_guess), restart, int(normal), int(fallback),
+                           int(tile_sb), int(tile_run))
 
 
 def dwf_cg(ctx, b_full, x_full, **opts):

@@ -43,7 +43,10 @@ def test_tune_record_is_well_formed():
                 continue
             e = json.loads(line)
             assert set(e) == {"key", "sb", "run", "ms"}
-            arch, dims, ls, prec, dirichlet = e["key"].split("/")
+            parts = e["key"].split("/")
+            arch, dims, ls, prec, dirichlet = parts[:5]
+            # the batched (multi-shift) schedule carries the batch size
+            assert len(parts) == 5 or (len(parts) == 6 and parts[5].startswith("batch") and int(parts[5][5:]) >= 1)
             L = [int(v) for v in dims.split("x")]
             Ls = int(ls[2:])
             assert len(L) == 4 and Ls >= 1 and prec[0] == "p" and dirichlet[0] == "d"

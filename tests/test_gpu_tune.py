@@ -84,3 +84,28 @@ def test_tune_argument_errors(case):
         with pytest.raises(dwf.DWFError) as e:
             dwf.dwf_tune_op(case.ctx, *args)
         assert e.value.status == dwf.DWF_EINVAL
+
+
+def test_multishift_tile_schedule_options(case):
+    """dwf_solver_opts.tile_sb / tile_run: a fixed batched schedule and an
+    autotuned one (tile_sb = -1) give bit-identical multi-shift solutions."""
+    T = torch()
+    shifts = synth.rational_shifts(3, 1e-2, 1.0)
+    bs = [to_gpu(case.half(s)) for s in (97, 98)]
+
+    def solve(**kw):
+        xs = [T.empty_like(bs[0]) for _ in range(len(bs) * len(shifts))]
+        s, _ = dwf.dwf_multishift_cg(case.ctx, bs, shifts, xs, tol=1e-9, mode=dwf.DWF_SOLVE_F64, **kw)
+        assert s == dwf.DWF_OK
+        return xs
+
+    a = solve(tile_sb=3, tile_run=2)
+    assert dwf.dwf_get_tile_schedule(case.ctx, dwf.DWF_SCHED_STENCIL_BATCHED) == (3, 2)
+    b = solve(tile_sb=-1)
+    print(f"autotuned batched schedule {dwf.dwf_get_tile_schedule(case.ctx, dwf.DWF_SCHED_STENCIL_BATCHED)}",
+          flush=True)
+    for u, v in zip(a, b):
+        assert T.equal(u, v)
+    with pytest.raises(dwf.DWFError) as e:
+        solve(tile_sb=40, tile_run=1)  # 40 sites x Ls 8 > 256 lanes
+    assert e.value.status == dwf.DWF_EINVAL
