@@ -355,8 +355,8 @@ dwf_status dwf_net_train_step(dwf_net net, int nbatch, const double *const *b_od
  * and the operator applied in BF16 storage, the cycle's residual and solution
  * staying FP32 (other modes: DWF_ENOTSUP).  Restart every
  * o->restart steps (default 16, at most 64) with the residual recomputed.
- * Stagnation means no 10% reduction of the residual norm over max(8 m, 256)
- * steps.  On stagnation or a non-finite residual it falls back to dwf_cg in
+ * Stagnation means no 10% reduction of the true residual norm (the FP64 one
+ * recomputed at the restarts) over max(8 m, 256) steps.  On stagnation or a non-finite residual it falls back to dwf_cg in
  * FP64 when o->fallback (the
  * statistics then say fell_back = 1).  Same source preparation and
  * reconstruction as dwf_cg; canonical FP64 full fields. */
