@@ -222,8 +222,13 @@ dwf_status dwf_cg(dwf_ctx ctx, const double *b_full, double *x_full, const dwf_s
  * rational-function solves of the DD-RHMC one-flavour action, Sec. 2.3.1).
  * b and x are arrays of canonical FP64 odd half fields (device pointers, the
  * pointer arrays themselves in host memory); st has nrhs*nshift entries (may
- * be NULL).  mode DWF_SOLVE_F64 or DWF_SOLVE_MIXED_F32 (FP32 Krylov space with
- * FP64 refinement of every shift). */
+ * be NULL).  mode DWF_SOLVE_F64 or DWF_SOLVE_MIXED_F32 (FP32 Krylov space).
+ * Every solution's residual is then recomputed in FP64.  In MIXED_F32 the
+ * systems that miss the tolerance are refined by defect correction: the FP64
+ * residuals of the right-hand sides of one shift are solved together, in FP32
+ * storage, and the corrections kept in a second FP32 term beside the solution
+ * (up to four passes, then the single-system mixed CG).  st[].reliable_updates
+ * counts a system's refinement iterations. */
 dwf_status dwf_multishift_cg(dwf_ctx ctx, int nrhs, const double *const *b_odd, int nshift,
                              const double *shifts, double *const *x_odd, const dwf_solver_opts *o,
                              dwf_solver_stats *st);

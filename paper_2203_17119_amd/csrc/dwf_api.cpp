@@ -344,7 +344,6 @@ int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduc
     if (alpha_slot >= 0 && (!dagger || nbatch > 1)) fail(DWF_EINVAL, "fused residual update needs Mpc^+, one field");
     ensure_links(c, prec);
     const int nb = std::max(1, nbatch);
-    if ((ws_y.data || ws_ta.data) && nb > 1) fail(DWF_EINVAL, "caller workspaces hold one field");
     Field y = ws_y.data ? ws_y : ws_batch(c, "mpc_y", prec, nb);
     if (nb > 1 && bstride != batch_stride(c, prec)) fail(DWF_EINVAL, "batched fields must use the batch stride");
     auto batched = [&](StencilSpec &s) {

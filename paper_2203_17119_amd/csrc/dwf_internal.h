@@ -350,7 +350,8 @@ void launch_stream_probe(Context &c, int kind, int unroll, bool nt, const void *
 // With dagger and alpha_slot >= 0 the result is not stored: out holds a
 // residual r on entry and becomes r - dscal[alpha_slot] Mpc^+ in, with the
 // partials of its |r|^2 (reduce implied).  The intermediate fields are
-// context workspaces unless ws_ta and ws_y (one field each) are given; ws_ta
+// context workspaces unless ws_ta and ws_y are given (one field each, or with
+// nbatch > 1 batches of at least nbatch members at the batch stride); ws_ta
 // is needed only when in_is_A_applied is false and dagger is not set.
 int apply_mpc(Context &c, int prec, bool dagger, Field in, Field out, bool reduce, bool in_is_A_applied = false,
               Field pa = Field{}, int nbatch = 1, long bstride = 0, int alpha_slot = -1, Field ws_ta = Field{},

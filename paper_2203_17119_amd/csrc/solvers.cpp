@@ -12,6 +12,7 @@
 // decisions.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <functional>
@@ -421,7 +422,10 @@ std::vector<WsKey> plan_multishift(int mode, int nrhs, int nshift)
     k.push_back({"mpc_ta", lp, nrhs, 0});
     for (const char *n : {"ms_b64", "ms_x64", "ms_t1", "ms_t2"}) k.push_back({n, P_F64, 0, 0});
     k.push_back({"ms_state", -1, 0, ms_state_bytes(nrhs, nshift)});
-    // the FP64 residual check and the refinement of systems that missed the tolerance
+    // the FP64 residual check and the refinement of systems that missed the
+    // tolerance: batched corrections, then the single-system CG
+    if (lp != P_F64)
+        for (const char *n : {"msr_E", "msr_D"}) k.push_back({n, lp, nrhs, 0});
     plan_cg_core(k, mode);
     return k;
 }
@@ -435,39 +439,30 @@ namespace dwf {
 // for the next system, so the sink consumes it on the stream before returning.
 using MsSink = std::function<void(int j, int k, Field x64)>;
 
-// Multi-shift CG on (Mpc^+ Mpc + shifts[k]) x_{j,k} = b_j for canonical FP64
-// odd fields b_odd[j] (device).  Arguments are validated by the caller.
-// Returns true when every system met the tolerance in FP64.
-static bool ms_solve(Context &c, int nrhs, const double *const *b_odd, int nshift, const double *shifts,
-                     const MsSink &sink, const dwf_solver_opts *o, dwf_solver_stats *st)
+// Buffers of one multi-shift CG run: per right-hand side (capacity >= nrhs) the
+// sources B, residuals R, A p, the operator's intermediates M, Y, TA; per
+// member (shift k, rhs j: member k nrhs + j, capacity >= nrhs nshift) the
+// solutions X and two direction sets (the current directions, and the new
+// ones, which hold the previous directions while their solution updates are
+// pending).  All use the batch stride of their precision.
+struct MsBufs {
+    Field B, R, AP, M, Y, TA;
+    Field X, P[2];
+};
+
+// Multi-shift CG iterations on (Mpc^+ Mpc + shifts[k]) X_{k,j} = B_j in storage
+// precision lp, from X = 0, until |r_{j,k}| <= rtol[j] |B_j| for every member or
+// maxi iterations.  its[q]: iterations of member q; act[q]: still active at
+// the end.  The host reads the members' activity every poll iterations.
+// Returns the iterations run.
+static int ms_krylov(Context &c, int lp, int nrhs, int nshift, const double *shifts, const MsBufs &bf,
+                     const double *rtol, int maxi, int poll, std::vector<int> &its, std::vector<int> &act)
 {
-    double tol, delta;
-    int maxit, mode;
-    bool guess;
-    fill_opts(o, tol, maxit, mode, delta, guess);
-    if (mode != DWF_SOLVE_F64 && mode != DWF_SOLVE_MIXED_F32)
-        fail(DWF_ENOTSUP, "multi-shift mode must be F64 or MIXED_F32");
-    const int lp = prec_of_mode(mode);
-    const bool mixed = lp != P_F64;
-    HIPCHECK(hipStreamSynchronize(c.stream));
-    const double t0 = now();
+    const long stride = batch_stride(c, lp);
+    const int nq = nrhs * nshift;
     int kmin = 0;
     for (int k = 1; k < nshift; k++)
         if (shifts[k] < shifts[kmin]) kmin = k;
-    const long stride = batch_stride(c, lp);
-    const int nq = nrhs * nshift;
-    // batches: B, R, AP, M over rhs; X and the direction sets over (shift, rhs), member k*nrhs + j
-    Field B = ws_batch(c, "ms_B", lp, nrhs), R = ws_batch(c, "ms_R", lp, nrhs);
-    Field AP = ws_batch(c, "ms_AP", lp, nrhs), M = ws_batch(c, "ms_M", lp, nrhs);
-    // two direction sets: the current directions, and the new ones (which hold
-    // the previous directions while their solution updates are pending)
-    Field X = ws_batch(c, "ms_X", lp, nq);
-    Field Pset[2] = {ws_batch(c, "ms_P", lp, nq), ws_batch(c, "ms_P2", lp, nq)};
-    Field b64 = ws_field(c, "ms_b64", P_F64), x64 = ws_field(c, "ms_x64", P_F64);
-    for (int j = 0; j < nrhs; j++) {
-        launch_import(c, P_F64, b_odd[j], b64, 0, 0);
-        launch_convert(c, P_F64, b64, lp, member(B, j, stride));
-    }
     // device state
     double *db = (double *)ws_raw(c, "ms_state", ms_state_bytes(nrhs, nshift));
     MsState s;
@@ -488,12 +483,12 @@ static bool ms_solve(Context &c, int nrhs, const double *const *b_odd, int nshif
     {
         std::vector<double> h(7 * nrhs + 6 * nq + nshift + 4 * nq, 0.0);
         std::vector<int> hi(2 * nq, 0);
-        ms_launch_norm2(c, lp, B, nrhs, stride, c.dscal + 16);
+        ms_launch_norm2(c, lp, bf.B, nrhs, stride, c.dscal + 16);
         read_scalars(c, 16, nrhs);
         for (int j = 0; j < nrhs; j++) {
-            h[j] = c.hscal[16 + j];                         // rho
-            h[3 * nrhs + j] = 1.0;                          // alpha_old
-            h[5 * nrhs + j] = tol * std::sqrt(c.hscal[16 + j]);  // target
+            h[j] = c.hscal[16 + j];                              // rho
+            h[3 * nrhs + j] = 1.0;                               // alpha_old
+            h[5 * nrhs + j] = rtol[j] * std::sqrt(c.hscal[16 + j]);  // target
         }
         for (int q = 0; q < nq; q++) h[7 * nrhs + q] = h[7 * nrhs + nq + q] = 1.0;  // zeta, zeta_old
         for (int k = 0; k < nshift; k++) h[7 * nrhs + 6 * nq + k] = shifts[k];
@@ -501,27 +496,27 @@ static bool ms_solve(Context &c, int nrhs, const double *const *b_odd, int nshif
         HIPCHECK(hipMemcpy(db, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
         HIPCHECK(hipMemcpy(s.active, hi.data(), hi.size() * sizeof(int), hipMemcpyHostToDevice));
     }
-    for (int j = 0; j < nrhs; j++) launch_copy(c, lp, member(B, j, stride), member(R, j, stride));
+    for (int j = 0; j < nrhs; j++) launch_copy(c, lp, member(bf.B, j, stride), member(bf.R, j, stride));
     for (int q = 0; q < nq; q++) {
-        launch_zero(c, lp, member(X, q, stride));
-        launch_copy(c, lp, member(B, q % nrhs, stride), member(Pset[0], q, stride));
+        launch_zero(c, lp, member(bf.X, q, stride));
+        launch_copy(c, lp, member(bf.B, q % nrhs, stride), member(bf.P[0], q, stride));
     }
-    const int maxi = maxit > 0 ? maxit : 100000;
-    std::vector<int> act(nq);
-    int it = 0, cur = 0;  // Pset[cur] holds the current directions
+    act.assign(nq, 1);
+    its.assign(nq, 0);
+    int it = 0, cur = 0;  // bf.P[cur] holds the current directions
     while (it < maxi) {
-        const Field Pbase = member(Pset[cur], kmin * nrhs, stride);
-        apply_mpc(c, lp, false, Pbase, M, false, false, Field{}, nrhs, stride);
-        apply_mpc(c, lp, true, M, AP, false, false, Field{}, nrhs, stride);
-        if (shifts[kmin] != 0.0) ms_launch_axpy(c, lp, shifts[kmin], Pbase, AP, nrhs, stride);
-        ms_launch_redot(c, lp, Pbase, AP, nrhs, stride, s.pap);
+        const Field Pbase = member(bf.P[cur], kmin * nrhs, stride);
+        apply_mpc(c, lp, false, Pbase, bf.M, false, false, Field{}, nrhs, stride, -1, bf.TA, bf.Y);
+        apply_mpc(c, lp, true, bf.M, bf.AP, false, false, Field{}, nrhs, stride, -1, bf.TA, bf.Y);
+        if (shifts[kmin] != 0.0) ms_launch_axpy(c, lp, shifts[kmin], Pbase, bf.AP, nrhs, stride);
+        ms_launch_redot(c, lp, Pbase, bf.AP, nrhs, stride, s.pap);
         it++;
         MsState si = s;
         si.coef = coefs[cur];
-        ms_launch_step(c, lp, si, R, AP, X, Pset[cur], Pset[1 - cur], coefs[1 - cur], nrhs, nshift, kmin, stride,
-                       rho_new, it);
+        ms_launch_step(c, lp, si, bf.R, bf.AP, bf.X, bf.P[cur], bf.P[1 - cur], coefs[1 - cur], nrhs, nshift, kmin,
+                       stride, rho_new, it);
         cur = 1 - cur;
-        if (it % 8 == 0 || it == maxi) {
+        if (it % poll == 0 || it == maxi) {
             HIPCHECK(hipMemcpyAsync(act.data(), s.active, nq * sizeof(int), hipMemcpyDeviceToHost, c.stream));
             HIPCHECK(hipStreamSynchronize(c.stream));
             int n = 0;
@@ -530,49 +525,152 @@ static bool ms_solve(Context &c, int nrhs, const double *const *b_odd, int nshif
         }
     }
     // an odd last iteration left its solution updates pending
-    if (it % 2 == 1) ms_launch_flush(c, lp, X, Pset[1 - cur], coefs[1 - cur], nrhs, nshift, stride);
-    std::vector<int> its(nq);
+    if (it % 2 == 1) ms_launch_flush(c, lp, bf.X, bf.P[1 - cur], coefs[1 - cur], nrhs, nshift, stride);
     HIPCHECK(hipMemcpy(its.data(), s.iters, nq * sizeof(int), hipMemcpyDeviceToHost));
     HIPCHECK(hipMemcpy(act.data(), s.active, nq * sizeof(int), hipMemcpyDeviceToHost));
-    const double t1 = now();
-    // FP64 true residual of every (rhs, shift); low-precision solutions are refined
-    bool all_ok = true;
-    Field t1f = ws_field(c, "ms_t1", P_F64), t2f = ws_field(c, "ms_t2", P_F64);
+    for (int q = 0; q < nq; q++)
+        if (act[q]) its[q] = it;
+    return it;
+}
+
+// Multi-shift CG on (Mpc^+ Mpc + shifts[k]) x_{j,k} = b_j for canonical FP64
+// odd fields b_odd[j] (device).  Arguments are validated by the caller.
+// Returns true when every system met the tolerance in FP64.
+//
+// Every solution's residual is then recomputed in FP64.  In MIXED_F32 the
+// solutions are refined by defect correction, batched over the right-hand
+// sides of one shift: the FP64 residuals of the systems that missed the
+// tolerance are solved together by the same CG iteration (one shift) in FP32
+// storage, warm-started in the sense that only the correction is solved for,
+// and the corrections accumulate in a second FP32 term beside the first
+// solve's solution (x = X + E, summed in FP64), so that the solution is not
+// limited by FP32 rounding of x itself.  A system still missing the tolerance
+// after kRefinePasses corrections is finished by the single-system mixed CG.
+static bool ms_solve(Context &c, int nrhs, const double *const *b_odd, int nshift, const double *shifts,
+                     const MsSink &sink, const dwf_solver_opts *o, dwf_solver_stats *st)
+{
+    constexpr int kRefinePasses = 4;
+    double tol, delta;
+    int maxit, mode;
+    bool guess;
+    fill_opts(o, tol, maxit, mode, delta, guess);
+    if (mode != DWF_SOLVE_F64 && mode != DWF_SOLVE_MIXED_F32)
+        fail(DWF_ENOTSUP, "multi-shift mode must be F64 or MIXED_F32");
+    const int lp = prec_of_mode(mode);
+    const bool mixed = lp != P_F64;
+    HIPCHECK(hipStreamSynchronize(c.stream));
+    const double t0 = now();
+    const long stride = batch_stride(c, lp);
+    const int nq = nrhs * nshift;
+    MsBufs bf;
+    bf.B = ws_batch(c, "ms_B", lp, nrhs);
+    bf.R = ws_batch(c, "ms_R", lp, nrhs);
+    bf.AP = ws_batch(c, "ms_AP", lp, nrhs);
+    bf.M = ws_batch(c, "ms_M", lp, nrhs);
+    bf.Y = ws_batch(c, "mpc_y", lp, nrhs);
+    bf.TA = ws_batch(c, "mpc_ta", lp, nrhs);
+    bf.X = ws_batch(c, "ms_X", lp, nq);
+    bf.P[0] = ws_batch(c, "ms_P", lp, nq);
+    bf.P[1] = ws_batch(c, "ms_P2", lp, nq);
+    Field b64 = ws_field(c, "ms_b64", P_F64), x64 = ws_field(c, "ms_x64", P_F64);
+    std::vector<double> b2(nrhs);
     for (int j = 0; j < nrhs; j++) {
         launch_import(c, P_F64, b_odd[j], b64, 0, 0);
-        const double b2 = norm2(c, P_F64, b64);
-        for (int k = 0; k < nshift; k++) {
-            const int q = k * nrhs + j;
-            launch_convert(c, lp, member(X, q, stride), P_F64, x64);
-            int extra = 0;
-            auto residual = [&]() {
-                apply_mpc(c, P_F64, false, x64, t1f, false);
-                apply_mpc(c, P_F64, true, t1f, t2f, false);
-                launch_axpby(c, P_F64, 1.0, t2f, shifts[k], x64, t2f);
-                launch_axpby(c, P_F64, 1.0, b64, -1.0, t2f, t2f);
-                return std::sqrt(norm2(c, P_F64, t2f) / b2);
-            };
-            double res = b2 > 0 ? residual() : 0.0;
-            if (b2 > 0 && (mixed || res > tol)) {
-                if (res > tol) {
-                    CoreStats cs = cg_core(c, mixed ? DWF_SOLVE_MIXED_F32 : DWF_SOLVE_F64, shifts[k], b64, x64, tol,
-                                           maxi, delta, true);
-                    extra = cs.iters;
-                    res = cs.rel_res;
+        b2[j] = norm2(c, P_F64, b64);
+        launch_convert(c, P_F64, b64, lp, member(bf.B, j, stride));
+    }
+    const int maxi = maxit > 0 ? maxit : 100000;
+    std::vector<int> its, act;
+    const std::vector<double> rtol(nrhs, tol);
+    ms_krylov(c, lp, nrhs, nshift, shifts, bf, rtol.data(), maxi, 8, its, act);
+    const double t1 = now();
+    // FP64 true residual of every (rhs, shift), and the refinement of the
+    // systems that missed the tolerance
+    Field t1f = ws_field(c, "ms_t1", P_F64), t2f = ws_field(c, "ms_t2", P_F64);
+    // refinement: the first solve's sources and direction sets are free now;
+    // E (corrections so far) and D (this pass's corrections) per rhs
+    MsBufs rb = bf;
+    Field E, D;
+    if (mixed) {
+        E = ws_batch(c, "msr_E", lp, nrhs);
+        D = ws_batch(c, "msr_D", lp, nrhs);
+        rb.X = D;
+    }
+    // x64 = X_q (+ E_j): the solution of system (j, k) in FP64
+    auto assemble = [&](int j, int k, bool with_e) {
+        launch_convert(c, lp, member(bf.X, k * nrhs + j, stride), P_F64, x64);
+        if (with_e) {
+            launch_convert(c, lp, member(E, j, stride), P_F64, t1f);
+            launch_axpby(c, P_F64, 1.0, x64, 1.0, t1f, x64);
+        }
+    };
+    // t2f = b_j - (Mpc^+ Mpc + shift) x64; returns |t2f| / |b_j|
+    auto residual = [&](int j, double shift) {
+        launch_import(c, P_F64, b_odd[j], b64, 0, 0);
+        apply_mpc(c, P_F64, false, x64, t1f, false);
+        apply_mpc(c, P_F64, true, t1f, t2f, false);
+        launch_axpby(c, P_F64, 1.0, t2f, shift, x64, t2f);
+        launch_axpby(c, P_F64, 1.0, b64, -1.0, t2f, t2f);
+        return std::sqrt(norm2(c, P_F64, t2f) / b2[j]);
+    };
+    bool all_ok = true;
+    std::vector<int> extra(nrhs);
+    std::vector<double> res(nrhs);
+    for (int k = 0; k < nshift; k++) {
+        std::fill(extra.begin(), extra.end(), 0);
+        std::vector<int> todo;
+        for (int j = 0; j < nrhs; j++) todo.push_back(j);
+        bool with_e = false;
+        for (int pass = 0; !todo.empty(); pass++) {
+            std::vector<int> fails;
+            std::vector<double> rt;
+            for (int j : todo) {
+                assemble(j, k, with_e);
+                res[j] = b2[j] > 0 ? residual(j, shifts[k]) : 0.0;
+                if (res[j] > tol && mixed && pass < kRefinePasses) {
+                    // the correction's source, and its relative target: 90% of the
+                    // tolerance (the FP32 recurrence tracks the FP64 residual of the
+                    // correction to about 1e-7 of |r|), not below what FP32
+                    // storage resolves
+                    launch_convert(c, P_F64, t2f, lp, member(rb.B, (int)fails.size(), stride));
+                    rt.push_back(std::max(0.9 * tol / res[j], 1e-5));
+                    fails.push_back(j);
+                    continue;
+                }
+                if (res[j] > tol) {
+                    // finish with the single-system CG, warm-started at x64
+                    launch_import(c, P_F64, b_odd[j], b64, 0, 0);
+                    CoreStats cs = cg_core(c, mode, shifts[k], b64, x64, tol, maxi, delta, true);
+                    extra[j] += cs.iters;
+                    res[j] = cs.rel_res;
+                }
+                sink(j, k, x64);
+                const bool ok = res[j] <= tol * 1.0000001;
+                all_ok = all_ok && ok;
+                if (st) {
+                    const int q = k * nrhs + j;
+                    dwf_solver_stats &sv = st[j * nshift + k];
+                    sv = dwf_solver_stats{};
+                    sv.iters = its[q] + extra[j];
+                    sv.reliable_updates = extra[j];
+                    sv.converged = ok;
+                    sv.res_normal = res[j];
+                    sv.t_solve = t1 - t0;
                 }
             }
-            sink(j, k, x64);
-            const bool ok = res <= tol * 1.0000001;
-            all_ok = all_ok && ok;
-            if (st) {
-                dwf_solver_stats &sv = st[j * nshift + k];
-                sv = dwf_solver_stats{};
-                sv.iters = (act[q] ? it : its[q]) + extra;
-                sv.reliable_updates = extra;
-                sv.converged = ok;
-                sv.res_normal = res;
-                sv.t_solve = t1 - t0;
+            if (fails.empty()) break;
+            const int nf = (int)fails.size();
+            std::vector<int> its2, act2;
+            // short solves: the activity is read every second iteration
+            ms_krylov(c, lp, nf, 1, &shifts[k], rb, rt.data(), maxi, 2, its2, act2);
+            for (int i = 0; i < nf; i++) {
+                const int j = fails[i];
+                if (!with_e) launch_zero(c, lp, member(E, j, stride));
+                launch_axpby(c, lp, 1.0, member(E, j, stride), 1.0, member(D, i, stride), member(E, j, stride));
+                extra[j] += its2[i];
             }
+            with_e = true;
+            todo = fails;
         }
     }
     HIPCHECK(hipStreamSynchronize(c.stream));
