@@ -245,15 +245,18 @@ struct MsState {
     double *shifts;                                               // [nshift]
 };
 void ms_launch_norm2(Context &c, int prec, Field a, int nb, long stride, double *out);
-void ms_launch_redot(Context &c, int prec, Field a, Field b, int nb, long stride, double *out);
-void ms_launch_axpy(Context &c, int prec, double a, Field x, Field y, int nb, long stride);
-// One multi-shift step: alpha, r -= alpha A p, |r|^2, the shift recurrences
-// (coefficients into s.coef), then the shifted directions into Pn.  Solution
-// updates go in pairs (see k_ms_update_b): an odd it leaves its update pending
-// (direction in P, coefficients in s.coef), the next applies it from Pn with
-// the coefficients cprev, and its own.
+// out[j] = Re<a_j, b_j> + sigma |a_j|^2
+void ms_launch_redot(Context &c, int prec, Field a, Field b, int nb, long stride, double *out, double sigma = 0.0);
+// One multi-shift step: alpha, r -= alpha (ap + sigma pbase) (ap: the normal
+// operator applied to the carrier's directions pbase, sigma: the carrier's
+// shift), |r|^2, the shift recurrences (coefficients into s.coef), then the
+// shifted directions into Pn and the operator's first factor of the carrier's
+// new directions into ta.  Solution updates go in pairs (see k_ms_update_b):
+// an odd it leaves its update pending (direction in P, coefficients in
+// s.coef), the next applies it from Pn with the coefficients cprev, and its own.
 void ms_launch_step(Context &c, int prec, const MsState &s, Field r, Field ap, Field X, Field P, Field Pn,
-                    const double *cprev, int nrhs, int nshift, int kmin, long stride, double *rho_new, int it);
+                    const double *cprev, int nrhs, int nshift, int kmin, long stride, double *rho_new, int it,
+                    Field pbase, double sigma, Field ta);
 // x += a p for every member whose coefficients in coef are on
 void ms_launch_flush(Context &c, int prec, Field X, Field P, const double *coef, int nrhs, int nshift, long stride);
 

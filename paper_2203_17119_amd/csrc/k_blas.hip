@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(BS) k_ms_update(int nshift, const Field *x, co
 // A shift freezes once |zeta| |r| <= tol |b| and its zeta is not updated
 // further; the lowest shift carries the Krylov space and freezes last.
 
-// batched |a_j|^2 and <a_j, b_j>: member blockIdx.y, partial[j][block]
+// batched |a_j|^2 and Re<a_j, b_j> + sigma |a_j|^2: member blockIdx.y, partial[j][block]
 template <typename S>
 __global__ void __launch_bounds__(BS) k_norm2_b(Field a, long stride, double *partial)
 {
@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(BS) k_norm2_b(Field a, long stride, double *pa
 }
 
 template <typename S>
-__global__ void __launch_bounds__(BS) k_redot_b(Field a, Field b, long stride, double *partial)
+__global__ void __launch_bounds__(BS) k_redot_b(Field a, Field b, long stride, double sigma, double *partial)
 {
     a = member(a, blockIdx.y, stride);
     b = member(b, blockIdx.y, stride);
@@ -380,7 +380,10 @@ __global__ void __launch_bounds__(BS) k_redot_b(Field a, Field b, long stride, d
         cx<C> u[12], v[12];
         load_spinor<S, C>(a, i, u);
         load_spinor<S, C>(b, i, v);
-        for (int c = 0; c < 12; c++) t += double(u[c].re) * double(v[c].re) + double(u[c].im) * double(v[c].im);
+        for (int c = 0; c < 12; c++) {
+            const double ur = double(u[c].re), ui = double(u[c].im);
+            t += ur * (double(v[c].re) + sigma * ur) + ui * (double(v[c].im) + sigma * ui);
+        }
     }
     t = block_sum(t);
     if (threadIdx.x == 0) partial[(long)blockIdx.y * gridDim.x + blockIdx.x] = t;
@@ -792,28 +795,14 @@ __global__ void __launch_bounds__(BS) k_gs_combine_bf(float4 *x, const uint2 *co
     }
 }
 
-// y_j += a x_j (host scalar), batched
+// r_j -= alpha_j (ap_j + sigma p_j) with alpha_j from the device, partial |r_j|^2
 template <typename S>
-__global__ void __launch_bounds__(BS) k_axpy_b(double a, Field x, Field y, long stride)
-{
-    x = member(x, blockIdx.y, stride);
-    y = member(y, blockIdx.y, stride);
-    using C = Cof<S>;
-    const long i = blockIdx.x * (long)BS + threadIdx.x;
-    if (i >= x.n) return;
-    cx<C> u[12], v[12];
-    load_spinor<S, C>(x, i, u);
-    load_spinor<S, C>(y, i, v);
-    for (int c = 0; c < 12; c++) v[c] = v[c] + C(a) * u[c];
-    store_spinor<S, C>(y, i, v);
-}
-
-// r_j -= alpha_j ap_j with alpha_j from the device, partial |r_j|^2
-template <typename S>
-__global__ void __launch_bounds__(BS) k_ms_residual(Field r, Field ap, long stride, const double *alpha, double *partial)
+__global__ void __launch_bounds__(BS) k_ms_residual(Field r, Field ap, Field p, double sigma, long stride,
+                                                     const double *alpha, double *partial)
 {
     r = member(r, blockIdx.y, stride);
     ap = member(ap, blockIdx.y, stride);
+    p = member(p, blockIdx.y, stride);
     using C = Cof<S>;
     const C al = C(alpha[blockIdx.y]);
     const long i = blockIdx.x * (long)BS + threadIdx.x;
@@ -822,6 +811,11 @@ __global__ void __launch_bounds__(BS) k_ms_residual(Field r, Field ap, long stri
         cx<C> u[12], v[12];
         load_spinor<S, C>(r, i, u);
         load_spinor<S, C>(ap, i, v);
+        if (sigma != 0.0) {
+            cx<C> w[12];
+            load_spinor<S, C>(p, i, w);
+            for (int c = 0; c < 12; c++) v[c] = v[c] + C(sigma) * w[c];
+        }
         for (int c = 0; c < 12; c++) {
             u[c] = u[c] - al * v[c];
             t += double(u[c].re) * double(u[c].re) + double(u[c].im) * double(u[c].im);
@@ -894,46 +888,71 @@ __global__ void k_ms_recur(MsState s, const double *rho_new, int nrhs, int nshif
 // is left pending (p stays in P); with flush = 1 x += a' p' of the previous
 // iteration (coefficients cprev, direction in Pn, read before pnew overwrites
 // it) and then x += a p are applied in one pass over x.  A member frozen in
-// this iteration still receives its pending update.
+// this iteration still receives its pending update.  For the Krylov carrier
+// (shift kmin) the kernel also writes ta = (b + c P5) pnew, the operator's
+// first factor, so that the next operator application starts from it; the
+// workgroup holds whole fifth-dimension columns (Ls x sb lanes, one 4D site
+// per row) and exchanges the carrier's new direction through LDS.
 template <typename S>
-__global__ void __launch_bounds__(BS) k_ms_update_b(int nrhs, int nshift, Field X, Field P, Field Pn, Field r,
-                                                     long stride, const double *coef, const double *cprev, int flush)
+__global__ void __launch_bounds__(256) k_ms_update_b(int nrhs, int nshift, int kmin, Field X, Field P, Field Pn,
+                                                     Field r, Field ta, long stride, const double *coef,
+                                                     const double *cprev, int flush, long vh, int Ls, double bb,
+                                                     double cc, double mf)
 {
     using C = Cof<S>;
     const int j = blockIdx.y;
+    const int s = threadIdx.x, l = threadIdx.y;
+    const long cb = (long)blockIdx.x * blockDim.y + l;
+    const bool valid = cb < vh;
+    const long i = cb * Ls + s;
+    extern __shared__ unsigned char smem[];
+    cx<C> *lds = (cx<C> *)smem;
     r = member(r, j, stride);
-    const long i = blockIdx.x * (long)BS + threadIdx.x;
-    if (i >= r.n) return;
     cx<C> rv[12];
-    load_spinor<S, C>(r, i, rv);
+    if (valid) load_spinor<S, C>(r, i, rv);
     for (int k = 0; k < nshift; k++) {
         const long q = k * nrhs + j;
         const double *cf = coef + 4 * q;
+        // both flags depend on the member only: the branch is uniform
         const bool on = cf[3] != 0.0, pend = flush && cprev[4 * q + 3] != 0.0;
         if (!on && !pend) continue;
         const Field p = member(P, q, stride), pn = member(Pn, q, stride);
         cx<C> pv[12];
-        if (on) load_spinor<S, C>(p, i, pv);
-        if (flush) {
-            const Field x = member(X, q, stride);
-            cx<C> xv[12];
-            load_spinor<S, C>(x, i, xv);
-            if (pend) {
-                const C ap = C(cprev[4 * q]);
-                cx<C> qv[12];
-                load_spinor<S, C>(pn, i, qv);
-                for (int c = 0; c < 12; c++) xv[c] = xv[c] + ap * qv[c];
+        if (valid) {
+            if (on) load_spinor<S, C>(p, i, pv);
+            if (flush) {
+                const Field x = member(X, q, stride);
+                cx<C> xv[12];
+                load_spinor<S, C>(x, i, xv);
+                if (pend) {
+                    const C ap = C(cprev[4 * q]);
+                    cx<C> qv[12];
+                    load_spinor<S, C>(pn, i, qv);
+                    for (int c = 0; c < 12; c++) xv[c] = xv[c] + ap * qv[c];
+                }
+                if (on) {
+                    const C a = C(cf[0]);
+                    for (int c = 0; c < 12; c++) xv[c] = xv[c] + a * pv[c];
+                }
+                store_spinor<S, C>(x, i, xv);
             }
             if (on) {
-                const C a = C(cf[0]);
-                for (int c = 0; c < 12; c++) xv[c] = xv[c] + a * pv[c];
+                const C z = C(cf[1]), b = C(cf[2]);
+                for (int c = 0; c < 12; c++) pv[c] = z * rv[c] + b * pv[c];
+                store_spinor<S, C>(pn, i, pv);
+                storage_round<S, C>(pv);
             }
-            store_spinor<S, C>(x, i, xv);
         }
-        if (on) {
-            const C z = C(cf[1]), b = C(cf[2]);
-            for (int c = 0; c < 12; c++) pv[c] = z * rv[c] + b * pv[c];
-            store_spinor<S, C>(pn, i, pv);
+        if (k == kmin && on) {
+            for (int c = 0; c < 12; c++) lds[(l * Ls + s) * 12 + c] = valid ? pv[c] : mk(C(0), C(0));
+            __syncthreads();
+            if (valid) {
+                const cx<C> *blk = lds + l * Ls * 12;
+                cx<C> out[12];
+                for (int c = 0; c < 12; c++)
+                    out[c] = C(bb) * pv[c] + C(cc) * shift5<C>(blk, c, s, Ls, false, C(mf));
+                store_spinor<S, C>(member(ta, j, stride), i, out);
+            }
         }
     }
 }
@@ -970,40 +989,40 @@ void ms_launch_norm2(Context &c, int prec, Field a, int nb, long stride, double 
     HIPCHECK(hipGetLastError());
 }
 
-void ms_launch_redot(Context &c, int prec, Field a, Field b, int nb, long stride, double *out)
+void ms_launch_redot(Context &c, int prec, Field a, Field b, int nb, long stride, double *out, double sigma)
 {
     const long np = (a.n + BS - 1) / BS;
     if (np * nb > c.partials_len) fail(DWF_EINVAL, "reduction buffer too small");
     Timer tm(c, DWF_K_BLAS, nb * 2 * (12.0 * elem_bytes(prec)) * a.n, 0);
-    DWF_DISPATCH(prec, k_redot_b, dim3((unsigned)np, nb), dim3(BS), 0, a, b, stride, c.partials);
+    DWF_DISPATCH(prec, k_redot_b, dim3((unsigned)np, nb), dim3(BS), 0, a, b, stride, sigma, c.partials);
     hipLaunchKernelGGL(k_finish_b, dim3(nb), dim3(BS), 0, c.stream, c.partials, (int)np, out);
     HIPCHECK(hipGetLastError());
 }
 
-void ms_launch_axpy(Context &c, int prec, double a, Field x, Field y, int nb, long stride)
-{
-    Timer tm(c, DWF_K_BLAS, nb * 3 * (12.0 * elem_bytes(prec)) * x.n, 0);
-    DWF_DISPATCH(prec, k_axpy_b, dim3((unsigned)((x.n + BS - 1) / BS), nb), dim3(BS), 0, a, x, y, stride);
-}
-
 void ms_launch_step(Context &c, int prec, const MsState &s, Field r, Field ap, Field X, Field P, Field Pn,
-                    const double *cprev, int nrhs, int nshift, int kmin, long stride, double *rho_new, int it)
+                    const double *cprev, int nrhs, int nshift, int kmin, long stride, double *rho_new, int it,
+                    Field pbase, double sigma, Field ta)
 {
     const long np = (r.n + BS - 1) / BS;
     if (np * nrhs > c.partials_len) fail(DWF_EINVAL, "reduction buffer too small");
+    if (r.n != c.n5h) fail(DWF_EINVAL, "multi-shift fields must be half fields of the context");
     hipLaunchKernelGGL(k_ms_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, c.stream, s, nrhs, nshift);
     {
-        Timer tm(c, DWF_K_BLAS, nrhs * 3 * (12.0 * elem_bytes(prec)) * r.n, 0);
-        DWF_DISPATCH(prec, k_ms_residual, dim3((unsigned)np, nrhs), dim3(BS), 0, r, ap, stride, s.alpha, c.partials);
+        Timer tm(c, DWF_K_BLAS, nrhs * (sigma != 0.0 ? 4 : 3) * (12.0 * elem_bytes(prec)) * r.n, 0);
+        DWF_DISPATCH(prec, k_ms_residual, dim3((unsigned)np, nrhs), dim3(BS), 0, r, ap, pbase, sigma, stride, s.alpha,
+                     c.partials);
     }
     hipLaunchKernelGGL(k_finish_b, dim3(nrhs), dim3(BS), 0, c.stream, c.partials, (int)np, rho_new);
     hipLaunchKernelGGL(k_ms_recur, dim3(nrhs), dim3(64), 0, c.stream, s, rho_new, nrhs, nshift, kmin, it);
     HIPCHECK(hipGetLastError());
     // pairs of iterations: the first (odd it) leaves its solution update pending
     const int flush = (it % 2 == 0) ? 1 : 0;
-    Timer tm(c, DWF_K_BLAS, nrhs * (1 + (flush ? 5.0 : 2.0) * nshift) * (12.0 * elem_bytes(prec)) * r.n, 0);
-    DWF_DISPATCH(prec, k_ms_update_b, dim3((unsigned)np, nrhs), dim3(BS), 0, nrhs, nshift, X, P, Pn, r, stride, s.coef,
-                 cprev, flush);
+    const int Ls = c.Ls, sb = default_sb(c);
+    const long nblk = (c.vh + sb - 1) / sb;
+    const size_t lds = (size_t)sb * Ls * 12 * (prec == P_F64 ? 16 : 8);
+    Timer tm(c, DWF_K_BLAS, nrhs * (2 + (flush ? 5.0 : 2.0) * nshift) * (12.0 * elem_bytes(prec)) * r.n, 0);
+    DWF_DISPATCH(prec, k_ms_update_b, dim3((unsigned)nblk, nrhs), dim3(Ls, sb), lds, nrhs, nshift, kmin, X, P, Pn, r,
+                 ta, stride, s.coef, cprev, flush, c.vh, Ls, c.p.b, c.p.c, c.p.mf);
 }
 
 void ms_launch_flush(Context &c, int prec, Field X, Field P, const double *coef, int nrhs, int nshift, long stride)

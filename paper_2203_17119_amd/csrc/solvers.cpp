@@ -501,20 +501,24 @@ static int ms_krylov(Context &c, int lp, int nrhs, int nshift, const double *shi
         launch_zero(c, lp, member(bf.X, q, stride));
         launch_copy(c, lp, member(bf.B, q % nrhs, stride), member(bf.P[0], q, stride));
     }
+    // the operator's first factor (b + c P5) of the carrier's directions; the
+    // step kernel keeps it up to date for the new directions
+    launch_slocal(c, lp, SL_A, bf.B, bf.TA, nrhs, stride);
     act.assign(nq, 1);
     its.assign(nq, 0);
     int it = 0, cur = 0;  // bf.P[cur] holds the current directions
     while (it < maxi) {
+        // AP = Mpc^+ Mpc p of the carrier; its shift enters the dot product
+        // and the residual update
         const Field Pbase = member(bf.P[cur], kmin * nrhs, stride);
-        apply_mpc(c, lp, false, Pbase, bf.M, false, false, Field{}, nrhs, stride, -1, bf.TA, bf.Y);
-        apply_mpc(c, lp, true, bf.M, bf.AP, false, false, Field{}, nrhs, stride, -1, bf.TA, bf.Y);
-        if (shifts[kmin] != 0.0) ms_launch_axpy(c, lp, shifts[kmin], Pbase, bf.AP, nrhs, stride);
-        ms_launch_redot(c, lp, Pbase, bf.AP, nrhs, stride, s.pap);
+        apply_mpc(c, lp, false, Pbase, bf.M, false, true, bf.TA, nrhs, stride, -1, Field{}, bf.Y);
+        apply_mpc(c, lp, true, bf.M, bf.AP, false, false, Field{}, nrhs, stride, -1, Field{}, bf.Y);
+        ms_launch_redot(c, lp, Pbase, bf.AP, nrhs, stride, s.pap, shifts[kmin]);
         it++;
         MsState si = s;
         si.coef = coefs[cur];
         ms_launch_step(c, lp, si, bf.R, bf.AP, bf.X, bf.P[cur], bf.P[1 - cur], coefs[1 - cur], nrhs, nshift, kmin,
-                       stride, rho_new, it);
+                       stride, rho_new, it, Pbase, shifts[kmin], bf.TA);
         cur = 1 - cur;
         if (it % poll == 0 || it == maxi) {
             HIPCHECK(hipMemcpyAsync(act.data(), s.active, nq * sizeof(int), hipMemcpyDeviceToHost, c.stream));
