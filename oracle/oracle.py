@@ -395,3 +395,129 @@ def ddrhmc_action(P: Params, U_full, U_dirichlet, phi_odd, quarter=None, minus_h
     v = np.asarray(phi_odd, dtype=np.complex128).ravel()
     psi = f @ v
     return float(np.real(np.vdot(psi, g @ psi)))
+
+
+# ------------------------------------------------------------ domain boundary
+# Sec. 2.1: the lattice splits into a domain Omega (mask 1) and its complement
+# Omega-bar (mask 0).  Ordered by domain, D = [[D_Omega, D_d], [D_dbar,
+# D_Omegabar]], with D_d and D_dbar the hops across the domain boundary.  The
+# cut operator D_cut = diag(D_Omega, D_Omegabar) is D on the gauge field whose
+# links between the domains are zero, so D_d + D_dbar = D - D_cut.
+#
+# The projector P_dbar keeps the components of a field on Omega that D_dbar
+# acts on (D_dbar P_dbar = D_dbar).  With D5 = Mooee - (1/2) H A, a site x of
+# Omega feeds Omega-bar only through the hop, which sees (1 + gamma_mu) A psi(x)
+# when x + mu is in Omega-bar and (1 - gamma_mu) A psi(x) when x - mu is.  The
+# spin-space mask Pi of the boundary is therefore (1 +- gamma_mu)/2 at a site
+# with one such neighbour, 1 at a site with two or more (the ranges of two
+# different projectors of this kind span the four spins), 0 elsewhere, and
+# P_dbar = A^-1 Pi A (A = b + c P5; for Shamir, c = 0, it is Pi itself).
+
+
+def coords(L, n):
+    x = []
+    for mu in range(4):
+        x.append(n % L[mu])
+        n //= L[mu]
+    return x
+
+
+def lexi(L, x):
+    return x[0] + L[0] * (x[1] + L[1] * (x[2] + L[2] * x[3]))
+
+
+def mask_cut(L, U, mask):
+    """The gauge field with every link U_mu(x) whose ends lie in different domains set to zero."""
+    U = np.array(U, dtype=np.complex128, copy=True).reshape(-1, 4, 3, 3)
+    mask = np.asarray(mask).ravel()
+    for n in range(U.shape[0]):
+        x = coords(L, n)
+        for mu in range(4):
+            y = list(x)
+            y[mu] = (y[mu] + 1) % L[mu]
+            if mask[n] != mask[lexi(L, y)]:
+                U[n, mu] = 0.0
+    return U
+
+
+def boundary_spin_mask(L, mask):
+    """Pi per site, shape (V, 4, 4)."""
+    mask = np.asarray(mask).ravel()
+    V = len(mask)
+    one = np.eye(4, dtype=np.complex128)
+    Pi = np.zeros((V, 4, 4), dtype=np.complex128)
+    for n in range(V):
+        if mask[n] != 1:
+            continue
+        x = coords(L, n)
+        links = []
+        for mu in range(4):
+            for sgn in (1, -1):
+                y = list(x)
+                y[mu] = (y[mu] + sgn) % L[mu]
+                if mask[lexi(L, y)] == 0:
+                    links.append((mu, sgn))
+        if len(links) == 1:
+            mu, sgn = links[0]
+            Pi[n] = 0.5 * (one + sgn * gamma(mu))
+        elif len(links) > 1:
+            Pi[n] = one
+    return Pi
+
+
+def a_site_matrix(P: Params, inverse=False) -> np.ndarray:
+    """A = b + c P5 (or its inverse) on the Ls x 4 x 3 components of one 4D site."""
+    m = 12 * P.Ls
+    E = np.eye(m, dtype=np.complex128).reshape(m, P.Ls, 4, 3)
+    A = (P.b * E + P.c * p5(P, E)).reshape(m, m).T  # column j = A e_j
+    return np.linalg.inv(A) if inverse else A
+
+
+def boundary_projector(P: Params, mask, psi) -> np.ndarray:
+    """P_dbar psi = A^-1 Pi A psi for a full field psi."""
+    V, m = P.V, 12 * P.Ls
+    A, Ai = a_site_matrix(P), a_site_matrix(P, inverse=True)
+    v = (np.asarray(psi, dtype=np.complex128).reshape(V, m) @ A.T).reshape(V, P.Ls, 4, 3)
+    v = np.einsum("nab,nsbc->nsac", boundary_spin_mask(P.L, mask), v)
+    return (v.reshape(V, m) @ Ai.T).reshape(P.full_shape())
+
+
+def dense_d5(P: Params, U) -> np.ndarray:
+    """Dense D5 on the full field, built column by column (small lattices only)."""
+    n = int(np.prod(P.full_shape()))
+    M = np.empty((n, n), dtype=np.complex128)
+    e = np.zeros(n, dtype=np.complex128)
+    for j in range(n):
+        e[j] = 1.0
+        M[:, j] = d5(P, U, e.reshape(P.full_shape())).ravel()
+        e[j] = 0.0
+    return M
+
+
+def dense_boundary_projector(P: Params, mask) -> np.ndarray:
+    n = int(np.prod(P.full_shape()))
+    E = np.eye(n, dtype=np.complex128)
+    return np.stack([boundary_projector(P, mask, E[:, j]).ravel() for j in range(n)], axis=1)
+
+
+def restrict(P: Params, mask, psi) -> np.ndarray:
+    """psi on the sites of Omega, zero on Omega-bar."""
+    keep = (np.asarray(mask).ravel() == 1).astype(np.float64)
+    return np.asarray(psi, dtype=np.complex128).reshape(P.full_shape()) * keep[:, None, None, None]
+
+
+def boundary_r(P: Params, U, U_cut, mask, psi, inverse=False):
+    """R psi = P psi - P D_Omega^-1 D_d D_Omegabar^-1 D_dbar psi, or
+    R^-1 psi = P psi - P D^-1 D_dbar psi (Sec. 2.1), by dense solves, for the
+    part of psi on Omega (these operators act on fields of Omega).  D_cut^-1
+    applied to a field on one domain is that domain's inverse, and D - D_cut
+    applied to it is the hop into the other domain."""
+    shp = P.full_shape()
+    D, Dc = dense_d5(P, U), dense_d5(P, U_cut)
+    off = D - Dc
+    v = restrict(P, mask, psi).ravel()
+    if inverse:
+        w = np.linalg.solve(D, off @ v)
+    else:
+        w = np.linalg.solve(Dc, off @ np.linalg.solve(Dc, off @ v))
+    return boundary_projector(P, mask, v.reshape(shp)) - boundary_projector(P, mask, w.reshape(shp))
