@@ -109,7 +109,10 @@ enum {
     DWF_OP_CG = 0,           /* dwf_cg in `mode`                                       */
     DWF_OP_MULTISHIFT = 1,   /* dwf_multishift_cg in `mode` with nrhs x nshift systems */
     DWF_OP_RATIONAL = 2,     /* dwf_rational_apply, `nshift` poles (nrhs ignored)      */
-    DWF_OP_SCHUR_APPLY = 3   /* dwf_schur_apply (mode, nrhs, nshift ignored)           */
+    DWF_OP_SCHUR_APPLY = 3,  /* dwf_schur_apply (mode, nrhs, nshift ignored)           */
+    DWF_OP_BOUNDARY = 4      /* dwf_boundary_apply on the full context, solves in
+                                `mode` (nrhs, nshift ignored; the cut context's own
+                                solves need DWF_OP_CG there)                       */
 };
 /* Bytes of caller workspace the operation needs on a context that has none
  * of its buffers yet (an upper bound otherwise).  DWF_EINVAL for an unknown
@@ -294,6 +297,55 @@ dwf_status dwf_ddrhmc_action(dwf_ctx ctx, dwf_ctx ctx_dirichlet, const dwf_ratio
  * orders not ascending or out of range, or unless 0 <= lo < hi (finite). */
 dwf_status dwf_chebyshev_filter(dwf_ctx ctx, int prec, const double *v_odd, double lo, double hi, int nout,
                                 const int *orders, double *const *out_odd);
+
+/* ------------------------------------------------------ domain boundary */
+
+/* The two-flavour boundary action (Sec. 2.1, the construction after eq.
+ * (schur)) splits the lattice into a domain Omega and its complement
+ * Omega-bar.  mask (device, int8, one entry per lexicographic 4D site
+ * n = x + Lx (y + Ly (z + Lz t))) is 1 on Omega and 0 on Omega-bar; every
+ * entry must be 0 or 1 and both domains non-empty (else DWF_EINVAL).  The
+ * boundary is found by comparing the mask with its shift by one site in each
+ * direction (Sec. 2.4, "Results"). */
+
+/* gauge_out = gauge_in with every link U_mu(x) whose ends x, x + mu lie in
+ * different domains set to zero (canonical FP64 gauge fields [n][mu][3][3],
+ * device; they may be the same buffer; the context supplies the lattice and
+ * stream).  A context created from the result applies the block-diagonal
+ * operator D_cut = diag(D_Omega, D_Omegabar) of eq. (schur). */
+dwf_status dwf_mask_links(dwf_ctx ctx, const int8_t *mask, const double *gauge_in, double *gauge_out);
+
+/* out = D5 in on canonical FP64 full fields (device). */
+dwf_status dwf_d5_apply(dwf_ctx ctx, const double *in_full, double *out_full);
+
+/* out = P in: the projector onto the components of a field on Omega that the
+ * boundary block D_dbar (Omega to Omega-bar) acts on, D_dbar P = D_dbar.  With
+ * D5 = Mooee - (1/2) H A the boundary hop sees (1 + gamma_mu) A psi at a site
+ * of Omega whose neighbour x + mu is in Omega-bar and (1 - gamma_mu) A psi for
+ * x - mu, so P = A^-1 Pi A, Pi being (1 +- gamma_mu)/2 at a boundary site with
+ * one neighbour in Omega-bar, 1 with two or more (the two ranges span all
+ * spins), 0 elsewhere (oblique for c != 0; for Shamir the orthogonal spin
+ * mask).  Canonical FP64 full fields (device).  DWF_ENOTSUP when
+ * A = b + c P5 is singular (b = 0). */
+dwf_status dwf_boundary_project(dwf_ctx ctx, const int8_t *mask, const double *in_full, double *out_full);
+
+/* out = R psi (inverse = 0) or R^-1 psi (inverse = 1) for the part of psi on
+ * Omega, with
+ *   R    = P - P D_Omega^-1 D_d D_Omegabar^-1 D_dbar,
+ *   R^-1 = P - P D^-1 D_dbar,
+ * D the operator of ctx and D_cut = diag(D_Omega, D_Omegabar) that of ctx_cut
+ * (the same lattice and parameters, its gauge field cut by dwf_mask_links with
+ * the same mask), D_d + D_dbar = D - D_cut.  R R^-1 = P, and det R on the
+ * range of P is the boundary determinant det(1 - D_Omega^-1 D_d D_Omegabar^-1
+ * D_dbar).  R takes two solves with ctx_cut, R^-1 one with ctx (dwf_cg with
+ * o, its x0_is_guess ignored).  Canonical FP64 full fields (device).  st (may
+ * be NULL): iterations and reliable updates summed over the solves, the
+ * largest of their residuals, converged when all are, wall time in seconds.
+ * Errors: DWF_EINVAL for null pointers, ctx_cut == ctx, contexts of different
+ * lattice or parameters, a bad mask or inverse; DWF_ENOCONV when a solve
+ * missed the tolerance (out is then computed from its last iterate). */
+dwf_status dwf_boundary_apply(dwf_ctx ctx, dwf_ctx ctx_cut, const int8_t *mask, int inverse, const double *in_full,
+                              double *out_full, const dwf_solver_opts *o, dwf_solver_stats *st);
 
 /* ---------------------------------------------- learned preconditioner */
 

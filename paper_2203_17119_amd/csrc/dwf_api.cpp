@@ -221,6 +221,16 @@ static void build_slocal(Context &c)
     for (int s = 0; s < n; s++)
         for (int t = 0; t < n; t++)
             Minv[idx(s, t)] = (s >= t) ? std::pow(al, s - t) / norm : -mf * std::pow(al, s - t + n) / norm;
+    // (b + c S_up)^-1 in the same closed form (zero when b = 0: the boundary
+    // operators then refuse the parameters)
+    std::vector<double> Ainv(n * n, 0.0);
+    if (b != 0.0) {
+        const double ga = -cc / b;
+        const double an = b * (1.0 + mf * std::pow(ga, n));
+        for (int s = 0; s < n; s++)
+            for (int t = 0; t < n; t++)
+                Ainv[idx(s, t)] = (s >= t) ? std::pow(ga, s - t) / an : -mf * std::pow(ga, s - t + n) / an;
+    }
     std::vector<std::vector<double>> blocks(2 * SL_NOP);
     auto setop = [&](int op, const std::vector<double> &up, const std::vector<double> &lo) {
         blocks[2 * op] = up;
@@ -235,6 +245,7 @@ static void build_slocal(Context &c)
     setop(SL_E1, mul(blocks[2 * SL_A], blocks[2 * SL_MINV]), mul(blocks[2 * SL_A + 1], blocks[2 * SL_MINV + 1]));
     setop(SL_E2, mul(blocks[2 * SL_MINVDAG], blocks[2 * SL_ADAG]),
           mul(blocks[2 * SL_MINVDAG + 1], blocks[2 * SL_ADAG + 1]));
+    setop(SL_AINV, Ainv, tr(Ainv));
     // twisted-circulant operators (polynomials in the shift, per chirality):
     // T[t][s] = f_{t-s} (t >= s), -mf f_{t-s+n} (t < s), the other block T^T
     auto twisted = [&](const std::vector<double> &T, const std::vector<double> &O, double *f) {

@@ -41,6 +41,7 @@ enum SlocalOp {
     SL_MINVDAG,     // (d + e P5^+)^-1
     SL_E1,          // A Mee^-1           (epilogue of the first Mpc stage)
     SL_E2,          // Mee^-+ A^+         (epilogue of the first Mpc^+ stage)
+    SL_AINV,        // (b + c P5)^-1      (domain-boundary projector)
     SL_NOP
 };
 
@@ -221,6 +222,14 @@ struct StencilSpec {
 // prec: storage precision of in/out/self; FP64 uses double arithmetic, the
 // others float.  Returns the number of partials written when reduce is set.
 int launch_stencil(Context &c, int prec, const StencilSpec &sp, Field in, Field self, Field out);
+
+// domain boundary (two-flavour boundary action): mask[n] over the lexicographic
+// 4D sites, nonzero on the domain.  Links between the domains zeroed (canonical
+// FP64 gauge fields, gin and gout may alias); on one parity of an FP64 field,
+// kind 0 applies the spin-space mask of the boundary sites, kind 1 keeps the
+// field on the domain (in and out may alias).
+void launch_mask_links(Context &c, const int8_t *mask, const double *gin, double *gout);
+void launch_boundary_mask(Context &c, const int8_t *mask, Field in, Field out, int parity, int kind);
 
 // s-local dense operator out = M in (M one of SlocalOp); in and out may alias
 void launch_slocal(Context &c, int prec, int op, Field in, Field out, int nbatch = 1, long bstride = 0);

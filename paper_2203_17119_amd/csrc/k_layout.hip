@@ -304,4 +304,103 @@ void launch_convert(Context &c, int pin, Field in, int pout, Field out)
     HIPCHECK(hipGetLastError());
 }
 
+// ----------------------------------------------------------- domain boundary
+//
+// The two-flavour boundary action splits the lattice into a domain Omega and
+// its complement (Sec. 2.1); mask[n] over the lexicographic 4D sites is
+// nonzero on Omega.  The boundary is found by comparing the mask with its
+// shift by one site in each direction (Sec. 2.4, "Results").
+
+__host__ __device__ __forceinline__ long shifted(const int L[4], const int x[4], int mu, int step)
+{
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    y[mu] = (y[mu] + step + L[mu]) % L[mu];
+    return lex(L, y);
+}
+
+// U_mu(x) = 0 where x and x + mu lie in different domains; canonical FP64
+// gauge [n][mu][3][3], one thread per (n, mu)
+__global__ void k_mask_links(Geo g, const int8_t *mask, const double2 *gin, double2 *gout)
+{
+    const long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long V = 2 * g.vh;
+    if (k >= 4 * V) return;
+    const long n = k / 4;
+    const int mu = (int)(k - 4 * n);
+    long r = n;
+    int x[4];
+    for (int d = 0; d < 4; d++) {
+        x[d] = (int)(r % g.L[d]);
+        r /= g.L[d];
+    }
+    const bool cut = (mask[n] != 0) != (mask[shifted(g.L, x, mu, 1)] != 0);
+    for (int e = 0; e < 9; e++) gout[k * 9 + e] = cut ? make_double2(0.0, 0.0) : gin[k * 9 + e];
+}
+
+// gamma_mu psi_a = f_a psi_perm(a) per colour in the chiral basis
+// gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_t = [[0, 1], [1, 0]]
+__device__ __forceinline__ cx<double> gamma_row(int mu, int a, const cx<double> v[12], int col)
+{
+    const int src = mu < 2 ? 3 - a : (a ^ 2);
+    const cx<double> u = v[src * 3 + col];
+    switch (mu) {
+    case 0: return (a < 2) ? mk(u.im, -u.re) : mk(-u.im, u.re);               // -i, -i, i, i
+    case 1: return (a == 0 || a == 3) ? mk(-u.re, -u.im) : u;                 // -1, 1, 1, -1
+    case 2: return (a == 0 || a == 3) ? mk(u.im, -u.re) : mk(-u.im, u.re);    // -i, i, i, -i
+    default: return u;                                                         // 1, 1, 1, 1
+    }
+}
+
+// kind 0: the spin-space mask of the boundary sites of Omega: (1 + gamma_mu)/2
+// at a site whose only neighbour outside Omega is x + mu, (1 - gamma_mu)/2 if
+// it is x - mu, 1 with two or more, 0 at every other site; kind 1: the field
+// on Omega, zero outside.  One parity of an FP64 internal field.
+__global__ void k_boundary_mask(Geo g, const int8_t *mask, Field in, Field out, int parity, int kind)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= g.vh * g.Ls) return;
+    const long j = i / g.Ls;
+    int x[4];
+    const long n = site_of_cb(g.L, g.perm_inv[j], parity, x);
+    cx<double> v[12];
+    load_spinor<F64, double>(in, i, v);
+    const bool inside = mask[n] != 0;
+    int nout = 0, mu0 = 0, sg0 = 1;
+    if (inside && kind == 0)
+        for (int mu = 0; mu < 4; mu++)
+            for (int sg = 1; sg >= -1; sg -= 2)
+                if (mask[shifted(g.L, x, mu, sg)] == 0) {
+                    nout++;
+                    mu0 = mu;
+                    sg0 = sg;
+                }
+    if (!inside || (kind == 0 && nout == 0)) {
+        for (int c = 0; c < 12; c++) v[c] = mk(0.0, 0.0);
+    } else if (kind == 0 && nout == 1) {
+        cx<double> w[12];
+        for (int a = 0; a < 4; a++)
+            for (int col = 0; col < 3; col++) {
+                const cx<double> gv = gamma_row(mu0, a, v, col);
+                w[a * 3 + col] = 0.5 * (v[a * 3 + col] + double(sg0) * gv);
+            }
+        for (int c = 0; c < 12; c++) v[c] = w[c];
+    }
+    store_spinor<F64, double>(out, i, v);
+}
+
+void launch_mask_links(Context &c, const int8_t *mask, const double *gin, double *gout)
+{
+    const Geo g = geo(c);
+    hipLaunchKernelGGL(k_mask_links, grid1(8 * c.vh), dim3(256), 0, c.stream, g, mask, (const double2 *)gin,
+                       (double2 *)gout);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_boundary_mask(Context &c, const int8_t *mask, Field in, Field out, int parity, int kind)
+{
+    const Geo g = geo(c);
+    hipLaunchKernelGGL(k_boundary_mask, grid1(c.n5h), dim3(256), 0, c.stream, g, mask, in, out, parity, kind);
+    HIPCHECK(hipGetLastError());
+}
+
 }  // namespace dwf

@@ -749,6 +749,16 @@ extern "C" dwf_status dwf_workspace_bytes(dwf_ctx ctx, int op, int mode, int nrh
     case DWF_OP_SCHUR_APPLY:
         for (const char *n : {"io_a", "io_b", "mpc_y", "mpc_ta"}) plan.push_back({n, P_F64, 0, 0});
         break;
+    case DWF_OP_BOUNDARY: {
+        // the solves on this context, and the boundary operators' own fields
+        plan = plan_cg(mode);
+        for (const char *n : {"bd_x0", "bd_x1", "bd_y0", "bd_y1", "bd_z0", "bd_z1", "bd_ax", "bd_pt"})
+            plan.push_back({n, P_F64, 0, 0});
+        const size_t cbytes = (size_t)2 * c.n5h * 12 * 2 * sizeof(double);
+        plan.push_back({"bd_can0", -1, 0, cbytes});
+        plan.push_back({"bd_can1", -1, 0, cbytes});
+        break;
+    }
     default: fail(DWF_EINVAL, "unknown operation");
     }
     *bytes = ws_plan_bytes(c, plan);

@@ -21,7 +21,7 @@ DWF_F64, DWF_F32, DWF_F16, DWF_BF16 = 0, 1, 2, 3
 DWF_SOLVE_F64, DWF_SOLVE_MIXED_F32, DWF_SOLVE_MIXED_F16, DWF_SOLVE_MIXED_BF16 = 0, 1, 2, 3
 DWF_K_DHOP, DWF_K_STENCIL, DWF_K_SLOCAL, DWF_K_BLAS, DWF_K_NET = 0, 1, 2, 3, 4
 DWF_NET_FWD_FP32, DWF_NET_FWD_MFMA_BF16 = 0, 1
-DWF_OP_CG, DWF_OP_MULTISHIFT, DWF_OP_RATIONAL, DWF_OP_SCHUR_APPLY = 0, 1, 2, 3
+DWF_OP_CG, DWF_OP_MULTISHIFT, DWF_OP_RATIONAL, DWF_OP_SCHUR_APPLY, DWF_OP_BOUNDARY = 0, 1, 2, 3, 4
 DWF_SCHED_STENCIL_BATCHED = 8
 DWF_TUNE_NORMAL, DWF_TUNE_BATCHED = 0, 1
 KCLASS_NAMES = {DWF_K_DHOP: "dhop", DWF_K_STENCIL: "stencil", DWF_K_SLOCAL: "slocal",
@@ -113,6 +113,11 @@ SIGNATURES = {
     "dwf_ddrhmc_action": ([_CTX, _CTX, C.POINTER(dwf_rational), C.POINTER(dwf_rational), _P,
                            C.POINTER(dwf_solver_opts), C.POINTER(_D), C.POINTER(dwf_solver_stats)], C.c_int32),
     "dwf_chebyshev_filter": ([_CTX, _I, _P, _D, _D, _I, C.POINTER(_I), C.POINTER(_P)], C.c_int32),
+    "dwf_mask_links": ([_CTX, _P, _P, _P], C.c_int32),
+    "dwf_d5_apply": ([_CTX, _P, _P], C.c_int32),
+    "dwf_boundary_project": ([_CTX, _P, _P, _P], C.c_int32),
+    "dwf_boundary_apply": ([_CTX, _CTX, _P, _I, _P, _P, C.POINTER(dwf_solver_opts), C.POINTER(dwf_solver_stats)],
+                           C.c_int32),
     "dwf_net_create": ([_CTX, _I, C.POINTER(_I), C.POINTER(_NET)], C.c_int32),
     "dwf_net_destroy": ([_NET], C.c_int32),
     "dwf_net_num_weights": ([_NET], C.c_int),
@@ -325,6 +330,30 @@ def dwf_rational_apply(ctx, r, in_odd, out_odd, **opts):
     st = dwf_solver_stats()
     s = _check(load().dwf_rational_apply(ctx, C.byref(r), _ptr(in_odd), _ptr(out_odd), C.byref(o), C.byref(st)),
                allow=(DWF_ENOCONV,))
+    return s, st.asdict()
+
+
+def dwf_mask_links(ctx, mask, gauge_in, gauge_out):
+    """gauge_out = gauge_in with the links between the domains of mask (int8, 1 on Omega) zeroed."""
+    _check(load().dwf_mask_links(ctx, _ptr(mask), _ptr(gauge_in), _ptr(gauge_out)))
+
+
+def dwf_d5_apply(ctx, in_full, out_full):
+    """out = D5 in on canonical FP64 full fields."""
+    _check(load().dwf_d5_apply(ctx, _ptr(in_full), _ptr(out_full)))
+
+
+def dwf_boundary_project(ctx, mask, in_full, out_full):
+    """out = P in, the projector onto what the boundary hop from Omega sees."""
+    _check(load().dwf_boundary_project(ctx, _ptr(mask), _ptr(in_full), _ptr(out_full)))
+
+
+def dwf_boundary_apply(ctx, ctx_cut, mask, in_full, out_full, inverse=False, **opts):
+    """out = R psi or R^-1 psi (inverse).  Returns (status, stats summed over the solves)."""
+    o = _opts(**opts)
+    st = dwf_solver_stats()
+    s = _check(load().dwf_boundary_apply(ctx, ctx_cut, _ptr(mask), int(bool(inverse)), _ptr(in_full),
+                                         _ptr(out_full), C.byref(o), C.byref(st)), allow=(DWF_ENOCONV,))
     return s, st.asdict()
 
 

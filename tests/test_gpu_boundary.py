@@ -1,0 +1,176 @@
+"""GPU parity of the domain-boundary operators of the two-flavour boundary
+action (Sec. 2.1): the link cut by a domain mask, D5 on full fields, the
+projector P and the operators R and R^-1, against the oracle (pinned in
+test_oracle_boundary.py), and the identities R R^-1 = P and D_dbar P = D_dbar
+on the GPU at 8^4 x 8."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Params
+from paper_2203_17119_amd import dwf, synth
+from gpu_helpers import relerr, to_gpu, to_host, torch
+from helpers import coords
+
+pytestmark = pytest.mark.gpu
+
+B, C, M5, MF = 1.5, 0.5, 1.8, 0.1
+
+
+def _mask_t(L, t_hi):
+    return (coords(L)[:, 3] < t_hi).astype(np.int8)
+
+
+def _mask_box(L, x_hi, t_hi):
+    x = coords(L)
+    return ((x[:, 0] < x_hi) & (x[:, 3] < t_hi)).astype(np.int8)
+
+
+class BCase:
+    """Full and cut contexts of one gauge field and domain mask."""
+
+    def __init__(self, L, Ls, mask, seed, c=C):
+        T = torch()
+        self.L, self.Ls, self.mask = tuple(L), Ls, mask
+        self.P = Params(L, Ls, B, c, M5, MF)
+        self.U = synth.gauge_field(L, 0.5, seed)
+        self.Uc = oracle.mask_cut(L, self.U, mask)
+        self.mask_dev = T.from_numpy(mask.astype(np.int8)).cuda()
+        self.full = dwf.Lattice(L, Ls, B, c, M5, MF, gauge=self.U)
+        U_dev = to_gpu(self.U)
+        self.Uc_dev = T.empty_like(U_dev)
+        dwf.dwf_mask_links(self.full.ctx, self.mask_dev, U_dev, self.Uc_dev)
+        self.cut = dwf.Lattice(L, Ls, B, c, M5, MF, gauge=self.Uc_dev)
+
+    def field(self, seed):
+        return synth.gaussian_fermion(self.L, self.Ls, seed)
+
+    def close(self):
+        self.full.close()
+        self.cut.close()
+
+
+SMALL = {
+    "t_split": dict(L=(2, 2, 2, 4), Ls=4, mask=lambda L: _mask_t(L, 2)),
+    "xt_box": dict(L=(4, 2, 2, 6), Ls=2, mask=lambda L: _mask_box(L, 2, 3)),
+}
+
+
+@pytest.fixture(scope="module", params=list(SMALL))
+def small(request):
+    cfg = SMALL[request.param]
+    print(f"\n[boundary case {request.param}: {cfg['L']} ls{cfg['Ls']}]", flush=True)
+    c = BCase(cfg["L"], cfg["Ls"], cfg["mask"](cfg["L"]), seed=23)
+    yield request.param, c
+    c.close()
+
+
+def test_mask_links_matches_oracle(small):
+    name, c = small
+    got = to_host(c.Uc_dev)
+    assert np.array_equal(got, c.Uc)
+    assert (got == 0).sum() > 0
+
+
+def test_d5_apply_matches_oracle(small):
+    name, c = small
+    for lat, U in ((c.full, c.U), (c.cut, c.Uc)):
+        psi = c.field(31)
+        out = torch().empty_like(to_gpu(psi))
+        dwf.dwf_d5_apply(lat.ctx, to_gpu(psi), out)
+        want = oracle.d5(c.P, U, psi)
+        assert relerr(to_host(out), want) < 1e-13
+
+
+def test_projector_matches_oracle(small):
+    name, c = small
+    psi = c.field(32)
+    x = to_gpu(psi)
+    out = torch().empty_like(x)
+    dwf.dwf_boundary_project(c.full.ctx, c.mask_dev, x, out)
+    want = oracle.boundary_projector(c.P, c.mask, psi)
+    got = to_host(out)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"{name}: |P psi - oracle| / max = {err:.2e}", flush=True)
+    assert err < 1e-13
+    # in place
+    dwf.dwf_boundary_project(c.full.ctx, c.mask_dev, x, x)
+    assert torch().equal(x, out)
+
+
+@pytest.mark.parametrize("inverse", [False, True])
+def test_r_matches_oracle(small, inverse):
+    name, c = small
+    psi = c.field(33)
+    out = torch().empty_like(to_gpu(psi))
+    s, st = dwf.dwf_boundary_apply(c.full.ctx, c.cut.ctx, c.mask_dev, to_gpu(psi), out, inverse=inverse,
+                                   tol=1e-12, mode=dwf.DWF_SOLVE_F64)
+    want = oracle.boundary_r(c.P, c.U, c.Uc, c.mask, psi, inverse=inverse)
+    err = relerr(to_host(out), want)
+    print(f"{name} {'R^-1' if inverse else 'R'}: rel err {err:.2e}, {st['iters']} CG iterations, "
+          f"largest full residual {st['res_full']:.1e}", flush=True)
+    assert s == dwf.DWF_OK and st["converged"] == 1
+    assert err < 1e-8
+
+
+def test_boundary_argument_errors(small):
+    name, c = small
+    T = torch()
+    psi = to_gpu(c.field(34))
+    out = T.empty_like(psi)
+    for bad in (T.full_like(c.mask_dev, 1), T.zeros_like(c.mask_dev), c.mask_dev * 2):
+        with pytest.raises(dwf.DWFError) as e:
+            dwf.dwf_boundary_project(c.full.ctx, bad, psi, out)
+        assert e.value.status == dwf.DWF_EINVAL
+    with pytest.raises(dwf.DWFError) as e:
+        dwf.dwf_boundary_apply(c.full.ctx, c.full.ctx, c.mask_dev, psi, out)
+    assert e.value.status == dwf.DWF_EINVAL
+    other = dwf.Lattice(c.L, c.Ls, B, C, M5, 2 * MF, gauge=c.Uc_dev)
+    try:
+        with pytest.raises(dwf.DWFError) as e:
+            dwf.dwf_boundary_apply(c.full.ctx, other.ctx, c.mask_dev, psi, out)
+        assert e.value.status == dwf.DWF_EINVAL
+    finally:
+        other.close()
+    shamir_b0 = dwf.Lattice(c.L, c.Ls, 0.0, 1.0, M5, MF, gauge=c.U)
+    try:
+        with pytest.raises(dwf.DWFError) as e:
+            dwf.dwf_boundary_project(shamir_b0.ctx, c.mask_dev, psi, out)
+        assert e.value.status == dwf.DWF_ENOTSUP
+    finally:
+        shamir_b0.close()
+
+
+def test_identities_8x8x8x8_ls8():
+    """At 8^4 x 8 with Omega = {t < 4}: D_dbar P = D_dbar through the two
+    contexts' D5, and R R^-1 = P, in FP64 and with mixed-precision solves."""
+    print("\n[boundary 8x8x8x8 ls8, Omega = t < 4]", flush=True)
+    L = (8, 8, 8, 8)
+    c = BCase(L, 8, _mask_t(L, 4), seed=29)
+    T = torch()
+    try:
+        psi = to_gpu(oracle.restrict(c.P, c.mask, c.field(35)))
+        p = T.empty_like(psi)
+        dwf.dwf_boundary_project(c.full.ctx, c.mask_dev, psi, p)
+
+        def dbar(v):
+            a, b = T.empty_like(v), T.empty_like(v)
+            dwf.dwf_d5_apply(c.full.ctx, v, a)
+            dwf.dwf_d5_apply(c.cut.ctx, v, b)
+            return a - b
+
+        want = dbar(psi)
+        assert float((dbar(p) - want).norm() / want.norm()) < 1e-13
+        for mode, tol, bound in ((dwf.DWF_SOLVE_F64, 1e-10, 1e-6), (dwf.DWF_SOLVE_MIXED_F16, 1e-10, 1e-6)):
+            rinv = T.empty_like(psi)
+            s1, st1 = dwf.dwf_boundary_apply(c.full.ctx, c.cut.ctx, c.mask_dev, psi, rinv, inverse=True, tol=tol,
+                                             mode=mode)
+            back = T.empty_like(psi)
+            s2, st2 = dwf.dwf_boundary_apply(c.full.ctx, c.cut.ctx, c.mask_dev, rinv, back, tol=tol, mode=mode)
+            err = float((back - p).norm() / p.norm())
+            print(f"mode {mode}: |R R^-1 psi - P psi| / |P psi| = {err:.2e}; R^-1 {st1['iters']} iterations "
+                  f"{st1['seconds']:.3f} s, R {st2['iters']} iterations {st2['seconds']:.3f} s", flush=True)
+            assert s1 == dwf.DWF_OK and s2 == dwf.DWF_OK
+            assert err < bound
+    finally:
+        c.close()
