@@ -377,6 +377,54 @@ def cpu_baseline(w, U, b_full, cg_iters):
     }
 
 
+def boundary_operators(dwf, synth, torch, tune_cache):
+    """The domain-boundary operators of the two-flavour boundary action on the
+    24^4 x 12 periodic lattice split at t = 12 (Omega = t < 12): R^-1 psi (one
+    solve on the whole lattice) and R (R^-1 psi) (two solves with the cut
+    operator), mixed FP16 solves to 1e-8, after a short warm-up that allocates
+    the workspaces; |R R^-1 psi - P psi| / |P psi| checks the pair."""
+    w = synth.WORKLOADS["24^4x12_fgcr"]
+    U = synth.gauge_field(w.dims, w.eps, w.gauge_seed)
+    T = w.dims[3]
+    t = np.arange(int(np.prod(w.dims))) // (w.dims[0] * w.dims[1] * w.dims[2])
+    mask = torch.from_numpy((t < T // 2).astype(np.int8)).cuda()
+    full = dwf.Lattice(w.dims, w.Ls, w.b, w.c, w.M5, w.mf, w.dirichlet, gauge=U)
+    U_dev = torch.from_numpy(np.ascontiguousarray(U)).cuda()
+    del U
+    Uc = torch.empty_like(U_dev)
+    dwf.dwf_mask_links(full.ctx, mask, U_dev, Uc)
+    del U_dev
+    cut = dwf.Lattice(w.dims, w.Ls, w.b, w.c, w.M5, w.mf, w.dirichlet, gauge=Uc)
+    del Uc
+    out = {"workload": f"24^4x12_fgcr split at t = {T // 2}: Omega = t < {T // 2}", "mode": "mixed_f16", "tol": w.tol}
+    try:
+        for lat in (full, cut):
+            dwf.dwf_tune(lat.ctx, dwf.DWF_F16, tune_cache)
+        psi = torch.from_numpy(synth.gaussian_fermion(w.dims, w.Ls, w.source_seeds[0])).cuda()
+        rinv, back, p = torch.empty_like(psi), torch.empty_like(psi), torch.empty_like(psi)
+
+        def apply(src, dst, inverse, maxit=0):
+            return dwf.dwf_boundary_apply(full.ctx, cut.ctx, mask, src, dst, inverse=inverse, tol=w.tol,
+                                          mode=dwf.DWF_SOLVE_MIXED_F16, maxit=maxit)
+
+        apply(psi, rinv, True, 20)
+        apply(psi, back, False, 20)
+        torch.cuda.synchronize()
+        s1, st1 = apply(psi, rinv, True)
+        s2, st2 = apply(rinv, back, False)
+        dwf.dwf_boundary_project(full.ctx, mask, psi, p)
+        out["r_inverse"] = {"status": s1, "seconds": round(st1["seconds"], 4), "cg_iters": st1["iters"],
+                            "res_full": st1["res_full"]}
+        out["r"] = {"status": s2, "seconds": round(st2["seconds"], 4), "cg_iters": st2["iters"],
+                    "res_full": st2["res_full"]}
+        out["identity_err"] = float((back - p).norm() / p.norm())
+        log(f"boundary operators: {out}")
+    finally:
+        full.close()
+        cut.close()
+    return out
+
+
 def c5_comparison(dwf, synth, torch, tune_cache, reps=3):
     """The learned preconditioner's deployment lattice, 24^4 x 12 periodic
     (mf 0.01, eps 0.7), source 2020: FP64 CG, mixed CG in FP32 and FP16
@@ -442,6 +490,8 @@ def main():
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the FGCR solve with the trained network preconditioner")
     ap.add_argument("--no-multishift", action="store_true", help="skip the batched multi-shift solve")
+    ap.add_argument("--boundary", action="store_true",
+                    help="also time the domain-boundary operators R and R^-1 on the 24^4 x 12 periodic lattice")
     ap.add_argument("--no-c5", action="store_true",
                     help="skip the 24^4 x 12 periodic comparison (FP64 CG, mixed CG, FGCR + network)")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
@@ -574,6 +624,13 @@ def main():
             del srcs, x
             torch.cuda.empty_cache()
         c5 = c5_comparison(dwf, synth, torch, tune_cache)
+    bd = None
+    if args.boundary:
+        if args.no_multishift and args.no_c5:
+            lat.close()
+            del srcs, x
+            torch.cuda.empty_cache()
+        bd = boundary_operators(dwf, synth, torch, tune_cache)
     cpu = None if args.no_cpu else cpu_baseline(w, U, b0_host, st64["iters"])
 
     ms_step = t_total / args.steps * 1e3
@@ -632,6 +689,7 @@ def main():
         "copy": copy,
         "bandwidth_probes": {k: {kk: v[kk] for kk in v if kk != "configs"} for k, v in ceiling.items()},
         "c5_24x24x24x24_ls12_periodic": c5,
+        "boundary_operators": bd,
         "dhop": table,
         "cpu_baseline": cpu,
     }
