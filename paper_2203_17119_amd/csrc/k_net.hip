@@ -207,9 +207,13 @@ __device__ __forceinline__ cx<float> raw_feat(typename std::conditional<BF, uint
     }
 }
 
-// Activations between layers may be BF16 pairs (in_bf16 / out_bf16): the
-// matrix cores round their B operand to BF16 anyway, and BF16 storage halves
-// the bytes of the eleven path reads of every input channel.
+// Activations between layers may be BF16 (in_bf16 / out_bf16): the matrix
+// cores round their B operand to BF16 anyway, and BF16 storage halves the bytes
+// of the eleven path reads of every input channel.  The BF16 activations keep
+// the two channels of a channel pair side by side,
+//   f[p][pair*3 + colour][i] = (channel 2 pair, channel 2 pair + 1), 8 bytes,
+// so that a lane reads both channels of a pair in one 8-byte load (the FP32
+// features keep one plane per channel).
 // Occupancy target: left free, the compiler puts the accumulators in AGPRs on
 // top of the VGPRs and two waves per SIMD fit, too few to cover the per-path
 // load latency.  With the accumulators in VGPRs, four waves fit without spills
@@ -273,16 +277,31 @@ __global__ void __launch_bounds__(256)
         } else {
             hv = ok && path_source(g, p, pi, j, s, src, sp);
         }
-        const long base = (long)sp * CIN * 3 * n + src;
+        if constexpr (IBF) {
+            const long base = (long)sp * NP * 3 * n + src;
 #pragma unroll
-        for (int q = 0; q < HP; q++)
-#pragma unroll
-            for (int e = 0; e < 2; e++)
+            for (int q = 0; q < HP; q++)
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    const long f = base + (long)((2 * (th * HP + q) + e) * 3 + c) * n;
-                    if (hv) raw[q][e][c] = ((const RawT *)in)[f];
+                    const long f = base + (long)((th * HP + q) * 3 + c) * n;
+                    if (hv) {
+                        const uint2 w = ((const uint2 *)in)[f];
+                        raw[q][0][c] = w.x;
+                        raw[q][1][c] = w.y;
+                    }
                 }
+        } else {
+            const long base = (long)sp * CIN * 3 * n + src;
+#pragma unroll
+            for (int q = 0; q < HP; q++)
+#pragma unroll
+                for (int e = 0; e < 2; e++)
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        const long f = base + (long)((2 * (th * HP + q) + e) * 3 + c) * n;
+                        if (hv) raw[q][e][c] = ((const RawT *)in)[f];
+                    }
+        }
         return hv;
     };
     // the paths in pmask, in order (uniform over the workgroup)
@@ -357,7 +376,6 @@ __global__ void __launch_bounds__(256)
     }
     // accumulator register r of tile tt holds row m' = 8 (r / 4) + 4 h + r % 4 of column
     // (tile * 32 + jc): colour col / MF_S, site col % MF_S
-    const long obase = (long)p * COUT * 3 * n;
 #pragma unroll
     for (int tt = 0; tt < 3; tt++) {
         const int col = (wave * 3 + tt) * 32 + jc;
@@ -365,18 +383,24 @@ __global__ void __launch_bounds__(256)
         const long i = i0 + (col - cc * MF_S);
         if (i >= n) continue;
 #pragma unroll
-        for (int q = 0; q < 4; q++)
-#pragma unroll
-            for (int hh = 0; hh < 2; hh++) {
-                const int a = 4 * q + 2 * h + hh;
-                if (a >= COUT) continue;
-                const long k = obase + (long)(a * 3 + cc) * n + i;
-                const float2 v = make_float2(acc[tt][4 * q + 2 * hh], acc[tt][4 * q + 2 * hh + 1]);
-                if constexpr (OBF)
-                    ((__hip_bfloat162 *)out)[k] = __float22bfloat162_rn(v);
-                else
-                    ((float2 *)out)[k] = v;
+        for (int q = 0; q < 4; q++) {
+            // channels a0 = 4 q + 2 h and a0 + 1: one channel pair
+            const int a0 = 4 * q + 2 * h;
+            if (a0 >= COUT) continue;
+            const float2 v0 = make_float2(acc[tt][4 * q], acc[tt][4 * q + 1]);
+            const float2 v1 = make_float2(acc[tt][4 * q + 2], acc[tt][4 * q + 3]);
+            if constexpr (OBF) {
+                const __hip_bfloat162 b0 = __float22bfloat162_rn(v0), b1 = __float22bfloat162_rn(v1);
+                uint2 w;
+                w.x = *(const uint32_t *)&b0;
+                w.y = *(const uint32_t *)&b1;
+                ((uint2 *)out)[(long)p * (COUT / 2) * 3 * n + (long)((a0 / 2) * 3 + cc) * n + i] = w;
+            } else {
+                const long k = (long)p * COUT * 3 * n + (long)(a0 * 3 + cc) * n + i;
+                ((float2 *)out)[k] = v0;
+                ((float2 *)out)[k + 3 * n] = v1;
             }
+        }
     }
 }
 

@@ -51,16 +51,18 @@ class BCase:
 
 
 SMALL = {
-    "t_split": dict(L=(2, 2, 2, 4), Ls=4, mask=lambda L: _mask_t(L, 2)),
-    "xt_box": dict(L=(4, 2, 2, 6), Ls=2, mask=lambda L: _mask_box(L, 2, 3)),
+    "t_split": dict(L=(2, 2, 2, 4), Ls=4, mask=lambda L: _mask_t(L, 2), c=C),
+    "xt_box": dict(L=(4, 2, 2, 6), Ls=2, mask=lambda L: _mask_box(L, 2, 3), c=C),
+    # Shamir (c = 0): the projector is the orthogonal spin mask
+    "t_split_shamir": dict(L=(2, 2, 2, 4), Ls=4, mask=lambda L: _mask_t(L, 2), c=0.0),
 }
 
 
 @pytest.fixture(scope="module", params=list(SMALL))
 def small(request):
     cfg = SMALL[request.param]
-    print(f"\n[boundary case {request.param}: {cfg['L']} ls{cfg['Ls']}]", flush=True)
-    c = BCase(cfg["L"], cfg["Ls"], cfg["mask"](cfg["L"]), seed=23)
+    print(f"\n[boundary case {request.param}: {cfg['L']} ls{cfg['Ls']} c={cfg['c']}]", flush=True)
+    c = BCase(cfg["L"], cfg["Ls"], cfg["mask"](cfg["L"]), seed=23, c=cfg["c"])
     yield request.param, c
     c.close()
 
@@ -125,7 +127,7 @@ def test_boundary_argument_errors(small):
     with pytest.raises(dwf.DWFError) as e:
         dwf.dwf_boundary_apply(c.full.ctx, c.full.ctx, c.mask_dev, psi, out)
     assert e.value.status == dwf.DWF_EINVAL
-    other = dwf.Lattice(c.L, c.Ls, B, C, M5, 2 * MF, gauge=c.Uc_dev)
+    other = dwf.Lattice(c.L, c.Ls, B, c.P.c, M5, 2 * MF, gauge=c.Uc_dev)
     try:
         with pytest.raises(dwf.DWFError) as e:
             dwf.dwf_boundary_apply(c.full.ctx, other.ctx, c.mask_dev, psi, out)
