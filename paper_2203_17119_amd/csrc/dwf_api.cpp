@@ -431,6 +431,10 @@ int launch_stencil(Context &c, int prec, const StencilSpec &sp, Field in, Field 
 
 void launch_slocal(Context &c, int prec, int op, Field in, Field out, int nbatch, long bstride)
 {
+    // the operators of the form e0 + e1 P5 need only the fifth-dimension neighbours
+    if (op == SL_A || op == SL_ADAG) return launch_slocal_shift(c, prec, c.p.b, c.p.c, op == SL_ADAG, in, out, nbatch, bstride);
+    if (op == SL_MOOEE || op == SL_MOOEEDAG)
+        return launch_slocal_shift(c, prec, c.d, c.e, op == SL_MOOEEDAG, in, out, nbatch, bstride);
     switch (prec) {
     case P_F64: launch_slocal_f64(c, op, in, out, nbatch, bstride); break;
     case P_F32: launch_slocal_f32(c, op, in, out, nbatch, bstride); break;

@@ -231,6 +231,11 @@ int launch_stencil(Context &c, int prec, const StencilSpec &sp, Field in, Field 
 void launch_mask_links(Context &c, const int8_t *mask, const double *gin, double *gout);
 void launch_boundary_mask(Context &c, const int8_t *mask, Field in, Field out, int parity, int kind);
 
+// s-local operator e0 + e1 P5 (dag: P5^+) from the fifth-dimension neighbours
+// (A, A^+, Mooee, Mooee^+; launch_slocal uses it for those); in and out may alias
+void launch_slocal_shift(Context &c, int prec, double e0, double e1, bool dag, Field in, Field out, int nbatch = 1,
+                         long bstride = 0);
+
 // s-local dense operator out = M in (M one of SlocalOp); in and out may alias
 void launch_slocal(Context &c, int prec, int op, Field in, Field out, int nbatch = 1, long bstride = 0);
 

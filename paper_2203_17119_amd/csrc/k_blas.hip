@@ -1032,6 +1032,56 @@ void ms_launch_flush(Context &c, int prec, Field X, Field P, const double *coef,
     DWF_DISPATCH(prec, k_ms_flush_b, dim3((unsigned)np, nrhs), dim3(BS), 0, nrhs, nshift, X, P, stride, coef);
 }
 
+// s-local operator of the form e0 + e1 P5 (dag: e0 + e1 P5^+): A, A^+, Mooee
+// and Mooee^+, from the fifth-dimension neighbours alone instead of a dense
+// Ls x Ls product (workgroup = Ls x sb lanes, one 4D site per row).  The
+// Ls x 12 block of a 4D site is staged component-major in LDS, so consecutive
+// lanes s touch consecutive words.  in and out may alias: every lane reads its
+// own element before the barrier.
+template <typename S>
+__global__ void __launch_bounds__(256) k_slocal_shift(Field in, Field out, double e0, double e1, int dag, double mf,
+                                                      long vh, int Ls, long bstride)
+{
+    using C = Cof<S>;
+    in = member(in, blockIdx.y, bstride);
+    out = member(out, blockIdx.y, bstride);
+    const int s = threadIdx.x, j = threadIdx.y, sb = blockDim.y;
+    const long cb = (long)blockIdx.x * sb + j;
+    const bool valid = cb < vh;
+    const long i = cb * Ls + s;
+    extern __shared__ unsigned char smem[];
+    cx<C> *rows = (cx<C> *)smem + (long)j * 12 * Ls;
+    cx<C> v[12];
+    if (valid) {
+        load_spinor<S, C>(in, i, v);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 12; c++) v[c] = mk(C(0), C(0));
+    }
+#pragma unroll
+    for (int c = 0; c < 12; c++) rows[c * Ls + s] = v[c];
+    __syncthreads();
+    if (!valid) return;
+    const C a0 = C(e0), a1 = C(e1);
+    cx<C> res[12];
+#pragma unroll
+    for (int c = 0; c < 12; c++) res[c] = a0 * v[c] + a1 * shift5t<C>(rows, c, s, Ls, dag != 0, C(mf));
+    store_spinor<S, C>(out, i, res);
+}
+
+void launch_slocal_shift(Context &c, int prec, double e0, double e1, bool dag, Field in, Field out, int nbatch,
+                         long bstride)
+{
+    const int Ls = c.Ls, sb = default_sb(c);
+    const long nblk = (c.vh + sb - 1) / sb;
+    const int nb = std::max(1, nbatch);
+    const size_t lds = (size_t)sb * Ls * 12 * (prec == P_F64 ? 16 : 8);
+    const double fb = 12.0 * elem_bytes(prec) + (prec == P_F16 ? 4.0 : 0.0);
+    Timer tm(c, DWF_K_SLOCAL, nb * 2.0 * fb * c.n5h, nb * 96.0 * c.n5h, prec);
+    DWF_DISPATCH(prec, k_slocal_shift, dim3((unsigned)nblk, (unsigned)nb), dim3(Ls, sb), lds, in, out, e0, e1,
+                 dag ? 1 : 0, c.p.mf, c.vh, Ls, nb > 1 ? bstride : 0L);
+}
+
 // plain 16-byte streaming copy, grid-stride
 __global__ void __launch_bounds__(BS) k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, long n)
 {
