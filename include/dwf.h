@@ -389,6 +389,14 @@ enum { DWF_NET_FWD_FP32 = 0, DWF_NET_FWD_MFMA_BF16 = 1 };
 dwf_status dwf_net_set_forward(dwf_net net, int mode);
 /* out = restrict_odd(N(embed_odd(in))); canonical FP64 odd half fields */
 dwf_status dwf_precond_apply(dwf_ctx ctx, dwf_net net, const double *in_odd, double *out_odd);
+/* The same on internal odd half fields (layout of dwf_import) in storage
+ * precisions in_prec and out_prec (DWF_F64/F32/F16/BF16; in and out distinct
+ * device buffers), as FGCR applies it.  With the matrix-core forward, an FP32
+ * input and an FP32 or BF16 output, the first layer reads the input spinor and
+ * the last writes the output spinor directly (no layout passes); the result
+ * is the same as through the feature layout. */
+dwf_status dwf_precond_apply_internal(dwf_ctx ctx, dwf_net net, int in_prec, const void *in, int out_prec,
+                                      void *out);
 /* Gradients of a real loss L through y = precond(in), given grad_out =
  * dL/dRe(y) + i dL/dIm(y): grad_in the same for the input (may be NULL) and
  * grad_w (host, FP32 pairs in the weight layout, may be NULL). */

@@ -219,10 +219,16 @@ __device__ __forceinline__ cx<float> raw_feat(typename std::conditional<BF, uint
 // load latency.  With the accumulators in VGPRs, four waves fit without spills
 // for CIN = 4 and three for wider inputs (whose prefetched features take more
 // registers).
+// io: bit 0 set: the input is an FP32 internal half spinor of the odd sites
+// (the four spin channels of the network's embedded input, zero on the even
+// sites) instead of FP32 features (FP32 input only); bits 1-2: the output is
+// written as an internal half spinor of the odd sites, 1 in FP32 and 2 in BF16
+// storage, instead of FP32 features (FP32 output of the last layer, p = 1 only).
+// The conversions between spinor and feature layouts then need no pass of their own.
 template <int CIN, int COUT, bool IBF, bool OBF>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(CIN <= 4 ? 4 : 3, CIN <= 4 ? 4 : 3))) k_ptc_fwd_mfma(NetGeo g, const void *in, void *out, const short *wpk, int p,
-                                                      long n, int pmask)
+                                                      long n, int pmask, int io)
 {
     static_assert(CIN % 4 == 0 && 2 * COUT <= 32, "channel counts");
     constexpr int NCOL = 3 * MF_S, NP = CIN / 2, HP = NP / 2;
@@ -290,6 +296,19 @@ __global__ void __launch_bounds__(256)
                         raw[q][1][c] = w.y;
                     }
                 }
+        } else if (CIN == 4 && (io & 1)) {
+            // the odd half spinor, component ch * 3 + colour in 16-byte planes of
+            // two: this thread's channel pair (2 th, 2 th + 1) is components
+            // 6 th .. 6 th + 5, whole planes 3 th .. 3 th + 2
+            hv = hv && sp == 1;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                if (!hv) continue;
+                const float4 w = ((const float4 *)in)[(long)(3 * th + k) * n + src];
+                const int m0 = 2 * k, m1 = 2 * k + 1;  // local components (channel e = m / 3, colour m % 3)
+                raw[0][m0 / 3][m0 % 3] = make_float2(w.x, w.y);
+                raw[0][m1 / 3][m1 % 3] = make_float2(w.z, w.w);
+            }
         } else {
             const long base = (long)sp * CIN * 3 * n + src;
 #pragma unroll
@@ -395,6 +414,16 @@ __global__ void __launch_bounds__(256)
                 w.x = *(const uint32_t *)&b0;
                 w.y = *(const uint32_t *)&b1;
                 ((uint2 *)out)[(long)p * (COUT / 2) * 3 * n + (long)((a0 / 2) * 3 + cc) * n + i] = w;
+            } else if (io >> 1 == 1) {
+                // FP32 odd half spinor: 16-byte planes of two components
+                const int c0 = a0 * 3 + cc, c1 = c0 + 3;
+                ((float2 *)out)[(long)(c0 >> 1) * 2 * n + 2 * i + (c0 & 1)] = v0;
+                ((float2 *)out)[(long)(c1 >> 1) * 2 * n + 2 * i + (c1 & 1)] = v1;
+            } else if (io >> 1 == 2) {
+                // BF16 odd half spinor: 16-byte planes of four components
+                const int c0 = a0 * 3 + cc, c1 = c0 + 3;
+                ((__hip_bfloat162 *)out)[(long)(c0 >> 2) * 4 * n + 4 * i + (c0 & 3)] = __float22bfloat162_rn(v0);
+                ((__hip_bfloat162 *)out)[(long)(c1 >> 2) * 4 * n + 4 * i + (c1 & 3)] = __float22bfloat162_rn(v1);
             } else {
                 const long k = (long)p * COUT * 3 * n + (long)(a0 * 3 + cc) * n + i;
                 ((float2 *)out)[k] = v0;
@@ -627,14 +656,16 @@ void launch_pack_mfma_weights(Context &c, int cin, int cout, const void *w_bf16,
 }
 
 void launch_ptc_layer_mfma(Context &c, int cin, int cout, const void *in, void *out, const short *pk, int p,
-                           bool in_bf16, bool out_bf16, int pmask)
+                           bool in_bf16, bool out_bf16, int pmask, int io)
 {
+    if (((io & 1) && (in_bf16 || cin != 4)) || ((io >> 1) && (out_bf16 || cout != 4 || p != 1)) || io > 5)
+        fail(DWF_EINVAL, "spinor input or output needs an FP32 four-channel side of the odd sites");
     const NetGeo g = net_geo(c);
     const dim3 grid((unsigned)((c.n5h + MF_S - 1) / MF_S)), blk(256);
     const double flops = (double)c.n5h * (11.0 * cout * cin * 3 * 8 + 8.0 * cin * 66);
     Timer tm(c, DWF_K_NET, (double)c.n5h * 3 * (11.0 * cin * (in_bf16 ? 4 : 8) + cout * (out_bf16 ? 4 : 8)), flops);
 #define NETK(CI, CO, IB, OB) \
-    hipLaunchKernelGGL((k_ptc_fwd_mfma<CI, CO, IB, OB>), grid, blk, 0, c.stream, g, in, out, pk, p, c.n5h, pmask)
+    hipLaunchKernelGGL((k_ptc_fwd_mfma<CI, CO, IB, OB>), grid, blk, 0, c.stream, g, in, out, pk, p, c.n5h, pmask, io)
 #define NETL(CI, CO)                        \
     do {                                    \
         if (in_bf16 && out_bf16)            \

@@ -24,7 +24,7 @@ void launch_ptc_layer(Context &c, int cin, int cout, const float2 *in, float2 *o
 size_t mfma_weight_elems(int cin);
 void launch_pack_mfma_weights(Context &c, int cin, int cout, const void *w_bf16, short *pk);
 void launch_ptc_layer_mfma(Context &c, int cin, int cout, const void *in, void *out, const short *pk, int p,
-                           bool in_bf16, bool out_bf16, int pmask = kAllPaths);
+                           bool in_bf16, bool out_bf16, int pmask = kAllPaths, int io = 0);
 int launch_ptc_wgrad(Context &c, int cin, int cout, const float2 *in, const float2 *gout, int p, double *partial,
                      long partial_len);
 void launch_wgrad_finish(Context &c, const double *partial, int nblk, int nw, float *gw, bool accumulate);
@@ -96,12 +96,18 @@ static void refresh_bf16(dwf_net_s *n)
 // is evaluated on odd sites only (the preconditioner's range)
 // (mfma: the matrix-core forward, BF16 operands with FP32 accumulation)
 // The network input is an odd-site field embedded with zeros on the even
-// sites (every caller fills acts[0] that way), so the first layer skips the
-// paths that only read even sites: for the odd output the eight hops (they
-// come from the other parity), for the even output the identity and s-paths.
+// sites, so the first layer skips the paths that only read even sites: for the
+// odd output the eight hops (they come from the other parity), for the even
+// output the identity and s-paths.  The forward therefore never reads the even
+// part of acts[0]; the callers that run the adjoint or train clear it.
 static constexpr int kHopPaths = 0x1fe, kLocalPaths = 0x601;
 
-static void net_forward(dwf_net_s *n, bool all_parities, bool mfma = false)
+// With the matrix-core forward the first layer may read the odd half spinor
+// in_sp (FP32) instead of acts[0], and the last layer (odd sites only) may
+// write the odd half spinor out_sp (FP32 or BF16, out_prec) instead of
+// acts[nlayer]: the layout conversions then cost no pass of their own.
+static void net_forward(dwf_net_s *n, bool all_parities, bool mfma = false, Field in_sp = {}, Field out_sp = {},
+                        int out_prec = P_F32)
 {
     Context &c = *n->c;
     for (int l = 0; l < n->nlayer; l++) {
@@ -111,9 +117,12 @@ static void net_forward(dwf_net_s *n, bool all_parities, bool mfma = false)
             if (mfma) {
                 // FP32 network input and output, BF16 activations in between
                 const bool ibf = l > 0, obf = !last;
-                launch_ptc_layer_mfma(c, n->chans[l], n->chans[l + 1], ibf ? n->acts_bf[l] : (const void *)n->acts[l],
-                                      obf ? n->acts_bf[l + 1] : (void *)n->acts[l + 1], n->wpk + n->pkoff[l], p, ibf,
-                                      obf, pmask);
+                const bool isp = l == 0 && in_sp.data, osp = last && out_sp.data && !all_parities;
+                const int io = (isp ? 1 : 0) | (osp ? (out_prec == P_BF16 ? 4 : 2) : 0);
+                const void *src = isp ? in_sp.data : ibf ? n->acts_bf[l] : (const void *)n->acts[l];
+                void *dst = osp ? out_sp.data : obf ? n->acts_bf[l + 1] : (void *)n->acts[l + 1];
+                launch_ptc_layer_mfma(c, n->chans[l], n->chans[l + 1], src, dst, n->wpk + n->pkoff[l], p, ibf, obf,
+                                      pmask, io);
             } else {
                 launch_ptc_layer(c, n->chans[l], n->chans[l + 1], n->acts[l], n->acts[l + 1],
                                  (const __hip_bfloat162 *)n->wbf + n->woff[l], p, pmask);
@@ -364,14 +373,23 @@ namespace dwf {
 static void precondition(dwf_net_s *n, int rprec, Field r, int zprec, Field z, bool normal)
 {
     Context &c = *n->c;
-    launch_spinor_to_feat(c, rprec, r, n->acts[0], 1, true);
+    const bool mfma = n->fwd == DWF_NET_FWD_MFMA_BF16;
+    if (!normal && mfma && rprec == P_F32 && (zprec == P_F32 || zprec == P_BF16)) {
+        // the first layer reads r and the last writes z in their spinor layouts
+        net_forward(n, false, true, r, z, zprec);
+        return;
+    }
+    // the forward alone reads only the odd sites of its input (the first
+    // layer's path mask), so the even part need not be cleared; the adjoint
+    // reads both parities
+    launch_spinor_to_feat(c, rprec, r, n->acts[0], 1, normal);
     if (normal) {
         // N^+ r: adjoint network on the embedded residual, then N on its result
         const float2 *adj = net_adjoint(n, n->acts[0]);
         launch_feat_to_spinor(c, zprec, adj, z, 1);  // keep odd part only
         launch_spinor_to_feat(c, zprec, z, n->acts[0], 1, true);
     }
-    net_forward(n, false, n->fwd == DWF_NET_FWD_MFMA_BF16);
+    net_forward(n, false, mfma);
     launch_feat_to_spinor(c, zprec, n->acts[n->nlayer], z, 1);
 }
 
@@ -404,6 +422,21 @@ static void fgcr_op(Context &c, int prec, Field in, Field out, bool normal)
 }
 
 }  // namespace dwf
+
+extern "C" dwf_status dwf_precond_apply_internal(dwf_ctx ctx, dwf_net net, int in_prec, const void *in, int out_prec,
+                                                 void *out)
+{
+    DWF_API_BEGIN
+    if (!ctx || !net) fail(DWF_EINVAL, "null context or network");
+    if (net->c != ctx) fail(DWF_EINVAL, "network belongs to another context");
+    if (!in || !out) fail(DWF_EINVAL, "null field");
+    if (in_prec < P_F64 || in_prec > P_BF16 || out_prec < P_F64 || out_prec > P_BF16)
+        fail(DWF_EINVAL, "unknown precision");
+    if (in == out) fail(DWF_EINVAL, "in and out must differ");
+    Context &c = *ctx;
+    precondition(net, in_prec, make_field(c, (void *)in, in_prec), out_prec, make_field(c, out, out_prec), false);
+    DWF_API_END
+}
 
 extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, double *x_full,
                                const dwf_solver_opts *o, dwf_solver_stats *st)

@@ -113,6 +113,7 @@ SIGNATURES = {
     "dwf_ddrhmc_action": ([_CTX, _CTX, C.POINTER(dwf_rational), C.POINTER(dwf_rational), _P,
                            C.POINTER(dwf_solver_opts), C.POINTER(_D), C.POINTER(dwf_solver_stats)], C.c_int32),
     "dwf_chebyshev_filter": ([_CTX, _I, _P, _D, _D, _I, C.POINTER(_I), C.POINTER(_P)], C.c_int32),
+    "dwf_precond_apply_internal": ([_CTX, _NET, _I, _P, _I, _P], C.c_int32),
     "dwf_mask_links": ([_CTX, _P, _P, _P], C.c_int32),
     "dwf_d5_apply": ([_CTX, _P, _P], C.c_int32),
     "dwf_boundary_project": ([_CTX, _P, _P, _P], C.c_int32),
@@ -412,6 +413,11 @@ def dwf_net_set_forward(net, mode):
 
 def dwf_precond_apply(ctx, net, in_odd, out_odd):
     _check(load().dwf_precond_apply(ctx, net, _ptr(in_odd), _ptr(out_odd)))
+
+
+def dwf_precond_apply_internal(ctx, net, in_prec, inp, out_prec, out):
+    """The preconditioner on internal odd fields of the given storage precisions."""
+    _check(load().dwf_precond_apply_internal(ctx, net, int(in_prec), _ptr(inp), int(out_prec), _ptr(out)))
 
 
 def dwf_net_backward(net, in_odd, grad_out_odd, grad_in_odd=None, want_w=True):

@@ -109,6 +109,43 @@ def test_precond_apply_mfma_matches_oracle(case, chans):
         dwf.dwf_net_destroy(net)
 
 
+@pytest.mark.parametrize("Ls", [4, 12])
+def test_precond_apply_internal_spinor_layouts(Ls):
+    """The preconditioner on internal fields as FGCR applies it: with the
+    matrix-core forward, an FP32 input and an FP32 or BF16 output, the first
+    layer reads the input spinor and the last writes the output spinor directly.
+    The FP32 result is bit-identical to the canonical entry point (which goes
+    through the feature layout), the BF16 one is its BF16 rounding, and the
+    FP64 internal path (through the feature layout) matches too."""
+    c = Case((4, 4, 2, 4), Ls, mf=0.05, dirichlet=(1, 0, 0, 1), eps=0.6, seed=57)
+    Ws = random_weights(CHANS, 6)
+    net = dwf.dwf_net_create(c.ctx, CHANS)
+    T = torch()
+    try:
+        dwf.dwf_net_set_weights(net, flat(Ws))
+        dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_MFMA_BF16)
+        x = to_gpu(c.half(67))
+        ref = T.empty_like(x)
+        dwf.dwf_precond_apply(c.ctx, net, x, ref)
+        ref_h = to_host(ref)
+        for pin, pout in ((dwf.DWF_F32, dwf.DWF_F32), (dwf.DWF_F32, dwf.DWF_BF16), (dwf.DWF_F64, dwf.DWF_F64)):
+            xi, yi = c.lat.internal(pin), c.lat.internal(pout)
+            dwf.dwf_import(c.ctx, 0, pin, x, xi)
+            dwf.dwf_precond_apply_internal(c.ctx, net, pin, xi, pout, yi)
+            y = T.empty_like(x)
+            dwf.dwf_export(c.ctx, 0, pout, yi, y)
+            got = to_host(y)
+            if pout == dwf.DWF_BF16:
+                want = bf16_round(ref_h.real) + 1j * bf16_round(ref_h.imag)
+            else:
+                want = ref_h
+            print(f"Ls={Ls} in {pin} out {pout}: max |diff| {np.abs(got - want).max():.2e}", flush=True)
+            assert np.array_equal(got, want)
+    finally:
+        dwf.dwf_net_destroy(net)
+        c.close()
+
+
 def test_precond_apply_mfma_ragged_tile():
     """A lattice whose 3 x (5D sites) columns do not fill the last 128-column tile."""
     c = Case((4, 2, 2, 2), 3, mf=0.1, dirichlet=(0, 1, 0, 0), eps=0.5, seed=52)
