@@ -377,6 +377,57 @@ def cpu_baseline(w, U, b_full, cg_iters):
     }
 
 
+def ddrhmc_action(dwf, synth, torch, tune_cache):
+    """The DD-RHMC one-flavour boundary action S = phi^+ r_q(A_d) r_m(A)
+    r_q(A_d) phi on 16^4 x 12: A from the whole lattice of one field
+    (periodic), A_d from the same field with every face cut; r_q ~ x^{1/4} and
+    r_m ~ x^{-1/2} are the committed degree-20 approximations on [1e-5, 1000].
+    Each multi-shift solve (two with A_d, one with A) runs in mixed FP32 to
+    1e-8 per shift; one untimed evaluation allocates the workspaces first."""
+    w = synth.WORKLOADS["16^4x12_multishift"]
+    U = synth.gauge_field(w.dims, w.eps, w.gauge_seed)
+    full = dwf.Lattice(w.dims, w.Ls, w.b, w.c, w.M5, w.mf, (0, 0, 0, 0), gauge=U)
+    cut = dwf.Lattice(w.dims, w.Ls, w.b, w.c, w.M5, w.mf, (1, 1, 1, 1), gauge=U)
+    del U
+    here = os.path.join(ROOT, "paper_2203_17119_amd", "rational")
+    coef = {}
+    for name in ("x0.25_1e-05_1000_n20.json", "x-0.5_1e-05_1000_n20.json"):
+        with open(os.path.join(here, name)) as fh:
+            coef[name] = json.load(fh)
+    rq = dwf.make_rational(*(coef["x0.25_1e-05_1000_n20.json"][k] for k in ("a0", "alpha", "beta")))
+    rm = dwf.make_rational(*(coef["x-0.5_1e-05_1000_n20.json"][k] for k in ("a0", "alpha", "beta")))
+    out = {"workload": "16^4x12_multishift field: whole lattice periodic, the block with every face cut",
+           "mode": "mixed_f32", "tol": w.tol, "poles": 20, "interval": [1e-5, 1000]}
+    try:
+        for lat in (full, cut):
+            dwf.dwf_tune(lat.ctx, dwf.DWF_F32, tune_cache)
+        V = int(np.prod(w.dims))
+        phi = torch.from_numpy(synth.gaussian_fermion(w.dims, w.Ls, w.source_seeds[0], nsites=V // 2)).cuda()
+        # the top of each spectrum (20 power steps of Mpc^+ Mpc), against the interval's upper end
+        tops = {}
+        for name, lat in (("A", full), ("A_d", cut)):
+            u, t = phi / phi.norm(), torch.empty_like(phi)
+            for _ in range(20):
+                dwf.dwf_schur_apply(lat.ctx, 0, u, t)
+                dwf.dwf_schur_apply(lat.ctx, 1, t, u)
+                lam = float(u.norm())
+                u /= lam
+            tops[name] = round(lam, 2)
+        out["spectrum_top"] = tops
+        dwf.dwf_ddrhmc_action(full.ctx, cut.ctx, rq, rm, phi, tol=w.tol, mode=dwf.DWF_SOLVE_MIXED_F32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, S, st = dwf.dwf_ddrhmc_action(full.ctx, cut.ctx, rq, rm, phi, tol=w.tol, mode=dwf.DWF_SOLVE_MIXED_F32)
+        torch.cuda.synchronize()
+        out.update({"status": s, "seconds": round(time.perf_counter() - t0, 4), "action": S,
+                    "worst_shift_iters": [x["iters"] for x in st]})
+        log(f"ddrhmc action: {out}")
+    finally:
+        full.close()
+        cut.close()
+    return out
+
+
 def boundary_operators(dwf, synth, torch, tune_cache):
     """The domain-boundary operators of the two-flavour boundary action on the
     24^4 x 12 periodic lattice split at t = 12 (Omega = t < 12): R^-1 psi (one
@@ -490,6 +541,8 @@ def main():
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the FGCR solve with the trained network preconditioner")
     ap.add_argument("--no-multishift", action="store_true", help="skip the batched multi-shift solve")
+    ap.add_argument("--ddrhmc", action="store_true",
+                    help="also time the DD-RHMC one-flavour boundary action on 16^4 x 12")
     ap.add_argument("--boundary", action="store_true",
                     help="also time the domain-boundary operators R and R^-1 on the 24^4 x 12 periodic lattice")
     ap.add_argument("--no-c5", action="store_true",
@@ -624,9 +677,16 @@ def main():
             del srcs, x
             torch.cuda.empty_cache()
         c5 = c5_comparison(dwf, synth, torch, tune_cache)
+    dd = None
+    if args.ddrhmc:
+        if args.no_multishift and args.no_c5:
+            lat.close()
+            del srcs, x
+            torch.cuda.empty_cache()
+        dd = ddrhmc_action(dwf, synth, torch, tune_cache)
     bd = None
     if args.boundary:
-        if args.no_multishift and args.no_c5:
+        if args.no_multishift and args.no_c5 and not args.ddrhmc:
             lat.close()
             del srcs, x
             torch.cuda.empty_cache()
@@ -690,6 +750,7 @@ def main():
         "bandwidth_probes": {k: {kk: v[kk] for kk in v if kk != "configs"} for k, v in ceiling.items()},
         "c5_24x24x24x24_ls12_periodic": c5,
         "boundary_operators": bd,
+        "ddrhmc_action": dd,
         "dhop": table,
         "cpu_baseline": cpu,
     }

@@ -67,7 +67,7 @@ def test_matrix_powers():
 
 @pytest.mark.parametrize("name,power", [("x0.25_0.01_100_n12.json", 0.25), ("x-0.5_0.01_100_n12.json", -0.5),
                                         ("x0.25_1e-05_100_n20.json", 0.25), ("x-0.5_1e-05_100_n20.json", -0.5),
-                                        ("x-0.5_1e-05_1000_n20.json", -0.5)])
+                                        ("x-0.5_1e-05_1000_n20.json", -0.5), ("x0.25_1e-05_1000_n20.json", 0.25)])
 def test_rational_matches_power_on_the_spectrum(name, power):
     r = load_rational(name)
     assert r["power"] == power and len(r["alpha"]) == r["degree"] and min(r["beta"]) > 0
