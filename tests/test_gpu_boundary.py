@@ -176,3 +176,38 @@ def test_identities_8x8x8x8_ls8():
             assert err < bound
     finally:
         c.close()
+
+
+def test_boundary_apply_in_caller_workspace():
+    """R^-1 with the full context's workspace carved from a torch buffer sized
+    by dwf_workspace_bytes(DWF_OP_BOUNDARY): nothing allocated by the library
+    on that context during the call, and the same result."""
+    print("\n[boundary in caller workspace, 4x4x4x4 ls4]", flush=True)
+    L = (4, 4, 4, 4)
+    T = torch()
+    ref_c, c = BCase(L, 4, _mask_t(L, 2), seed=37), BCase(L, 4, _mask_t(L, 2), seed=37)
+    try:
+        psi = to_gpu(c.field(38))
+        want = T.empty_like(psi)
+        dwf.dwf_boundary_apply(ref_c.full.ctx, ref_c.cut.ctx, ref_c.mask_dev, psi, want, inverse=True, tol=1e-10)
+        # the cut context allocates its own buffers on first use; do that first
+        got = T.empty_like(psi)
+        dwf.dwf_boundary_apply(c.full.ctx, c.cut.ctx, c.mask_dev, psi, got, inverse=True, tol=1e-10, maxit=1)
+        c.full.close()
+        c.full = dwf.Lattice(L, 4, B, C, M5, MF, gauge=c.U)
+        need = dwf.dwf_workspace_bytes(c.full.ctx, dwf.DWF_OP_BOUNDARY, dwf.DWF_SOLVE_F64)
+        ws = T.empty(need, dtype=T.uint8, device="cuda")
+        dwf.dwf_prepare_links(c.full.ctx, dwf.DWF_F64)
+        dwf.dwf_set_workspace(c.full.ctx, ws)
+        T.cuda.synchronize()
+        before = T.cuda.mem_get_info()[0]
+        s, st = dwf.dwf_boundary_apply(c.full.ctx, c.cut.ctx, c.mask_dev, psi, got, inverse=True, tol=1e-10)
+        T.cuda.synchronize()
+        after = T.cuda.mem_get_info()[0]
+        used = dwf.dwf_workspace_used(c.full.ctx)
+        print(f"need {need} B, used {used} B, free memory change {after - before} B", flush=True)
+        assert s == dwf.DWF_OK and 0 < used <= need and after == before
+        assert T.equal(got, want)
+    finally:
+        ref_c.close()
+        c.close()
