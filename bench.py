@@ -377,6 +377,60 @@ def cpu_baseline(w, U, b_full, cg_iters):
     }
 
 
+def small_solves(dwf, synth, torch):
+    """The small periodic workload (4^4 x 8) solved in full by the oracle (FP64
+    CGNE on the host cores) and by the library (FP64 CGNE on the GPU), to
+    1e-10, with the oracle's solution as the check of the GPU's; and the
+    16^4 x 12 Dirichlet block solved on the GPU, the oracle's time for it
+    extrapolated from one application of its normal operator."""
+    import oracle
+
+    w = synth.WORKLOADS["4^4x8_periodic"]
+    U = synth.gauge_field(w.dims, w.eps, w.gauge_seed)
+    b = synth.gaussian_fermion(w.dims, w.Ls, w.source_seeds[0])
+    P = oracle.Params(w.dims, w.Ls, w.b, w.c, w.M5, w.mf)
+    t0 = time.perf_counter()
+    x_or, it_or, res_or = oracle.cgne(P, U, b, w.tol)
+    t_or = time.perf_counter() - t0
+    lat = dwf.Lattice(w.dims, w.Ls, w.b, w.c, w.M5, w.mf, w.dirichlet, gauge=U)
+    try:
+        bg = torch.from_numpy(b).cuda()
+        xg = torch.zeros_like(bg)
+        dwf.dwf_cg(lat.ctx, bg, xg, tol=w.tol)
+        xg.zero_()
+        s, st = dwf.dwf_cg(lat.ctx, bg, xg, tol=w.tol)
+        diff = float(np.linalg.norm(xg.cpu().numpy() - x_or) / np.linalg.norm(x_or))
+    finally:
+        lat.close()
+    out = {"c1": {"workload": f"4^4x8_periodic, FP64 CGNE to {w.tol:g}, solved in full",
+                  "oracle_seconds": round(t_or, 4), "oracle_iters": int(it_or),
+                  "gpu_seconds": round(st["seconds"], 4), "gpu_iters": st["iters"], "solution_rel_diff": diff}}
+    # 16^4 x 12 Dirichlet: the GPU FP64 solve in full, the oracle's one
+    # normal-operator application times its iteration count
+    w = synth.WORKLOADS["16^4x12_dirichlet"]
+    U = synth.gauge_field(w.dims, w.eps, w.gauge_seed)
+    b = synth.gaussian_fermion(w.dims, w.Ls, w.source_seeds[0])
+    lat = dwf.Lattice(w.dims, w.Ls, w.b, w.c, w.M5, w.mf, w.dirichlet, gauge=U)
+    try:
+        bg = torch.from_numpy(b).cuda()
+        xg = torch.zeros_like(bg)
+        dwf.dwf_cg(lat.ctx, bg, xg, tol=w.tol, maxit=20)
+        xg.zero_()
+        s, st = dwf.dwf_cg(lat.ctx, bg, xg, tol=w.tol)
+    finally:
+        lat.close()
+    P = oracle.Params(w.dims, w.Ls, w.b, w.c, w.M5, w.mf)
+    Ud = oracle.dirichlet(w.dims, U, w.dirichlet)
+    odd = oracle.pick(P, b, 1)
+    t0 = time.perf_counter()
+    oracle.mpc(P, Ud, oracle.mpc(P, Ud, odd), True)
+    t_op = time.perf_counter() - t0
+    out["c2"] = {"workload": f"16^4x12_dirichlet, FP64 CGNE to {w.tol:g}", "gpu_seconds": round(st["seconds"], 4),
+                 "gpu_iters": st["iters"], "oracle_normal_op_seconds": round(t_op, 3),
+                 "oracle_seconds_extrapolated": round(t_op * st["iters"], 1)}
+    return out
+
+
 def ddrhmc_action(dwf, synth, torch, tune_cache):
     """The DD-RHMC one-flavour boundary action S = phi^+ r_q(A_d) r_m(A)
     r_q(A_d) phi on 16^4 x 12: A from the whole lattice of one field
@@ -692,6 +746,9 @@ def main():
             torch.cuda.empty_cache()
         bd = boundary_operators(dwf, synth, torch, tune_cache)
     cpu = None if args.no_cpu else cpu_baseline(w, U, b0_host, st64["iters"])
+    if cpu is not None:
+        cpu["small_solves"] = small_solves(dwf, synth, torch)
+        log(f"small solves: {cpu['small_solves']}")
 
     ms_step = t_total / args.steps * 1e3
     tmixed = float(np.median([s["seconds"] for s in stats]))
