@@ -328,7 +328,8 @@ void launch_cg_update_p(Context &c, int prec, Field r, Field p, Field pout, Fiel
 long gs_partials_needed(const Context &c, int nv);
 void launch_gs_dots(Context &c, int prec, const void *const *X_dev, int nv, Field y, double *partial, double *out);
 // prec is the precision of the basis vectors (X, W, y, w, z, q), rprec that of
-// the residual r and the solution x: FP64/FP64, FP32/FP32 or BF16/FP32.
+// the residual r and the solution x: FP64/FP64, FP32/FP32 or BF16/FP32.  With
+// an empty w (and no W_dev; BF16 basis only) y alone is projected.
 void launch_gs_project(Context &c, int prec, int rprec, const void *const *X_dev, const void *const *W_dev, int nv,
                        const double *dots, const double *nq, Field y, Field w, Field r, double *partial, double *out);
 int launch_gs_update(Context &c, int prec, int rprec, Field x, Field z, Field r, Field q, const double *coef);
@@ -336,6 +337,11 @@ int launch_gs_update(Context &c, int prec, int rprec, Field x, Field z, Field r,
 // their pointers), a_j from coef[3j..3j+2] as in gs_update; x FP32.  With it
 // the per-step update may pass an empty x.
 void launch_gs_combine(Context &c, int prec, Field x, const void *const *Z_dev, int nz, const double *coef);
+// coefficients cc (3 nz doubles, the form gs_combine reads) that combine nz
+// unprojected directions into the update the projected ones would give:
+// dots[k stride ..] holds step k's projection dots, nq the per-step info
+// {|q_k|^2, <q_k, r>}; one thread on the device
+void launch_gs_raw_coef(Context &c, int nz, int stride, const double *dots, const double *nq, double *cc);
 // x += dscal[ia] p, x in the accumulator precision of prec
 void launch_axpy_dev(Context &c, int prec, Field x, Field p, int ia);
 // device scalar arithmetic: dscal[out] = dscal[num] / dscal[den]

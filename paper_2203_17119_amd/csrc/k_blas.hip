@@ -656,6 +656,10 @@ __global__ void __launch_bounds__(BS) k_gs_dots_bf(const uint2 *const *X, int nv
     }
 }
 
+// PW false: only y is projected (w and W unused); the caller keeps its
+// preconditioned directions as they were made and combines them at the restart
+// with coefficients transformed by k_gs_raw_coef.
+template <bool PW>
 __global__ void __launch_bounds__(BS) k_gs_project_bf(const uint2 *const *X, const uint2 *const *W, int nv,
                                                       const double *dots, const double *nq, uint2 *y, uint2 *w,
                                                       const float4 *r, long m2, long nsite, double *partial)
@@ -667,30 +671,33 @@ __global__ void __launch_bounds__(BS) k_gs_project_bf(const uint2 *const *X, con
     for (int e = 0; e < GS_PPT; e++) {
         const long k = base + (long)e * BS;
         yv[e] = k < m2 ? bf_pair(y[k]) : make_float4(0.f, 0.f, 0.f, 0.f);
-        wv[e] = k < m2 ? bf_pair(w[k]) : make_float4(0.f, 0.f, 0.f, 0.f);
+        if constexpr (PW) wv[e] = k < m2 ? bf_pair(w[k]) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     for (int j = 0; j < nv; j++) {
         const double inv = 1.0 / nq[3 * j];
         const float bre = float(dots[2 * j] * inv), bim = float(dots[2 * j + 1] * inv);
-        const uint2 *xj = X[j], *wj = W[j];
+        const uint2 *xj = X[j];
         uint2 xr[GS_PPT], vr[GS_PPT];
 #pragma unroll
         for (int e = 0; e < GS_PPT; e++) {
             const long k = base + (long)e * BS;
             xr[e] = k < m2 ? xj[k] : make_uint2(0u, 0u);
-            vr[e] = k < m2 ? wj[k] : make_uint2(0u, 0u);
+            if constexpr (PW) vr[e] = k < m2 ? W[j][k] : make_uint2(0u, 0u);
         }
 #pragma unroll
         for (int e = 0; e < GS_PPT; e++) {
-            const float4 xd = bf_pair(xr[e]), vd = bf_pair(vr[e]);
+            const float4 xd = bf_pair(xr[e]);
             yv[e].x -= bre * xd.x - bim * xd.y;
             yv[e].y -= bre * xd.y + bim * xd.x;
             yv[e].z -= bre * xd.z - bim * xd.w;
             yv[e].w -= bre * xd.w + bim * xd.z;
-            wv[e].x -= bre * vd.x - bim * vd.y;
-            wv[e].y -= bre * vd.y + bim * vd.x;
-            wv[e].z -= bre * vd.z - bim * vd.w;
-            wv[e].w -= bre * vd.w + bim * vd.z;
+            if constexpr (PW) {
+                const float4 vd = bf_pair(vr[e]);
+                wv[e].x -= bre * vd.x - bim * vd.y;
+                wv[e].y -= bre * vd.y + bim * vd.x;
+                wv[e].z -= bre * vd.z - bim * vd.w;
+                wv[e].w -= bre * vd.w + bim * vd.z;
+            }
         }
     }
     double n2 = 0, dre = 0, dim_ = 0;
@@ -700,7 +707,7 @@ __global__ void __launch_bounds__(BS) k_gs_project_bf(const uint2 *const *X, con
         if (k >= m2) continue;
         const uint2 yb = bf_pack(yv[e]);
         y[k] = yb;
-        w[k] = bf_pack(wv[e]);
+        if constexpr (PW) w[k] = bf_pack(wv[e]);
         const float4 ys = bf_pair(yb);  // as stored
         const float4 rv = r[res_piece(k, nsite)];
         n2 += double(ys.x) * ys.x + double(ys.y) * ys.y + double(ys.z) * ys.z + double(ys.w) * ys.w;
@@ -792,6 +799,31 @@ __global__ void __launch_bounds__(BS) k_gs_combine_bf(float4 *x, const uint2 *co
         xv.z = float(xv.z + acc[e].z);
         xv.w = float(xv.w + acc[e].w);
         x[kr] = xv;
+    }
+}
+
+// Solution coefficients for directions kept as they were made.  With the
+// projected directions zt_k = z_k - sum_{j<k} b_jk zt_j (b_jk the projection
+// coefficient of step k against vector j: dots[k stride + 2 j] / nq[3 j]),
+// Z = Zt (1 + B) with B strictly upper triangular, so the update
+// x += sum_k a_k zt_k (a_k = <q_k, r> / |q_k|^2 from nq) equals
+// x += sum_k c_k z_k with (1 + B) c = a, solved by back substitution in FP64.
+// cc[3k] = 1, cc[3k + 1 .. 2] = c_k, the form k_gs_combine_bf reads.  One thread.
+__global__ void k_gs_raw_coef(int nz, int stride, const double *dots, const double *nq, double *cc)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int k = nz - 1; k >= 0; k--) {
+        const double inv = 1.0 / nq[3 * k];
+        double re = nq[3 * k + 1] * inv, im = nq[3 * k + 2] * inv;
+        for (int j = k + 1; j < nz; j++) {
+            const double bre = dots[(long)j * stride + 2 * k] * inv, bim = dots[(long)j * stride + 2 * k + 1] * inv;
+            const double cre = cc[3 * j + 1], cim = cc[3 * j + 2];
+            re -= bre * cre - bim * cim;
+            im -= bre * cim + bim * cre;
+        }
+        cc[3 * k] = 1.0;
+        cc[3 * k + 1] = re;
+        cc[3 * k + 2] = im;
     }
 }
 
@@ -1394,12 +1426,19 @@ void launch_gs_project(Context &c, int prec, int rprec, const void *const *X_dev
 {
     const long m = 12 * y.n, nblk = prec == P_BF16 ? gs_blocks_bf(m) : gs_blocks(m);
     gs_prec_check(prec, rprec, m);
-    Timer tm(c, DWF_K_BLAS, ((2.0 * nv + 4.0) * gs_elem_bytes(prec) + gs_elem_bytes(rprec)) * m,
-             (16.0 * nv + 12.0) * m, prec);
-    if (prec == P_BF16)
-        hipLaunchKernelGGL(k_gs_project_bf, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (const uint2 *const *)X_dev,
-                           (const uint2 *const *)W_dev, nv, dots, nq, (uint2 *)y.data, (uint2 *)w.data,
-                           (const float4 *)r.data, m / 2, y.n, partial);
+    const bool pw = w.data != nullptr;
+    if (!pw && (prec != P_BF16 || W_dev)) fail(DWF_EINVAL, "projection of y alone needs a BF16 basis and no W");
+    const double vecs = pw ? 2.0 * nv + 4.0 : nv + 2.0;
+    Timer tm(c, DWF_K_BLAS, (vecs * gs_elem_bytes(prec) + gs_elem_bytes(rprec)) * m,
+             ((pw ? 16.0 : 8.0) * nv + 12.0) * m, prec);
+    if (prec == P_BF16 && pw)
+        hipLaunchKernelGGL(k_gs_project_bf<true>, dim3((unsigned)nblk), dim3(BS), 0, c.stream,
+                           (const uint2 *const *)X_dev, (const uint2 *const *)W_dev, nv, dots, nq, (uint2 *)y.data,
+                           (uint2 *)w.data, (const float4 *)r.data, m / 2, y.n, partial);
+    else if (prec == P_BF16)
+        hipLaunchKernelGGL(k_gs_project_bf<false>, dim3((unsigned)nblk), dim3(BS), 0, c.stream,
+                           (const uint2 *const *)X_dev, (const uint2 *const *)nullptr, nv, dots, nq,
+                           (uint2 *)y.data, (uint2 *)nullptr, (const float4 *)r.data, m / 2, y.n, partial);
     else if (prec == P_F64)
         hipLaunchKernelGGL(k_gs_project<double2>, dim3((unsigned)nblk), dim3(BS), 0, c.stream,
                            (const double2 *const *)X_dev, (const double2 *const *)W_dev, nv, dots, nq,
@@ -1444,6 +1483,13 @@ void launch_gs_combine(Context &c, int prec, Field x, const void *const *Z_dev, 
     Timer tm(c, DWF_K_BLAS, (nz * 4.0 + 16.0) * m, 8.0 * nz * m, prec);
     hipLaunchKernelGGL(k_gs_combine_bf, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (float4 *)x.data,
                        (const uint2 *const *)Z_dev, nz, coef, m / 2, x.n);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_gs_raw_coef(Context &c, int nz, int stride, const double *dots, const double *nq, double *cc)
+{
+    if (nz < 1 || nz > GS_MAXV || stride < 2 * nz) fail(DWF_EINVAL, "raw-direction coefficients of 1..64 directions");
+    hipLaunchKernelGGL(k_gs_raw_coef, dim3(1), dim3(64), 0, c.stream, nz, stride, dots, nq, cc);
     HIPCHECK(hipGetLastError());
 }
 

@@ -484,7 +484,8 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
     }
     Field rl = mixed ? ws_field(c, "fg_rl", rp) : r, xl = mixed ? ws_field(c, "fg_xl", rp) : x;
     // device pointer tables of the Krylov vectors, Gram-Schmidt coefficients
-    // (dots[2m]; info[3k] = {|q_k|^2, <q_k, r>} per step) and partial sums
+    // (dots[2m] per step; info[3k] = {|q_k|^2, <q_k, r>} per step; cc[3m], the
+    // combination coefficients of a BF16 cycle) and partial sums
     struct Dev {
         void *p = nullptr;
         ~Dev()
@@ -493,7 +494,7 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
         }
     } tab, coef, part;
     HIPCHECK(hipMalloc(&tab.p, 2 * m * sizeof(void *)));
-    HIPCHECK(hipMalloc(&coef.p, (2 * m + 3 * m) * sizeof(double)));
+    HIPCHECK(hipMalloc(&coef.p, (2 * m * m + 3 * m + 3 * m) * sizeof(double)));
     HIPCHECK(hipMalloc(&part.p, gs_partials_needed(c, m) * sizeof(double)));
     {
         std::vector<const void *> h(2 * m);
@@ -505,7 +506,7 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
     }
     void *const *qtab = (void *const *)tab.p;
     void *const *ztab = qtab + m;
-    double *dots = (double *)coef.p, *info = dots + 2 * m;
+    double *dots = (double *)coef.p, *info = dots + 2 * m * m, *cc = info + 3 * m;
     double *partial = (double *)part.p;
     HIPCHECK(hipStreamSynchronize(c.stream));
     const double t1w = wall();
@@ -523,7 +524,12 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
     int best_it = 0;
     while (!conv && !stalled && it < maxit) {
         int k = 0, ndir = 0;  // ndir: directions of this cycle applied to the residual
-        // with a BF16 basis the cycle's solution update is combined at the restart
+        // With a BF16 basis the cycle's solution update is combined at the
+        // restart, from the directions as the preconditioner made them: only
+        // their operator images are projected, and the projection coefficients
+        // of every step are kept to transform the combination (as flexible
+        // GMRES keeps its raw directions).  That halves the Gram-Schmidt
+        // traffic of the directions.
         const bool defer_x = lp == P_BF16;
         if (mixed) launch_convert(c, P_F64, r, rp, rl);
         for (; k < m && it < maxit; k++) {
@@ -533,9 +539,10 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
             fgcr_op(c, lp, Z[k], Q[k], normal);
             // classical Gram-Schmidt against the cycle's earlier directions in
             // one pass over the vectors; the residual stays orthogonal to them
-            if (k > 0) launch_gs_dots(c, lp, (const void *const *)qtab, k, Q[k], partial, dots);
-            launch_gs_project(c, lp, rp, (const void *const *)qtab, (const void *const *)ztab, k, dots, info, Q[k],
-                              Z[k], rl, partial, info + 3 * k);
+            double *dk = defer_x ? dots + 2 * m * k : dots;
+            if (k > 0) launch_gs_dots(c, lp, (const void *const *)qtab, k, Q[k], partial, dk);
+            launch_gs_project(c, lp, rp, (const void *const *)qtab, defer_x ? nullptr : (const void *const *)ztab, k,
+                              dk, info, Q[k], defer_x ? Field{} : Z[k], rl, partial, info + 3 * k);
             const int np = launch_gs_update(c, lp, rp, defer_x ? Field{} : xl, Z[k], rl, Q[k], info + 3 * k);
             ndir = k + 1;
             launch_finish(c, np, 1, 12);
@@ -549,7 +556,10 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
             if (rn <= tol * bn) break;
         }
         // restart: fold the low-precision solution in, true residual in FP64
-        if (defer_x && ndir > 0) launch_gs_combine(c, lp, xl, (const void *const *)ztab, ndir, info);
+        if (defer_x && ndir > 0) {
+            launch_gs_raw_coef(c, ndir, 2 * m, dots, info, cc);
+            launch_gs_combine(c, lp, xl, (const void *const *)ztab, ndir, cc);
+        }
         if (mixed) launch_accumulate_low(c, rp, x, xl);
         fgcr_op(c, P_F64, x, t1, normal);
         launch_axpby(c, P_F64, 1.0, rhs, -1.0, t1, r);
