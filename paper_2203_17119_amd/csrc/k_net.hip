@@ -177,11 +177,14 @@ __global__ void k_pack_mfma_weights(const __hip_bfloat162 *w, short *pk)
 }
 
 // One workgroup takes MF_S consecutive 5D sites (3 MF_S columns, column =
-// colour * MF_S + site).  Per path, every thread transports the input channels
-// of one site (two threads per site, half the channels each): one link load,
-// 3 x 3 complex products per channel on the vector units, BF16 rounding, into
-// LDS as B operand rows [channel pair][column].  The four wavefronts then run
-// the path's MFMA steps, three column tiles each.
+// colour * MF_S + site).  Per hop path, every thread transports the input
+// channels of one site (two threads per site, half the channels each): one
+// link load, 3 x 3 complex products per channel on the vector units, BF16
+// rounding, into LDS as B operand rows [channel pair][column].  The four
+// wavefronts then run the path's MFMA steps, three column tiles each.  The
+// identity and the two fifth-dimension paths read the same sites of the
+// output parity: they take one phase, from one load of the workgroup's sites
+// and one halo site on either side.
 static constexpr int MF_S = 128;
 
 // feature element k of a plane array in FP32 pairs or BF16 pairs
@@ -231,9 +234,12 @@ __global__ void __launch_bounds__(256)
                                                       long n, int pmask, int io)
 {
     static_assert(CIN % 4 == 0 && 2 * COUT <= 32, "channel counts");
-    constexpr int NCOL = 3 * MF_S, NP = CIN / 2, HP = NP / 2;
+    constexpr int NP = CIN / 2, HP = NP / 2;
+    // LDS column of (colour, site): the workgroup's sites with one halo site
+    // on either side (for the fifth-dimension paths), CS columns per colour
+    constexpr int CS = MF_S + 2, NCOLP = 3 * CS;
     constexpr int JMAX = MF_S / 8 + 2;  // 4D sites a workgroup spans when Ls >= 8
-    __shared__ bf16x4 Tb[NP * NCOL];
+    __shared__ bf16x4 Tb[NP * NCOLP];
     __shared__ cx<float> lks[JMAX * 72];
     __shared__ int nbl[JMAX * 8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, jc = lane & 31;
@@ -250,64 +256,45 @@ __global__ void __launch_bounds__(256)
     // instead of every lane loading them again for every path.
     const bool staged = g.Ls >= 8;
     const long j0 = i0 / g.Ls;
-    if (staged) {
-        const long ilast = (i0 + MF_S < n ? i0 + MF_S : n) - 1;
-        const int nj = (int)(ilast / g.Ls - j0) + 1;
-        const float2 *lsrc = (p ? g.lsm1 : g.lsm0) + j0 * 72;
-        for (int k = tid; k < nj * 72; k += 256) lks[k] = c2(lsrc[k]);
-        const int *nsrc = g.nbr_sm + ((long)p * g.vh + j0) * 8;
-        for (int k = tid; k < nj * 8; k += 256) nbl[k] = nsrc[k];
-        __syncthreads();
-    }
     const int jl = ok ? (int)(j - j0) : 0;  // local 4D site of this lane's transport role
     f32x16 acc[3];
 #pragma unroll
     for (int t = 0; t < 3; t++)
 #pragma unroll
         for (int r = 0; r < 16; r++) acc[t][r] = 0.f;
-    // Feature loads of a path are issued at the start of the previous path's
-    // matrix-core phase, so they are in flight through it and its barrier;
-    // only the accumulators and operands are live there, so this costs no
-    // registers at the peak (the transport phase).
+    // Feature loads of a hop path are issued at the start of the previous
+    // phase's matrix-core work, so they are in flight through it and its
+    // barrier; only the accumulators and operands are live there, so this
+    // costs no registers at the peak (the transport phase).
     using RawT = typename std::conditional<IBF, uint32_t, float2>::type;
-    RawT raw[HP][2][3];
-    auto fetch = [&](int pi) -> bool {
-        long src = 0;
-        int sp = p;
-        bool hv;
-        if (staged && pi >= 1 && pi <= 8) {
-            const int nb = nbl[jl * 8 + pi - 1];
-            src = (long)(nb < 0 ? 0 : nb) * g.Ls + s;
-            sp = 1 - p;
-            hv = ok && nb >= 0;
-        } else {
-            hv = ok && path_source(g, p, pi, j, s, src, sp);
-        }
+    // the thread's half `half` of the input channel pairs at 5D site src of
+    // parity sp; returns whether the site holds data
+    auto load = [&](long src, int sp, bool hv, int half, RawT (&rw)[HP][2][3]) -> bool {
         if constexpr (IBF) {
             const long base = (long)sp * NP * 3 * n + src;
 #pragma unroll
             for (int q = 0; q < HP; q++)
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    const long f = base + (long)((th * HP + q) * 3 + c) * n;
+                    const long f = base + (long)((half * HP + q) * 3 + c) * n;
                     if (hv) {
                         const uint2 w = ((const uint2 *)in)[f];
-                        raw[q][0][c] = w.x;
-                        raw[q][1][c] = w.y;
+                        rw[q][0][c] = w.x;
+                        rw[q][1][c] = w.y;
                     }
                 }
         } else if (CIN == 4 && (io & 1)) {
             // the odd half spinor, component ch * 3 + colour in 16-byte planes of
-            // two: this thread's channel pair (2 th, 2 th + 1) is components
-            // 6 th .. 6 th + 5, whole planes 3 th .. 3 th + 2
+            // two: channel pair (2 half, 2 half + 1) is components 6 half ..
+            // 6 half + 5, whole planes 3 half .. 3 half + 2
             hv = hv && sp == 1;
 #pragma unroll
             for (int k = 0; k < 3; k++) {
                 if (!hv) continue;
-                const float4 w = ((const float4 *)in)[(long)(3 * th + k) * n + src];
+                const float4 w = ((const float4 *)in)[(long)(3 * half + k) * n + src];
                 const int m0 = 2 * k, m1 = 2 * k + 1;  // local components (channel e = m / 3, colour m % 3)
-                raw[0][m0 / 3][m0 % 3] = make_float2(w.x, w.y);
-                raw[0][m1 / 3][m1 % 3] = make_float2(w.z, w.w);
+                rw[0][m0 / 3][m0 % 3] = make_float2(w.x, w.y);
+                rw[0][m1 / 3][m1 % 3] = make_float2(w.z, w.w);
             }
         } else {
             const long base = (long)sp * CIN * 3 * n + src;
@@ -317,41 +304,39 @@ __global__ void __launch_bounds__(256)
                 for (int e = 0; e < 2; e++)
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
-                        const long f = base + (long)((2 * (th * HP + q) + e) * 3 + c) * n;
-                        if (hv) raw[q][e][c] = ((const RawT *)in)[f];
+                        const long f = base + (long)((2 * (half * HP + q) + e) * 3 + c) * n;
+                        if (hv) rw[q][e][c] = ((const RawT *)in)[f];
                     }
         }
         return hv;
     };
-    // the paths in pmask, in order (uniform over the workgroup)
-    int plist[11], npath = 0;
-#pragma unroll
-    for (int q = 0; q < 11; q++)
-        if (pmask >> q & 1) plist[npath++] = q;
-    bool have = npath > 0 ? fetch(plist[0]) : false;
-    for (int qi = 0; qi < npath; qi++) {
-        const int pi = plist[qi];
-        const bool hop = pi >= 1 && pi <= 8;
-        cx<float> u[9];
-        if (have && hop) {
-            if (staged) {
-#pragma unroll
-                for (int k = 0; k < 9; k++) u[k] = lks[jl * 72 + (pi - 1) * 9 + k];
-            } else {
-                const float2 *L = (p ? g.links1 : g.links0) + (long)(pi - 1) * 9 * g.vh + j;
-#pragma unroll
-                for (int k = 0; k < 9; k++) u[k] = c2(L[(long)k * g.vh]);
-            }
+    RawT raw[HP][2][3];
+    auto fetch = [&](int pi) -> bool {  // hop path pi (1..8) of this thread's transport role
+        long src = 0;
+        int sp = p;
+        bool hv;
+        if (staged) {
+            const int nb = nbl[jl * 8 + pi - 1];
+            src = (long)(nb < 0 ? 0 : nb) * g.Ls + s;
+            sp = 1 - p;
+            hv = ok && nb >= 0;
+        } else {
+            hv = ok && path_source(g, p, pi, j, s, src, sp);
         }
+        return load(src, sp, hv, th, raw);
+    };
+    // transported (hop) or plain features of one site into LDS column col of
+    // every colour, channel pairs of half `half`, rounded to BF16
+    auto put = [&](const RawT (&rw)[HP][2][3], bool hv, bool hop, const cx<float> (&u)[9], int half, int col) {
 #pragma unroll
         for (int q = 0; q < HP; q++) {
-            const int pp = th * HP + q;
+            const int pp = half * HP + q;
             cx<float> t[2][3];
 #pragma unroll
             for (int e = 0; e < 2; e++) {
-                if (have) {
-                    const cx<float> v0 = raw_feat<IBF>(raw[q][e][0]), v1 = raw_feat<IBF>(raw[q][e][1]),
-                                    v2 = raw_feat<IBF>(raw[q][e][2]);
+                if (hv) {
+                    const cx<float> v0 = raw_feat<IBF>(rw[q][e][0]), v1 = raw_feat<IBF>(rw[q][e][1]),
+                                    v2 = raw_feat<IBF>(rw[q][e][2]);
                     if (hop) {
 #pragma unroll
                         for (int r = 0; r < 3; r++) {
@@ -376,22 +361,132 @@ __global__ void __launch_bounds__(256)
                 v[1] = bf16_bits(t[0][r].im);
                 v[2] = bf16_bits(t[1][r].re);
                 v[3] = bf16_bits(t[1][r].im);
-                Tb[pp * NCOL + r * MF_S + ts] = v;
+                Tb[pp * NCOLP + r * CS + col] = v;
             }
         }
-        __syncthreads();
-        const bool have_next = (qi + 1 < npath) ? fetch(plist[qi + 1]) : false;
+    };
+    // B operand column of each of this lane's three tiles: colour block of CS
+    // columns, the site one past the left halo
+    // and in zmask bit tt (bit 3 + tt) whether the site's s + 1 (s - 1) is past
+    // a wall
+    int bcol[3], zmask = 0;
+    const int r0 = (int)(i0 % g.Ls);  // s of the workgroup's first site
+#pragma unroll
+    for (int tt = 0; tt < 3; tt++) {
+        const int col = (wave * 3 + tt) * 32 + jc, cc = col / MF_S, site = col - cc * MF_S;
+        bcol[tt] = cc * CS + site + 1;
+        const int sl = (r0 + site) % g.Ls;
+        zmask |= (sl == g.Ls - 1 ? 1 : 0) << tt | (sl == 0 ? 8 : 0) << tt;
+    }
+    // shift 0: the column itself; +1 / -1: the fifth-dimension neighbour,
+    // zero where it is past a wall
+    auto mfma_path = [&](int pi, int shift) {
+        const int zm = shift > 0 ? zmask : shift < 0 ? zmask >> 3 : 0;
 #pragma unroll
         for (int st = 0; st < CIN / 4; st++) {
             const bf16x4 a = A[(pi * (CIN / 4) + st) * 64];
 #pragma unroll
             for (int tt = 0; tt < 3; tt++) {
-                const bf16x4 b = Tb[(2 * st + h) * NCOL + (wave * 3 + tt) * 32 + jc];
+                bf16x4 b = Tb[(2 * st + h) * NCOLP + bcol[tt] + shift];
+                if (zm >> tt & 1) b = bf16x4{0, 0, 0, 0};
                 acc[tt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[tt], 0, 0, 0);
             }
         }
+    };
+    // one element (channel pair pp, colour c) of a halo site of the output
+    // parity, as a BF16 B operand entry
+    auto halo = [&](long hs, int pp, int c) -> bf16x4 {
+        bf16x4 v = {0, 0, 0, 0};
+        if (hs < 0 || hs >= n) return v;
+        if constexpr (IBF) {
+            const uint2 w = ((const uint2 *)in)[(long)p * NP * 3 * n + (long)(pp * 3 + c) * n + hs];
+            __builtin_memcpy(&v, &w, sizeof(v));
+        } else {
+            float2 f0, f1;
+            if (CIN == 4 && (io & 1)) {
+                if (p != 1) return v;  // the spinor holds the odd sites only
+                const int m0 = 2 * pp * 3 + c, m1 = m0 + 3;  // components channel * 3 + colour
+                f0 = ((const float2 *)in)[(long)(m0 >> 1) * 2 * n + 2 * hs + (m0 & 1)];
+                f1 = ((const float2 *)in)[(long)(m1 >> 1) * 2 * n + 2 * hs + (m1 & 1)];
+            } else {
+                const long base = (long)p * CIN * 3 * n + hs;
+                f0 = ((const float2 *)in)[base + (long)(2 * pp * 3 + c) * n];
+                f1 = ((const float2 *)in)[base + (long)((2 * pp + 1) * 3 + c) * n];
+            }
+            v[0] = bf16_bits(f0.x);
+            v[1] = bf16_bits(f0.y);
+            v[2] = bf16_bits(f1.x);
+            v[3] = bf16_bits(f1.y);
+        }
+        return v;
+    };
+    // Paths that read the output's own parity (identity, s + 1, s - 1) share
+    // one load of the workgroup's sites plus one site on either side: their
+    // B operands are the same LDS columns, shifted by one site for the
+    // fifth-dimension paths.
+    const int own = pmask & ((1 << 0) | (1 << 9) | (1 << 10));
+    int hops = pmask & 0x1fe;  // hop paths still to run, in order (uniform over the workgroup)
+    auto next_hop = [&]() -> int {
+        if (!hops) return -1;
+        const int q = __builtin_ctz(hops);
+        hops &= hops - 1;
+        return q;
+    };
+    // Phases: the own-parity paths (OWN) if any, then the hop paths.  One loop
+    // with one matrix-core site keeps the accumulators in place.
+    constexpr int OWN = 16;
+    int cur = own ? OWN : next_hop();
+    int pi_first = own ? next_hop() : -1;  // the hop that follows the own phase
+    bool have = false;
+    // the own-parity load is issued first, so that it is in flight while the
+    // links are staged; launches without hop paths stage nothing
+    if (cur == OWN) have = load(it, p, ok, th, raw);
+    if (staged && (pmask & 0x1fe)) {
+        const long ilast = (i0 + MF_S < n ? i0 + MF_S : n) - 1;
+        const int nj = (int)(ilast / g.Ls - j0) + 1;
+        const float2 *lsrc = (p ? g.lsm1 : g.lsm0) + j0 * 72;
+        for (int k = tid; k < nj * 72; k += 256) lks[k] = c2(lsrc[k]);
+        const int *nsrc = g.nbr_sm + ((long)p * g.vh + j0) * 8;
+        for (int k = tid; k < nj * 8; k += 256) nbl[k] = nsrc[k];
+        __syncthreads();
+    }
+    if (cur > 0 && cur != OWN) have = fetch(cur);
+    const cx<float> unone[9] = {};
+    while (cur > 0) {
+        const bool ownph = cur == OWN;
+        if (ownph) {
+            const int hk = tid % (NP * 3), hside = tid / (NP * 3);
+            if (hside < 2)
+                Tb[(hk / 3) * NCOLP + (hk % 3) * CS + (hside ? MF_S + 1 : 0)] =
+                    halo(hside ? i0 + MF_S : i0 - 1, hk / 3, hk % 3);
+            put(raw, have, false, unone, th, ts + 1);
+        } else {
+            cx<float> u[9];
+            if (have) {
+                if (staged) {
+#pragma unroll
+                    for (int k = 0; k < 9; k++) u[k] = lks[jl * 72 + (cur - 1) * 9 + k];
+                } else {
+                    const float2 *L = (p ? g.links1 : g.links0) + (long)(cur - 1) * 9 * g.vh + j;
+#pragma unroll
+                    for (int k = 0; k < 9; k++) u[k] = c2(L[(long)k * g.vh]);
+                }
+            }
+            put(raw, have, true, u, th, ts + 1);
+        }
+        __syncthreads();
+        const int nxt = ownph ? pi_first : next_hop();
+        const bool have_next = nxt > 0 ? fetch(nxt) : false;
+        // the phase's paths, one at a time so that only one path's operands are live
+        const int npath = ownph ? 3 : 1;
+        for (int k = 0; k < npath; k++) {
+            const int pk = ownph ? (k == 0 ? 0 : 8 + k) : cur;  // own: identity, s + 1, s - 1
+            if (ownph && !(own >> pk & 1)) continue;
+            mfma_path(pk, !ownph || k == 0 ? 0 : k == 1 ? 1 : -1);
+        }
         __syncthreads();
         have = have_next;
+        cur = nxt;
     }
     // accumulator register r of tile tt holds row m' = 8 (r / 4) + 4 h + r % 4 of column
     // (tile * 32 + jc): colour col / MF_S, site col % MF_S
