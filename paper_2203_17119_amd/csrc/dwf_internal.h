@@ -332,7 +332,9 @@ void launch_gs_dots(Context &c, int prec, const void *const *X_dev, int nv, Fiel
 // an empty w (and no W_dev; BF16 basis only) y alone is projected.
 void launch_gs_project(Context &c, int prec, int rprec, const void *const *X_dev, const void *const *W_dev, int nv,
                        const double *dots, const double *nq, Field y, Field w, Field r, double *partial, double *out);
-int launch_gs_update(Context &c, int prec, int rprec, Field x, Field z, Field r, Field q, const double *coef);
+// rb (BF16 basis only): also write the updated r rounded to BF16
+int launch_gs_update(Context &c, int prec, int rprec, Field x, Field z, Field r, Field q, const double *coef,
+                     Field rb = {});
 // BF16 basis: x += sum_j a_j Z_j over nz directions (Z_dev: device array of
 // their pointers), a_j from coef[3j..3j+2] as in gs_update; x FP32.  With it
 // the per-step update may pass an empty x.

@@ -725,9 +725,11 @@ __global__ void __launch_bounds__(BS) k_gs_project_bf(const uint2 *const *X, con
 }
 
 // x += a z (skipped when x is null: the caller combines the cycle's directions
-// into x at the restart, k_gs_combine_bf), r -= a q, partials of |r|^2
+// into x at the restart, k_gs_combine_bf), r -= a q, partials of |r|^2; rb,
+// if not null, receives the new r rounded to BF16 (in the basis layout)
 __global__ void __launch_bounds__(BS) k_gs_update_bf(float4 *x, const uint2 *z, float4 *r, const uint2 *q,
-                                                     const double *coef, long m2, long nsite, double *partial)
+                                                     const double *coef, long m2, long nsite, double *partial,
+                                                     uint2 *rb)
 {
     const long base = (long)blockIdx.x * BS * GS_PPT + threadIdx.x;
     const double inv = 1.0 / coef[0];
@@ -754,6 +756,7 @@ __global__ void __launch_bounds__(BS) k_gs_update_bf(float4 *x, const uint2 *z, 
         rv.z = float(rv.z - (are * qv.z - aim * qv.w));
         rv.w = float(rv.w - (are * qv.w + aim * qv.z));
         r[kr] = rv;
+        if (rb) rb[k] = bf_pack(rv);
         n2 += double(rv.x) * rv.x + double(rv.y) * rv.y + double(rv.z) * rv.z + double(rv.w) * rv.w;
     }
     n2 = block_sum(n2);
@@ -1452,18 +1455,21 @@ void launch_gs_project(Context &c, int prec, int rprec, const void *const *X_dev
     HIPCHECK(hipGetLastError());
 }
 
-int launch_gs_update(Context &c, int prec, int rprec, Field x, Field z, Field r, Field q, const double *coef)
+int launch_gs_update(Context &c, int prec, int rprec, Field x, Field z, Field r, Field q, const double *coef,
+                     Field rb)
 {
     const long m = 12 * r.n, nblk = prec == P_BF16 ? gs_blocks_bf(m) : gs_blocks(m);
     gs_prec_check(prec, rprec, m);
     if (!x.data && prec != P_BF16) fail(DWF_EINVAL, "Gram-Schmidt update needs x");
     need_partials(c, nblk, 1);
+    if (rb.data && (prec != P_BF16 || rb.n != r.n)) fail(DWF_EINVAL, "BF16 residual copy needs a BF16 basis");
     const double xb = x.data ? gs_elem_bytes(prec) + 2.0 * gs_elem_bytes(rprec) : 0.0;
-    Timer tm(c, DWF_K_BLAS, (gs_elem_bytes(prec) + 2.0 * gs_elem_bytes(rprec) + xb) * m, 18.0 * m, prec);
+    const double rbb = rb.data ? gs_elem_bytes(P_BF16) : 0.0;
+    Timer tm(c, DWF_K_BLAS, (gs_elem_bytes(prec) + 2.0 * gs_elem_bytes(rprec) + xb + rbb) * m, 18.0 * m, prec);
     if (prec == P_BF16)
         hipLaunchKernelGGL(k_gs_update_bf, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (float4 *)x.data,
                            (const uint2 *)z.data, (float4 *)r.data, (const uint2 *)q.data, coef, m / 2, r.n,
-                           c.partials);
+                           c.partials, (uint2 *)rb.data);
     else if (prec == P_F64)
         hipLaunchKernelGGL(k_gs_update<double2>, dim3((unsigned)nblk), dim3(BS), 0, c.stream, (double2 *)x.data,
                            (const double2 *)z.data, (double2 *)r.data, (const double2 *)q.data, coef, m, c.partials);

@@ -222,18 +222,20 @@ __device__ __forceinline__ cx<float> raw_feat(typename std::conditional<BF, uint
 // load latency.  With the accumulators in VGPRs, four waves fit without spills
 // for CIN = 4 and three for wider inputs (whose prefetched features take more
 // registers).
-// io: bit 0 set: the input is an FP32 internal half spinor of the odd sites
-// (the four spin channels of the network's embedded input, zero on the even
-// sites) instead of FP32 features (FP32 input only); bits 1-2: the output is
+// io: bit 0 set: the input is an internal half spinor of the odd sites (the
+// four spin channels of the network's embedded input, zero on the even sites),
+// FP32 or (IBF) BF16, instead of features (first layer only); bits 1-2: the output is
 // written as an internal half spinor of the odd sites, 1 in FP32 and 2 in BF16
 // storage, instead of FP32 features (FP32 output of the last layer, p = 1 only).
 // The conversions between spinor and feature layouts then need no pass of their own.
-template <int CIN, int COUT, bool IBF, bool OBF>
+// BSP: the input is the BF16 odd half spinor (IBF, CIN = 4, io bit 0).
+template <int CIN, int COUT, bool IBF, bool OBF, bool BSP = false>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(CIN <= 4 ? 4 : 3, CIN <= 4 ? 4 : 3))) k_ptc_fwd_mfma(NetGeo g, const void *in, void *out, const short *wpk, int p,
                                                       long n, int pmask, int io)
 {
     static_assert(CIN % 4 == 0 && 2 * COUT <= 32, "channel counts");
+    static_assert(!BSP || (IBF && CIN == 4), "the BF16 spinor input has four channels");
     constexpr int NP = CIN / 2, HP = NP / 2;
     // LDS column of (colour, site): the workgroup's sites with one halo site
     // on either side (for the fifth-dimension paths), CS columns per colour
@@ -270,6 +272,30 @@ __global__ void __launch_bounds__(256)
     // the thread's half `half` of the input channel pairs at 5D site src of
     // parity sp; returns whether the site holds data
     auto load = [&](long src, int sp, bool hv, int half, RawT (&rw)[HP][2][3]) -> bool {
+        if constexpr (BSP) {
+            {
+                // the BF16 odd half spinor: component ch * 3 + colour is word
+                // (m & 3) of 16-byte plane m >> 2; channel pair (2 half,
+                // 2 half + 1) is components 6 half .. 6 half + 5: a whole plane
+                // and half of the middle one
+                hv = hv && sp == 1;
+                if (!hv) return false;
+                const uint32_t *w = (const uint32_t *)in;
+                uint32_t m[6];
+                if (half == 0) {
+                    const uint4 a = *(const uint4 *)(w + 4 * src);
+                    const uint2 b = *(const uint2 *)(w + 4 * n + 4 * src);
+                    m[0] = a.x, m[1] = a.y, m[2] = a.z, m[3] = a.w, m[4] = b.x, m[5] = b.y;
+                } else {
+                    const uint2 b = *(const uint2 *)(w + 4 * n + 4 * src + 2);
+                    const uint4 a = *(const uint4 *)(w + 8 * n + 4 * src);
+                    m[0] = b.x, m[1] = b.y, m[2] = a.x, m[3] = a.y, m[4] = a.z, m[5] = a.w;
+                }
+#pragma unroll
+                for (int k = 0; k < 6; k++) rw[0][k / 3][k % 3] = m[k];
+                return true;
+            }
+        }
         if constexpr (IBF) {
             const long base = (long)sp * NP * 3 * n + src;
 #pragma unroll
@@ -399,7 +425,16 @@ __global__ void __launch_bounds__(256)
         bf16x4 v = {0, 0, 0, 0};
         if (hs < 0 || hs >= n) return v;
         if constexpr (IBF) {
-            const uint2 w = ((const uint2 *)in)[(long)p * NP * 3 * n + (long)(pp * 3 + c) * n + hs];
+            uint2 w;
+            if constexpr (BSP) {
+                if (p != 1) return v;  // the spinor holds the odd sites only
+                const uint32_t *w32 = (const uint32_t *)in;
+                const int m0 = 2 * pp * 3 + c, m1 = m0 + 3;  // components channel * 3 + colour
+                w.x = w32[(long)(m0 >> 2) * 4 * n + 4 * hs + (m0 & 3)];
+                w.y = w32[(long)(m1 >> 2) * 4 * n + 4 * hs + (m1 & 3)];
+            } else {
+                w = ((const uint2 *)in)[(long)p * NP * 3 * n + (long)(pp * 3 + c) * n + hs];
+            }
             __builtin_memcpy(&v, &w, sizeof(v));
         } else {
             float2 f0, f1;
@@ -753,14 +788,17 @@ void launch_pack_mfma_weights(Context &c, int cin, int cout, const void *w_bf16,
 void launch_ptc_layer_mfma(Context &c, int cin, int cout, const void *in, void *out, const short *pk, int p,
                            bool in_bf16, bool out_bf16, int pmask, int io)
 {
-    if (((io & 1) && (in_bf16 || cin != 4)) || ((io >> 1) && (out_bf16 || cout != 4 || p != 1)) || io > 5)
-        fail(DWF_EINVAL, "spinor input or output needs an FP32 four-channel side of the odd sites");
+    if (((io & 1) && cin != 4) || ((io >> 1) && (out_bf16 || cout != 4 || p != 1)) || io > 5)
+        fail(DWF_EINVAL, "spinor input (FP32 or BF16) or output (FP32) needs a four-channel side of the odd sites");
     const NetGeo g = net_geo(c);
     const dim3 grid((unsigned)((c.n5h + MF_S - 1) / MF_S)), blk(256);
     const double flops = (double)c.n5h * (11.0 * cout * cin * 3 * 8 + 8.0 * cin * 66);
     Timer tm(c, DWF_K_NET, (double)c.n5h * 3 * (11.0 * cin * (in_bf16 ? 4 : 8) + cout * (out_bf16 ? 4 : 8)), flops);
 #define NETK(CI, CO, IB, OB) \
     hipLaunchKernelGGL((k_ptc_fwd_mfma<CI, CO, IB, OB>), grid, blk, 0, c.stream, g, in, out, pk, p, c.n5h, pmask, io)
+#define NETS(CO)                                                                                               \
+    hipLaunchKernelGGL((k_ptc_fwd_mfma<4, CO, true, true, true>), grid, blk, 0, c.stream, g, in, out, pk, p, \
+                       c.n5h, pmask, io)
 #define NETL(CI, CO)                        \
     do {                                    \
         if (in_bf16 && out_bf16)            \
@@ -772,6 +810,16 @@ void launch_ptc_layer_mfma(Context &c, int cin, int cout, const void *in, void *
         else                                \
             NETK(CI, CO, false, false);     \
     } while (0)
+    if ((io & 1) && in_bf16) {
+        // the BF16 spinor input feeds a first layer with BF16 activations out
+        if (!out_bf16) fail(DWF_EINVAL, "a BF16 spinor input needs BF16 activations out");
+        if (cout == 4) NETS(4);
+        else if (cout == 8) NETS(8);
+        else if (cout == 12) NETS(12);
+        else fail(DWF_ENOTSUP, "layer channel counts must be 4, 8 or 12");
+        HIPCHECK(hipGetLastError());
+        return;
+    }
     if (cin == 4 && cout == 12) NETL(4, 12);
     else if (cin == 12 && cout == 12) NETL(12, 12);
     else if (cin == 12 && cout == 4) NETL(12, 4);
@@ -783,6 +831,7 @@ void launch_ptc_layer_mfma(Context &c, int cin, int cout, const void *in, void *
     else if (cin == 8 && cout == 12) NETL(8, 12);
     else fail(DWF_ENOTSUP, "layer channel counts must be 4, 8 or 12");
 #undef NETL
+#undef NETS
 #undef NETK
     HIPCHECK(hipGetLastError());
 }

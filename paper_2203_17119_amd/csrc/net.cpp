@@ -103,11 +103,11 @@ static void refresh_bf16(dwf_net_s *n)
 static constexpr int kHopPaths = 0x1fe, kLocalPaths = 0x601;
 
 // With the matrix-core forward the first layer may read the odd half spinor
-// in_sp (FP32) instead of acts[0], and the last layer (odd sites only) may
-// write the odd half spinor out_sp (FP32 or BF16, out_prec) instead of
-// acts[nlayer]: the layout conversions then cost no pass of their own.
+// in_sp (FP32 or BF16, in_prec) instead of acts[0], and the last layer (odd
+// sites only) may write the odd half spinor out_sp (FP32 or BF16, out_prec)
+// instead of acts[nlayer]: the layout conversions then cost no pass of their own.
 static void net_forward(dwf_net_s *n, bool all_parities, bool mfma = false, Field in_sp = {}, Field out_sp = {},
-                        int out_prec = P_F32)
+                        int out_prec = P_F32, int in_prec = P_F32)
 {
     Context &c = *n->c;
     for (int l = 0; l < n->nlayer; l++) {
@@ -115,9 +115,9 @@ static void net_forward(dwf_net_s *n, bool all_parities, bool mfma = false, Fiel
         for (int p = (last && !all_parities) ? 1 : 0; p < 2; p++) {
             const int pmask = l > 0 ? kAllPaths : (p == 1 ? kLocalPaths : kHopPaths);
             if (mfma) {
-                // FP32 network input and output, BF16 activations in between
-                const bool ibf = l > 0, obf = !last;
+                // FP32 (or BF16 spinor) network input, FP32 output, BF16 activations in between
                 const bool isp = l == 0 && in_sp.data, osp = last && out_sp.data && !all_parities;
+                const bool ibf = l > 0 || (isp && in_prec == P_BF16), obf = !last;
                 const int io = (isp ? 1 : 0) | (osp ? (out_prec == P_BF16 ? 4 : 2) : 0);
                 const void *src = isp ? in_sp.data : ibf ? n->acts_bf[l] : (const void *)n->acts[l];
                 void *dst = osp ? out_sp.data : obf ? n->acts_bf[l + 1] : (void *)n->acts[l + 1];
@@ -374,9 +374,9 @@ static void precondition(dwf_net_s *n, int rprec, Field r, int zprec, Field z, b
 {
     Context &c = *n->c;
     const bool mfma = n->fwd == DWF_NET_FWD_MFMA_BF16;
-    if (!normal && mfma && rprec == P_F32 && (zprec == P_F32 || zprec == P_BF16)) {
+    if (!normal && mfma && (rprec == P_F32 || rprec == P_BF16) && (zprec == P_F32 || zprec == P_BF16)) {
         // the first layer reads r and the last writes z in their spinor layouts
-        net_forward(n, false, true, r, z, zprec);
+        net_forward(n, false, true, r, z, zprec, rprec);
         return;
     }
     // the forward alone reads only the odd sites of its input (the first
@@ -483,6 +483,12 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
         Q.push_back(ws_field(c, "fg_q" + std::to_string(k), lp));
     }
     Field rl = mixed ? ws_field(c, "fg_rl", rp) : r, xl = mixed ? ws_field(c, "fg_xl", rp) : x;
+    // With a BF16 basis and the matrix-core forward the network reads a BF16
+    // copy of the cycle's residual, written by the update kernel beside the
+    // FP32 one: its first layer rounds its operands to BF16 anyway, and the
+    // gathers of its first layer then move half the bytes.
+    const bool rb_in = lp == P_BF16 && net && net->fwd == DWF_NET_FWD_MFMA_BF16 && !normal;
+    Field rb = rb_in ? ws_field(c, "fg_rb", P_BF16) : Field{};
     // device pointer tables of the Krylov vectors, Gram-Schmidt coefficients
     // (dots[2m] per step; info[3k] = {|q_k|^2, <q_k, r>} per step; cc[3m], the
     // combination coefficients of a BF16 cycle) and partial sums
@@ -532,8 +538,10 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
         // traffic of the directions.
         const bool defer_x = lp == P_BF16;
         if (mixed) launch_convert(c, P_F64, r, rp, rl);
+        if (rb_in) launch_convert(c, P_F64, r, P_BF16, rb);
         for (; k < m && it < maxit; k++) {
-            if (net) precondition(net, rp, rl, lp, Z[k], normal);
+            if (rb_in) precondition(net, P_BF16, rb, lp, Z[k], normal);
+            else if (net) precondition(net, rp, rl, lp, Z[k], normal);
             else if (rp == lp) launch_copy(c, lp, rl, Z[k]);
             else launch_convert(c, rp, rl, lp, Z[k]);
             fgcr_op(c, lp, Z[k], Q[k], normal);
@@ -543,7 +551,7 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
             if (k > 0) launch_gs_dots(c, lp, (const void *const *)qtab, k, Q[k], partial, dk);
             launch_gs_project(c, lp, rp, (const void *const *)qtab, defer_x ? nullptr : (const void *const *)ztab, k,
                               dk, info, Q[k], defer_x ? Field{} : Z[k], rl, partial, info + 3 * k);
-            const int np = launch_gs_update(c, lp, rp, defer_x ? Field{} : xl, Z[k], rl, Q[k], info + 3 * k);
+            const int np = launch_gs_update(c, lp, rp, defer_x ? Field{} : xl, Z[k], rl, Q[k], info + 3 * k, rb);
             ndir = k + 1;
             launch_finish(c, np, 1, 12);
             read_scalars(c, 12, 1);

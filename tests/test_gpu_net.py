@@ -116,7 +116,9 @@ def test_precond_apply_internal_spinor_layouts(Ls):
     layer reads the input spinor and the last writes the output spinor directly.
     The FP32 result is bit-identical to the canonical entry point (which goes
     through the feature layout), the BF16 one is its BF16 rounding, and the
-    FP64 internal path (through the feature layout) matches too."""
+    FP64 internal path (through the feature layout) matches too.  A BF16 input
+    spinor (read by the first layer as FGCR with a BF16 basis passes its
+    residual) gives the canonical result of the same BF16-rounded input."""
     c = Case((4, 4, 2, 4), Ls, mf=0.05, dirichlet=(1, 0, 0, 1), eps=0.6, seed=57)
     Ws = random_weights(CHANS, 6)
     net = dwf.dwf_net_create(c.ctx, CHANS)
@@ -140,6 +142,21 @@ def test_precond_apply_internal_spinor_layouts(Ls):
             else:
                 want = ref_h
             print(f"Ls={Ls} in {pin} out {pout}: max |diff| {np.abs(got - want).max():.2e}", flush=True)
+            assert np.array_equal(got, want)
+        xh = to_host(x)
+        xb = to_gpu((bf16_round(xh.real) + 1j * bf16_round(xh.imag)).astype(xh.dtype))
+        refb = T.empty_like(xb)
+        dwf.dwf_precond_apply(c.ctx, net, xb, refb)
+        refb_h = to_host(refb)
+        for pout in (dwf.DWF_F32, dwf.DWF_BF16):
+            xi, yi = c.lat.internal(dwf.DWF_BF16), c.lat.internal(pout)
+            dwf.dwf_import(c.ctx, 0, dwf.DWF_BF16, xb, xi)
+            dwf.dwf_precond_apply_internal(c.ctx, net, dwf.DWF_BF16, xi, pout, yi)
+            y = T.empty_like(xb)
+            dwf.dwf_export(c.ctx, 0, pout, yi, y)
+            got = to_host(y)
+            want = refb_h if pout == dwf.DWF_F32 else bf16_round(refb_h.real) + 1j * bf16_round(refb_h.imag)
+            print(f"Ls={Ls} in {dwf.DWF_BF16} out {pout}: max |diff| {np.abs(got - want).max():.2e}", flush=True)
             assert np.array_equal(got, want)
     finally:
         dwf.dwf_net_destroy(net)
