@@ -374,7 +374,10 @@ static void precondition(dwf_net_s *n, int rprec, Field r, int zprec, Field z, b
 {
     Context &c = *n->c;
     const bool mfma = n->fwd == DWF_NET_FWD_MFMA_BF16;
-    if (!normal && mfma && (rprec == P_F32 || rprec == P_BF16) && (zprec == P_F32 || zprec == P_BF16)) {
+    // (a BF16 input spinor feeds a first layer that writes BF16 activations:
+    // a network of one layer takes the feature path)
+    const bool rsp = rprec == P_F32 || (rprec == P_BF16 && n->nlayer >= 2);
+    if (!normal && mfma && rsp && (zprec == P_F32 || zprec == P_BF16)) {
         // the first layer reads r and the last writes z in their spinor layouts
         net_forward(n, false, true, r, z, zprec, rprec);
         return;
@@ -487,7 +490,7 @@ extern "C" dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, d
     // copy of the cycle's residual, written by the update kernel beside the
     // FP32 one: its first layer rounds its operands to BF16 anyway, and the
     // gathers of its first layer then move half the bytes.
-    const bool rb_in = lp == P_BF16 && net && net->fwd == DWF_NET_FWD_MFMA_BF16 && !normal;
+    const bool rb_in = lp == P_BF16 && net && net->fwd == DWF_NET_FWD_MFMA_BF16 && !normal && net->nlayer >= 2;
     Field rb = rb_in ? ws_field(c, "fg_rb", P_BF16) : Field{};
     // device pointer tables of the Krylov vectors, Gram-Schmidt coefficients
     // (dots[2m] per step; info[3k] = {|q_k|^2, <q_k, r>} per step; cc[3m], the

@@ -163,6 +163,32 @@ def test_precond_apply_internal_spinor_layouts(Ls):
         c.close()
 
 
+def test_precond_apply_internal_bf16_input_one_layer():
+    """A one-layer network has no BF16 activations for a BF16 input spinor to
+    feed: the internal entry point then takes the feature path, with the same
+    result as the canonical entry point on the BF16-rounded input."""
+    c = Case((4, 4, 2, 4), 8, mf=0.05, dirichlet=(0, 0, 0, 1), eps=0.6, seed=58)
+    chans = [4, 4]
+    net = dwf.dwf_net_create(c.ctx, chans)
+    T = torch()
+    try:
+        dwf.dwf_net_set_weights(net, flat(random_weights(chans, 7)))
+        dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_MFMA_BF16)
+        xh = c.half(68)
+        xb = to_gpu((bf16_round(xh.real) + 1j * bf16_round(xh.imag)).astype(xh.dtype))
+        ref = T.empty_like(xb)
+        dwf.dwf_precond_apply(c.ctx, net, xb, ref)
+        xi, yi = c.lat.internal(dwf.DWF_BF16), c.lat.internal(dwf.DWF_F32)
+        dwf.dwf_import(c.ctx, 0, dwf.DWF_BF16, xb, xi)
+        dwf.dwf_precond_apply_internal(c.ctx, net, dwf.DWF_BF16, xi, dwf.DWF_F32, yi)
+        y = T.empty_like(xb)
+        dwf.dwf_export(c.ctx, 0, dwf.DWF_F32, yi, y)
+        assert np.array_equal(to_host(y), to_host(ref))
+    finally:
+        dwf.dwf_net_destroy(net)
+        c.close()
+
+
 def test_precond_apply_mfma_ragged_tile():
     """A lattice whose 3 x (5D sites) columns do not fill the last 128-column tile."""
     c = Case((4, 2, 2, 2), 3, mf=0.1, dirichlet=(0, 1, 0, 0), eps=0.5, seed=52)
