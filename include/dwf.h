@@ -392,9 +392,10 @@ dwf_status dwf_precond_apply(dwf_ctx ctx, dwf_net net, const double *in_odd, dou
 /* The same on internal odd half fields (layout of dwf_import) in storage
  * precisions in_prec and out_prec (DWF_F64/F32/F16/BF16; in and out distinct
  * device buffers), as FGCR applies it.  With the matrix-core forward, an FP32
- * input and an FP32 or BF16 output, the first layer reads the input spinor and
- * the last writes the output spinor directly (no layout passes); the result
- * is the same as through the feature layout. */
+ * input (or a BF16 one, for networks of two layers or more) and an FP32 or
+ * BF16 output, the first layer reads the input spinor and the last writes the
+ * output spinor directly (no layout passes); the result is the same as
+ * through the feature layout. */
 dwf_status dwf_precond_apply_internal(dwf_ctx ctx, dwf_net net, int in_prec, const void *in, int out_prec,
                                       void *out);
 /* Gradients of a real loss L through y = precond(in), given grad_out =
@@ -418,13 +419,16 @@ dwf_status dwf_net_train_step(dwf_net net, int nbatch, const double *const *b_od
  * in FP64 at every restart; DWF_SOLVE_MIXED_BF16 does the same with the
  * Krylov basis (network outputs and their operator images) stored in BF16
  * and the operator applied in BF16 storage, the cycle's residual and solution
- * staying FP32 (other modes: DWF_ENOTSUP).  Restart every
- * o->restart steps (default 16, at most 64) with the residual recomputed.
- * Stagnation means no 10% reduction of the true residual norm (the FP64 one
- * recomputed at the restarts) over max(8 m, 256) steps.  On stagnation or a non-finite residual it falls back to dwf_cg in
- * FP64 when o->fallback (the
- * statistics then say fell_back = 1).  Same source preparation and
- * reconstruction as dwf_cg; canonical FP64 full fields. */
+ * staying FP32 (other modes: DWF_ENOTSUP); in that mode only the images are
+ * orthogonalised, and the cycle's solution update is combined at the restart
+ * from the directions as the network made them, and the matrix-core network
+ * reads a BF16 copy of the residual.  Restart every o->restart steps (default
+ * 16, at most 64) with the residual recomputed.  Stagnation means no 10%
+ * reduction of the true residual norm (the FP64 one recomputed at the
+ * restarts) over max(8 m, 256) steps.  On stagnation or a non-finite residual
+ * it falls back to dwf_cg in FP64 when o->fallback (the statistics then say
+ * fell_back = 1).  Same source preparation and reconstruction as dwf_cg;
+ * canonical FP64 full fields. */
 dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, double *x_full, const dwf_solver_opts *o,
                     dwf_solver_stats *st);
 
