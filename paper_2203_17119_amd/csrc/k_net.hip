@@ -176,15 +176,15 @@ __global__ void k_pack_mfma_weights(const __hip_bfloat162 *w, short *pk)
     pk[t] = bf16_bits(v);
 }
 
-// One workgroup takes MF_S consecutive 5D sites (3 MF_S columns, column =
-// colour * MF_S + site).  Per hop path, every thread transports the input
-// channels of one site (two threads per site, half the channels each): one
-// link load, 3 x 3 complex products per channel on the vector units, BF16
-// rounding, into LDS as B operand rows [channel pair][column].  The four
-// wavefronts then run the path's MFMA steps, three column tiles each.  The
-// identity and the two fifth-dimension paths read the same sites of the
-// output parity: they take one phase, from one load of the workgroup's sites
-// and one halo site on either side.
+// One workgroup takes MF_S consecutive 5D sites, 32 per wavefront.  Per hop
+// path, every lane transports the input channels of one of its wavefront's
+// sites (two lanes per site, half the channels each): one link load, 3 x 3
+// complex products per channel on the vector units, BF16 rounding, into the
+// wavefront's LDS rows as B operand [channel pair][colour][site].  The
+// wavefront then runs the path's MFMA steps on its three tiles (one per
+// colour, 32 sites each).  The identity and the two fifth-dimension paths
+// read the same sites of the output parity: they take one phase, from one
+// load of the wavefront's sites and one halo site on either side.
 static constexpr int MF_S = 128;
 
 // feature element k of a plane array in FP32 pairs or BF16 pairs
@@ -237,17 +237,22 @@ __global__ void __launch_bounds__(256)
     static_assert(CIN % 4 == 0 && 2 * COUT <= 32, "channel counts");
     static_assert(!BSP || (IBF && CIN == 4), "the BF16 spinor input has four channels");
     constexpr int NP = CIN / 2, HP = NP / 2;
-    // LDS column of (colour, site): the workgroup's sites with one halo site
-    // on either side (for the fifth-dimension paths), CS columns per colour
-    constexpr int CS = MF_S + 2, NCOLP = 3 * CS;
+    // Each wavefront owns 32 of the workgroup's sites: its lanes transport
+    // them (lane: site jc, half h of the channel pairs) and its matrix-core
+    // tiles are their three colours, so the B operands a wavefront reads are
+    // the ones it wrote, and the phases need no workgroup barrier.  LDS rows
+    // [channel pair][colour] of CSW columns per wavefront: its 32 sites with
+    // one halo site on either side (for the fifth-dimension paths).
+    constexpr int CSW = 32 + 2, WREG = NP * 3 * CSW;
     constexpr int JMAX = MF_S / 8 + 2;  // 4D sites a workgroup spans when Ls >= 8
-    __shared__ bf16x4 Tb[NP * NCOLP];
+    __shared__ bf16x4 Tb[4 * WREG];
     __shared__ cx<float> lks[JMAX * 72];
     __shared__ int nbl[JMAX * 8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, jc = lane & 31;
     const long i0 = (long)blockIdx.x * MF_S;
+    bf16x4 *Tw = Tb + wave * WREG;
     // transport role: site ts, channel pairs [th HP, th HP + HP)
-    const int ts = tid % MF_S, th = tid / MF_S;
+    const int ts = 32 * wave + jc, th = h;
     const long it = i0 + ts;
     const bool ok = it < n;
     const long j = ok ? it / g.Ls : 0;
@@ -265,9 +270,9 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int r = 0; r < 16; r++) acc[t][r] = 0.f;
     // Feature loads of a hop path are issued at the start of the previous
-    // phase's matrix-core work, so they are in flight through it and its
-    // barrier; only the accumulators and operands are live there, so this
-    // costs no registers at the peak (the transport phase).
+    // phase's matrix-core work, so they are in flight through it; only the
+    // accumulators and operands are live there, so this costs no registers at
+    // the peak (the transport phase).
     using RawT = typename std::conditional<IBF, uint32_t, float2>::type;
     // the thread's half `half` of the input channel pairs at 5D site src of
     // parity sp; returns whether the site holds data
@@ -387,37 +392,36 @@ __global__ void __launch_bounds__(256)
                 v[1] = bf16_bits(t[0][r].im);
                 v[2] = bf16_bits(t[1][r].re);
                 v[3] = bf16_bits(t[1][r].im);
-                Tb[pp * NCOLP + r * CS + col] = v;
+                Tw[(pp * 3 + r) * CSW + col] = v;
             }
         }
     };
-    // B operand column of each of this lane's three tiles: colour block of CS
-    // columns, the site one past the left halo
-    // and in zmask bit tt (bit 3 + tt) whether the site's s + 1 (s - 1) is past
-    // a wall
-    int bcol[3], zmask = 0;
-    const int r0 = (int)(i0 % g.Ls);  // s of the workgroup's first site
-#pragma unroll
-    for (int tt = 0; tt < 3; tt++) {
-        const int col = (wave * 3 + tt) * 32 + jc, cc = col / MF_S, site = col - cc * MF_S;
-        bcol[tt] = cc * CS + site + 1;
-        const int sl = (r0 + site) % g.Ls;
-        zmask |= (sl == g.Ls - 1 ? 1 : 0) << tt | (sl == 0 ? 8 : 0) << tt;
-    }
+    // tile tt of this lane is colour tt of site ts (column jc); zup / zdn:
+    // the site's s + 1 / s - 1 is past a wall
+    const int sl = (int)((i0 + ts) % g.Ls);
+    const bool zup = sl == g.Ls - 1, zdn = sl == 0;
     // shift 0: the column itself; +1 / -1: the fifth-dimension neighbour,
     // zero where it is past a wall
     auto mfma_path = [&](int pi, int shift) {
-        const int zm = shift > 0 ? zmask : shift < 0 ? zmask >> 3 : 0;
+        const bool zero = shift > 0 ? zup : shift < 0 ? zdn : false;
 #pragma unroll
         for (int st = 0; st < CIN / 4; st++) {
             const bf16x4 a = A[(pi * (CIN / 4) + st) * 64];
 #pragma unroll
             for (int tt = 0; tt < 3; tt++) {
-                bf16x4 b = Tb[(2 * st + h) * NCOLP + bcol[tt] + shift];
-                if (zm >> tt & 1) b = bf16x4{0, 0, 0, 0};
+                bf16x4 b = Tw[((2 * st + h) * 3 + tt) * CSW + jc + 1 + shift];
+                if (zero) b = bf16x4{0, 0, 0, 0};
                 acc[tt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[tt], 0, 0, 0);
             }
         }
+    };
+    // the wavefront's LDS writes are complete and ordered against its later
+    // reads (LDS serves a wavefront's accesses in order; this keeps the
+    // compiler from moving them across)
+    auto wave_sync = [&]() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
     // one element (channel pair pp, colour c) of a halo site of the output
     // parity, as a BF16 B operand entry
@@ -490,11 +494,12 @@ __global__ void __launch_bounds__(256)
     while (cur > 0) {
         const bool ownph = cur == OWN;
         if (ownph) {
-            const int hk = tid % (NP * 3), hside = tid / (NP * 3);
+            // the two halo sites of this wavefront's 32: lane = (side, pair, colour)
+            const int hk = lane % (NP * 3), hside = lane / (NP * 3);
             if (hside < 2)
-                Tb[(hk / 3) * NCOLP + (hk % 3) * CS + (hside ? MF_S + 1 : 0)] =
-                    halo(hside ? i0 + MF_S : i0 - 1, hk / 3, hk % 3);
-            put(raw, have, false, unone, th, ts + 1);
+                Tw[hk * CSW + (hside ? CSW - 1 : 0)] =
+                    halo(hside ? i0 + 32 * wave + 32 : i0 + 32 * wave - 1, hk / 3, hk % 3);
+            put(raw, have, false, unone, th, jc + 1);
         } else {
             cx<float> u[9];
             if (have) {
@@ -507,9 +512,9 @@ __global__ void __launch_bounds__(256)
                     for (int k = 0; k < 9; k++) u[k] = c2(L[(long)k * g.vh]);
                 }
             }
-            put(raw, have, true, u, th, ts + 1);
+            put(raw, have, true, u, th, jc + 1);
         }
-        __syncthreads();
+        wave_sync();
         const int nxt = ownph ? pi_first : next_hop();
         const bool have_next = nxt > 0 ? fetch(nxt) : false;
         // the phase's paths, one at a time so that only one path's operands are live
@@ -519,17 +524,16 @@ __global__ void __launch_bounds__(256)
             if (ownph && !(own >> pk & 1)) continue;
             mfma_path(pk, !ownph || k == 0 ? 0 : k == 1 ? 1 : -1);
         }
-        __syncthreads();
+        wave_sync();
         have = have_next;
         cur = nxt;
     }
-    // accumulator register r of tile tt holds row m' = 8 (r / 4) + 4 h + r % 4 of column
-    // (tile * 32 + jc): colour col / MF_S, site col % MF_S
+    // accumulator register r of tile tt holds row m' = 8 (r / 4) + 4 h + r % 4 of
+    // column jc: colour tt of site ts
 #pragma unroll
     for (int tt = 0; tt < 3; tt++) {
-        const int col = (wave * 3 + tt) * 32 + jc;
-        const int cc = col / MF_S;
-        const long i = i0 + (col - cc * MF_S);
+        const int cc = tt;
+        const long i = it;
         if (i >= n) continue;
 #pragma unroll
         for (int q = 0; q < 4; q++) {
