@@ -149,6 +149,15 @@ __global__ void __launch_bounds__(256) k_ptc_fwd(NetGeo g, const float2 *in, flo
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// A 4 -> 4 layer has 8 real rows: in a 32 x 32 tile 24 of the 32 rows, and 12
+// of the 16 accumulators per lane, would hold nothing.  It runs as 16 x 16 x 16
+// tiles instead (half the accumulator registers, so five wavefronts fit per
+// SIMD instead of four with BF16 inputs), the K range of one path (8) in the
+// lower half of the tile's 16 and zeros in the upper.
+template <int CIN, int COUT>
+constexpr bool kMfma16 = CIN == 4 && COUT == 4;
 
 __device__ __forceinline__ short bf16_bits(float f)
 {
@@ -157,18 +166,21 @@ __device__ __forceinline__ short bf16_bits(float f)
 }
 
 // A operand of a CIN -> COUT layer: pk[(step * 64 + lane) * 4 + e] = A[m'][k'],
-// m' = lane % 32, k' = 8 step + 4 (lane / 32) + e
+// m' = lane % 32, k' = 8 step + 4 (lane / 32) + e; for the 16 x 16 x 16 tiles
+// m' = lane % 16, k' = 8 step + 4 (lane / 16) + e, zero for lane / 16 >= 2
 template <int CIN, int COUT>
 __global__ void k_pack_mfma_weights(const __hip_bfloat162 *w, short *pk)
 {
     constexpr int NSTEP = 11 * CIN / 4;
+    constexpr bool M16 = kMfma16<CIN, COUT>;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= NSTEP * 64 * 4) return;
     const int e = t & 3, lane = (t >> 2) & 63, step = t >> 8;
-    const int mr = lane & 31, kr = 8 * step + 4 * (lane >> 5) + e;
+    const int mr = M16 ? lane & 15 : lane & 31;
+    const int kr = 8 * step + 4 * (M16 ? lane >> 4 : lane >> 5) + e;
     const int a = mr >> 1, rho = mr & 1, q = kr >> 1, sig = kr & 1;
     float v = 0.f;
-    if (a < COUT) {
+    if (a < COUT && (!M16 || (lane >> 4) < 2)) {
         const int pi = q / CIN, b = q % CIN;
         const float2 wf = __bfloat1622float2(w[(pi * COUT + a) * CIN + b]);
         v = (rho == 0) ? (sig == 0 ? wf.x : -wf.y) : (sig == 0 ? wf.y : wf.x);
@@ -221,7 +233,7 @@ __device__ __forceinline__ cx<float> raw_feat(typename std::conditional<BF, uint
 // top of the VGPRs and two waves per SIMD fit, too few to cover the per-path
 // load latency.  With the accumulators in VGPRs, four waves fit without spills
 // for CIN = 4 and three for wider inputs (whose prefetched features take more
-// registers).
+// registers); five for the 4 -> 4 layer on its 16 x 16 tiles with BF16 input.
 // io: bit 0 set: the input is an internal half spinor of the odd sites (the
 // four spin channels of the network's embedded input, zero on the even sites),
 // FP32 or (IBF) BF16, instead of features (first layer only); bits 1-2: the output is
@@ -231,7 +243,8 @@ __device__ __forceinline__ cx<float> raw_feat(typename std::conditional<BF, uint
 // BSP: the input is the BF16 odd half spinor (IBF, CIN = 4, io bit 0).
 template <int CIN, int COUT, bool IBF, bool OBF, bool BSP = false>
 __global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(CIN <= 4 ? 4 : 3, CIN <= 4 ? 4 : 3))) k_ptc_fwd_mfma(NetGeo g, const void *in, void *out, const short *wpk, int p,
+    __attribute__((amdgpu_waves_per_eu(kMfma16<CIN, COUT> && IBF ? 5 : CIN <= 4 ? 4 : 3,
+                                       kMfma16<CIN, COUT> && IBF ? 5 : CIN <= 4 ? 4 : 3))) k_ptc_fwd_mfma(NetGeo g, const void *in, void *out, const short *wpk, int p,
                                                       long n, int pmask, int io)
 {
     static_assert(CIN % 4 == 0 && 2 * COUT <= 32, "channel counts");
@@ -264,11 +277,16 @@ __global__ void __launch_bounds__(256)
     const bool staged = g.Ls >= 8;
     const long j0 = i0 / g.Ls;
     const int jl = ok ? (int)(j - j0) : 0;  // local 4D site of this lane's transport role
-    f32x16 acc[3];
+    // accumulators: three 32 x 32 tiles (one per colour), or six 16 x 16 tiles
+    // (colour, half of the wavefront's sites)
+    constexpr bool M16 = kMfma16<CIN, COUT>;
+    constexpr int NT = M16 ? 6 : 3, NR = M16 ? 4 : 16;
+    using AccT = typename std::conditional<M16, f32x4, f32x16>::type;
+    AccT acc[NT];
 #pragma unroll
-    for (int t = 0; t < 3; t++)
+    for (int t = 0; t < NT; t++)
 #pragma unroll
-        for (int r = 0; r < 16; r++) acc[t][r] = 0.f;
+        for (int r = 0; r < NR; r++) acc[t][r] = 0.f;
     // Feature loads of a hop path are issued at the start of the previous
     // phase's matrix-core work, so they are in flight through it; only the
     // accumulators and operands are live there, so this costs no registers at
@@ -402,16 +420,41 @@ __global__ void __launch_bounds__(256)
     const bool zup = sl == g.Ls - 1, zdn = sl == 0;
     // shift 0: the column itself; +1 / -1: the fifth-dimension neighbour,
     // zero where it is past a wall
+    // 16 x 16 tiles: lane column n16 (site 16 hf + n16 of the wavefront), K
+    // group g16 (pair g16 of the path for g16 < 2, zeros above)
+    const int n16 = lane & 15, g16 = lane >> 4;
+    bool zup16[2] = {false, false}, zdn16[2] = {false, false};
+    if constexpr (M16) {
+#pragma unroll
+        for (int hf = 0; hf < 2; hf++) {
+            const int sl16 = (int)((i0 + 32 * wave + 16 * hf + n16) % g.Ls);
+            zup16[hf] = sl16 == g.Ls - 1;
+            zdn16[hf] = sl16 == 0;
+        }
+    }
     auto mfma_path = [&](int pi, int shift) {
-        const bool zero = shift > 0 ? zup : shift < 0 ? zdn : false;
+        if constexpr (M16) {
+            const bf16x4 a = A[pi * 64];
 #pragma unroll
-        for (int st = 0; st < CIN / 4; st++) {
-            const bf16x4 a = A[(pi * (CIN / 4) + st) * 64];
+            for (int tt = 0; tt < 3; tt++)
 #pragma unroll
-            for (int tt = 0; tt < 3; tt++) {
-                bf16x4 b = Tw[((2 * st + h) * 3 + tt) * CSW + jc + 1 + shift];
-                if (zero) b = bf16x4{0, 0, 0, 0};
-                acc[tt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[tt], 0, 0, 0);
+                for (int hf = 0; hf < 2; hf++) {
+                    bf16x4 b = {0, 0, 0, 0};
+                    const bool zero = shift > 0 ? zup16[hf] : shift < 0 ? zdn16[hf] : false;
+                    if (g16 < 2 && !zero) b = Tw[(g16 * 3 + tt) * CSW + 16 * hf + n16 + 1 + shift];
+                    acc[2 * tt + hf] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[2 * tt + hf], 0, 0, 0);
+                }
+        } else {
+            const bool zero = shift > 0 ? zup : shift < 0 ? zdn : false;
+#pragma unroll
+            for (int st = 0; st < CIN / 4; st++) {
+                const bf16x4 a = A[(pi * (CIN / 4) + st) * 64];
+#pragma unroll
+                for (int tt = 0; tt < 3; tt++) {
+                    bf16x4 b = Tw[((2 * st + h) * 3 + tt) * CSW + jc + 1 + shift];
+                    if (zero) b = bf16x4{0, 0, 0, 0};
+                    acc[tt] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[tt], 0, 0, 0);
+                }
             }
         }
     };
@@ -528,40 +571,58 @@ __global__ void __launch_bounds__(256)
         have = have_next;
         cur = nxt;
     }
-    // accumulator register r of tile tt holds row m' = 8 (r / 4) + 4 h + r % 4 of
-    // column jc: colour tt of site ts
+    // one channel pair (a0, a0 + 1) of colour cc at output site i
+    auto store = [&](int a0, int cc, long i, float2 v0, float2 v1) {
+        if constexpr (OBF) {
+            const __hip_bfloat162 b0 = __float22bfloat162_rn(v0), b1 = __float22bfloat162_rn(v1);
+            uint2 w;
+            w.x = *(const uint32_t *)&b0;
+            w.y = *(const uint32_t *)&b1;
+            ((uint2 *)out)[(long)p * (COUT / 2) * 3 * n + (long)((a0 / 2) * 3 + cc) * n + i] = w;
+        } else if (io >> 1 == 1) {
+            // FP32 odd half spinor: 16-byte planes of two components
+            const int c0 = a0 * 3 + cc, c1 = c0 + 3;
+            ((float2 *)out)[(long)(c0 >> 1) * 2 * n + 2 * i + (c0 & 1)] = v0;
+            ((float2 *)out)[(long)(c1 >> 1) * 2 * n + 2 * i + (c1 & 1)] = v1;
+        } else if (io >> 1 == 2) {
+            // BF16 odd half spinor: 16-byte planes of four components
+            const int c0 = a0 * 3 + cc, c1 = c0 + 3;
+            ((__hip_bfloat162 *)out)[(long)(c0 >> 2) * 4 * n + 4 * i + (c0 & 3)] = __float22bfloat162_rn(v0);
+            ((__hip_bfloat162 *)out)[(long)(c1 >> 2) * 4 * n + 4 * i + (c1 & 3)] = __float22bfloat162_rn(v1);
+        } else {
+            const long k = (long)p * COUT * 3 * n + (long)(a0 * 3 + cc) * n + i;
+            ((float2 *)out)[k] = v0;
+            ((float2 *)out)[k + 3 * n] = v1;
+        }
+    };
+    if constexpr (M16) {
+        // accumulator register r of tile (tt, hf) holds row 4 g16 + r of column
+        // n16: channels 2 g16 and 2 g16 + 1 (re, im each) of colour tt at site
+        // 16 hf + n16 of the wavefront; rows 8 and up are zero
+        if (g16 < 2) {
 #pragma unroll
-    for (int tt = 0; tt < 3; tt++) {
-        const int cc = tt;
-        const long i = it;
-        if (i >= n) continue;
+            for (int tt = 0; tt < 3; tt++)
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            // channels a0 = 4 q + 2 h and a0 + 1: one channel pair
-            const int a0 = 4 * q + 2 * h;
-            if (a0 >= COUT) continue;
-            const float2 v0 = make_float2(acc[tt][4 * q], acc[tt][4 * q + 1]);
-            const float2 v1 = make_float2(acc[tt][4 * q + 2], acc[tt][4 * q + 3]);
-            if constexpr (OBF) {
-                const __hip_bfloat162 b0 = __float22bfloat162_rn(v0), b1 = __float22bfloat162_rn(v1);
-                uint2 w;
-                w.x = *(const uint32_t *)&b0;
-                w.y = *(const uint32_t *)&b1;
-                ((uint2 *)out)[(long)p * (COUT / 2) * 3 * n + (long)((a0 / 2) * 3 + cc) * n + i] = w;
-            } else if (io >> 1 == 1) {
-                // FP32 odd half spinor: 16-byte planes of two components
-                const int c0 = a0 * 3 + cc, c1 = c0 + 3;
-                ((float2 *)out)[(long)(c0 >> 1) * 2 * n + 2 * i + (c0 & 1)] = v0;
-                ((float2 *)out)[(long)(c1 >> 1) * 2 * n + 2 * i + (c1 & 1)] = v1;
-            } else if (io >> 1 == 2) {
-                // BF16 odd half spinor: 16-byte planes of four components
-                const int c0 = a0 * 3 + cc, c1 = c0 + 3;
-                ((__hip_bfloat162 *)out)[(long)(c0 >> 2) * 4 * n + 4 * i + (c0 & 3)] = __float22bfloat162_rn(v0);
-                ((__hip_bfloat162 *)out)[(long)(c1 >> 2) * 4 * n + 4 * i + (c1 & 3)] = __float22bfloat162_rn(v1);
-            } else {
-                const long k = (long)p * COUT * 3 * n + (long)(a0 * 3 + cc) * n + i;
-                ((float2 *)out)[k] = v0;
-                ((float2 *)out)[k + 3 * n] = v1;
+                for (int hf = 0; hf < 2; hf++) {
+                    const long i = i0 + 32 * wave + 16 * hf + n16;
+                    if (i >= n) continue;
+                    const AccT &v = acc[2 * tt + hf];
+                    store(2 * g16, tt, i, make_float2(v[0], v[1]), make_float2(v[2], v[3]));
+                }
+        }
+    } else {
+        // accumulator register r of tile tt holds row m' = 8 (r / 4) + 4 h + r % 4 of
+        // column jc: colour tt of site ts
+#pragma unroll
+        for (int tt = 0; tt < 3; tt++) {
+            if (it >= n) continue;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                // channels a0 = 4 q + 2 h and a0 + 1: one channel pair
+                const int a0 = 4 * q + 2 * h;
+                if (a0 >= COUT) continue;
+                store(a0, tt, it, make_float2(acc[tt][4 * q], acc[tt][4 * q + 1]),
+                      make_float2(acc[tt][4 * q + 2], acc[tt][4 * q + 3]));
             }
         }
     }
