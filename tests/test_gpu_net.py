@@ -82,13 +82,15 @@ def test_precond_apply_matches_oracle(case):
         dwf.dwf_net_destroy(net)
 
 
-@pytest.mark.parametrize("chans", [CHANS, [4, 8, 12, 8, 4], [4, 4]])
+@pytest.mark.parametrize("chans", [CHANS, [4, 8, 12, 8, 4], [4, 4], [4, 4, 4]])
 def test_precond_apply_mfma_matches_oracle(case, chans):
     """Matrix-core forward: every transported input is rounded to BF16 (unit
     roundoff 2^-9) before the FP32-accumulated channel mixing, with the same
     BF16 weights as the oracle, and the activations between layers are stored
     in BF16 (another 2^-9).  Without cancellation a layer's relative error is
-    at most 2^-8; four layers compound to (1 + 2^-8)^4 - 1 = 1.57e-2."""
+    at most 2^-8; four layers compound to (1 + 2^-8)^4 - 1 = 1.57e-2.  The
+    4 -> 4 layers run on 16 x 16 tiles ([4, 4]: FP32 input, [4, 4, 4]: the
+    second layer on BF16 activations)."""
     Ws = random_weights(chans, 3)
     net = dwf.dwf_net_create(case.ctx, chans)
     try:
@@ -109,8 +111,9 @@ def test_precond_apply_mfma_matches_oracle(case, chans):
         dwf.dwf_net_destroy(net)
 
 
+@pytest.mark.parametrize("chans", [CHANS, [4, 4, 4]])
 @pytest.mark.parametrize("Ls", [4, 12])
-def test_precond_apply_internal_spinor_layouts(Ls):
+def test_precond_apply_internal_spinor_layouts(Ls, chans):
     """The preconditioner on internal fields as FGCR applies it: with the
     matrix-core forward, an FP32 input and an FP32 or BF16 output, the first
     layer reads the input spinor and the last writes the output spinor directly.
@@ -120,8 +123,8 @@ def test_precond_apply_internal_spinor_layouts(Ls):
     spinor (read by the first layer as FGCR with a BF16 basis passes its
     residual) gives the canonical result of the same BF16-rounded input."""
     c = Case((4, 4, 2, 4), Ls, mf=0.05, dirichlet=(1, 0, 0, 1), eps=0.6, seed=57)
-    Ws = random_weights(CHANS, 6)
-    net = dwf.dwf_net_create(c.ctx, CHANS)
+    Ws = random_weights(chans, 6)
+    net = dwf.dwf_net_create(c.ctx, chans)
     T = torch()
     try:
         dwf.dwf_net_set_weights(net, flat(Ws))
@@ -141,7 +144,7 @@ def test_precond_apply_internal_spinor_layouts(Ls):
                 want = bf16_round(ref_h.real) + 1j * bf16_round(ref_h.imag)
             else:
                 want = ref_h
-            print(f"Ls={Ls} in {pin} out {pout}: max |diff| {np.abs(got - want).max():.2e}", flush=True)
+            print(f"{chans} Ls={Ls} in {pin} out {pout}: max |diff| {np.abs(got - want).max():.2e}", flush=True)
             assert np.array_equal(got, want)
         xh = to_host(x)
         xb = to_gpu((bf16_round(xh.real) + 1j * bf16_round(xh.imag)).astype(xh.dtype))
@@ -156,7 +159,7 @@ def test_precond_apply_internal_spinor_layouts(Ls):
             dwf.dwf_export(c.ctx, 0, pout, yi, y)
             got = to_host(y)
             want = refb_h if pout == dwf.DWF_F32 else bf16_round(refb_h.real) + 1j * bf16_round(refb_h.imag)
-            print(f"Ls={Ls} in {dwf.DWF_BF16} out {pout}: max |diff| {np.abs(got - want).max():.2e}", flush=True)
+            print(f"{chans} Ls={Ls} in {dwf.DWF_BF16} out {pout}: max |diff| {np.abs(got - want).max():.2e}", flush=True)
             assert np.array_equal(got, want)
     finally:
         dwf.dwf_net_destroy(net)
@@ -189,11 +192,12 @@ def test_precond_apply_internal_bf16_input_one_layer():
         c.close()
 
 
-def test_precond_apply_mfma_ragged_tile():
+@pytest.mark.parametrize("chans", [CHANS, [4, 4, 4]])
+def test_precond_apply_mfma_ragged_tile(chans):
     """A lattice whose 3 x (5D sites) columns do not fill the last 128-column tile."""
     c = Case((4, 2, 2, 2), 3, mf=0.1, dirichlet=(0, 1, 0, 0), eps=0.5, seed=52)
-    Ws = random_weights(CHANS, 4)
-    net = dwf.dwf_net_create(c.ctx, CHANS)
+    Ws = random_weights(chans, 4)
+    net = dwf.dwf_net_create(c.ctx, chans)
     try:
         dwf.dwf_net_set_weights(net, flat(Ws))
         dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_MFMA_BF16)
@@ -207,15 +211,16 @@ def test_precond_apply_mfma_ragged_tile():
         c.close()
 
 
+@pytest.mark.parametrize("chans", [CHANS, [4, 4, 4]])
 @pytest.mark.parametrize("Ls", [8, 9, 12, 16])
-def test_precond_apply_mfma_staged_links(Ls):
+def test_precond_apply_mfma_staged_links(Ls, chans):
     """Ls >= 8: the matrix-core forward stages the links and neighbour indices
     of a workgroup's 4D sites in LDS.  A 128-site tile then starts inside a 4D
     site (Ls = 9, 12) and the last tile is ragged; bound as in the matrix-core
     test above."""
     c = Case((4, 2, 2, 2), Ls, mf=0.1, dirichlet=(1, 0, 0, 1), eps=0.5, seed=53 + Ls)
-    Ws = random_weights(CHANS, 5)
-    net = dwf.dwf_net_create(c.ctx, CHANS)
+    Ws = random_weights(chans, 5)
+    net = dwf.dwf_net_create(c.ctx, chans)
     try:
         dwf.dwf_net_set_weights(net, flat(Ws))
         dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_MFMA_BF16)
@@ -224,7 +229,7 @@ def test_precond_apply_mfma_staged_links(Ls):
         dwf.dwf_precond_apply(c.ctx, net, to_gpu(x), out)
         expect = oracle.pick(c.P, oracle_forward(c, Ws, x)[-1], 1)
         err = relerr(to_host(out), expect)
-        print(f"mfma forward Ls={Ls}: relative error {err:.2e}", flush=True)
+        print(f"mfma forward {chans} Ls={Ls}: relative error {err:.2e}", flush=True)
         assert err < 2e-2
     finally:
         dwf.dwf_net_destroy(net)
