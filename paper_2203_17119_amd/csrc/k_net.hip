@@ -320,14 +320,15 @@ __global__ void __launch_bounds__(256)
             }
         }
         if constexpr (IBF) {
-            const long base = (long)sp * NP * 3 * n + src;
+            // a uniform plane base and one 32-bit lane offset per load
+            const uint32_t voff = (uint32_t)((src + (long)half * HP * 3 * n) * 8);
 #pragma unroll
             for (int q = 0; q < HP; q++)
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    const long f = base + (long)((half * HP + q) * 3 + c) * n;
+                    const char *pb = (const char *)in + (long)(sp * NP * 3 + q * 3 + c) * n * 8;
                     if (hv) {
-                        const uint2 w = ((const uint2 *)in)[f];
+                        const uint2 w = *(const uint2 *)(pb + voff);
                         rw[q][0][c] = w.x;
                         rw[q][1][c] = w.y;
                     }
