@@ -9,6 +9,8 @@
   pair per shift re-checked with the oracle's Mpc.
 * 24^4 x Ls=12 periodic: FGCR with the trained network, its solution checked
   by the oracle's D5 residual at sampled sites.
+* 32^4 x Ls=12: the committed trained networks with the matrix-core forward
+  against the oracle's network on the whole lattice.
 """
 import os
 
@@ -89,6 +91,44 @@ def test_mixed_cg_32x32x32x32_ls12_sampled_residual(c3):
     # the sampled residual is an unbiased estimate of the full one
     ratio = np.linalg.norm(r) / np.linalg.norm(b[sites])
     assert ratio < 5 * st["res_full"] + 1e-10
+
+
+@pytest.mark.parametrize("weights", ["ptc_4-4-4_8x8x8x8_ls8.npz", "ptc_4-12-12-12-4_8x8x8x8_ls8.npz"])
+def test_network_32x32x32x32_ls12_matches_oracle(c3, weights):
+    """The committed trained networks (the compact 4-4-4 one beats CG on this
+    lattice) with the matrix-core forward (the launch configuration FGCR
+    uses), against the oracle's network on the whole lattice.  Bound as for the small lattices
+    (BF16 operands and activations: 2e-2 globally); every site's error is
+    also bounded relative to the root-mean-square site norm, which catches
+    a wrong tile, tail or Dirichlet face at any site without being fooled by
+    sites whose exact output is small."""
+    c, w = c3
+    data = np.load(os.path.join(os.path.dirname(dwf.__file__), "weights", weights))
+    chans = [int(v) for v in data["chans"]]
+    flat = np.asarray(data["weights"])
+    Ws, off = [], 0
+    for l in range(len(chans) - 1):
+        n = 11 * chans[l + 1] * chans[l]
+        Ws.append(flat[off:off + n].reshape(11, chans[l + 1], chans[l]))
+        off += n
+    print(f"\n[32^4x12 network {chans}]", flush=True)
+    net = dwf.dwf_net_create(c.ctx, chans)
+    try:
+        dwf.dwf_net_set_weights(net, flat)
+        dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_MFMA_BF16)
+        x = c.half(77)
+        out = torch().empty_like(to_gpu(x))
+        dwf.dwf_precond_apply(c.ctx, net, to_gpu(x), out)
+        got = to_host(out).reshape(-1, 12)
+        want = oracle.net_apply(c.P, c.Ud, Ws, x).reshape(-1, 12)
+        err = relerr(got, want)
+        rms = np.sqrt(np.mean(np.sum(np.abs(want) ** 2, axis=1)))
+        site = float(np.max(np.linalg.norm(got - want, axis=1)) / rms)
+        print(f"relative error {err:.2e}, largest site error / rms site norm {site:.2e}", flush=True)
+        assert err < 2e-2
+        assert site < 0.1
+    finally:
+        dwf.dwf_net_destroy(net)
 
 
 @pytest.mark.parametrize("mode", [dwf.DWF_SOLVE_F64, dwf.DWF_SOLVE_MIXED_F32])
