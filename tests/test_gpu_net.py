@@ -359,7 +359,7 @@ def test_trained_network_gain_over_plain_gcr():
     field: FGCR with the network must reach 1e-8 in the FP64 full residual,
     checked by the oracle's D5, in fewer steps than plain GCR needs (or where
     plain GCR stagnates).  Plain FP64 CG, the method without the network and
-    the judge of it, solves the same source to the same target.  The network
+    the measure it is compared with, solves the same source to the same target.  The network
     must save operator applications against CG (one Mpc per FGCR step, two
     per CG iteration); wall time is set beside it and not asserted: each
     network application costs several Mpc."""
