@@ -418,6 +418,42 @@ def test_trained_network_gain_over_plain_gcr():
         c.close()
 
 
+def test_compact_network_fgcr_bf16_basis():
+    """The committed compact 4-4-4 network (the one the benchmark's fastest
+    solve uses) in FGCR with the BF16 basis on an unseen 8^4 x 8 field: the
+    matrix-core forward on 16 x 16 tiles, the network reading the BF16 copy of
+    the residual and the directions combined unprojected at the restarts.  The
+    solve reaches 1e-8 without the CG fallback, checked by the oracle's D5.
+    (On this periodic field the compact network saves little: about as many
+    Mpc applications as FP64 CG, which is printed beside it; it gains on the
+    Dirichlet block of the benchmark.)"""
+    import os
+    path = os.path.join(os.path.dirname(dwf.__file__), "weights", "ptc_4-4-4_8x8x8x8_ls8.npz")
+    data = np.load(path)
+    w = synth.WORKLOADS["8^4x8_train"]
+    print("\n[8^4x8 field 1201, compact network]", flush=True)
+    c = Case(w.dims, w.Ls, mf=w.mf, dirichlet=w.dirichlet, eps=w.eps, seed=1201)
+    net = dwf.dwf_net_create(c.ctx, [int(v) for v in data["chans"]])
+    try:
+        dwf.dwf_net_set_weights(net, data["weights"])
+        dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_MFMA_BF16)
+        b = c.full(4343)
+        x = torch().zeros_like(to_gpu(b))
+        s_cg, st_cg = dwf.dwf_cg(c.ctx, to_gpu(b), x, tol=1e-8, mode=dwf.DWF_SOLVE_F64)
+        x.zero_()
+        s, st = dwf.dwf_fgcr(c.ctx, net, to_gpu(b), x, tol=1e-8, restart=16, maxit=2000, fallback=False,
+                             mode=dwf.DWF_SOLVE_MIXED_BF16)
+        r = b - oracle.d5(c.P, c.Ud, to_host(x))
+        rel = np.linalg.norm(r) / np.linalg.norm(b)
+        print(f"FP64 CG {st_cg['iters']} iterations ({2 * st_cg['iters']} Mpc); compact FGCR status {s}, "
+              f"{st['iters']} steps (one Mpc each), oracle residual {rel:.2e}", flush=True)
+        assert s_cg == dwf.DWF_OK and s == dwf.DWF_OK and st["fell_back"] == 0
+        assert rel < 1e-7
+    finally:
+        dwf.dwf_net_destroy(net)
+        c.close()
+
+
 def test_adam_step_matches_oracle(case):
     """Three training steps of the library, each against the FP64 Adam reference
     (oracle.adam_step, Kingma & Ba with bias correction) applied to the library's
