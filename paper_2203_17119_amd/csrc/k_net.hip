@@ -296,30 +296,27 @@ __global__ void __launch_bounds__(256)
     // parity sp; returns whether the site holds data
     auto load = [&](long src, int sp, bool hv, int half, RawT (&rw)[HP][2][3]) -> bool {
         if constexpr (BSP) {
-            {
-                // the BF16 odd half spinor: component ch * 3 + colour is word
-                // (m & 3) of 16-byte plane m >> 2; channel pair (2 half,
-                // 2 half + 1) is components 6 half .. 6 half + 5: a whole plane
-                // and half of the middle one
-                hv = hv && sp == 1;
-                if (!hv) return false;
-                const uint32_t *w = (const uint32_t *)in;
-                uint32_t m[6];
-                if (half == 0) {
-                    const uint4 a = *(const uint4 *)(w + 4 * src);
-                    const uint2 b = *(const uint2 *)(w + 4 * n + 4 * src);
-                    m[0] = a.x, m[1] = a.y, m[2] = a.z, m[3] = a.w, m[4] = b.x, m[5] = b.y;
-                } else {
-                    const uint2 b = *(const uint2 *)(w + 4 * n + 4 * src + 2);
-                    const uint4 a = *(const uint4 *)(w + 8 * n + 4 * src);
-                    m[0] = b.x, m[1] = b.y, m[2] = a.x, m[3] = a.y, m[4] = a.z, m[5] = a.w;
-                }
-#pragma unroll
-                for (int k = 0; k < 6; k++) rw[0][k / 3][k % 3] = m[k];
-                return true;
+            // the BF16 odd half spinor: component ch * 3 + colour is word
+            // (m & 3) of 16-byte plane m >> 2; channel pair (2 half,
+            // 2 half + 1) is components 6 half .. 6 half + 5: a whole plane
+            // and half of the middle one
+            hv = hv && sp == 1;
+            if (!hv) return false;
+            const uint32_t *w = (const uint32_t *)in;
+            uint32_t m[6];
+            if (half == 0) {
+                const uint4 a = *(const uint4 *)(w + 4 * src);
+                const uint2 b = *(const uint2 *)(w + 4 * n + 4 * src);
+                m[0] = a.x, m[1] = a.y, m[2] = a.z, m[3] = a.w, m[4] = b.x, m[5] = b.y;
+            } else {
+                const uint2 b = *(const uint2 *)(w + 4 * n + 4 * src + 2);
+                const uint4 a = *(const uint4 *)(w + 8 * n + 4 * src);
+                m[0] = b.x, m[1] = b.y, m[2] = a.x, m[3] = a.y, m[4] = a.z, m[5] = a.w;
             }
-        }
-        if constexpr (IBF) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) rw[0][k / 3][k % 3] = m[k];
+            return true;
+        } else if constexpr (IBF) {
             // a uniform plane base and one 32-bit lane offset per load
             const uint32_t voff = (uint32_t)((src + (long)half * HP * 3 * n) * 8);
 #pragma unroll
