@@ -347,6 +347,28 @@ def test_fgcr_bf16_basis_reaches_tolerance(case, normal):
         dwf.dwf_net_destroy(net)
 
 
+@pytest.mark.parametrize("restart,tol,normal", [(1, 0.05, True), (64, 1e-9, False)])
+def test_fgcr_bf16_basis_restart_extremes(case, restart, tol, normal):
+    """The cycle lengths at the ends of the allowed range with the BF16 basis,
+    whose solution update is combined at the restart from the unprojected
+    directions: one direction per cycle (the combination is the step's own
+    coefficient) and the longest cycle (64 directions, the largest triangular
+    system of the combination).  Plain GCR, checked by the oracle's D5.  One
+    direction per cycle is the minimal-residual iteration, which stalls on the
+    non-normal Schur operator: it runs on the normal equations, to a loose
+    tolerance."""
+    b = case.full(84)
+    x = torch().zeros_like(to_gpu(b))
+    status, st = dwf.dwf_fgcr(case.ctx, None, to_gpu(b), x, tol=tol, restart=restart, maxit=20000,
+                              normal=normal, fallback=False, mode=dwf.DWF_SOLVE_MIXED_BF16)
+    r = b - oracle.d5(case.P, case.Ud, to_host(x))
+    rel = np.linalg.norm(r) / np.linalg.norm(b)
+    print(f"GCR({restart}) BF16 basis to {tol:g}: status {status}, {st['iters']} steps, oracle residual {rel:.2e}",
+          flush=True)
+    assert status == dwf.DWF_OK and st["fell_back"] == 0
+    assert rel < 10 * tol
+
+
 def test_fgcr_without_fallback_reports_noconv(case):
     b = case.full(82)
     x = torch().zeros_like(to_gpu(b))
