@@ -428,7 +428,10 @@ dwf_status dwf_net_train_step(dwf_net net, int nbatch, const double *const *b_od
  * restarts) over max(8 m, 256) steps.  On stagnation or a non-finite residual
  * it falls back to dwf_cg in FP64 when o->fallback (the statistics then say
  * fell_back = 1).  Same source preparation and reconstruction as dwf_cg;
- * canonical FP64 full fields. */
+ * canonical FP64 full fields.  Its vectors are context workspace fields; its
+ * Gram-Schmidt coefficient tables and partial sums (O(m^2) doubles plus one
+ * per workgroup) are allocated and freed by each call, also while a caller
+ * workspace is set, so FGCR has no entry in the workspace operations. */
 dwf_status dwf_fgcr(dwf_ctx ctx, dwf_net net, const double *b_full, double *x_full, const dwf_solver_opts *o,
                     dwf_solver_stats *st);
 
