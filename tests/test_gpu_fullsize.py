@@ -11,6 +11,9 @@
   by the oracle's D5 residual at sampled sites.
 * 32^4 x Ls=12: the committed trained networks with the matrix-core forward
   against the oracle's network on the whole lattice.
+* Chebyshev filter: every storage precision against the oracle on the whole
+  16^4 x Ls=12 block; at 32^4 x Ls=12 its first orders and its three-term
+  recurrence at the benchmark's orders, through the FP64 Schur operator.
 """
 import os
 
@@ -199,3 +202,102 @@ def test_fgcr_learned_24x24x24x24_ls12_periodic():
     finally:
         dwf.dwf_net_destroy(net)
         c.close()
+
+
+# unit roundoff of each storage precision (FP16 and BF16 relative to a site's scale)
+UNIT = {dwf.DWF_F64: 1.1e-16, dwf.DWF_F32: 6e-8, dwf.DWF_F16: 4.9e-4, dwf.DWF_BF16: 3.9e-3}
+
+
+def test_chebyshev_16x16x16x16_ls12_matches_oracle():
+    """The Chebyshev filter (Sec. 2.4) in every storage precision on the
+    16^4 x Ls=12 Dirichlet block, against the oracle's recurrence on the whole
+    lattice.  hi is twice a four-step oracle power estimate of the top of
+    A = Mpc^+ Mpc (an overestimate only widens the interval), lo = hi / 100.
+    Bounds as on the small lattices: an error made at step j reaches step k
+    through U_{k-j}, at most k - j + 1 on [-1, 1], so after k steps it is
+    below (k + 1)(k + 2) u; the first two orders are also checked site by site
+    (one application of A reads a site's 4-hop neighbourhood, hence 50 u)."""
+    w = synth.WORKLOADS["16^4x12_dirichlet"]
+    print("\n[16^4x12 dirichlet, Chebyshev filter against the oracle]", flush=True)
+    c = Case(w.dims, w.Ls, mf=w.mf, dirichlet=w.dirichlet, eps=w.eps, seed=w.gauge_seed)
+    try:
+        v = c.half(2718)
+        u = v / np.linalg.norm(v)
+        for _ in range(4):
+            u = oracle.mpc(c.P, c.Ud, oracle.mpc(c.P, c.Ud, u), True)
+            lam = np.linalg.norm(u)
+            u /= lam
+        hi = 2.0 * lam
+        lo = hi / 100
+        orders = [0, 1, 2, 5, 8]
+        want = oracle.chebyshev(c.P, c.Ud, v, lo, hi, orders)
+        g = to_gpu(v)
+        for prec in (dwf.DWF_F64, dwf.DWF_F32, dwf.DWF_F16, dwf.DWF_BF16):
+            outs = [torch().empty_like(g) for _ in orders]
+            dwf.dwf_chebyshev_filter(c.ctx, g, lo, hi, orders, outs, prec=prec)
+            for k, o, e in zip(orders, outs, want):
+                got = to_host(o)
+                err, serr = relerr(got, e), site_relerr(got, e)
+                print(f"prec {prec} order {k}: relative error {err:.2e}, worst site {serr:.2e}", flush=True)
+                assert err < max(1e-11, (k + 1) * (k + 2) * UNIT[prec]), (prec, k)
+                if k <= 1:
+                    assert serr < max(1e-10, 50 * UNIT[prec]), (prec, k)
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("prec", [dwf.DWF_F64, dwf.DWF_F16])
+def test_chebyshev_32x32x32x32_ls12_recurrence(c3, prec):
+    """At 32^4 x Ls=12, where the oracle's recurrence takes minutes, the
+    filter's outputs at the benchmark's orders and their neighbours are
+    checked by what holds at any size: T_0 v = v, T_1 v = x(A) v and
+    T_{k+1} v + T_{k-1} v = 2 x(A) T_k v, with x(A) = (2 A - (hi + lo)) /
+    (hi - lo) applied in FP64 by the Schur operator (whose hop is checked
+    against the oracle at sampled sites above).  The filter rounds each new
+    vector once, and inside x(A) the stored Mpc w and A w, each scaled by
+    2 / (hi - lo) against |A| <= hi: a step's residual is below about 9 u of
+    the largest of its three vectors; the bound is 12 u (1e-12 in FP64)."""
+    c, w = c3
+    T = torch()
+    print(f"\n[32^4x12 Chebyshev filter recurrence, prec {prec}]", flush=True)
+    v = to_gpu(c.half(4242))
+
+    def A(x):
+        t, y = T.empty_like(x), T.empty_like(x)
+        dwf.dwf_schur_apply(c.ctx, 0, x, t)
+        dwf.dwf_schur_apply(c.ctx, 1, t, y)
+        return y
+
+    u = v / v.norm()
+    for _ in range(20):
+        u = A(u)
+        lam = float(u.norm())
+        u /= lam
+    del u
+    hi = 1.1 * lam
+    lo = hi / 100
+    a, sh = 2.0 / (hi - lo), -(hi + lo) / (hi - lo)
+    orders = [0, 1, 7, 8, 9, 31, 32, 33]
+    outs = [T.empty_like(v) for _ in orders]
+    dwf.dwf_tune(c.ctx, dwf.DWF_F16, tuned_cache())
+    dwf.dwf_chebyshev_filter(c.ctx, v, lo, hi, orders, outs, prec=prec)
+    T.cuda.synchronize()
+    bound = max(1e-12, 12 * UNIT[prec])
+    out = dict(zip(orders, outs))
+    e0 = float((out[0] - v).norm() / v.norm())
+    x1 = a * A(v) + sh * v
+    e1 = float((out[1] - x1).norm() / x1.norm())
+    d = (out[1] - x1).reshape(-1, 12).norm(dim=1)
+    n = x1.reshape(-1, 12).norm(dim=1)
+    keep = n > 1e-6 * n.max()
+    s1 = float((d[keep] / n[keep]).max())
+    del x1, d, n, keep
+    print(f"T_0 v - v: {e0:.2e}; T_1 v - x(A) v: {e1:.2e}, worst site {s1:.2e}", flush=True)
+    assert e0 < UNIT[prec] + 1e-15 and e1 < bound and s1 < max(1e-10, 50 * UNIT[prec])
+    for k in (8, 32):
+        r = out[k + 1] + out[k - 1] - 2 * (a * A(out[k]) + sh * out[k])
+        top = max(float(out[j].norm()) for j in (k - 1, k, k + 1))
+        rel = float(r.norm()) / top
+        print(f"order {k}: |T_(k+1) v + T_(k-1) v - 2 x(A) T_k v| / max norm = {rel:.2e} "
+              f"(|T_k v| / |v| = {float(out[k].norm() / v.norm()):.3f})", flush=True)
+        assert rel < bound, k
