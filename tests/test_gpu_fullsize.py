@@ -78,9 +78,11 @@ def test_dhop_32x32x32x32_ls12_sampled(c3):
     assert site_relerr(got, expect) < SITE_TOL[dwf.DWF_F16]
 
 
-def test_mixed_cg_32x32x32x32_ls12_sampled_residual(c3):
+@pytest.mark.parametrize("src", range(4))
+def test_mixed_cg_32x32x32x32_ls12_sampled_residual(c3, src):
+    """Each of the workload's four sources, as the benchmark cycles them."""
     c, w = c3
-    b = c.full(w.source_seeds[0])
+    b = c.full(w.source_seeds[src])
     bg = to_gpu(b)
     x = torch().zeros_like(bg)
     dwf.dwf_tune(c.ctx, dwf.DWF_F16, tuned_cache())
@@ -89,7 +91,7 @@ def test_mixed_cg_32x32x32x32_ls12_sampled_residual(c3):
     assert status == dwf.DWF_OK and st["res_normal"] <= w.tol * 1.0000001
     assert st["res_full"] < 1e-6
     xh = to_host(x)
-    sites = np.random.default_rng(7).choice(c.P.V, 2 * NSAMPLE, replace=False)
+    sites = np.random.default_rng(7 + src).choice(c.P.V, 2 * NSAMPLE, replace=False)
     r = b[sites] - oracle.d5_sites(c.P, c.Ud, xh, sites)
     # the sampled residual is an unbiased estimate of the full one
     ratio = np.linalg.norm(r) / np.linalg.norm(b[sites])
