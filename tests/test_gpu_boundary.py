@@ -2,7 +2,7 @@
 action (Sec. 2.1): the link cut by a domain mask, D5 on full fields, the
 projector P and the operators R and R^-1, against the oracle (pinned in
 test_oracle_boundary.py), and the identities R R^-1 = P and D_dbar P = D_dbar
-on the GPU at 8^4 x 8."""
+on the GPU at 8^4 x 8 and at the benchmark's 24^4 x 12 periodic split."""
 import numpy as np
 import pytest
 
@@ -211,3 +211,68 @@ def test_boundary_apply_in_caller_workspace():
     finally:
         ref_c.close()
         c.close()
+
+
+def test_boundary_24x24x24x24_ls12_periodic_split():
+    """The benchmark's configuration: the 24^4 x 12 periodic lattice (mf 0.01,
+    eps 0.7) split at t = 12, Omega = t < 12, solves in mixed FP16 storage to
+    1e-8.  The cut links and the projector against the oracle on the whole
+    lattice, D_dbar P = D_dbar through the two contexts' D5, and
+    R R^-1 psi = P psi within 1e4 times the solves' tolerance, the ratio of
+    the 8^4 x 8 test (three solves, each error amplified by the operators of
+    the chain)."""
+    w = synth.WORKLOADS["24^4x12_fgcr"]
+    L = tuple(w.dims)
+    print(f"\n[boundary {L} ls{w.Ls} periodic, Omega = t < {L[3] // 2}, mixed FP16 solves]", flush=True)
+    T = torch()
+    P = Params(L, w.Ls, w.b, w.c, w.M5, w.mf)
+    U = synth.gauge_field(L, w.eps, w.gauge_seed)
+    mask = _mask_t(L, L[3] // 2)
+    mask_dev = T.from_numpy(mask).cuda()
+    full = dwf.Lattice(L, w.Ls, w.b, w.c, w.M5, w.mf, w.dirichlet, gauge=U)
+    cut = None
+    try:
+        U_dev = to_gpu(U)
+        Uc_dev = T.empty_like(U_dev)
+        dwf.dwf_mask_links(full.ctx, mask_dev, U_dev, Uc_dev)
+        del U_dev
+        assert np.array_equal(to_host(Uc_dev), oracle.mask_cut(L, U, mask))
+        cut = dwf.Lattice(L, w.Ls, w.b, w.c, w.M5, w.mf, w.dirichlet, gauge=Uc_dev)
+        del Uc_dev, U
+        psi_h = synth.gaussian_fermion(L, w.Ls, w.source_seeds[0])
+        psi = to_gpu(psi_h)
+        p = T.empty_like(psi)
+        dwf.dwf_boundary_project(full.ctx, mask_dev, psi, p)
+        want = oracle.boundary_projector(P, mask, psi_h)
+        err = float(np.abs(to_host(p) - want).max() / np.abs(want).max())
+        print(f"|P psi - oracle| / max = {err:.2e}", flush=True)
+        assert err < 1e-13
+        del want, psi_h
+        a, b = T.empty_like(psi), T.empty_like(psi)
+        keep = T.from_numpy(mask.astype(np.float64)).cuda().reshape(-1, 1, 1, 1)
+
+        def dbar(v):
+            dwf.dwf_d5_apply(full.ctx, v, a)
+            dwf.dwf_d5_apply(cut.ctx, v, b)
+            return a - b
+
+        on = psi * keep
+        ref = dbar(on)
+        e_dp = float((dbar(p) - ref).norm() / ref.norm())
+        del on, ref, keep
+        rinv, back = T.empty_like(psi), T.empty_like(psi)
+        s1, st1 = dwf.dwf_boundary_apply(full.ctx, cut.ctx, mask_dev, psi, rinv, inverse=True, tol=w.tol,
+                                         mode=dwf.DWF_SOLVE_MIXED_F16)
+        s2, st2 = dwf.dwf_boundary_apply(full.ctx, cut.ctx, mask_dev, rinv, back, tol=w.tol,
+                                         mode=dwf.DWF_SOLVE_MIXED_F16)
+        err = float((back - p).norm() / p.norm())
+        print(f"|D_dbar P psi - D_dbar psi| / |D_dbar psi| = {e_dp:.2e}; |R R^-1 psi - P psi| / |P psi| = "
+              f"{err:.2e}; R^-1 {st1['iters']} iterations {st1['seconds']:.3f} s, R {st2['iters']} iterations "
+              f"{st2['seconds']:.3f} s", flush=True)
+        assert e_dp < 1e-13
+        assert s1 == dwf.DWF_OK and s2 == dwf.DWF_OK
+        assert err < 1e4 * w.tol
+    finally:
+        full.close()
+        if cut is not None:
+            cut.close()
