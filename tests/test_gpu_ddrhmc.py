@@ -14,6 +14,9 @@ Tolerances, from the solver's guarantee: every shifted system meets
 and the absolute error of r(A) v is at most e = tol |v| sum_k |alpha_k| / (lmin + beta_k).
 The action's error follows from the two errors e_q (of psi) and e_m (of chi):
 |dS| <= e_q |r_m(A)| (2 |psi| + e_q) + (|psi| + e_q) e_m.
+
+Beyond the dense oracle's reach (8^4 x 8, and the benchmark's 16^4 x 12 field
+with both operators) the inverse square root is checked by A r_m(A)^2 v = v.
 """
 import json
 import os
@@ -187,6 +190,51 @@ def test_inverse_square_root_squared_at_8x8x8x8_ls8():
         err = np.linalg.norm(z - v) / vn
         print(f"|A r(A)^2 v - v| / |v| = {err:.2e} (bound {bound:.2e}), worst shift {st1['iters']} iters",
               flush=True)
+        assert err <= bound
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("which", ["periodic", "cut"])
+def test_inverse_square_root_squared_16x16x16x16_ls12(which):
+    """The benchmark's DD-RHMC field (16^4 x 12, mf 0.01, eps 0.7): the
+    whole-lattice operator A and the block operator A_d with every face cut,
+    each through the degree-20 approximation of x^{-1/2} on [1e-5, 1000]
+    that the benchmark applies: A r_m(A)^2 v = v within the bound of the
+    8^4 x 8 test (the spectrum's top from eight oracle power steps, margin
+    1.5), the last A applied by the oracle on the whole lattice."""
+    from paper_2203_17119_amd import synth
+    w = synth.WORKLOADS["16^4x12_multishift"]
+    r = load_rational("x-0.5_1e-05_1000_n20.json")
+    mask = (0, 0, 0, 0) if which == "periodic" else (1, 1, 1, 1)
+    print(f"\n[ddrhmc 16x16x16x16_ls12 {which}: A r_m(A)^2 v = v]", flush=True)
+    c = Case(w.dims, w.Ls, mf=w.mf, dirichlet=mask, eps=w.eps, seed=w.gauge_seed)
+    try:
+        v = c.half(w.source_seeds[0])
+        u = v / np.linalg.norm(v)
+        for _ in range(8):
+            u = oracle.mpc(c.P, c.Ud, oracle.mpc(c.P, c.Ud, u), True)
+            top = np.linalg.norm(u)
+            u = u / top
+        del u
+        top *= 1.5
+        assert top < r["hi"]
+        tol = 1e-11
+        rm = dwf.make_rational(*coeffs(r))
+        a = to_gpu(v)
+        y = torch().empty_like(a)
+        s1, st1 = dwf.dwf_rational_apply(c.ctx, rm, a, y, tol=tol)
+        yn = float(y.norm())
+        s2, st2 = dwf.dwf_rational_apply(c.ctx, rm, y, y, tol=tol)
+        assert s1 == s2 == dwf.DWF_OK, (st1, st2)
+        z = oracle.mpc(c.P, c.Ud, oracle.mpc(c.P, c.Ud, to_host(y)), True)
+        eps = r["max_rel_error"]
+        vn = np.linalg.norm(v)
+        s0 = sum(abs(al) / be for al, be in zip(r["alpha"], r["beta"]))
+        bound = 2 * eps + eps ** 2 + tol * s0 * (np.sqrt(top) * (1 + eps) + top * yn / vn)
+        err = np.linalg.norm(z - v) / vn
+        print(f"spectrum top {top / 1.5:.1f}: |A r(A)^2 v - v| / |v| = {err:.2e} (bound {bound:.2e}), "
+              f"worst shift {st1['iters']} iterations, {st1['seconds']:.2f} s", flush=True)
         assert err <= bound
     finally:
         c.close()
