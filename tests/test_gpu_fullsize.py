@@ -10,7 +10,8 @@
 * 24^4 x Ls=12 periodic: FGCR with the trained network, its solution checked
   by the oracle's D5 residual at sampled sites.
 * 32^4 x Ls=12: the committed trained networks with the matrix-core forward
-  against the oracle's network on the whole lattice.
+  against the oracle's network on the whole lattice, and FGCR with each of
+  them, its solution checked by the oracle's D5 at sampled sites.
 * Chebyshev filter: every storage precision against the oracle on the whole
   16^4 x Ls=12 block; at 32^4 x Ls=12 its first orders and its three-term
   recurrence at the benchmark's orders, through the FP64 Schur operator.
@@ -132,6 +133,38 @@ def test_network_32x32x32x32_ls12_matches_oracle(c3, weights):
         print(f"relative error {err:.2e}, largest site error / rms site norm {site:.2e}", flush=True)
         assert err < 2e-2
         assert site < 0.1
+    finally:
+        dwf.dwf_net_destroy(net)
+
+
+@pytest.mark.parametrize("weights", ["ptc_4-4-4_8x8x8x8_ls8.npz", "ptc_4-12-12-12-4_8x8x8x8_ls8.npz"])
+def test_fgcr_learned_32x32x32x32_ls12_sampled_residual(c3, weights):
+    """The benchmark's learned-preconditioner leg: FGCR(16) with a committed
+    network, matrix-core forward, BF16 Krylov basis, on the first source, no
+    CG fallback; it converges in the FP64 full residual, and its solution is
+    checked by the oracle's D5 at sampled sites."""
+    c, w = c3
+    data = np.load(os.path.join(os.path.dirname(dwf.__file__), "weights", weights))
+    print(f"\n[32^4x12 FGCR(16) + {weights}]", flush=True)
+    net = dwf.dwf_net_create(c.ctx, [int(v) for v in data["chans"]])
+    try:
+        dwf.dwf_net_set_weights(net, data["weights"])
+        dwf.dwf_net_set_forward(net, dwf.DWF_NET_FWD_MFMA_BF16)
+        b = c.full(w.source_seeds[0])
+        bg = to_gpu(b)
+        x = torch().zeros_like(bg)
+        dwf.dwf_tune(c.ctx, dwf.DWF_F16, tuned_cache())
+        s, st = dwf.dwf_fgcr(c.ctx, net, bg, x, tol=w.tol, restart=16, maxit=2000, fallback=False,
+                             mode=dwf.DWF_SOLVE_MIXED_BF16)
+        print(f"status {s}: {st['iters']} steps {st['seconds']:.3f} s, full residual {st['res_full']:.2e}", flush=True)
+        # FGCR stops on the Schur residual; the full one lands near it
+        assert s == dwf.DWF_OK and st["fell_back"] == 0 and st["res_full"] <= 1.5 * w.tol
+        xh = to_host(x)
+        sites = np.random.default_rng(9).choice(c.P.V, 2 * NSAMPLE, replace=False)
+        r = b[sites] - oracle.d5_sites(c.P, c.Ud, xh, sites)
+        ratio = np.linalg.norm(r) / np.linalg.norm(b[sites])
+        print(f"sampled oracle residual {ratio:.2e}", flush=True)
+        assert ratio < 5 * st["res_full"] + 1e-10
     finally:
         dwf.dwf_net_destroy(net)
 
