@@ -23,7 +23,7 @@ import pytest
 
 import oracle
 from paper_2203_17119_amd import dwf, synth
-from gpu_helpers import SITE_TOL, Case, relerr, site_relerr, to_gpu, to_host, torch
+from gpu_helpers import SITE_TOL, TOL, Case, relerr, site_relerr, to_gpu, to_host, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -77,6 +77,18 @@ def test_dhop_32x32x32x32_ls12_sampled(c3):
           flush=True)
     assert relerr(got, expect) < 2e-3
     assert site_relerr(got, expect) < SITE_TOL[dwf.DWF_F16]
+    # the other storage precisions, in the same schedule
+    for prec in (dwf.DWF_F32, dwf.DWF_BF16):
+        a, b = c.lat.internal(prec), c.lat.internal(prec)
+        dwf.dwf_import(c.ctx, 0, prec, xg, a)
+        dwf.dwf_dhop_internal(c.ctx, prec, 1, 0, a, b)
+        dwf.dwf_export(c.ctx, 0, prec, b, out)
+        del a, b
+        got = out[torch().from_numpy(cbs).cuda()].cpu().numpy()
+        print(f"prec {prec} dhop at sampled sites: global {relerr(got, expect):.2e}, "
+              f"worst site {site_relerr(got, expect):.2e}", flush=True)
+        assert relerr(got, expect) < TOL[prec]
+        assert site_relerr(got, expect) < SITE_TOL[prec]
 
 
 @pytest.mark.parametrize("src", range(4))
