@@ -105,3 +105,25 @@ def test_rational_action_within_its_bound():
     bound = action_bound(rq["max_rel_error"], rm["max_rel_error"], np.linalg.eigvalsh(A)[0] ** -0.5,
                          np.vdot(psi, psi).real)
     assert S > 0 and abs(Sr - S) <= bound, (S, Sr, bound)
+
+
+@pytest.mark.parametrize("name", ["x0.25_0.01_100_n12.json", "x-0.5_0.01_100_n12.json", "x0.25_1e-05_100_n20.json",
+                                  "x-0.5_1e-05_100_n20.json", "x-0.5_1e-05_1000_n20.json", "x0.25_1e-05_1000_n20.json"])
+def test_rational_error_equioscillates(name):
+    """A best relative approximation of type (n, n) has a relative error that
+    reaches its maximum with alternating signs at least 2n + 2 times on the
+    interval (Chebyshev's alternation theorem); a bounded but not best fit,
+    or a file whose poles or residues were perturbed, does not."""
+    r = load_rational(name)
+    n, p = r["degree"], r["power"]
+    x = np.geomspace(r["lo"], r["hi"], 400001)
+    e = (r["a0"] + sum(a / (x + b) for a, b in zip(r["alpha"], r["beta"]))) / x ** p - 1
+    emax = np.abs(e).max()
+    assert r["max_rel_error"] * (1 - 1e-2) <= emax <= r["max_rel_error"] * (1 + 1e-3)  # the stated error is the one reached
+    # local extrema of e (the two end points included), kept where |e| is near the maximum
+    inner = np.where((np.diff(np.sign(np.diff(e))) != 0))[0] + 1
+    idx = np.concatenate(([0], inner, [len(x) - 1]))
+    peaks = [i for i in idx if abs(e[i]) >= 0.99 * emax]
+    signs = np.sign(e[peaks])
+    alternations = 1 + int(np.count_nonzero(signs[1:] != signs[:-1]))
+    assert alternations >= 2 * n + 2, (alternations, 2 * n + 2)
